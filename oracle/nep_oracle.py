@@ -314,6 +314,29 @@ class NEPOracle:
         return np.array([L, acc[0], acc[1], acc[2]]), grad.numpy()
 
 
+    def cotangent_grad(self, theta_np, structures, e_bar, f_bar, v_bar, nbr_cache=None):
+        """Gradient of sum_n e_bar[n] E(n) + sum_i f_bar_i . F_i + sum_n v_bar[n] . W(n)
+        with respect to the parameters (a vector-Jacobian product written as the
+        derivative of that contraction).  f_bar: list of [n,3] or [N,3]."""
+        theta = torch.tensor(np.asarray(theta_np, np.float32).astype(np.float64), dtype=DT, requires_grad=True)
+        S = len(structures)
+        e_bar = np.asarray(e_bar, np.float64)
+        v_bar = np.asarray(v_bar, np.float64).reshape(S, 6)
+        if not isinstance(f_bar, (list, tuple)):
+            fb = np.asarray(f_bar, np.float64).reshape(-1, 3)
+            offs = np.cumsum([0] + [st.n for st in structures])
+            f_bar = [fb[offs[k]:offs[k + 1]] for k in range(S)]
+        grad = torch.zeros(self.sz.n_params, dtype=DT)
+        for k, st in enumerate(structures):
+            nb = nbr_cache[k] if nbr_cache is not None else None
+            r = self.structure(theta, st, nb, create_graph=True)
+            c = (e_bar[k] * r["E"] + (torch.tensor(np.asarray(f_bar[k], np.float64), dtype=DT) * r["F"]).sum()
+                 + (torch.tensor(v_bar[k], dtype=DT) * voigt(r["W"])).sum())
+            (g,) = torch.autograd.grad(c, theta)
+            grad += g
+        return grad.numpy()
+
+
 def four_body(S2: torch.Tensor) -> torch.Tensor:
     """q4_n = tr(M_n^3) with M_n the traceless symmetric matrix that the l = 2
     sums S_n2m represent: M_zz = S_20/3, M_xz = S_21, M_yz = S_22,

@@ -1,0 +1,240 @@
+// Device-side arithmetic of the NEP descriptor, written for gfx950 (wave64).
+//
+// Radial basis: Eq. 6 with the Chebyshev recursion (A1.1, A1.5) and the cosine
+// cutoff (A2.1-A2.2).  Angular basis: the Cartesian harmonics of Appendix B for
+// l <= 4, evaluated on the unit vector u = d/|d| (on the unit sphere r^2 = 1, so
+// the polynomials simplify), with their Cartesian gradients.  Because
+// B_lm(d) = b_lm(d/|d|) has degree 0, grad_d B_lm = (I - u u^T) grad b(u) / |d|
+// for any extension of b off the sphere.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nep {
+
+constexpr int kWave = 64;
+
+template <int T_, int NR_, int NA_, int KR_, int KA_, int L3_, int L4_, int L5_>
+struct Cfg {
+  static constexpr int T = T_, NR = NR_, NA = NA_, KR = KR_, KA = KA_;
+  static constexpr int L3 = L3_, L4 = L4_, L5 = L5_;
+  static constexpr int LMAX = (L3 > L4 ? (L3 > L5 ? L3 : L5) : (L4 > L5 ? L4 : L5));
+  static constexpr int Y = LMAX * (LMAX + 2);
+  static constexpr int D = NR + NA * L3 + (L4 ? NA : 0) + (L5 ? NA : 0);
+  static constexpr int PS = T * NR * KR + T * NA * KA;  // c-grad slots of one center species
+};
+
+// ------------------------------------------------------------------ radial
+// f_k(r) = (T_k(xi) + 1)/2 * f_c(r), xi = 2 (r/rc - 1)^2 - 1, and df_k/dr.
+template <int K>
+__device__ __forceinline__ void radial_basis(float r, float inv_rc, float (&f)[K]) {
+  const float x = r * inv_rc - 1.0f;
+  const float xi = 2.0f * x * x - 1.0f;
+  const float fc = 0.5f + 0.5f * cospif(r * inv_rc);
+  float t0 = 1.0f, t1 = xi;
+  f[0] = fc;
+  if (K > 1) f[1] = 0.5f * (xi + 1.0f) * fc;
+#pragma unroll
+  for (int k = 2; k < K; ++k) {
+    const float t2 = 2.0f * xi * t1 - t0;
+    f[k] = 0.5f * (t2 + 1.0f) * fc;
+    t0 = t1;
+    t1 = t2;
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void radial_basis_d(float r, float inv_rc, float (&f)[K], float (&fp)[K]) {
+  const float x = r * inv_rc - 1.0f;
+  const float xi = 2.0f * x * x - 1.0f;
+  const float dxi = 4.0f * x * inv_rc;
+  float s, c;
+  sincospif(r * inv_rc, &s, &c);
+  const float fc = 0.5f + 0.5f * c;
+  const float fcp = -0.5f * 3.14159265358979f * inv_rc * s;
+  float t0 = 1.0f, t1 = xi, d0 = 0.0f, d1 = 1.0f;
+  f[0] = fc;
+  fp[0] = fcp;
+  if (K > 1) {
+    f[1] = 0.5f * (xi + 1.0f) * fc;
+    fp[1] = 0.5f * dxi * fc + 0.5f * (xi + 1.0f) * fcp;
+  }
+#pragma unroll
+  for (int k = 2; k < K; ++k) {
+    const float t2 = 2.0f * xi * t1 - t0;
+    const float d2 = 2.0f * t1 + 2.0f * xi * d1 - d0;
+    f[k] = 0.5f * (t2 + 1.0f) * fc;
+    fp[k] = 0.5f * d2 * dxi * fc + 0.5f * (t2 + 1.0f) * fcp;
+    t0 = t1;
+    t1 = t2;
+    d0 = d1;
+    d1 = d2;
+  }
+}
+
+// ---------------------------------------------------------------- angular
+// C_lm * 4 pi for l = 1..4 in Appendix-B order.  C_lm = 1 / (integral over the
+// unit sphere of b_lm^2), which makes sum_m C_lm B_lm(u) B_lm(v) equal to
+// (2l+1)/(4 pi) P_l(u.v) (the addition theorem behind Eq. 7).
+__device__ __forceinline__ float clm(int lm) {
+  constexpr float inv4pi = 0.0795774715459477f;
+  constexpr float c[24] = {3.f, 3.f, 3.f,
+                           1.25f, 15.f, 15.f, 3.75f, 3.75f,
+                           1.75f, 2.625f, 2.625f, 26.25f, 26.25f, 4.375f, 4.375f,
+                           0.140625f, 5.625f, 5.625f, 2.8125f, 2.8125f, 39.375f, 39.375f,
+                           4.921875f, 4.921875f};
+  return c[lm] * inv4pi;
+}
+
+// b_lm(u) for |u| = 1, l = 1..LM (Appendix B with r = 1).
+template <int LM>
+__device__ __forceinline__ void harm_val(float x, float y, float z, float (&b)[LM * (LM + 2)]) {
+  b[0] = z;
+  b[1] = x;
+  b[2] = y;
+  if constexpr (LM >= 2) {
+    b[3] = 3.0f * z * z - 1.0f;
+    b[4] = x * z;
+    b[5] = y * z;
+    b[6] = x * x - y * y;
+    b[7] = 2.0f * x * y;
+  }
+  if constexpr (LM >= 3) {
+    const float z2 = z * z, x2 = x * x, y2 = y * y;
+    b[8] = (5.0f * z2 - 3.0f) * z;
+    b[9] = (5.0f * z2 - 1.0f) * x;
+    b[10] = (5.0f * z2 - 1.0f) * y;
+    b[11] = (x2 - y2) * z;
+    b[12] = 2.0f * x * y * z;
+    b[13] = (x2 - 3.0f * y2) * x;
+    b[14] = (3.0f * x2 - y2) * y;
+  }
+  if constexpr (LM >= 4) {
+    const float z2 = z * z, x2 = x * x, y2 = y * y;
+    b[15] = (35.0f * z2 - 30.0f) * z2 + 3.0f;
+    b[16] = (7.0f * z2 - 3.0f) * z * x;
+    b[17] = (7.0f * z2 - 3.0f) * z * y;
+    b[18] = (7.0f * z2 - 1.0f) * (x2 - y2);
+    b[19] = (7.0f * z2 - 1.0f) * 2.0f * x * y;
+    b[20] = (x2 - 3.0f * y2) * x * z;
+    b[21] = (3.0f * x2 - y2) * y * z;
+    b[22] = x2 * x2 - 6.0f * x2 * y2 + y2 * y2;
+    b[23] = 4.0f * x * y * (x2 - y2);
+  }
+}
+
+// Cartesian gradient of each b_lm at u: (gx, gy, gz)[lm].  Delivered through a
+// functor so that callers contract it on the fly without storing 3*Y values.
+template <int LM, class Fn>
+__device__ __forceinline__ void harm_grad(float x, float y, float z, Fn&& fn) {
+  fn(0, 0.f, 0.f, 1.f);
+  fn(1, 1.f, 0.f, 0.f);
+  fn(2, 0.f, 1.f, 0.f);
+  if constexpr (LM >= 2) {
+    fn(3, 0.f, 0.f, 6.0f * z);
+    fn(4, z, 0.f, x);
+    fn(5, 0.f, z, y);
+    fn(6, 2.0f * x, -2.0f * y, 0.f);
+    fn(7, 2.0f * y, 2.0f * x, 0.f);
+  }
+  if constexpr (LM >= 3) {
+    const float z2 = z * z, x2 = x * x, y2 = y * y;
+    fn(8, 0.f, 0.f, 15.0f * z2 - 3.0f);
+    fn(9, 5.0f * z2 - 1.0f, 0.f, 10.0f * x * z);
+    fn(10, 0.f, 5.0f * z2 - 1.0f, 10.0f * y * z);
+    fn(11, 2.0f * x * z, -2.0f * y * z, x2 - y2);
+    fn(12, 2.0f * y * z, 2.0f * x * z, 2.0f * x * y);
+    fn(13, 3.0f * (x2 - y2), -6.0f * x * y, 0.f);
+    fn(14, 6.0f * x * y, 3.0f * (x2 - y2), 0.f);
+  }
+  if constexpr (LM >= 4) {
+    const float z2 = z * z, x2 = x * x, y2 = y * y;
+    const float a = 7.0f * z2 - 1.0f;
+    const float c = (7.0f * z2 - 3.0f) * z;
+    fn(15, 0.f, 0.f, (140.0f * z2 - 60.0f) * z);
+    fn(16, c, 0.f, (21.0f * z2 - 3.0f) * x);
+    fn(17, 0.f, c, (21.0f * z2 - 3.0f) * y);
+    fn(18, 2.0f * x * a, -2.0f * y * a, 14.0f * z * (x2 - y2));
+    fn(19, 2.0f * y * a, 2.0f * x * a, 28.0f * x * y * z);
+    fn(20, 3.0f * (x2 - y2) * z, -6.0f * x * y * z, (x2 - 3.0f * y2) * x);
+    fn(21, 6.0f * x * y * z, 3.0f * (x2 - y2) * z, (3.0f * x2 - y2) * y);
+    fn(22, 4.0f * x * (x2 - 3.0f * y2), 4.0f * y * (y2 - 3.0f * x2), 0.f);
+    fn(23, 4.0f * y * (3.0f * x2 - y2), 4.0f * x * (x2 - 3.0f * y2), 0.f);
+  }
+}
+
+// ------------------------------------------------- 4-body and 5-body terms
+// The l = 2 sums (S_20..S_24) are the components of a traceless symmetric
+// matrix M: M_zz = S_20/3, M_xz = S_21, M_yz = S_22, M_xx - M_yy = S_23,
+// M_xy = S_24/2.  q4 = tr(M^3); dq4/dS_m = tr(Q E_m) with Q = 3 M^2, where E_m
+// is dM/dS_m, and the Hessian applied to a tangent is tr(Q' E_m) with
+// Q' = 3 (Mdot M + M Mdot).
+struct Sym3 {
+  float xx, yy, zz, xy, xz, yz;
+};
+
+__device__ __forceinline__ Sym3 sym_of(float s0, float s1, float s2, float s3, float s4) {
+  Sym3 m;
+  m.zz = s0 * (1.0f / 3.0f);
+  m.xx = -s0 * (1.0f / 6.0f) + 0.5f * s3;
+  m.yy = -s0 * (1.0f / 6.0f) - 0.5f * s3;
+  m.xy = 0.5f * s4;
+  m.xz = s1;
+  m.yz = s2;
+  return m;
+}
+
+// symmetric part of A*B for symmetric A, B: (AB + BA)/2
+__device__ __forceinline__ Sym3 sym_mul(const Sym3& a, const Sym3& b) {
+  Sym3 c;
+  c.xx = a.xx * b.xx + a.xy * b.xy + a.xz * b.xz;
+  c.yy = a.xy * b.xy + a.yy * b.yy + a.yz * b.yz;
+  c.zz = a.xz * b.xz + a.yz * b.yz + a.zz * b.zz;
+  const float xy1 = a.xx * b.xy + a.xy * b.yy + a.xz * b.yz;
+  const float xy2 = b.xx * a.xy + b.xy * a.yy + b.xz * a.yz;
+  const float xz1 = a.xx * b.xz + a.xy * b.yz + a.xz * b.zz;
+  const float xz2 = b.xx * a.xz + b.xy * a.yz + b.xz * a.zz;
+  const float yz1 = a.xy * b.xz + a.yy * b.yz + a.yz * b.zz;
+  const float yz2 = b.xy * a.xz + b.yy * a.yz + b.yz * a.zz;
+  c.xy = 0.5f * (xy1 + xy2);
+  c.xz = 0.5f * (xz1 + xz2);
+  c.yz = 0.5f * (yz1 + yz2);
+  return c;
+}
+
+// tr(A B) for symmetric A, B
+__device__ __forceinline__ float sym_dot(const Sym3& a, const Sym3& b) {
+  return a.xx * b.xx + a.yy * b.yy + a.zz * b.zz + 2.0f * (a.xy * b.xy + a.xz * b.xz + a.yz * b.yz);
+}
+
+// tr(Q E_m), m = 0..4, for symmetric Q
+__device__ __forceinline__ void sym_proj(const Sym3& q, float (&o)[5]) {
+  o[0] = (q.zz - 0.5f * (q.xx + q.yy)) * (1.0f / 3.0f);
+  o[1] = 2.0f * q.xz;
+  o[2] = 2.0f * q.yz;
+  o[3] = 0.5f * (q.xx - q.yy);
+  o[4] = q.xy;
+}
+
+// ----------------------------------------------------------- wave helpers
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Image shift of a neighbor code: code = 9(sx+1) + 3(sy+1) + (sz+1).
+__device__ __forceinline__ void decode_shift(uint32_t code, float& sx, float& sy, float& sz) {
+  const int c = (int)code;
+  sx = (float)(c / 9 - 1);
+  sy = (float)((c / 3) % 3 - 1);
+  sz = (float)(c % 3 - 1);
+}
+
+}  // namespace nep

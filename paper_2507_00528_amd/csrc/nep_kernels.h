@@ -1,0 +1,99 @@
+// HIP kernels of the NEP loss-and-gradient path (gfx950, wave64).
+//
+// Data flow of one loss-and-gradient evaluation:
+//   neighbors -> species order -> forward (descriptors, network, partial forces)
+//   -> force gather -> per-structure loss and cotangents -> adjoint (tangent
+//   pass, network adjoint, parameter partials) -> W0 reduction -> final gradient
+//   reduction -> Adam.
+// Per-atom kernels run in "species order": atoms grouped by species, each
+// group padded to a multiple of 64, so every wavefront evaluates one species'
+// network with wave-uniform weights.  Padding lanes act as atoms without
+// neighbors and write nothing.
+#pragma once
+#include "nep_device.h"
+
+namespace nep {
+
+enum : int { FL_OVERFLOW = 1, FL_NONFINITE = 2, FL_BOX = 4, FL_TYPE = 8, FL_POS = 16 };
+
+// ---------------------------------------------------------------- arguments
+struct NbrArgs {
+  int N, S, T, capR, capA;
+  float rcR, rcA;
+  const int* aoff;
+  const float* box;
+  const float* pos;
+  const int* type;
+  uint32_t* idxR;
+  int* cntR;
+  uint32_t* idxA;
+  int* cntA;
+  int* astruct;
+  int* flags;
+};
+
+struct PairLists {
+  const uint32_t* idxR;
+  const int* cntR;
+  const uint32_t* idxA;
+  const int* cntA;
+  const int* revR;
+  const int* revA;
+  int capR, capA;
+};
+
+struct FwdArgs {
+  int N, Npad, H;
+  float inv_rcR, inv_rcA;
+  const int* order;
+  const int* astruct;
+  const float* box;
+  const float* pos;
+  const int* type;
+  PairLists nb;
+  const float* cR;
+  const float* cA;
+  const float* nn;  // per species block of H*D + 2H + 1
+  int nn_stride;
+  float* G;        // [D][Npad] species order (may be null)
+  float* Guser;    // [D][N] atom order (may be null)
+  float* Sst;      // [NA*Y][Npad] (may be null)
+  float* Ep;       // [D][Npad] (may be null)
+  float* X;        // [H][Npad] (may be null)
+  float* eatom;    // [N] atom order (may be null)
+  float* eatom2;   // second copy for the caller (may be null)
+  float* fR;       // [3][capR][N]
+  float* fA;       // [3][capA][N]
+  float* wv;       // [6][N]
+  int do_mlp, do_force;
+};
+
+struct AdjArgs {
+  int N, Npad, H, S;
+  float inv_rcR, inv_rcA;
+  const int* order;
+  const int* astruct;
+  const float* box;
+  const float* pos;
+  const int* type;
+  PairLists nb;
+  const float* cR;
+  const float* cA;
+  const float* nn;
+  int nn_stride;
+  const float* Sst;   // [NA*Y][Npad]
+  const float* Ep;    // [D][Npad]
+  const float* X;     // [H][Npad]
+  const float* eps;   // [S] dL/dE(n)
+  const float* fbar;  // [3][N] dL/dF
+  const float* wbar;  // [S][6] dL/dW(n)
+  float* Gd;          // [D][Npad]
+  float* Sd;          // [NA*Y][Npad]
+  float* beta;        // [H][Npad]
+  float* w1s;         // [H][Npad]
+  float* part;        // [n_waves][PW] wave partial sums
+  int* wave_species;  // [n_waves]
+  int PW;
+};
+
+}  // namespace nep

@@ -1,0 +1,1786 @@
+// libnep: HIP kernels and C ABI for one NEP loss-and-gradient evaluation on
+// MI355X (gfx950).  The declarations and contracts are in include/nep.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/nep.h"
+#include "nep_kernels.h"
+
+namespace nep {
+
+// =============================================================== neighbors
+// One thread per atom i scans the atoms j of its own structure.  For each j
+// the per-axis test |(x_j - x_i) + s L| < rc keeps the candidate shifts, and
+// every candidate (j, s) is tested exactly with the float64 predicate of
+// Eq. 2, evaluated without fused multiply-add.  j runs ascending and the
+// shifts in code order, so the lists come out in canonical order.
+__device__ __forceinline__ unsigned axis_candidates(double d0, double L, double rc) {
+  unsigned m = 0;
+  if (fabs(__dadd_rn(d0, -L)) < rc) m |= 1u;
+  if (fabs(d0) < rc) m |= 2u;
+  if (fabs(__dadd_rn(d0, L)) < rc) m |= 4u;
+  return m;
+}
+
+__global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.N) return;
+  int lo = 0, hi = a.S;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (a.aoff[mid] <= i) lo = mid; else hi = mid;
+  }
+  const int s = lo;
+  a.astruct[i] = s;
+  const int a0 = max(a.aoff[s], 0), a1 = min(a.aoff[s + 1], a.N);
+  const float Lxf = a.box[3 * s], Lyf = a.box[3 * s + 1], Lzf = a.box[3 * s + 2];
+  int fl = 0;
+  const int ti = a.type[i];
+  if (ti < 0 || ti >= a.T) fl |= FL_TYPE;
+  const float xf = a.pos[i], yf = a.pos[a.N + i], zf = a.pos[2 * a.N + i];
+  if (!(xf >= 0.f && xf < Lxf && yf >= 0.f && yf < Lyf && zf >= 0.f && zf < Lzf)) fl |= FL_POS;
+  if (!(Lxf >= a.rcR && Lyf >= a.rcR && Lzf >= a.rcR)) {
+    a.cntR[i] = 0;
+    a.cntA[i] = 0;
+    atomicOr(a.flags, fl | FL_BOX);
+    return;
+  }
+  const double rcR = (double)a.rcR, rcA = (double)a.rcA;
+  const double rcR2 = rcR * rcR, rcA2 = rcA * rcA;  // exact: float squared in double
+  const double Lx = Lxf, Ly = Lyf, Lz = Lzf;
+  const double xi = xf, yi = yf, zi = zf;
+  int nR = 0, nA = 0;
+  for (int j = a0; j < a1; ++j) {
+    const double x0 = __dadd_rn((double)a.pos[j], -xi);
+    const unsigned mx = axis_candidates(x0, Lx, rcR);
+    if (!mx) continue;
+    const double y0 = __dadd_rn((double)a.pos[a.N + j], -yi);
+    const unsigned my = axis_candidates(y0, Ly, rcR);
+    if (!my) continue;
+    const double z0 = __dadd_rn((double)a.pos[2 * a.N + j], -zi);
+    const unsigned mz = axis_candidates(z0, Lz, rcR);
+    if (!mz) continue;
+    for (int sx = 0; sx < 3; ++sx) {
+      if (!((mx >> sx) & 1u)) continue;
+      const double dx = sx == 1 ? x0 : __dadd_rn(x0, sx == 0 ? -Lx : Lx);
+      const double dx2 = __dmul_rn(dx, dx);
+      for (int sy = 0; sy < 3; ++sy) {
+        if (!((my >> sy) & 1u)) continue;
+        const double dy = sy == 1 ? y0 : __dadd_rn(y0, sy == 0 ? -Ly : Ly);
+        const double dxy = __dadd_rn(dx2, __dmul_rn(dy, dy));
+        for (int sz = 0; sz < 3; ++sz) {
+          if (!((mz >> sz) & 1u)) continue;
+          const int code = 9 * sx + 3 * sy + sz;
+          if (j == i && code == 13) continue;
+          const double dz = sz == 1 ? z0 : __dadd_rn(z0, sz == 0 ? -Lz : Lz);
+          const double d2 = __dadd_rn(dxy, __dmul_rn(dz, dz));
+          if (d2 < rcR2) {
+            const uint32_t e = ((uint32_t)j << 5) | (uint32_t)code;
+            if (nR < a.capR) a.idxR[(size_t)nR * a.N + i] = e;
+            ++nR;
+            if (d2 < rcA2) {
+              if (nA < a.capA) a.idxA[(size_t)nA * a.N + i] = e;
+              ++nA;
+            }
+          }
+        }
+      }
+    }
+  }
+  a.cntR[i] = nR;
+  a.cntA[i] = nA;
+  if (nR > a.capR || nA > a.capA) fl |= FL_OVERFLOW;
+  if (fl) atomicOr(a.flags, fl);
+}
+
+// Position of the reverse entry (i, -s) in j's list, by binary search over
+// the canonically ordered entries.
+__global__ __launch_bounds__(256) void k_reverse(int N, const uint32_t* __restrict__ idx,
+                                                 const int* __restrict__ cnt, int cap, int* __restrict__ rev) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int n = min(cnt[i], cap);
+  for (int k = 0; k < n; ++k) {
+    const uint32_t e = idx[(size_t)k * N + i];
+    const int j = (int)(e >> 5);
+    const uint32_t key = ((uint32_t)i << 5) | (26u - (e & 31u));
+    const int m = min(cnt[j], cap);
+    int lo = 0, hi = m;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (idx[(size_t)mid * N + j] < key) lo = mid + 1; else hi = mid;
+    }
+    rev[(size_t)k * N + i] = (lo < m && idx[(size_t)lo * N + j] == key) ? lo : -1;
+  }
+}
+
+// ============================================================ species order
+constexpr int kOrdBlk = 1024;
+
+__global__ __launch_bounds__(kOrdBlk) void k_order_count(int N, int Npad, int T, const int* __restrict__ type,
+                                                         int* __restrict__ blkcnt, int* __restrict__ order) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < Npad; q += gridDim.x * blockDim.x) order[q] = -1;
+  __shared__ int cnt[8];
+  if (threadIdx.x < T) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int i = blockIdx.x * kOrdBlk + threadIdx.x;
+  if (i < N) {
+    const int t = type[i];
+    if (t >= 0 && t < T) atomicAdd(&cnt[t], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < T) blkcnt[blockIdx.x * T + threadIdx.x] = cnt[threadIdx.x];
+}
+
+// Exclusive scan of the per-block counts; species segments start on
+// multiples of 64 so that no wavefront mixes species.  seg[2t], seg[2t+1] =
+// start and count of species t.
+__global__ void k_order_scan(int nblk, int T, int* __restrict__ blk, int* __restrict__ seg) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int start = 0;
+  for (int t = 0; t < T; ++t) {
+    int run = start;
+    for (int b = 0; b < nblk; ++b) {
+      const int c = blk[b * T + t];
+      blk[b * T + t] = run;
+      run += c;
+    }
+    seg[2 * t] = start;
+    seg[2 * t + 1] = run - start;
+    start += ((run - start) + kWave - 1) / kWave * kWave;
+  }
+}
+
+__global__ __launch_bounds__(kOrdBlk) void k_order_scatter(int N, int T, const int* __restrict__ type,
+                                                           const int* __restrict__ blkoff, int* __restrict__ order) {
+  __shared__ int wcnt[kOrdBlk / kWave][8];
+  const int i = blockIdx.x * kOrdBlk + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int t = i < N ? type[i] : -1;
+  int rank = 0;
+  for (int tt = 0; tt < T; ++tt) {
+    const unsigned long long m = __ballot(t == tt);
+    if (t == tt) rank = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wcnt[wid][tt] = __popcll(m);
+  }
+  __syncthreads();
+  if (i < N && t >= 0 && t < T) {
+    int before = 0;
+    for (int w = 0; w < wid; ++w) before += wcnt[w][t];
+    order[blkoff[blockIdx.x * T + t] + before + rank] = i;
+  }
+}
+
+// ================================================================= helpers
+template <int T, int NA, int KA>
+__device__ __forceinline__ float coef_sel(const float* __restrict__ cI, int J, int n, int k) {
+  float c = cI[(0 * NA + n) * KA + k];
+#pragma unroll
+  for (int t = 1; t < T; ++t) c = (J == t) ? cI[(t * NA + n) * KA + k] : c;
+  return c;
+}
+
+struct PairGeom {
+  int j;
+  float dx, dy, dz, r, inv_r;
+};
+
+__device__ __forceinline__ PairGeom pair_geom(uint32_t e, const float* __restrict__ pos, int N, float xi, float yi,
+                                              float zi, float Lx, float Ly, float Lz) {
+  PairGeom g;
+  g.j = (int)(e >> 5);
+  float sx, sy, sz;
+  decode_shift(e & 31u, sx, sy, sz);
+  g.dx = (pos[g.j] - xi) + sx * Lx;
+  g.dy = (pos[N + g.j] - yi) + sy * Ly;
+  g.dz = (pos[2 * N + g.j] - zi) + sz * Lz;
+  g.r = sqrtf(g.dx * g.dx + g.dy * g.dy + g.dz * g.dz);
+  g.inv_r = 1.0f / g.r;
+  return g;
+}
+
+struct WaveCtx {
+  int p, i, I, lane, wave;
+  bool valid, any;
+};
+
+__device__ __forceinline__ WaveCtx wave_ctx(const int* __restrict__ order, const int* __restrict__ type, int Npad) {
+  WaveCtx c;
+  c.p = blockIdx.x * blockDim.x + threadIdx.x;
+  c.lane = threadIdx.x & (kWave - 1);
+  c.wave = c.p / kWave;
+  const int iraw = c.p < Npad ? order[c.p] : -1;
+  c.valid = iraw >= 0;
+  const unsigned long long vm = __ballot(c.valid);
+  c.any = vm != 0ull;
+  if (!c.any) {
+    c.i = 0;
+    c.I = 0;
+    return c;
+  }
+  const int lead = __ffsll(vm) - 1;
+  const int ilead = __shfl(iraw, lead, kWave);
+  c.i = c.valid ? iraw : ilead;
+  c.I = __builtin_amdgcn_readfirstlane(type[ilead]);
+  return c;
+}
+
+// ================================================================= forward
+// Per atom (species order): radial sums F[J][k] = sum_{j of type J} f_k(r_ij)
+// give q_n = sum_{J,k} c^R_{IJnk} F[J][k] (Eqs. 5-6); angular sums S_nlm
+// (Eq. 8) give q_nl (Eq. 7) and the 4-/5-body invariants; the per-species
+// network gives E_i and E' = dE_i/dG (D1.1-D1.5).  With forces on, the partial
+// force f_ij = dE_i/dr_ij of every listed pair is stored (C3.6) together with
+// this atom's share -sum_j f_ij (x) r_ij of the virial.
+template <class C>
+__global__ __launch_bounds__(256) void k_forward(FwdArgs a) {
+  constexpr int T = C::T, NR = C::NR, NA = C::NA, KR = C::KR, KA = C::KA, Y = C::Y, D = C::D, LM = C::LMAX;
+  constexpr int L3 = C::L3, L4 = C::L4, L5 = C::L5;
+  const WaveCtx w = wave_ctx(a.order, a.type, a.Npad);
+  if (!w.any) return;
+  const int N = a.N, i = w.i, I = w.I, p = w.p;
+  const int s = a.astruct[i];
+  const float Lx = a.box[3 * s], Ly = a.box[3 * s + 1], Lz = a.box[3 * s + 2];
+  const float xi = a.pos[i], yi = a.pos[N + i], zi = a.pos[2 * N + i];
+  const int nR = w.valid ? min(a.nb.cntR[i], a.nb.capR) : 0;
+  const int nA = w.valid ? min(a.nb.cntA[i], a.nb.capA) : 0;
+  const float* __restrict__ cRI = a.cR + (size_t)I * T * NR * KR;
+  const float* __restrict__ cAI = a.cA + (size_t)I * T * NA * KA;
+
+  // ---- radial descriptors
+  float FR[T][KR];
+#pragma unroll
+  for (int t = 0; t < T; ++t)
+#pragma unroll
+    for (int k = 0; k < KR; ++k) FR[t][k] = 0.f;
+  for (int k = 0; k < nR; ++k) {
+    const PairGeom g = pair_geom(a.nb.idxR[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+    float f[KR];
+    radial_basis<KR>(g.r, a.inv_rcR, f);
+    const int J = a.type[g.j];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const float m = (T == 1 || J == t) ? 1.f : 0.f;
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) FR[t][kk] = fmaf(m, f[kk], FR[t][kk]);
+    }
+  }
+  float G[D];
+#pragma unroll
+  for (int n = 0; n < NR; ++n) {
+    float acc = 0.f;
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int k = 0; k < KR; ++k) acc = fmaf(cRI[(t * NR + n) * KR + k], FR[t][k], acc);
+    G[n] = acc;
+  }
+
+  // ---- angular sums S_nlm
+  float S[NA][Y];
+#pragma unroll
+  for (int n = 0; n < NA; ++n)
+#pragma unroll
+    for (int q = 0; q < Y; ++q) S[n][q] = 0.f;
+  for (int k = 0; k < nA; ++k) {
+    const PairGeom g = pair_geom(a.nb.idxA[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+    float f[KA];
+    radial_basis<KA>(g.r, a.inv_rcA, f);
+    const int J = a.type[g.j];
+    float gn[NA];
+#pragma unroll
+    for (int n = 0; n < NA; ++n) {
+      float acc = 0.f;
+#pragma unroll
+      for (int kk = 0; kk < KA; ++kk) acc = fmaf(coef_sel<T, NA, KA>(cAI, J, n, kk), f[kk], acc);
+      gn[n] = acc;
+    }
+    float B[Y];
+    harm_val<LM>(g.dx * g.inv_r, g.dy * g.inv_r, g.dz * g.inv_r, B);
+#pragma unroll
+    for (int n = 0; n < NA; ++n)
+#pragma unroll
+      for (int q = 0; q < Y; ++q) S[n][q] = fmaf(gn[n], B[q], S[n][q]);
+  }
+
+  // ---- angular descriptors
+#pragma unroll
+  for (int l = 1; l <= L3; ++l)
+#pragma unroll
+    for (int n = 0; n < NA; ++n) {
+      float acc = 0.f;
+#pragma unroll
+      for (int m = 0; m < 2 * l + 1; ++m) {
+        const int q = (l - 1) * (l + 1) + m;
+        acc = fmaf(clm(q) * S[n][q], S[n][q], acc);
+      }
+      G[NR + (l - 1) * NA + n] = acc;
+    }
+  if constexpr (L4 != 0) {
+#pragma unroll
+    for (int n = 0; n < NA; ++n) {
+      const Sym3 M = sym_of(S[n][3], S[n][4], S[n][5], S[n][6], S[n][7]);
+      G[NR + L3 * NA + n] = sym_dot(sym_mul(M, M), M);
+    }
+  }
+  if constexpr (L5 != 0) {
+#pragma unroll
+    for (int n = 0; n < NA; ++n) {
+      const float P = S[n][0] * S[n][0] + S[n][1] * S[n][1] + S[n][2] * S[n][2];
+      G[NR + L3 * NA + (L4 ? NA : 0) + n] = P * P;
+    }
+  }
+  if (w.valid) {
+    if (a.G)
+#pragma unroll
+      for (int v = 0; v < D; ++v) a.G[(size_t)v * a.Npad + p] = G[v];
+    if (a.Guser)
+#pragma unroll
+      for (int v = 0; v < D; ++v) a.Guser[(size_t)v * N + i] = G[v];
+    if (a.Sst)
+#pragma unroll
+      for (int n = 0; n < NA; ++n)
+#pragma unroll
+        for (int q = 0; q < Y; ++q) a.Sst[(size_t)(n * Y + q) * a.Npad + p] = S[n][q];
+  }
+  if (!a.do_mlp) return;
+
+  // ---- network: E_i and E' (wave-uniform species weights)
+  const int H = a.H;
+  const float* __restrict__ W = a.nn + (size_t)I * a.nn_stride;
+  const float* __restrict__ b0 = W + (size_t)H * D;
+  const float* __restrict__ w1 = b0 + H;
+  float Ep[D];
+#pragma unroll
+  for (int v = 0; v < D; ++v) Ep[v] = 0.f;
+  float E = w1[H];
+  for (int mu = 0; mu < H; ++mu) {
+    const float* __restrict__ wr = W + (size_t)mu * D;
+    float z = b0[mu];
+#pragma unroll
+    for (int v = 0; v < D; ++v) z = fmaf(wr[v], G[v], z);
+    const float x = tanhf(z);
+    E = fmaf(w1[mu], x, E);
+    const float sg = w1[mu] * (1.0f - x * x);
+#pragma unroll
+    for (int v = 0; v < D; ++v) Ep[v] = fmaf(sg, wr[v], Ep[v]);
+    if (w.valid && a.X) a.X[(size_t)mu * a.Npad + p] = x;
+  }
+  if (w.valid) {
+    if (a.Ep)
+#pragma unroll
+      for (int v = 0; v < D; ++v) a.Ep[(size_t)v * a.Npad + p] = Ep[v];
+    if (a.eatom) a.eatom[i] = E;
+    if (a.eatom2) a.eatom2[i] = E;
+  }
+  if (!a.do_force) return;
+
+  // ---- radial partial forces: f_ij = (sum_k h_Jk f'_k(r)) r_hat,
+  //      h_Jk = sum_n E'_n c^R_{IJnk}
+  float hR[T][KR];
+#pragma unroll
+  for (int t = 0; t < T; ++t)
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      float acc = 0.f;
+#pragma unroll
+      for (int n = 0; n < NR; ++n) acc = fmaf(Ep[n], cRI[(t * NR + n) * KR + k], acc);
+      hR[t][k] = acc;
+    }
+  float vxx = 0.f, vyy = 0.f, vzz = 0.f, vxy = 0.f, vyz = 0.f, vzx = 0.f;
+  const size_t capN_R = (size_t)a.nb.capR * N, capN_A = (size_t)a.nb.capA * N;
+  for (int k = 0; k < nR; ++k) {
+    const PairGeom g = pair_geom(a.nb.idxR[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+    float f[KR], fp[KR];
+    radial_basis_d<KR>(g.r, a.inv_rcR, f, fp);
+    const int J = a.type[g.j];
+    float sc = 0.f;
+#pragma unroll
+    for (int kk = 0; kk < KR; ++kk) {
+      float h = hR[0][kk];
+#pragma unroll
+      for (int t = 1; t < T; ++t) h = (J == t) ? hR[t][kk] : h;
+      sc = fmaf(h, fp[kk], sc);
+    }
+    sc *= g.inv_r;
+    const float fx = sc * g.dx, fy = sc * g.dy, fz = sc * g.dz;
+    a.fR[(size_t)k * N + i] = fx;
+    a.fR[capN_R + (size_t)k * N + i] = fy;
+    a.fR[2 * capN_R + (size_t)k * N + i] = fz;
+    vxx -= fx * g.dx; vyy -= fy * g.dy; vzz -= fz * g.dz;
+    vxy -= fx * g.dy; vyz -= fy * g.dz; vzx -= fz * g.dx;
+  }
+
+  // ---- A_nlm = sum_v E'_v dG_v/dS_nlm (overwrites S)
+#pragma unroll
+  for (int n = 0; n < NA; ++n) {
+    float a4[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, a5[3] = {0.f, 0.f, 0.f};
+    if constexpr (L4 != 0) {
+      const Sym3 M = sym_of(S[n][3], S[n][4], S[n][5], S[n][6], S[n][7]);
+      float o[5];
+      sym_proj(sym_mul(M, M), o);
+      const float e4 = 3.0f * Ep[NR + L3 * NA + n];
+#pragma unroll
+      for (int m = 0; m < 5; ++m) a4[m] = e4 * o[m];
+    }
+    if constexpr (L5 != 0) {
+      const float P = S[n][0] * S[n][0] + S[n][1] * S[n][1] + S[n][2] * S[n][2];
+      const float e5 = 4.0f * Ep[NR + L3 * NA + (L4 ? NA : 0) + n] * P;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) a5[m] = e5 * S[n][m];
+    }
+#pragma unroll
+    for (int q = 0; q < Y; ++q) {
+      int l = 1;
+      while ((l) * (l + 2) <= q) ++l;  // q in [(l-1)(l+1), l(l+2))
+      float v = (l <= L3) ? 2.0f * clm(q) * Ep[NR + (l - 1) * NA + n] * S[n][q] : 0.f;
+      if (L4 && q >= 3 && q < 8) v += a4[q - 3];
+      if (L5 && q < 3) v += a5[q];
+      S[n][q] = v;
+    }
+  }
+
+  // ---- angular partial forces: f_ij = sum_nlm A_nlm (g'_n r_hat B_lm + g_n grad B_lm)
+  for (int k = 0; k < nA; ++k) {
+    const PairGeom g = pair_geom(a.nb.idxA[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+    const float ux = g.dx * g.inv_r, uy = g.dy * g.inv_r, uz = g.dz * g.inv_r;
+    float f[KA], fp[KA];
+    radial_basis_d<KA>(g.r, a.inv_rcA, f, fp);
+    const int J = a.type[g.j];
+    float gn[NA], gp[NA];
+#pragma unroll
+    for (int n = 0; n < NA; ++n) {
+      float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+      for (int kk = 0; kk < KA; ++kk) {
+        const float c = coef_sel<T, NA, KA>(cAI, J, n, kk);
+        s0 = fmaf(c, f[kk], s0);
+        s1 = fmaf(c, fp[kk], s1);
+      }
+      gn[n] = s0;
+      gp[n] = s1;
+    }
+    float B[Y];
+    harm_val<LM>(ux, uy, uz, B);
+    float vv = 0.f;
+    float uu[Y];
+#pragma unroll
+    for (int q = 0; q < Y; ++q) {
+      float su = 0.f, sv = 0.f;
+#pragma unroll
+      for (int n = 0; n < NA; ++n) {
+        su = fmaf(S[n][q], gn[n], su);
+        sv = fmaf(S[n][q], gp[n], sv);
+      }
+      uu[q] = su;
+      vv = fmaf(sv, B[q], vv);
+    }
+    float gx = 0.f, gy = 0.f, gz = 0.f;
+    harm_grad<LM>(ux, uy, uz, [&](int q, float ax, float ay, float az) {
+      gx = fmaf(uu[q], ax, gx);
+      gy = fmaf(uu[q], ay, gy);
+      gz = fmaf(uu[q], az, gz);
+    });
+    const float rad = ux * gx + uy * gy + uz * gz;
+    const float fx = vv * ux + (gx - rad * ux) * g.inv_r;
+    const float fy = vv * uy + (gy - rad * uy) * g.inv_r;
+    const float fz = vv * uz + (gz - rad * uz) * g.inv_r;
+    a.fA[(size_t)k * N + i] = fx;
+    a.fA[capN_A + (size_t)k * N + i] = fy;
+    a.fA[2 * capN_A + (size_t)k * N + i] = fz;
+    vxx -= fx * g.dx; vyy -= fy * g.dy; vzz -= fz * g.dz;
+    vxy -= fx * g.dy; vyz -= fy * g.dz; vzx -= fz * g.dx;
+  }
+  if (w.valid) {
+    a.wv[i] = vxx;
+    a.wv[(size_t)N + i] = vyy;
+    a.wv[(size_t)2 * N + i] = vzz;
+    a.wv[(size_t)3 * N + i] = vxy;
+    a.wv[(size_t)4 * N + i] = vyz;
+    a.wv[(size_t)5 * N + i] = vzx;
+  }
+}
+
+// F_i = sum_j f_ij - f_ji (Eq. 3), gathering f_ji through the reverse index.
+__global__ __launch_bounds__(256) void k_force_gather(int N, PairLists nb, const float* __restrict__ fR,
+                                                      const float* __restrict__ fA, float* __restrict__ F,
+                                                      float* __restrict__ Fuser) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  float fx = 0.f, fy = 0.f, fz = 0.f;
+  {
+    const size_t cN = (size_t)nb.capR * N;
+    const int n = min(nb.cntR[i], nb.capR);
+    for (int k = 0; k < n; ++k) {
+      const int j = (int)(nb.idxR[(size_t)k * N + i] >> 5);
+      const size_t o = (size_t)k * N + i;
+      fx += fR[o];
+      fy += fR[cN + o];
+      fz += fR[2 * cN + o];
+      const int rk = nb.revR[o];
+      if (rk >= 0) {
+        const size_t q = (size_t)rk * N + j;
+        fx -= fR[q];
+        fy -= fR[cN + q];
+        fz -= fR[2 * cN + q];
+      }
+    }
+  }
+  {
+    const size_t cN = (size_t)nb.capA * N;
+    const int n = min(nb.cntA[i], nb.capA);
+    for (int k = 0; k < n; ++k) {
+      const int j = (int)(nb.idxA[(size_t)k * N + i] >> 5);
+      const size_t o = (size_t)k * N + i;
+      fx += fA[o];
+      fy += fA[cN + o];
+      fz += fA[2 * cN + o];
+      const int rk = nb.revA[o];
+      if (rk >= 0) {
+        const size_t q = (size_t)rk * N + j;
+        fx -= fA[q];
+        fy -= fA[cN + q];
+        fz -= fA[2 * cN + q];
+      }
+    }
+  }
+  F[i] = fx;
+  F[N + i] = fy;
+  F[2 * N + i] = fz;
+  if (Fuser) {
+    Fuser[i] = fx;
+    Fuser[N + i] = fy;
+    Fuser[2 * N + i] = fz;
+  }
+}
+
+// ==================================================================== loss
+// One block per structure: E(n), W(n) and, with labels, the loss terms of
+// Eqs. 10-12 and the cotangents dL/dE(n), dL/dF_i, dL/dW(n).  Sums run in
+// float64 in a fixed order.
+constexpr int kRedBlk = 256;
+
+struct StructArgs {
+  int S, N;
+  const int* aoff;
+  const float* eatom;
+  const float* wv;
+  const float* F;
+  const float* Et;
+  const float* Ft;
+  const float* Wt;
+  float le, lf, lv;
+  float* Es;
+  float* Ws;
+  float* Es_user;
+  float* Ws_user;
+  float* eps;
+  float* wbar;
+  float* fbar;
+  double* lpart;  // [S][3]
+};
+
+__global__ __launch_bounds__(kRedBlk) void k_struct(StructArgs a) {
+  __shared__ double red[8][kRedBlk];
+  const int s = blockIdx.x;
+  const int a0 = a.aoff[s], a1 = a.aoff[s + 1];
+  const int N = a.N;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const bool lab = a.Et != nullptr;
+  const float cf = 2.0f * a.lf / (3.0f * (float)max(N, 1));
+  for (int i = a0 + threadIdx.x; i < a1; i += kRedBlk) {
+    acc[0] += a.eatom[i];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[1 + c] += a.wv[(size_t)c * N + i];
+    if (lab) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float d = a.F[(size_t)c * N + i] - a.Ft[(size_t)c * N + i];
+        acc[7] += (double)d * d;
+        a.fbar[(size_t)c * N + i] = cf * d;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) red[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int st = kRedBlk / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double E = red[0][0];
+    a.Es[s] = (float)E;
+    if (a.Es_user) a.Es_user[s] = (float)E;
+    for (int c = 0; c < 6; ++c) {
+      a.Ws[6 * s + c] = (float)red[1 + c][0];
+      if (a.Ws_user) a.Ws_user[6 * s + c] = (float)red[1 + c][0];
+    }
+    if (lab) {
+      const int n = a1 - a0;
+      double le = 0, lv = 0;
+      if (n > 0) {
+        const double e = (E - (double)a.Et[s]) / n;
+        le = e * e;
+        a.eps[s] = (float)(2.0 * a.le * e / ((double)a.S * n));
+        for (int c = 0; c < 6; ++c) {
+          const double wc = (red[1 + c][0] - (double)a.Wt[6 * s + c]) / n;
+          lv += wc * wc;
+          a.wbar[6 * s + c] = (float)(2.0 * a.lv * wc / (6.0 * a.S * n));
+        }
+      } else {
+        a.eps[s] = 0.f;
+        for (int c = 0; c < 6; ++c) a.wbar[6 * s + c] = 0.f;
+      }
+      a.lpart[3 * s] = le;
+      a.lpart[3 * s + 1] = red[7][0];
+      a.lpart[3 * s + 2] = lv;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kRedBlk) void k_loss_final(int S, int N, float le, float lf, float lv,
+                                                        const double* __restrict__ lpart, float* __restrict__ loss,
+                                                        int* __restrict__ flags) {
+  __shared__ double red[3][kRedBlk];
+  double acc[3] = {0, 0, 0};
+  for (int s = threadIdx.x; s < S; s += kRedBlk)
+    for (int q = 0; q < 3; ++q) acc[q] += lpart[3 * s + q];
+  for (int q = 0; q < 3; ++q) red[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int st = kRedBlk / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st)
+      for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double Le = S > 0 ? red[0][0] / S : 0.0;
+    const double Lf = N > 0 ? red[1][0] / (3.0 * N) : 0.0;
+    const double Lv = S > 0 ? red[2][0] / (6.0 * S) : 0.0;
+    const double L = le * Le + lf * Lf + lv * Lv;
+    loss[0] = (float)L;
+    loss[1] = (float)Le;
+    loss[2] = (float)Lf;
+    loss[3] = (float)Lv;
+    if (flags && !isfinite(L)) atomicOr(flags, FL_NONFINITE);
+  }
+}
+
+// ================================================================= adjoint
+// Per atom (species order), with the cotangents eps = dL/dE(n),
+// Fbar = dL/dF and Gamma = dL/dW(n) frozen, the parameter gradient is the
+// gradient of  Phi_i = eps E_i - E'_i . Gdot_i,  Gdot_i = sum_j dG_i/dr_ij t_ij,
+// t_ij = Fbar_j - Fbar_i + Gamma r_ij  (the E, F and V terms of Eqs. 13-16
+// contracted with the residuals; the force and virial parts are the mixed
+// second derivatives of C1.4-C3.20 and D1.11-D1.17 applied to t).
+//   network:  a = W0 Gdot, beta = w1 sigma (eps + 2 x a):
+//             dPhi/dW0 = beta G^T - (w1 sigma) Gdot^T, dPhi/db0 = beta,
+//             dPhi/dw1 = eps x - sigma a, dPhi/db1 = eps, Gbar = W0^T beta
+//   radial:   dPhi/dc^R_{IJnk} = Gbar_n F[J][k] - E'_n Fp[J][k],
+//             Fp[J][k] = sum_{j of type J} f'_k(r_ij) (r_hat . t)
+//   angular:  dPhi/dc^A_{IJnk} = sum_{j of type J} f_k X_n - f'_k (r_hat . t) Y_n,
+//             X_n = sum_lm Sbar_nlm B_lm - A_nlm grad B_lm . t, Y_n = sum_lm A_nlm B_lm
+//   with Sbar = Gbar . dG/dS - E' . d2G/dS2 Sdot (the pairwise coupling that
+//   Algorithm 1 enumerates).
+// Sums over the atoms of a wavefront are reduced with shuffles and written
+// as one partial per wavefront; W0 partials go through k_w0_grad.
+template <class C>
+__global__ __launch_bounds__(256) void k_adjoint(AdjArgs a) {
+  constexpr int T = C::T, NR = C::NR, NA = C::NA, KR = C::KR, KA = C::KA, Y = C::Y, D = C::D, LM = C::LMAX;
+  constexpr int L3 = C::L3, L4 = C::L4, L5 = C::L5, PS = C::PS;
+  const WaveCtx w = wave_ctx(a.order, a.type, a.Npad);
+  const int nwaves = a.Npad / kWave;
+  if (w.lane == 0 && w.wave < nwaves) a.wave_species[w.wave] = w.any ? w.I : -1;
+  if (!w.any) return;
+  const int N = a.N, i = w.i, I = w.I, p = w.p, H = a.H;
+  const int s = a.astruct[i];
+  const float Lx = a.box[3 * s], Ly = a.box[3 * s + 1], Lz = a.box[3 * s + 2];
+  const float xi = a.pos[i], yi = a.pos[N + i], zi = a.pos[2 * N + i];
+  const int nR = w.valid ? min(a.nb.cntR[i], a.nb.capR) : 0;
+  const int nA = w.valid ? min(a.nb.cntA[i], a.nb.capA) : 0;
+  const float* __restrict__ cRI = a.cR + (size_t)I * T * NR * KR;
+  const float* __restrict__ cAI = a.cA + (size_t)I * T * NA * KA;
+  const float eps = w.valid ? a.eps[s] : 0.f;
+  const float* wb = a.wbar + 6 * s;
+  const float gxx = wb[0], gyy = wb[1], gzz = wb[2], gxy = wb[3], gyz = wb[4], gzx = wb[5];
+  const float fbx = a.fbar[i], fby = a.fbar[N + i], fbz = a.fbar[2 * N + i];
+  float* part = a.part + (size_t)w.wave * a.PW;
+
+  // ---- radial tangent pass
+  float FR[T][KR], FP[T][KR];
+#pragma unroll
+  for (int t = 0; t < T; ++t)
+#pragma unroll
+    for (int k = 0; k < KR; ++k) FR[t][k] = FP[t][k] = 0.f;
+  for (int k = 0; k < nR; ++k) {
+    const PairGeom g = pair_geom(a.nb.idxR[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+    const float tx = (a.fbar[g.j] - fbx) + gxx * g.dx + gxy * g.dy;
+    const float ty = (a.fbar[N + g.j] - fby) + gyy * g.dy + gyz * g.dz;
+    const float tz = (a.fbar[2 * N + g.j] - fbz) + gzz * g.dz + gzx * g.dx;
+    const float dt = (g.dx * tx + g.dy * ty + g.dz * tz) * g.inv_r;
+    float f[KR], fp[KR];
+    radial_basis_d<KR>(g.r, a.inv_rcR, f, fp);
+    const int J = a.type[g.j];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const float m = (T == 1 || J == t) ? 1.f : 0.f;
+      const float md = m * dt;
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) {
+        FR[t][kk] = fmaf(m, f[kk], FR[t][kk]);
+        FP[t][kk] = fmaf(md, fp[kk], FP[t][kk]);
+      }
+    }
+  }
+  float Gd[D];
+#pragma unroll
+  for (int n = 0; n < NR; ++n) {
+    float acc = 0.f;
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int k = 0; k < KR; ++k) acc = fmaf(cRI[(t * NR + n) * KR + k], FP[t][k], acc);
+    Gd[n] = acc;
+  }
+
+  // ---- angular tangent pass: Sdot_nlm = sum_j g'_n (r_hat.t) B_lm + g_n grad B_lm . t
+  {
+    float Sd[NA][Y];
+#pragma unroll
+    for (int n = 0; n < NA; ++n)
+#pragma unroll
+      for (int q = 0; q < Y; ++q) Sd[n][q] = 0.f;
+    for (int k = 0; k < nA; ++k) {
+      const PairGeom g = pair_geom(a.nb.idxA[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+      const float ux = g.dx * g.inv_r, uy = g.dy * g.inv_r, uz = g.dz * g.inv_r;
+      const float tx = (a.fbar[g.j] - fbx) + gxx * g.dx + gxy * g.dy;
+      const float ty = (a.fbar[N + g.j] - fby) + gyy * g.dy + gyz * g.dz;
+      const float tz = (a.fbar[2 * N + g.j] - fbz) + gzz * g.dz + gzx * g.dx;
+      const float dt = ux * tx + uy * ty + uz * tz;
+      float f[KA], fp[KA];
+      radial_basis_d<KA>(g.r, a.inv_rcA, f, fp);
+      const int J = a.type[g.j];
+      float gn[NA], gpd[NA];
+#pragma unroll
+      for (int n = 0; n < NA; ++n) {
+        float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+        for (int kk = 0; kk < KA; ++kk) {
+          const float c = coef_sel<T, NA, KA>(cAI, J, n, kk);
+          s0 = fmaf(c, f[kk], s0);
+          s1 = fmaf(c, fp[kk], s1);
+        }
+        gn[n] = s0;
+        gpd[n] = s1 * dt;
+      }
+      float B[Y];
+      harm_val<LM>(ux, uy, uz, B);
+#pragma unroll
+      for (int n = 0; n < NA; ++n)
+#pragma unroll
+        for (int q = 0; q < Y; ++q) Sd[n][q] = fmaf(gpd[n], B[q], Sd[n][q]);
+      harm_grad<LM>(ux, uy, uz, [&](int q, float ax, float ay, float az) {
+        const float gbt = ((ax * tx + ay * ty + az * tz) - (ax * ux + ay * uy + az * uz) * dt) * g.inv_r;
+#pragma unroll
+        for (int n = 0; n < NA; ++n) Sd[n][q] = fmaf(gn[n], gbt, Sd[n][q]);
+      });
+    }
+    // Gdot of the angular descriptors, using the stored S
+#pragma unroll
+    for (int n = 0; n < NA; ++n) {
+      float Sn[Y];
+#pragma unroll
+      for (int q = 0; q < Y; ++q) Sn[q] = a.Sst[(size_t)(n * Y + q) * a.Npad + p];
+#pragma unroll
+      for (int l = 1; l <= L3; ++l) {
+        float acc = 0.f;
+#pragma unroll
+        for (int m = 0; m < 2 * l + 1; ++m) {
+          const int q = (l - 1) * (l + 1) + m;
+          acc = fmaf(2.0f * clm(q) * Sn[q], Sd[n][q], acc);
+        }
+        Gd[NR + (l - 1) * NA + n] = acc;
+      }
+      if constexpr (L4 != 0) {
+        const Sym3 M = sym_of(Sn[3], Sn[4], Sn[5], Sn[6], Sn[7]);
+        const Sym3 Md = sym_of(Sd[n][3], Sd[n][4], Sd[n][5], Sd[n][6], Sd[n][7]);
+        Gd[NR + L3 * NA + n] = 3.0f * sym_dot(sym_mul(M, M), Md);
+      }
+      if constexpr (L5 != 0) {
+        const float P = Sn[0] * Sn[0] + Sn[1] * Sn[1] + Sn[2] * Sn[2];
+        const float SS = Sn[0] * Sd[n][0] + Sn[1] * Sd[n][1] + Sn[2] * Sd[n][2];
+        Gd[NR + L3 * NA + (L4 ? NA : 0) + n] = 4.0f * P * SS;
+      }
+      if (w.valid)
+#pragma unroll
+        for (int q = 0; q < Y; ++q) a.Sd[(size_t)(n * Y + q) * a.Npad + p] = Sd[n][q];
+    }
+  }
+  if (w.valid)
+#pragma unroll
+    for (int v = 0; v < D; ++v) a.Gd[(size_t)v * a.Npad + p] = Gd[v];
+
+  // ---- network adjoint
+  const float* __restrict__ W = a.nn + (size_t)I * a.nn_stride;
+  const float* __restrict__ w1 = W + (size_t)H * D + H;
+  float Gb[D];
+#pragma unroll
+  for (int v = 0; v < D; ++v) Gb[v] = 0.f;
+  for (int mu = 0; mu < H; ++mu) {
+    const float* __restrict__ wr = W + (size_t)mu * D;
+    float aa = 0.f;
+#pragma unroll
+    for (int v = 0; v < D; ++v) aa = fmaf(wr[v], Gd[v], aa);
+    const float x = a.X[(size_t)mu * a.Npad + p];
+    const float sg = 1.0f - x * x;
+    const float ws = w1[mu] * sg;
+    const float be = w.valid ? ws * (eps + 2.0f * x * aa) : 0.f;
+#pragma unroll
+    for (int v = 0; v < D; ++v) Gb[v] = fmaf(be, wr[v], Gb[v]);
+    a.beta[(size_t)mu * a.Npad + p] = be;
+    a.w1s[(size_t)mu * a.Npad + p] = w.valid ? ws : 0.f;
+    const float r0 = wave_sum(be);
+    const float r1 = wave_sum(w.valid ? eps * x - sg * aa : 0.f);
+    if (w.lane == 0) {
+      part[PS + mu] = r0;
+      part[PS + H + mu] = r1;
+    }
+  }
+  {
+    const float r = wave_sum(eps);
+    if (w.lane == 0) part[PS + 2 * H] = r;
+  }
+
+  // ---- radial coefficient gradient
+  float Ep[D];
+#pragma unroll
+  for (int v = 0; v < D; ++v) Ep[v] = a.Ep[(size_t)v * a.Npad + p];
+#pragma unroll
+  for (int t = 0; t < T; ++t)
+#pragma unroll
+    for (int n = 0; n < NR; ++n)
+#pragma unroll
+      for (int k = 0; k < KR; ++k) {
+        const float v = w.valid ? Gb[n] * FR[t][k] - Ep[n] * FP[t][k] : 0.f;
+        const float r = wave_sum(v);
+        if (w.lane == 0) part[(t * NR + n) * KR + k] = r;
+      }
+
+  // ---- angular coefficient gradient, one radial channel n at a time
+  for (int n = 0; n < NA; ++n) {
+    float Sn[Y], Sdn[Y], An[Y], Sb[Y];
+#pragma unroll
+    for (int q = 0; q < Y; ++q) {
+      Sn[q] = a.Sst[(size_t)(n * Y + q) * a.Npad + p];
+      Sdn[q] = a.Sd[(size_t)(n * Y + q) * a.Npad + p];
+    }
+#pragma unroll
+    for (int q = 0; q < Y; ++q) {
+      int l = 1;
+      while (l * (l + 2) <= q) ++l;
+      if (l <= L3) {
+        const int v = NR + (l - 1) * NA + n;
+        const float c2 = 2.0f * clm(q);
+        An[q] = c2 * Ep[v] * Sn[q];
+        Sb[q] = c2 * (Gb[v] * Sn[q] - Ep[v] * Sdn[q]);
+      } else {
+        An[q] = 0.f;
+        Sb[q] = 0.f;
+      }
+    }
+    if constexpr (L4 != 0) {
+      const int v = NR + L3 * NA + n;
+      const Sym3 M = sym_of(Sn[3], Sn[4], Sn[5], Sn[6], Sn[7]);
+      const Sym3 Md = sym_of(Sdn[3], Sdn[4], Sdn[5], Sdn[6], Sdn[7]);
+      float o[5], od[5];
+      sym_proj(sym_mul(M, M), o);
+      sym_proj(sym_mul(Md, M), od);
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        An[3 + m] += 3.0f * Ep[v] * o[m];
+        Sb[3 + m] += 3.0f * Gb[v] * o[m] - 6.0f * Ep[v] * od[m];
+      }
+    }
+    if constexpr (L5 != 0) {
+      const int v = NR + L3 * NA + (L4 ? NA : 0) + n;
+      const float P = Sn[0] * Sn[0] + Sn[1] * Sn[1] + Sn[2] * Sn[2];
+      const float SS = Sn[0] * Sdn[0] + Sn[1] * Sdn[1] + Sn[2] * Sdn[2];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        An[m] += 4.0f * Ep[v] * P * Sn[m];
+        Sb[m] += 4.0f * Gb[v] * P * Sn[m] - Ep[v] * (8.0f * SS * Sn[m] + 4.0f * P * Sdn[m]);
+      }
+    }
+    float cb[T][KA];
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int k = 0; k < KA; ++k) cb[t][k] = 0.f;
+    for (int k = 0; k < nA; ++k) {
+      const PairGeom g = pair_geom(a.nb.idxA[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+      const float ux = g.dx * g.inv_r, uy = g.dy * g.inv_r, uz = g.dz * g.inv_r;
+      const float tx = (a.fbar[g.j] - fbx) + gxx * g.dx + gxy * g.dy;
+      const float ty = (a.fbar[N + g.j] - fby) + gyy * g.dy + gyz * g.dz;
+      const float tz = (a.fbar[2 * N + g.j] - fbz) + gzz * g.dz + gzx * g.dx;
+      const float dt = ux * tx + uy * ty + uz * tz;
+      float f[KA], fp[KA];
+      radial_basis_d<KA>(g.r, a.inv_rcA, f, fp);
+      const int J = a.type[g.j];
+      float B[Y];
+      harm_val<LM>(ux, uy, uz, B);
+      float X = 0.f, Yv = 0.f;
+#pragma unroll
+      for (int q = 0; q < Y; ++q) {
+        X = fmaf(Sb[q], B[q], X);
+        Yv = fmaf(An[q], B[q], Yv);
+      }
+      float at = 0.f, au = 0.f;
+      harm_grad<LM>(ux, uy, uz, [&](int q, float ax, float ay, float az) {
+        at = fmaf(An[q], ax * tx + ay * ty + az * tz, at);
+        au = fmaf(An[q], ax * ux + ay * uy + az * uz, au);
+      });
+      X -= (at - au * dt) * g.inv_r;
+      const float Yd = Yv * dt;
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const float m = (T == 1 || J == t) ? 1.f : 0.f;
+        const float mX = m * X, mY = m * Yd;
+#pragma unroll
+        for (int kk = 0; kk < KA; ++kk) cb[t][kk] = fmaf(mX, f[kk], fmaf(-mY, fp[kk], cb[t][kk]));
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int k = 0; k < KA; ++k) {
+        const float r = wave_sum(cb[t][k]);
+        if (w.lane == 0) part[T * NR * KR + (t * NA + n) * KA + k] = r;
+      }
+  }
+}
+
+// sum over the atoms of species I of beta G^T - (w1 sigma) Gdot^T, tiled
+// 4 x 4 per thread over (hidden unit, descriptor) with atom tiles in LDS.
+constexpr int kW0Atoms = 32;
+
+__global__ __launch_bounds__(256) void k_w0_grad(int Npad, int H, int D, int NB, const int* __restrict__ seg,
+                                                 const float* __restrict__ beta, const float* __restrict__ w1s,
+                                                 const float* __restrict__ G, const float* __restrict__ Gd,
+                                                 float* __restrict__ w0part) {
+  extern __shared__ float lds[];
+  const int HP = (H + 3) & ~3, DP = (D + 3) & ~3;
+  float* bl = lds;                       // [kW0Atoms][HP]
+  float* sl = bl + kW0Atoms * HP;        // [kW0Atoms][HP]
+  float* gl = sl + kW0Atoms * HP;        // [kW0Atoms][DP]
+  float* dl = gl + kW0Atoms * DP;        // [kW0Atoms][DP]
+  const int I = blockIdx.y, b = blockIdx.x;
+  const int start = seg[2 * I], count = seg[2 * I + 1];
+  const int chunk = (count + NB - 1) / NB;
+  const int p0 = start + b * chunk;
+  const int p1 = min(start + count, p0 + chunk);
+  const int ntm = HP / 4, ntv = DP / 4, ntile = ntm * ntv;
+  constexpr int kMaxTiles = 4;
+  float acc[kMaxTiles][4][4];
+#pragma unroll
+  for (int u = 0; u < kMaxTiles; ++u)
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[u][x][y] = 0.f;
+  for (int base = p0; base < p1; base += kW0Atoms) {
+    const int na = min(kW0Atoms, p1 - base);
+    for (int q = threadIdx.x; q < kW0Atoms * HP; q += blockDim.x) {
+      const int u = q / kW0Atoms, at = q % kW0Atoms;
+      const bool ok = u < H && at < na;
+      bl[at * HP + u] = ok ? beta[(size_t)u * Npad + base + at] : 0.f;
+      sl[at * HP + u] = ok ? w1s[(size_t)u * Npad + base + at] : 0.f;
+    }
+    for (int q = threadIdx.x; q < kW0Atoms * DP; q += blockDim.x) {
+      const int v = q / kW0Atoms, at = q % kW0Atoms;
+      const bool ok = v < D && at < na;
+      gl[at * DP + v] = ok ? G[(size_t)v * Npad + base + at] : 0.f;
+      dl[at * DP + v] = ok ? Gd[(size_t)v * Npad + base + at] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kMaxTiles; ++u) {
+      const int tile = threadIdx.x + u * blockDim.x;
+      if (tile >= ntile) break;
+      const int m0 = (tile / ntv) * 4, v0 = (tile % ntv) * 4;
+      for (int at = 0; at < na; ++at) {
+        const float4 bb = *reinterpret_cast<const float4*>(bl + at * HP + m0);
+        const float4 ss = *reinterpret_cast<const float4*>(sl + at * HP + m0);
+        const float4 gg = *reinterpret_cast<const float4*>(gl + at * DP + v0);
+        const float4 dd = *reinterpret_cast<const float4*>(dl + at * DP + v0);
+        const float bv[4] = {bb.x, bb.y, bb.z, bb.w}, sv[4] = {ss.x, ss.y, ss.z, ss.w};
+        const float gv[4] = {gg.x, gg.y, gg.z, gg.w}, dv[4] = {dd.x, dd.y, dd.z, dd.w};
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) acc[u][x][y] = fmaf(bv[x], gv[y], fmaf(-sv[x], dv[y], acc[u][x][y]));
+      }
+    }
+    __syncthreads();
+  }
+  float* out = w0part + ((size_t)I * NB + b) * H * D;
+#pragma unroll
+  for (int u = 0; u < kMaxTiles; ++u) {
+    const int tile = threadIdx.x + u * blockDim.x;
+    if (tile >= ntile) break;
+    const int m0 = (tile / ntv) * 4, v0 = (tile % ntv) * 4;
+    for (int x = 0; x < 4; ++x)
+      for (int y = 0; y < 4; ++y)
+        if (m0 + x < H && v0 + y < D) out[(m0 + x) * D + v0 + y] = acc[u][x][y];
+  }
+}
+
+// Final gradient: float64 sums of the per-wavefront and per-block partials in
+// a fixed order.
+struct GradArgs {
+  int T, NR, NA, KR, KA, H, D, nwaves, PW, NB;
+  const float* part;
+  const int* wspecies;
+  const float* w0part;
+  float* grad;
+};
+
+__global__ __launch_bounds__(256) void k_grad_final(GradArgs a) {
+  const int P_R = a.T * a.T * a.NR * a.KR, P_A = a.T * a.T * a.NA * a.KA;
+  const int blk = a.H * a.D + 2 * a.H + 1;
+  const int P = P_R + P_A + a.T * blk;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= P) return;
+  const int PSR = a.T * a.NR * a.KR;
+  int I, slot = -1;
+  if (q < P_R) {
+    I = q / PSR;
+    slot = q % PSR;
+  } else if (q < P_R + P_A) {
+    const int r = q - P_R, PSA = a.T * a.NA * a.KA;
+    I = r / PSA;
+    slot = PSR + r % PSA;
+  } else {
+    const int r = q - P_R - P_A;
+    I = r / blk;
+    const int o = r % blk;
+    if (o < a.H * a.D) {
+      double s = 0.0;
+      for (int b = 0; b < a.NB; ++b) s += a.w0part[((size_t)I * a.NB + b) * a.H * a.D + o];
+      a.grad[q] = (float)s;
+      return;
+    }
+    slot = PSR + a.T * a.NA * a.KA + (o - a.H * a.D);
+  }
+  double s = 0.0;
+  for (int wv = 0; wv < a.nwaves; ++wv)
+    if (a.wspecies[wv] == I) s += a.part[(size_t)wv * a.PW + slot];
+  a.grad[q] = (float)s;
+}
+
+// ==================================================================== Adam
+__device__ __forceinline__ void adam_one(float* __restrict__ th, float* __restrict__ m, float* __restrict__ v,
+                                         float g, float lr, float b1, float b2, float eps, float c1, float c2,
+                                         int64_t q) {
+  const float mm = b1 * m[q] + (1.0f - b1) * g;
+  const float vv = b2 * v[q] + (1.0f - b2) * g * g;
+  m[q] = mm;
+  v[q] = vv;
+  th[q] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+}
+
+__global__ __launch_bounds__(256) void k_adam(int64_t P, float* __restrict__ th, float* __restrict__ m,
+                                              float* __restrict__ v, const float* __restrict__ g, float lr, float b1,
+                                              float b2, float eps, float c1, float c2) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < P) adam_one(th, m, v, g[q], lr, b1, b2, eps, c1, c2, q);
+}
+
+struct AdamDev {
+  float lr_start, lr_stop;
+  int64_t n_warmup, n_total;
+  float b1, b2, eps;
+};
+
+__device__ float lr_at(const AdamDev& c, int64_t s) {
+  if (c.n_total <= 0) return c.lr_start;
+  if (s < c.n_warmup) return c.lr_stop + (float)((double)s / (double)c.n_warmup) * (c.lr_start - c.lr_stop);
+  double fr = (double)(s - c.n_warmup) / (double)max((int64_t)1, c.n_total - c.n_warmup);
+  fr = fr > 1.0 ? 1.0 : fr;
+  return c.lr_stop + (c.lr_start - c.lr_stop) * 0.5f * (1.0f + (float)cos(3.14159265358979323846 * fr));
+}
+
+// Adam with the step counter read from device memory (graph replays).
+__global__ __launch_bounds__(256) void k_adam_dev(int64_t P, float* __restrict__ th, float* __restrict__ m,
+                                                  float* __restrict__ v, const float* __restrict__ g,
+                                                  const int* __restrict__ step, AdamDev c) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= P) return;
+  const int st = *step;
+  const float lr = lr_at(c, (int64_t)(st - 1));
+  const float c1 = 1.0f - powf(c.b1, (float)st), c2 = 1.0f - powf(c.b2, (float)st);
+  adam_one(th, m, v, g[q], lr, c.b1, c.b2, c.eps, c1, c2, q);
+}
+
+__global__ void k_step_inc(int* step) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *step += 1;
+}
+
+__global__ void k_fill_i32(int* p, int n, int v) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) p[q] = v;
+}
+
+__global__ void k_fill_f32(float* p, int64_t n, float v) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) p[q] = v;
+}
+
+// ================================================================ dispatch
+struct Ops {
+  int T, NR, NA, KR, KA, L3, L4, L5, D, Y, PS;
+  void (*forward)(const FwdArgs&, dim3, hipStream_t);
+  void (*adjoint)(const AdjArgs&, dim3, hipStream_t);
+};
+
+template <class C>
+static void launch_forward(const FwdArgs& a, dim3 grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_forward<C>, grid, dim3(256), 0, st, a);
+}
+template <class C>
+static void launch_adjoint(const AdjArgs& a, dim3 grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_adjoint<C>, grid, dim3(256), 0, st, a);
+}
+template <class C>
+static Ops make_ops() {
+  return Ops{C::T, C::NR, C::NA, C::KR, C::KA, C::L3, C::L4, C::L5, C::D, C::Y, C::PS,
+             &launch_forward<C>, &launch_adjoint<C>};
+}
+
+// Compiled-in model sizes (n_types, n_rad, n_ang, k_rad, k_ang, l3, l4, l5).
+static const Ops kOps[] = {
+    make_ops<Cfg<2, 5, 5, 9, 9, 4, 0, 0>>(),    // 3-body NEP, basis 8, n_max 4
+    make_ops<Cfg<2, 7, 5, 11, 11, 4, 2, 1>>(),  // 3/4/5-body NEP, basis 10, n_max 6/4
+    make_ops<Cfg<2, 3, 2, 4, 3, 4, 2, 1>>(),    // small two-species model
+    make_ops<Cfg<1, 4, 3, 6, 5, 2, 2, 0>>(),    // small one-species model
+};
+
+}  // namespace nep
+
+// ===================================================================== ABI
+using namespace nep;
+
+namespace {
+
+const Ops* find_ops(const nep_model* m) {
+  for (const Ops& o : kOps)
+    if (o.T == m->n_types && o.NR == m->n_rad && o.NA == m->n_ang && o.KR == m->k_rad && o.KA == m->k_ang &&
+        o.L3 == m->l3 && o.L4 == m->l4 && o.L5 == m->l5)
+      return &o;
+  return nullptr;
+}
+
+int model_valid(const nep_model* m) {
+  if (!m) return NEP_ERR_ARG;
+  if (m->n_types < 1 || m->n_types > 8 || m->n_rad < 1 || m->n_ang < 0 || m->k_rad < 1 || m->k_ang < 1 ||
+      m->l3 < 0 || m->l3 > 4 || (m->l4 != 0 && m->l4 != 2) || (m->l5 != 0 && m->l5 != 1) || m->hidden < 1 ||
+      m->hidden > 256 || !(m->rc_rad > 0.f) || !(m->rc_ang > 0.f) || m->rc_ang > m->rc_rad || m->cap_rad < 1 ||
+      m->cap_ang < 1 || m->cap_rad > 4096 || m->cap_ang > 4096)
+    return NEP_ERR_ARG;
+  return NEP_OK;
+}
+
+int32_t desc_count(const nep_model* m) {
+  return m->n_rad + m->n_ang * m->l3 + (m->l4 ? m->n_ang : 0) + (m->l5 ? m->n_ang : 0);
+}
+
+int64_t param_count(const nep_model* m) {
+  const int64_t T = m->n_types, D = desc_count(m), H = m->hidden;
+  return T * T * (m->n_rad * m->k_rad + m->n_ang * m->k_ang) + T * (H * D + 2 * H + 1);
+}
+
+size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+constexpr int kW0Blocks = 64;
+
+struct Layout {
+  int N, S, T, D, Y, H, Npad, nwaves, nblk, PW, NA, capR, capA;
+  size_t order, seg, blk, astruct, revR, revA, G, Sst, Ep, X, eatom, fR, fA, wv, F, fbar, Es, Ws, eps, wbar, lpart,
+      Gd, Sd, beta, w1s, part, wsp, w0part, total;
+};
+
+Layout make_layout(const nep_model* m, const Ops* o, int S, int N) {
+  Layout L{};
+  L.N = N;
+  L.S = S;
+  L.T = m->n_types;
+  L.D = o->D;
+  L.Y = o->Y;
+  L.H = m->hidden;
+  L.NA = m->n_ang;
+  L.capR = m->cap_rad;
+  L.capA = m->cap_ang;
+  L.Npad = ((N + kWave - 1) / kWave) * kWave + L.T * kWave;
+  L.nwaves = L.Npad / kWave;
+  L.nblk = N > 0 ? (N + kOrdBlk - 1) / kOrdBlk : 1;
+  L.PW = o->PS + 2 * L.H + 1;
+  const size_t Np = L.Npad, Nn = (size_t)(N > 0 ? N : 1), Ss = (size_t)(S > 0 ? S : 1);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = off;
+    off += al(bytes);
+    return r;
+  };
+  L.order = take(4 * Np);
+  L.seg = take(4 * 2 * 8);
+  L.blk = take(4 * (size_t)L.nblk * L.T);
+  L.astruct = take(4 * Nn);
+  L.revR = take(4 * (size_t)L.capR * Nn);
+  L.revA = take(4 * (size_t)L.capA * Nn);
+  L.G = take(4 * (size_t)L.D * Np);
+  L.Sst = take(4 * (size_t)L.NA * L.Y * Np);
+  L.Ep = take(4 * (size_t)L.D * Np);
+  L.X = take(4 * (size_t)L.H * Np);
+  L.eatom = take(4 * Nn);
+  L.fR = take(4 * 3 * (size_t)L.capR * Nn);
+  L.fA = take(4 * 3 * (size_t)L.capA * Nn);
+  L.wv = take(4 * 6 * Nn);
+  L.F = take(4 * 3 * Nn);
+  L.fbar = take(4 * 3 * Nn);
+  L.Es = take(4 * Ss);
+  L.Ws = take(4 * 6 * Ss);
+  L.eps = take(4 * Ss);
+  L.wbar = take(4 * 6 * Ss);
+  L.lpart = take(8 * 3 * Ss);
+  L.Gd = take(4 * (size_t)L.D * Np);
+  L.Sd = take(4 * (size_t)L.NA * L.Y * Np);
+  L.beta = take(4 * (size_t)L.H * Np);
+  L.w1s = take(4 * (size_t)L.H * Np);
+  L.part = take(4 * (size_t)L.nwaves * L.PW);
+  L.wsp = take(4 * (size_t)L.nwaves);
+  L.w0part = take(4 * (size_t)L.T * kW0Blocks * L.H * L.D);
+  L.total = off;
+  return L;
+}
+
+template <class P>
+P* at(void* ws, size_t off) {
+  return reinterpret_cast<P*>(static_cast<char*>(ws) + off);
+}
+
+int check_batch(const nep_batch* b) {
+  if (!b || b->n_struct < 0 || b->n_atom < 0 || b->n_atom >= (1 << 27)) return NEP_ERR_ARG;
+  if (b->n_struct == 0 && b->n_atom != 0) return NEP_ERR_ARG;
+  if (b->n_struct > 0 && (!b->atom_offset || !b->box)) return NEP_ERR_ARG;
+  if (b->n_atom > 0 && (!b->pos || !b->type)) return NEP_ERR_ARG;
+  return NEP_OK;
+}
+
+int check_ws(const void* ws) {
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u)) return NEP_ERR_WORKSPACE;
+  return NEP_OK;
+}
+
+int check_nbrs(const nep_neighbors* n, int N) {
+  if (!n) return NEP_ERR_ARG;
+  if (N > 0 && (!n->idx_rad || !n->cnt_rad || !n->idx_ang || !n->cnt_ang)) return NEP_ERR_ARG;
+  return NEP_OK;
+}
+
+// Optional per-launch timing (nep_profile_loss_grad).
+struct Prof {
+  hipStream_t st;
+  std::vector<hipEvent_t> ev;
+  std::vector<const char*> names;
+  void begin() {
+    hipEvent_t e;
+    (void)hipEventCreate(&e);
+    (void)hipEventRecord(e, st);
+    ev.push_back(e);
+  }
+  void end(const char* n) {
+    begin();
+    names.push_back(n);
+  }
+};
+
+#define NEP_LAUNCH(prof, name, ...)  \
+  do {                               \
+    if (prof) (prof)->begin();       \
+    __VA_ARGS__;                     \
+    if (prof) (prof)->end(name);     \
+  } while (0)
+
+int hip_ok() { return hipGetLastError() == hipSuccess ? NEP_OK : NEP_ERR_HIP; }
+
+struct Ctx {
+  const nep_model* m;
+  const Ops* o;
+  const nep_batch* b;
+  Layout L;
+  void* ws;
+  hipStream_t st;
+};
+
+int grid1(int n, int blk = 256) { return (n + blk - 1) / blk; }
+
+PairLists pair_lists(const Ctx& c, const nep_neighbors* nb) {
+  PairLists p;
+  p.idxR = nb->idx_rad;
+  p.cntR = nb->cnt_rad;
+  p.idxA = nb->idx_ang;
+  p.cntA = nb->cnt_ang;
+  p.revR = at<int>(c.ws, c.L.revR);
+  p.revA = at<int>(c.ws, c.L.revA);
+  p.capR = c.m->cap_rad;
+  p.capA = c.m->cap_ang;
+  return p;
+}
+
+void run_neighbors(const Ctx& c, nep_neighbors* nb, int32_t* flags, Prof* pr) {
+  const int N = c.L.N;
+  if (N == 0) return;
+  NbrArgs a;
+  a.N = N;
+  a.S = c.b->n_struct;
+  a.T = c.m->n_types;
+  a.capR = c.m->cap_rad;
+  a.capA = c.m->cap_ang;
+  a.rcR = c.m->rc_rad;
+  a.rcA = c.m->rc_ang;
+  a.aoff = c.b->atom_offset;
+  a.box = c.b->box;
+  a.pos = c.b->pos;
+  a.type = c.b->type;
+  a.idxR = nb->idx_rad;
+  a.cntR = nb->cnt_rad;
+  a.idxA = nb->idx_ang;
+  a.cntA = nb->cnt_ang;
+  a.astruct = at<int>(c.ws, c.L.astruct);
+  a.flags = flags;
+  NEP_LAUNCH(pr, "neighbors", hipLaunchKernelGGL(k_neighbors, dim3(grid1(N)), dim3(256), 0, c.st, a));
+  NEP_LAUNCH(pr, "reverse_rad",
+             hipLaunchKernelGGL(k_reverse, dim3(grid1(N)), dim3(256), 0, c.st, N, nb->idx_rad, nb->cnt_rad,
+                                c.m->cap_rad, at<int>(c.ws, c.L.revR)));
+  NEP_LAUNCH(pr, "reverse_ang",
+             hipLaunchKernelGGL(k_reverse, dim3(grid1(N)), dim3(256), 0, c.st, N, nb->idx_ang, nb->cnt_ang,
+                                c.m->cap_ang, at<int>(c.ws, c.L.revA)));
+  int* order = at<int>(c.ws, c.L.order);
+  int* blk = at<int>(c.ws, c.L.blk);
+  int* seg = at<int>(c.ws, c.L.seg);
+  NEP_LAUNCH(pr, "order_count",
+             hipLaunchKernelGGL(k_order_count, dim3(c.L.nblk), dim3(kOrdBlk), 0, c.st, N, c.L.Npad, c.L.T, c.b->type,
+                                blk, order));
+  NEP_LAUNCH(pr, "order_scan", hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, c.st, c.L.nblk, c.L.T, blk, seg));
+  NEP_LAUNCH(pr, "order_scatter",
+             hipLaunchKernelGGL(k_order_scatter, dim3(c.L.nblk), dim3(kOrdBlk), 0, c.st, N, c.L.T, c.b->type, blk,
+                                order));
+}
+
+FwdArgs fwd_args(const Ctx& c, const nep_neighbors* nb, const float* params) {
+  FwdArgs a;
+  const nep_model* m = c.m;
+  a.N = c.L.N;
+  a.Npad = c.L.Npad;
+  a.H = m->hidden;
+  a.inv_rcR = 1.0f / m->rc_rad;
+  a.inv_rcA = 1.0f / m->rc_ang;
+  a.order = at<int>(c.ws, c.L.order);
+  a.astruct = at<int>(c.ws, c.L.astruct);
+  a.box = c.b->box;
+  a.pos = c.b->pos;
+  a.type = c.b->type;
+  a.nb = pair_lists(c, nb);
+  const int T = m->n_types;
+  a.cR = params;
+  a.cA = params + (size_t)T * T * m->n_rad * m->k_rad;
+  a.nn = a.cA + (size_t)T * T * m->n_ang * m->k_ang;
+  a.nn_stride = m->hidden * c.o->D + 2 * m->hidden + 1;
+  a.G = at<float>(c.ws, c.L.G);
+  a.Guser = nullptr;
+  a.Sst = at<float>(c.ws, c.L.Sst);
+  a.Ep = at<float>(c.ws, c.L.Ep);
+  a.X = at<float>(c.ws, c.L.X);
+  a.eatom = at<float>(c.ws, c.L.eatom);
+  a.eatom2 = nullptr;
+  a.fR = at<float>(c.ws, c.L.fR);
+  a.fA = at<float>(c.ws, c.L.fA);
+  a.wv = at<float>(c.ws, c.L.wv);
+  a.do_mlp = 1;
+  a.do_force = 1;
+  return a;
+}
+
+// forward + force gather + per-structure sums (+ loss when labels given)
+void run_forward(const Ctx& c, const nep_neighbors* nb, const float* params, float* e_atom, float* e_struct,
+                 float* force, float* virial, const nep_labels* lab, const float* lam, float* loss, int32_t* flags,
+                 Prof* pr) {
+  const int N = c.L.N, S = c.b->n_struct;
+  if (N > 0) {
+    FwdArgs a = fwd_args(c, nb, params);
+    a.eatom2 = e_atom;
+    NEP_LAUNCH(pr, "forward", c.o->forward(a, dim3(grid1(c.L.Npad)), c.st));
+    NEP_LAUNCH(pr, "force_gather",
+               hipLaunchKernelGGL(k_force_gather, dim3(grid1(N)), dim3(256), 0, c.st, N, a.nb, a.fR, a.fA,
+                                  at<float>(c.ws, c.L.F), force));
+  }
+  if (S > 0) {
+    StructArgs s;
+    s.S = S;
+    s.N = N;
+    s.aoff = c.b->atom_offset;
+    s.eatom = at<float>(c.ws, c.L.eatom);
+    s.wv = at<float>(c.ws, c.L.wv);
+    s.F = at<float>(c.ws, c.L.F);
+    s.Et = lab ? lab->energy : nullptr;
+    s.Ft = lab ? lab->force : nullptr;
+    s.Wt = lab ? lab->virial : nullptr;
+    s.le = lam ? lam[0] : 0.f;
+    s.lf = lam ? lam[1] : 0.f;
+    s.lv = lam ? lam[2] : 0.f;
+    s.Es = at<float>(c.ws, c.L.Es);
+    s.Ws = at<float>(c.ws, c.L.Ws);
+    s.Es_user = e_struct;
+    s.Ws_user = virial;
+    s.eps = at<float>(c.ws, c.L.eps);
+    s.wbar = at<float>(c.ws, c.L.wbar);
+    s.fbar = at<float>(c.ws, c.L.fbar);
+    s.lpart = at<double>(c.ws, c.L.lpart);
+    NEP_LAUNCH(pr, "struct_sums", hipLaunchKernelGGL(k_struct, dim3(S), dim3(kRedBlk), 0, c.st, s));
+    if (lab)
+      NEP_LAUNCH(pr, "loss_final",
+                 hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kRedBlk), 0, c.st, S, N, s.le, s.lf, s.lv, s.lpart,
+                                    loss, flags));
+  }
+}
+
+// adjoint + gradient reductions; cotangents from eps/fbar/wbar pointers
+void run_adjoint(const Ctx& c, const nep_neighbors* nb, const float* params, const float* eps, const float* fbar,
+                 const float* wbar, float* grad, Prof* pr) {
+  const nep_model* m = c.m;
+  const int N = c.L.N;
+  if (N > 0) {
+    AdjArgs a;
+    a.N = N;
+    a.Npad = c.L.Npad;
+    a.H = m->hidden;
+    a.S = c.b->n_struct;
+    a.inv_rcR = 1.0f / m->rc_rad;
+    a.inv_rcA = 1.0f / m->rc_ang;
+    a.order = at<int>(c.ws, c.L.order);
+    a.astruct = at<int>(c.ws, c.L.astruct);
+    a.box = c.b->box;
+    a.pos = c.b->pos;
+    a.type = c.b->type;
+    a.nb = pair_lists(c, nb);
+    const int T = m->n_types;
+    a.cR = params;
+    a.cA = params + (size_t)T * T * m->n_rad * m->k_rad;
+    a.nn = a.cA + (size_t)T * T * m->n_ang * m->k_ang;
+    a.nn_stride = m->hidden * c.o->D + 2 * m->hidden + 1;
+    a.Sst = at<float>(c.ws, c.L.Sst);
+    a.Ep = at<float>(c.ws, c.L.Ep);
+    a.X = at<float>(c.ws, c.L.X);
+    a.eps = eps;
+    a.fbar = fbar;
+    a.wbar = wbar;
+    a.Gd = at<float>(c.ws, c.L.Gd);
+    a.Sd = at<float>(c.ws, c.L.Sd);
+    a.beta = at<float>(c.ws, c.L.beta);
+    a.w1s = at<float>(c.ws, c.L.w1s);
+    a.part = at<float>(c.ws, c.L.part);
+    a.wave_species = at<int>(c.ws, c.L.wsp);
+    a.PW = c.L.PW;
+    NEP_LAUNCH(pr, "adjoint", c.o->adjoint(a, dim3(grid1(c.L.Npad)), c.st));
+    const int HP = (m->hidden + 3) & ~3, DP = (c.o->D + 3) & ~3;
+    const size_t lds = sizeof(float) * kW0Atoms * 2 * (HP + DP);
+    NEP_LAUNCH(pr, "w0_grad",
+               hipLaunchKernelGGL(k_w0_grad, dim3(kW0Blocks, T), dim3(256), lds, c.st, c.L.Npad, m->hidden, c.o->D,
+                                  kW0Blocks, at<int>(c.ws, c.L.seg), a.beta, a.w1s, at<float>(c.ws, c.L.G), a.Gd,
+                                  at<float>(c.ws, c.L.w0part)));
+    GradArgs g;
+    g.T = T;
+    g.NR = m->n_rad;
+    g.NA = m->n_ang;
+    g.KR = m->k_rad;
+    g.KA = m->k_ang;
+    g.H = m->hidden;
+    g.D = c.o->D;
+    g.nwaves = c.L.nwaves;
+    g.PW = c.L.PW;
+    g.NB = kW0Blocks;
+    g.part = a.part;
+    g.wspecies = a.wave_species;
+    g.w0part = at<float>(c.ws, c.L.w0part);
+    g.grad = grad;
+    NEP_LAUNCH(pr, "grad_final",
+               hipLaunchKernelGGL(k_grad_final, dim3(grid1((int)param_count(m))), dim3(256), 0, c.st, g));
+  } else {
+    const int64_t P = param_count(m);
+    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, c.st, grad, P, 0.f);
+  }
+}
+
+int setup(Ctx& c, const nep_model* m, const nep_batch* b, void* ws, void* stream) {
+  int rc = model_valid(m);
+  if (rc) return rc;
+  c.o = find_ops(m);
+  if (!c.o) return NEP_ERR_ARG;
+  if (((m->hidden + 3) / 4) * ((c.o->D + 3) / 4) > 4 * 256) return NEP_ERR_ARG;  // W0 tiles per block
+  if ((rc = check_batch(b))) return rc;
+  if ((rc = check_ws(ws))) return rc;
+  c.m = m;
+  c.b = b;
+  c.ws = ws;
+  c.st = static_cast<hipStream_t>(stream);
+  c.L = make_layout(m, c.o, b->n_struct, b->n_atom);
+  return NEP_OK;
+}
+
+int loss_grad_seq(Ctx& c, nep_neighbors* nb, const float* params, const nep_labels* labels, const float* lam,
+                  float* loss, float* grad, float* e_struct, float* force, float* virial, int32_t* flags, Prof* pr,
+                  bool with_neighbors) {
+  if (with_neighbors) run_neighbors(c, nb, flags, pr);
+  run_forward(c, nb, params, nullptr, e_struct, force, virial, labels, lam, loss, flags, pr);
+  run_adjoint(c, nb, params, at<float>(c.ws, c.L.eps), at<float>(c.ws, c.L.fbar), at<float>(c.ws, c.L.wbar), grad,
+              pr);
+  return hip_ok();
+}
+
+struct GraphHandle {
+  hipGraph_t g;
+  hipGraphExec_t e;
+};
+
+}  // namespace
+
+extern "C" {
+
+int64_t nep_param_count(const nep_model* m) {
+  const int rc = model_valid(m);
+  return rc ? rc : param_count(m);
+}
+
+int32_t nep_descriptor_count(const nep_model* m) {
+  const int rc = model_valid(m);
+  return rc ? rc : desc_count(m);
+}
+
+int nep_model_supported(const nep_model* m) {
+  const int rc = model_valid(m);
+  if (rc) return rc;
+  return find_ops(m) ? NEP_OK : NEP_ERR_ARG;
+}
+
+int nep_workspace_bytes(const nep_model* m, int32_t n_struct, int32_t n_atom, size_t* bytes) {
+  int rc = nep_model_supported(m);
+  if (rc) return rc;
+  if (!bytes || n_struct < 0 || n_atom < 0 || n_atom >= (1 << 27)) return NEP_ERR_ARG;
+  *bytes = make_layout(m, find_ops(m), n_struct, n_atom).total;
+  return NEP_OK;
+}
+
+int nep_build_neighbors(const nep_model* m, const nep_batch* b, nep_neighbors* out, void* ws, int32_t* d_flags,
+                        void* stream) {
+  Ctx c;
+  int rc = setup(c, m, b, ws, stream);
+  if (rc) return rc;
+  if ((rc = check_nbrs(out, b->n_atom))) return rc;
+  if (!d_flags) return NEP_ERR_ARG;
+  run_neighbors(c, out, d_flags, nullptr);
+  return hip_ok();
+}
+
+int nep_descriptors(const nep_model* m, const nep_batch* b, const nep_neighbors* nb, const float* params, float* G,
+                    void* ws, void* stream) {
+  Ctx c;
+  int rc = setup(c, m, b, ws, stream);
+  if (rc) return rc;
+  if ((rc = check_nbrs(nb, b->n_atom))) return rc;
+  if (b->n_atom > 0 && (!params || !G)) return NEP_ERR_ARG;
+  if (b->n_atom == 0) return NEP_OK;
+  FwdArgs a = fwd_args(c, nb, params);
+  a.Guser = G;
+  a.do_mlp = 0;
+  a.do_force = 0;
+  c.o->forward(a, dim3(grid1(c.L.Npad)), c.st);
+  return hip_ok();
+}
+
+int nep_energy_force_virial(const nep_model* m, const nep_batch* b, const nep_neighbors* nb, const float* params,
+                            float* e_atom, float* e_struct, float* force, float* virial, void* ws, void* stream) {
+  Ctx c;
+  int rc = setup(c, m, b, ws, stream);
+  if (rc) return rc;
+  if ((rc = check_nbrs(nb, b->n_atom))) return rc;
+  if (!params) return NEP_ERR_ARG;
+  run_forward(c, nb, params, e_atom, e_struct, force, virial, nullptr, nullptr, nullptr, nullptr, nullptr);
+  return hip_ok();
+}
+
+int nep_vjp(const nep_model* m, const nep_batch* b, const nep_neighbors* nb, const float* params, const float* e_bar,
+            const float* f_bar, const float* v_bar, float* grad, void* ws, void* stream) {
+  Ctx c;
+  int rc = setup(c, m, b, ws, stream);
+  if (rc) return rc;
+  if ((rc = check_nbrs(nb, b->n_atom))) return rc;
+  if (!params || !grad) return NEP_ERR_ARG;
+  if (b->n_atom > 0 && (!e_bar || !f_bar || !v_bar)) return NEP_ERR_ARG;
+  if (b->n_atom > 0) {
+    FwdArgs a = fwd_args(c, nb, params);
+    a.do_force = 0;
+    c.o->forward(a, dim3(grid1(c.L.Npad)), c.st);
+  }
+  run_adjoint(c, nb, params, e_bar, f_bar, v_bar, grad, nullptr);
+  return hip_ok();
+}
+
+int nep_loss_grad(const nep_model* m, const nep_batch* b, const nep_neighbors* nb, const float* params,
+                  const nep_labels* labels, const float lambda[3], float* loss, float* grad, float* e_struct,
+                  float* force, float* virial, void* ws, int32_t* d_flags, void* stream) {
+  Ctx c;
+  int rc = setup(c, m, b, ws, stream);
+  if (rc) return rc;
+  if ((rc = check_nbrs(nb, b->n_atom))) return rc;
+  if (!params || !labels || !lambda || !loss || !grad) return NEP_ERR_ARG;
+  if (b->n_struct > 0 && (!labels->energy || !labels->virial)) return NEP_ERR_ARG;
+  if (b->n_atom > 0 && !labels->force) return NEP_ERR_ARG;
+  return loss_grad_seq(c, const_cast<nep_neighbors*>(nb), params, labels, lambda, loss, grad, e_struct, force, virial,
+                       d_flags, nullptr, false);
+}
+
+int nep_adam_step(int64_t P, float* params, float* mm, float* vv, const float* grad, float lr, float beta1,
+                  float beta2, float eps, int32_t step, void* stream) {
+  if (P < 0 || step < 1 || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f)) return NEP_ERR_ARG;
+  if (P == 0) return NEP_OK;
+  if (!params || !mm || !vv || !grad) return NEP_ERR_ARG;
+  const float c1 = 1.0f - (float)std::pow((double)beta1, (double)step);
+  const float c2 = 1.0f - (float)std::pow((double)beta2, (double)step);
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, static_cast<hipStream_t>(stream), P,
+                     params, mm, vv, grad, lr, beta1, beta2, eps, c1, c2);
+  return hip_ok();
+}
+
+float nep_lr_schedule(int64_t s, float lr_start, float lr_stop, int64_t n_warmup, int64_t n_total) {
+  if (n_total <= 0) return lr_start;
+  if (s < n_warmup) return lr_stop + (float)((double)s / (double)n_warmup) * (lr_start - lr_stop);
+  double fr = (double)(s - n_warmup) / (double)std::max<int64_t>(1, n_total - n_warmup);
+  fr = fr > 1.0 ? 1.0 : fr;
+  return lr_stop + (lr_start - lr_stop) * 0.5f * (1.0f + (float)std::cos(3.14159265358979323846 * fr));
+}
+
+int nep_train_step_graph_create(const nep_model* m, const nep_batch* b, nep_neighbors* nb, const nep_labels* labels,
+                                const float lambda[3], float* params, float* mm, float* vv, float* grad, float* loss,
+                                int32_t* d_step, const nep_adam_config* adam, void* ws, int32_t* d_flags,
+                                void* stream, void** graph) {
+  Ctx c;
+  int rc = setup(c, m, b, ws, stream);
+  if (rc) return rc;
+  if ((rc = check_nbrs(nb, b->n_atom))) return rc;
+  if (!labels || !lambda || !params || !mm || !vv || !grad || !loss || !d_step || !adam || !d_flags || !graph)
+    return NEP_ERR_ARG;
+  hipStream_t cap;
+  if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return NEP_ERR_HIP;
+  c.st = cap;
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipStreamDestroy(cap);
+    return NEP_ERR_HIP;
+  }
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, cap, d_flags, 1, 0);
+  loss_grad_seq(c, nb, params, labels, lambda, loss, grad, nullptr, nullptr, nullptr, d_flags, nullptr, true);
+  const int64_t P = param_count(m);
+  AdamDev ad{adam->lr_start, adam->lr_stop, adam->n_warmup, adam->n_total, adam->beta1, adam->beta2, adam->eps};
+  hipLaunchKernelGGL(k_adam_dev, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, cap, P, params, mm, vv, grad,
+                     d_step, ad);
+  hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(64), 0, cap, d_step);
+  const hipError_t e1 = hipStreamEndCapture(cap, &g);
+  (void)hipStreamDestroy(cap);
+  if (e1 != hipSuccess || !g) return NEP_ERR_HIP;
+  hipGraphExec_t ex;
+  if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return NEP_ERR_HIP;
+  }
+  GraphHandle* h = new (std::nothrow) GraphHandle{g, ex};
+  if (!h) {
+    (void)hipGraphExecDestroy(ex);
+    (void)hipGraphDestroy(g);
+    return NEP_ERR_HIP;
+  }
+  *graph = h;
+  return NEP_OK;
+}
+
+int nep_train_step_graph_launch(void* graph, void* stream) {
+  if (!graph) return NEP_ERR_ARG;
+  GraphHandle* h = static_cast<GraphHandle*>(graph);
+  return hipGraphLaunch(h->e, static_cast<hipStream_t>(stream)) == hipSuccess ? NEP_OK : NEP_ERR_HIP;
+}
+
+int nep_train_step_graph_destroy(void* graph) {
+  if (!graph) return NEP_OK;
+  GraphHandle* h = static_cast<GraphHandle*>(graph);
+  (void)hipGraphExecDestroy(h->e);
+  (void)hipGraphDestroy(h->g);
+  delete h;
+  return NEP_OK;
+}
+
+int nep_profile_loss_grad(const nep_model* m, const nep_batch* b, nep_neighbors* nb, const float* params,
+                          const nep_labels* labels, const float lambda[3], float* loss, float* grad, void* ws,
+                          int32_t* d_flags, void* stream, float* ms, const char** names, int32_t max_kernels,
+                          int32_t* n_kernels) {
+  Ctx c;
+  int rc = setup(c, m, b, ws, stream);
+  if (rc) return rc;
+  if ((rc = check_nbrs(nb, b->n_atom))) return rc;
+  if (!labels || !lambda || !params || !loss || !grad || !d_flags || !n_kernels) return NEP_ERR_ARG;
+  Prof pr;
+  pr.st = c.st;
+  rc = loss_grad_seq(c, nb, params, labels, lambda, loss, grad, nullptr, nullptr, nullptr, d_flags, &pr, true);
+  if (hipStreamSynchronize(c.st) != hipSuccess) rc = NEP_ERR_HIP;
+  const int n = (int)pr.names.size();
+  *n_kernels = n;
+  for (int k = 0; k < n && k < max_kernels; ++k) {
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, pr.ev[2 * k], pr.ev[2 * k + 1]);
+    if (ms) ms[k] = t;
+    if (names) names[k] = pr.names[k];
+  }
+  for (hipEvent_t e : pr.ev) (void)hipEventDestroy(e);
+  return rc;
+}
+
+int nep_flags_status(int32_t f) {
+  if (f & FL_BOX) return NEP_ERR_BOX;
+  if (f & FL_TYPE) return NEP_ERR_TYPE;
+  if (f & FL_POS) return NEP_ERR_POSITION;
+  if (f & FL_OVERFLOW) return NEP_ERR_NBR_OVERFLOW;
+  if (f & FL_NONFINITE) return NEP_ERR_NONFINITE;
+  return NEP_OK;
+}
+
+const char* nep_status_string(int code) {
+  switch (code) {
+    case NEP_OK: return "ok";
+    case NEP_ERR_ARG: return "invalid argument or unsupported model";
+    case NEP_ERR_BOX: return "a box edge is shorter than rc_rad";
+    case NEP_ERR_NBR_OVERFLOW: return "neighbor list capacity exceeded";
+    case NEP_ERR_NONFINITE: return "loss is not finite";
+    case NEP_ERR_HIP: return "HIP runtime error";
+    case NEP_ERR_WORKSPACE: return "workspace missing or not 256-byte aligned";
+    case NEP_ERR_TYPE: return "atom type out of range";
+    case NEP_ERR_POSITION: return "coordinate outside [0, L)";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

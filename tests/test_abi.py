@@ -1,0 +1,87 @@
+"""The C ABI without a GPU: the library loads, exports every entry point that
+include/nep.h declares, and its host-only calls and argument validation work
+(no kernel is launched here)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import lr_schedule as oracle_lr
+from paper_2507_00528_amd import _lib, nep, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "nep.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nep_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    lib = _lib.load()
+    declared = header_functions()
+    assert len(declared) >= 15
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(n for n, _, _ in _lib.SIGNATURES) == declared
+
+
+def test_counts_match_the_oracle_layout():
+    for sz in (synth.SIZES_SMALL, synth.SIZES_LARGE, synth.SIZES_TINY, synth.SIZES_MONO):
+        m = nep.Model.of(sz)
+        assert nep.param_count(m) == sz.n_params
+        assert nep.descriptor_count(m) == sz.n_desc
+        assert nep.model_supported(m)
+    assert nep.param_count(nep.Model.of(synth.SIZES_LARGE)) == 4430
+    assert nep.param_count(nep.Model.of(synth.SIZES_SMALL)) == 1982
+
+
+def test_unsupported_and_invalid_models():
+    m = nep.Model.of(synth.SIZES_SMALL)
+    m.k_rad = 7
+    assert not nep.model_supported(m)
+    with pytest.raises(nep.NEPError):
+        nep.workspace_bytes(m, 1, 10)
+    bad = nep.Model.of(synth.SIZES_SMALL)
+    bad.rc_ang = 7.0   # rc_ang > rc_rad
+    assert _lib.load().nep_param_count(C.byref(bad.c())) == -1
+
+
+def test_workspace_grows_with_batch():
+    m = nep.Model.of(synth.SIZES_LARGE)
+    a = nep.workspace_bytes(m, 10, 1000)
+    b = nep.workspace_bytes(m, 10, 2000)
+    assert 0 < a < b
+    assert nep.workspace_bytes(m, 0, 0) > 0
+
+
+def test_validation_rejects_before_launch():
+    lib = _lib.load()
+    m = nep.Model.of(synth.SIZES_SMALL).c()
+    b = _lib.NepBatch(1, 10, None, None, None, None)   # NULL arrays
+    nb = _lib.NepNeighbors(None, None, None, None)
+    assert lib.nep_build_neighbors(C.byref(m), C.byref(b), C.byref(nb), None, None, None) == -1
+    b2 = _lib.NepBatch(0, 0, None, None, None, None)
+    assert lib.nep_build_neighbors(C.byref(m), C.byref(b2), C.byref(nb), None, None, None) == -6  # no workspace
+    assert lib.nep_build_neighbors(C.byref(m), C.byref(b2), C.byref(nb), C.c_void_p(0x1001), None, None) == -6
+    assert lib.nep_adam_step(10, None, None, None, None, 1e-3, 0.9, 0.999, 1e-8, 0, None) == -1  # step < 1
+    assert lib.nep_train_step_graph_launch(None, None) == -1
+
+
+def test_status_strings_and_flags():
+    lib = _lib.load()
+    for code in range(0, -9, -1):
+        assert lib.nep_status_string(code).decode() not in ("", "unknown status")
+    assert lib.nep_flags_status(0) == 0
+    assert lib.nep_flags_status(nep.NEP_FLAG_NBR_OVERFLOW) == -3
+    assert lib.nep_flags_status(nep.NEP_FLAG_BOX | nep.NEP_FLAG_NBR_OVERFLOW) == -2
+    assert lib.nep_flags_status(nep.NEP_FLAG_NONFINITE) == -4
+
+
+def test_lr_schedule_matches_eq17():
+    for s in (0, 3, 10, 40, 100, 150):
+        assert nep.lr_schedule(s, 1e-3, 1e-5, 10, 100) == pytest.approx(oracle_lr(s, 1e-3, 1e-5, 10, 100), rel=1e-5)
+    assert nep.lr_schedule(7, 2e-3, 1e-5, 0, 0) == pytest.approx(2e-3)
