@@ -14,6 +14,17 @@ namespace nep {
 
 constexpr int kWave = 64;
 
+// Read-only parameter arrays are addressed through the constant address
+// space: with a wave-uniform address the loads become scalar (s_load) and the
+// values live in SGPRs, feeding VALU instructions as scalar operands.
+template <class T>
+using cptr = const __attribute__((address_space(4))) T*;
+
+template <class T>
+__device__ __forceinline__ cptr<T> as_const(const T* p) {
+  return (cptr<T>)(p);
+}
+
 template <int T_, int NR_, int NA_, int KR_, int KA_, int L3_, int L4_, int L5_>
 struct Cfg {
   static constexpr int T = T_, NR = NR_, NA = NA_, KR = KR_, KA = KA_;

@@ -28,75 +28,112 @@ __device__ __forceinline__ unsigned axis_candidates(double d0, double L, double 
   return m;
 }
 
-__global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.N) return;
-  int lo = 0, hi = a.S;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (a.aoff[mid] <= i) lo = mid; else hi = mid;
+constexpr int kNbrBlk = 256;
+
+__global__ __launch_bounds__(kNbrBlk) void k_neighbors(NbrArgs a) {
+  __shared__ float tx[kNbrBlk], ty[kNbrBlk], tz[kNbrBlk];
+  __shared__ int srange[2];
+  const int b0 = blockIdx.x * kNbrBlk;
+  const int i = b0 + threadIdx.x;
+  const bool live = i < a.N;
+  // structure of this atom (binary search over atom_offset)
+  int s = 0;
+  {
+    const int q = live ? i : a.N - 1;
+    int lo = 0, hi = a.S;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (a.aoff[mid] <= q) lo = mid; else hi = mid;
+    }
+    s = lo;
   }
-  const int s = lo;
-  a.astruct[i] = s;
+  if (threadIdx.x == 0) srange[0] = s;
+  if (threadIdx.x == kNbrBlk - 1 || i == a.N - 1) srange[1] = s;
   const int a0 = max(a.aoff[s], 0), a1 = min(a.aoff[s + 1], a.N);
-  const float Lxf = a.box[3 * s], Lyf = a.box[3 * s + 1], Lzf = a.box[3 * s + 2];
+  __syncthreads();
+  const int j_lo = max(a.aoff[srange[0]], 0), j_hi = min(a.aoff[srange[1] + 1], a.N);
+
   int fl = 0;
-  const int ti = a.type[i];
-  if (ti < 0 || ti >= a.T) fl |= FL_TYPE;
-  const float xf = a.pos[i], yf = a.pos[a.N + i], zf = a.pos[2 * a.N + i];
-  if (!(xf >= 0.f && xf < Lxf && yf >= 0.f && yf < Lyf && zf >= 0.f && zf < Lzf)) fl |= FL_POS;
-  if (!(Lxf >= a.rcR && Lyf >= a.rcR && Lzf >= a.rcR)) {
-    a.cntR[i] = 0;
-    a.cntA[i] = 0;
-    atomicOr(a.flags, fl | FL_BOX);
-    return;
+  bool ok = live;
+  float Lxf = 0.f, Lyf = 0.f, Lzf = 0.f;
+  double xi = 0.0, yi = 0.0, zi = 0.0;
+  if (live) {
+    a.astruct[i] = s;
+    Lxf = a.box[3 * s];
+    Lyf = a.box[3 * s + 1];
+    Lzf = a.box[3 * s + 2];
+    const int ti = a.type[i];
+    if (ti < 0 || ti >= a.T) fl |= FL_TYPE;
+    const float xf = a.pos[i], yf = a.pos[a.N + i], zf = a.pos[2 * a.N + i];
+    if (!(xf >= 0.f && xf < Lxf && yf >= 0.f && yf < Lyf && zf >= 0.f && zf < Lzf)) fl |= FL_POS;
+    if (!(Lxf >= a.rcR && Lyf >= a.rcR && Lzf >= a.rcR)) {
+      fl |= FL_BOX;
+      ok = false;
+    }
+    xi = xf;
+    yi = yf;
+    zi = zf;
   }
   const double rcR = (double)a.rcR, rcA = (double)a.rcA;
   const double rcR2 = rcR * rcR, rcA2 = rcA * rcA;  // exact: float squared in double
   const double Lx = Lxf, Ly = Lyf, Lz = Lzf;
-  const double xi = xf, yi = yf, zi = zf;
   int nR = 0, nA = 0;
-  for (int j = a0; j < a1; ++j) {
-    const double x0 = __dadd_rn((double)a.pos[j], -xi);
-    const unsigned mx = axis_candidates(x0, Lx, rcR);
-    if (!mx) continue;
-    const double y0 = __dadd_rn((double)a.pos[a.N + j], -yi);
-    const unsigned my = axis_candidates(y0, Ly, rcR);
-    if (!my) continue;
-    const double z0 = __dadd_rn((double)a.pos[2 * a.N + j], -zi);
-    const unsigned mz = axis_candidates(z0, Lz, rcR);
-    if (!mz) continue;
-    for (int sx = 0; sx < 3; ++sx) {
-      if (!((mx >> sx) & 1u)) continue;
-      const double dx = sx == 1 ? x0 : __dadd_rn(x0, sx == 0 ? -Lx : Lx);
-      const double dx2 = __dmul_rn(dx, dx);
-      for (int sy = 0; sy < 3; ++sy) {
-        if (!((my >> sy) & 1u)) continue;
-        const double dy = sy == 1 ? y0 : __dadd_rn(y0, sy == 0 ? -Ly : Ly);
-        const double dxy = __dadd_rn(dx2, __dmul_rn(dy, dy));
-        for (int sz = 0; sz < 3; ++sz) {
-          if (!((mz >> sz) & 1u)) continue;
-          const int code = 9 * sx + 3 * sy + sz;
-          if (j == i && code == 13) continue;
-          const double dz = sz == 1 ? z0 : __dadd_rn(z0, sz == 0 ? -Lz : Lz);
-          const double d2 = __dadd_rn(dxy, __dmul_rn(dz, dz));
-          if (d2 < rcR2) {
-            const uint32_t e = ((uint32_t)j << 5) | (uint32_t)code;
-            if (nR < a.capR) a.idxR[(size_t)nR * a.N + i] = e;
-            ++nR;
-            if (d2 < rcA2) {
-              if (nA < a.capA) a.idxA[(size_t)nA * a.N + i] = e;
-              ++nA;
+  for (int t0 = j_lo; t0 < j_hi; t0 += kNbrBlk) {
+    const int jt = t0 + threadIdx.x;
+    if (jt < j_hi) {
+      tx[threadIdx.x] = a.pos[jt];
+      ty[threadIdx.x] = a.pos[a.N + jt];
+      tz[threadIdx.x] = a.pos[2 * a.N + jt];
+    }
+    __syncthreads();
+    const int jb = ok ? max(a0, t0) : 0, je = ok ? min(a1, t0 + kNbrBlk) : 0;
+    for (int j = jb; j < je; ++j) {
+      const int q = j - t0;
+      const double x0 = __dadd_rn((double)tx[q], -xi);
+      const unsigned mx = axis_candidates(x0, Lx, rcR);
+      if (!mx) continue;
+      const double y0 = __dadd_rn((double)ty[q], -yi);
+      const unsigned my = axis_candidates(y0, Ly, rcR);
+      if (!my) continue;
+      const double z0 = __dadd_rn((double)tz[q], -zi);
+      const unsigned mz = axis_candidates(z0, Lz, rcR);
+      if (!mz) continue;
+      // candidate shifts per axis are the set bits of mx, my, mz (one bit
+      // each unless the cell edge is shorter than 2 rc); codes stay ascending
+      for (unsigned bx = mx; bx; bx &= bx - 1u) {
+        const int sx = __builtin_ctz(bx);
+        const double dx = sx == 1 ? x0 : __dadd_rn(x0, sx == 0 ? -Lx : Lx);
+        const double dx2 = __dmul_rn(dx, dx);
+        for (unsigned by = my; by; by &= by - 1u) {
+          const int sy = __builtin_ctz(by);
+          const double dy = sy == 1 ? y0 : __dadd_rn(y0, sy == 0 ? -Ly : Ly);
+          const double dxy = __dadd_rn(dx2, __dmul_rn(dy, dy));
+          for (unsigned bz = mz; bz; bz &= bz - 1u) {
+            const int sz = __builtin_ctz(bz);
+            const int code = 9 * sx + 3 * sy + sz;
+            const double dz = sz == 1 ? z0 : __dadd_rn(z0, sz == 0 ? -Lz : Lz);
+            const double d2 = __dadd_rn(dxy, __dmul_rn(dz, dz));
+            if (d2 < rcR2 && !(j == i && code == 13)) {
+              const uint32_t e = ((uint32_t)j << 5) | (uint32_t)code;
+              if (nR < a.capR) a.idxR[(size_t)nR * a.N + i] = e;
+              ++nR;
+              if (d2 < rcA2) {
+                if (nA < a.capA) a.idxA[(size_t)nA * a.N + i] = e;
+                ++nA;
+              }
             }
           }
         }
       }
     }
+    __syncthreads();
   }
-  a.cntR[i] = nR;
-  a.cntA[i] = nA;
-  if (nR > a.capR || nA > a.capA) fl |= FL_OVERFLOW;
-  if (fl) atomicOr(a.flags, fl);
+  if (live) {
+    a.cntR[i] = nR;
+    a.cntA[i] = nA;
+    if (nR > a.capR || nA > a.capA) fl |= FL_OVERFLOW;
+    if (fl) atomicOr(a.flags, fl);
+  }
 }
 
 // Position of the reverse entry (i, -s) in j's list, by binary search over
@@ -104,20 +141,18 @@ __global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
 __global__ __launch_bounds__(256) void k_reverse(int N, const uint32_t* __restrict__ idx,
                                                  const int* __restrict__ cnt, int cap, int* __restrict__ rev) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const int n = min(cnt[i], cap);
-  for (int k = 0; k < n; ++k) {
-    const uint32_t e = idx[(size_t)k * N + i];
-    const int j = (int)(e >> 5);
-    const uint32_t key = ((uint32_t)i << 5) | (26u - (e & 31u));
-    const int m = min(cnt[j], cap);
-    int lo = 0, hi = m;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (idx[(size_t)mid * N + j] < key) lo = mid + 1; else hi = mid;
-    }
-    rev[(size_t)k * N + i] = (lo < m && idx[(size_t)lo * N + j] == key) ? lo : -1;
+  const int k = blockIdx.y;
+  if (i >= N || k >= min(cnt[i], cap)) return;
+  const uint32_t e = idx[(size_t)k * N + i];
+  const int j = (int)(e >> 5);
+  const uint32_t key = ((uint32_t)i << 5) | (26u - (e & 31u));
+  const int m = min(cnt[j], cap);
+  int lo = 0, hi = m;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (idx[(size_t)mid * N + j] < key) lo = mid + 1; else hi = mid;
   }
+  rev[(size_t)k * N + i] = (lo < m && idx[(size_t)lo * N + j] == key) ? lo : -1;
 }
 
 // ============================================================ species order
@@ -179,7 +214,7 @@ __global__ __launch_bounds__(kOrdBlk) void k_order_scatter(int N, int T, const i
 
 // ================================================================= helpers
 template <int T, int NA, int KA>
-__device__ __forceinline__ float coef_sel(const float* __restrict__ cI, int J, int n, int k) {
+__device__ __forceinline__ float coef_sel(cptr<float> cI, int J, int n, int k) {
   float c = cI[(0 * NA + n) * KA + k];
 #pragma unroll
   for (int t = 1; t < T; ++t) c = (J == t) ? cI[(t * NA + n) * KA + k] : c;
@@ -250,8 +285,8 @@ __global__ __launch_bounds__(256) void k_forward(FwdArgs a) {
   const float xi = a.pos[i], yi = a.pos[N + i], zi = a.pos[2 * N + i];
   const int nR = w.valid ? min(a.nb.cntR[i], a.nb.capR) : 0;
   const int nA = w.valid ? min(a.nb.cntA[i], a.nb.capA) : 0;
-  const float* __restrict__ cRI = a.cR + (size_t)I * T * NR * KR;
-  const float* __restrict__ cAI = a.cA + (size_t)I * T * NA * KA;
+  const cptr<float> cRI = as_const(a.cR) + (size_t)I * T * NR * KR;
+  const cptr<float> cAI = as_const(a.cA) + (size_t)I * T * NA * KA;
 
   // ---- radial descriptors
   float FR[T][KR];
@@ -353,15 +388,15 @@ __global__ __launch_bounds__(256) void k_forward(FwdArgs a) {
 
   // ---- network: E_i and E' (wave-uniform species weights)
   const int H = a.H;
-  const float* __restrict__ W = a.nn + (size_t)I * a.nn_stride;
-  const float* __restrict__ b0 = W + (size_t)H * D;
-  const float* __restrict__ w1 = b0 + H;
+  const cptr<float> W = as_const(a.nn) + (size_t)I * a.nn_stride;
+  const cptr<float> b0 = W + (size_t)H * D;
+  const cptr<float> w1 = b0 + H;
   float Ep[D];
 #pragma unroll
   for (int v = 0; v < D; ++v) Ep[v] = 0.f;
   float E = w1[H];
   for (int mu = 0; mu < H; ++mu) {
-    const float* __restrict__ wr = W + (size_t)mu * D;
+    const cptr<float> wr = W + (size_t)mu * D;
     float z = b0[mu];
 #pragma unroll
     for (int v = 0; v < D; ++v) z = fmaf(wr[v], G[v], z);
@@ -706,8 +741,8 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs a) {
   const float xi = a.pos[i], yi = a.pos[N + i], zi = a.pos[2 * N + i];
   const int nR = w.valid ? min(a.nb.cntR[i], a.nb.capR) : 0;
   const int nA = w.valid ? min(a.nb.cntA[i], a.nb.capA) : 0;
-  const float* __restrict__ cRI = a.cR + (size_t)I * T * NR * KR;
-  const float* __restrict__ cAI = a.cA + (size_t)I * T * NA * KA;
+  const cptr<float> cRI = as_const(a.cR) + (size_t)I * T * NR * KR;
+  const cptr<float> cAI = as_const(a.cA) + (size_t)I * T * NA * KA;
   const float eps = w.valid ? a.eps[s] : 0.f;
   const float* wb = a.wbar + 6 * s;
   const float gxx = wb[0], gyy = wb[1], gzz = wb[2], gxy = wb[3], gyz = wb[4], gzx = wb[5];
@@ -829,13 +864,13 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs a) {
     for (int v = 0; v < D; ++v) a.Gd[(size_t)v * a.Npad + p] = Gd[v];
 
   // ---- network adjoint
-  const float* __restrict__ W = a.nn + (size_t)I * a.nn_stride;
-  const float* __restrict__ w1 = W + (size_t)H * D + H;
+  const cptr<float> W = as_const(a.nn) + (size_t)I * a.nn_stride;
+  const cptr<float> w1 = W + (size_t)H * D + H;
   float Gb[D];
 #pragma unroll
   for (int v = 0; v < D; ++v) Gb[v] = 0.f;
   for (int mu = 0; mu < H; ++mu) {
-    const float* __restrict__ wr = W + (size_t)mu * D;
+    const cptr<float> wr = W + (size_t)mu * D;
     float aa = 0.f;
 #pragma unroll
     for (int v = 0; v < D; ++v) aa = fmaf(wr[v], Gd[v], aa);
@@ -969,7 +1004,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs a) {
 
 // sum over the atoms of species I of beta G^T - (w1 sigma) Gdot^T, tiled
 // 4 x 4 per thread over (hidden unit, descriptor) with atom tiles in LDS.
-constexpr int kW0Atoms = 32;
+constexpr int kW0Atoms = 64;
 
 __global__ __launch_bounds__(256) void k_w0_grad(int Npad, int H, int D, int NB, const int* __restrict__ seg,
                                                  const float* __restrict__ beta, const float* __restrict__ w1s,
@@ -1043,7 +1078,8 @@ __global__ __launch_bounds__(256) void k_w0_grad(int Npad, int H, int D, int NB,
 }
 
 // Final gradient: float64 sums of the per-wavefront and per-block partials in
-// a fixed order.
+// a fixed order.  Blocks [0, T*PW) each reduce one (species, slot) column of
+// the wavefront partials; the remaining blocks sum the W0 block partials.
 struct GradArgs {
   int T, NR, NA, KR, KA, H, D, nwaves, PW, NB;
   const float* part;
@@ -1053,36 +1089,41 @@ struct GradArgs {
 };
 
 __global__ __launch_bounds__(256) void k_grad_final(GradArgs a) {
+  __shared__ double red[256];
   const int P_R = a.T * a.T * a.NR * a.KR, P_A = a.T * a.T * a.NA * a.KA;
   const int blk = a.H * a.D + 2 * a.H + 1;
-  const int P = P_R + P_A + a.T * blk;
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= P) return;
-  const int PSR = a.T * a.NR * a.KR;
-  int I, slot = -1;
-  if (q < P_R) {
-    I = q / PSR;
-    slot = q % PSR;
-  } else if (q < P_R + P_A) {
-    const int r = q - P_R, PSA = a.T * a.NA * a.KA;
-    I = r / PSA;
-    slot = PSR + r % PSA;
-  } else {
-    const int r = q - P_R - P_A;
-    I = r / blk;
-    const int o = r % blk;
-    if (o < a.H * a.D) {
-      double s = 0.0;
-      for (int b = 0; b < a.NB; ++b) s += a.w0part[((size_t)I * a.NB + b) * a.H * a.D + o];
-      a.grad[q] = (float)s;
-      return;
+  const int PSR = a.T * a.NR * a.KR, PSA = a.T * a.NA * a.KA;
+  const int ncol = a.T * a.PW;
+  if ((int)blockIdx.x < ncol) {
+    const int I = blockIdx.x / a.PW, slot = blockIdx.x % a.PW;
+    double s = 0.0;
+    for (int w = threadIdx.x; w < a.nwaves; w += blockDim.x)
+      if (a.wspecies[w] == I) s += a.part[(size_t)w * a.PW + slot];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+      __syncthreads();
     }
-    slot = PSR + a.T * a.NA * a.KA + (o - a.H * a.D);
+    if (threadIdx.x != 0) return;
+    int q;
+    if (slot < PSR) {
+      q = I * PSR + slot;                          // c^R[I][J][n][k]
+    } else if (slot < PSR + PSA) {
+      q = P_R + I * PSA + (slot - PSR);            // c^A[I][J][n][k]
+    } else {
+      const int o = slot - PSR - PSA;              // b0, w1, b1
+      q = P_R + P_A + I * blk + a.H * a.D + o;
+    }
+    a.grad[q] = (float)red[0];
+    return;
   }
+  const int q = (blockIdx.x - ncol) * blockDim.x + threadIdx.x;
+  if (q >= a.T * a.H * a.D) return;
+  const int I = q / (a.H * a.D), o = q % (a.H * a.D);
   double s = 0.0;
-  for (int wv = 0; wv < a.nwaves; ++wv)
-    if (a.wspecies[wv] == I) s += a.part[(size_t)wv * a.PW + slot];
-  a.grad[q] = (float)s;
+  for (int b = 0; b < a.NB; ++b) s += a.w0part[((size_t)I * a.NB + b) * a.H * a.D + o];
+  a.grad[P_R + P_A + I * blk + o] = (float)s;
 }
 
 // ==================================================================== Adam
@@ -1208,7 +1249,7 @@ int64_t param_count(const nep_model* m) {
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
-constexpr int kW0Blocks = 64;
+constexpr int kW0Blocks = 256;
 
 struct Layout {
   int N, S, T, D, Y, H, Npad, nwaves, nblk, PW, NA, capR, capA;
@@ -1365,13 +1406,13 @@ void run_neighbors(const Ctx& c, nep_neighbors* nb, int32_t* flags, Prof* pr) {
   a.cntA = nb->cnt_ang;
   a.astruct = at<int>(c.ws, c.L.astruct);
   a.flags = flags;
-  NEP_LAUNCH(pr, "neighbors", hipLaunchKernelGGL(k_neighbors, dim3(grid1(N)), dim3(256), 0, c.st, a));
+  NEP_LAUNCH(pr, "neighbors", hipLaunchKernelGGL(k_neighbors, dim3(grid1(N, kNbrBlk)), dim3(kNbrBlk), 0, c.st, a));
   NEP_LAUNCH(pr, "reverse_rad",
-             hipLaunchKernelGGL(k_reverse, dim3(grid1(N)), dim3(256), 0, c.st, N, nb->idx_rad, nb->cnt_rad,
-                                c.m->cap_rad, at<int>(c.ws, c.L.revR)));
+             hipLaunchKernelGGL(k_reverse, dim3(grid1(N), c.m->cap_rad), dim3(256), 0, c.st, N, nb->idx_rad,
+                                nb->cnt_rad, c.m->cap_rad, at<int>(c.ws, c.L.revR)));
   NEP_LAUNCH(pr, "reverse_ang",
-             hipLaunchKernelGGL(k_reverse, dim3(grid1(N)), dim3(256), 0, c.st, N, nb->idx_ang, nb->cnt_ang,
-                                c.m->cap_ang, at<int>(c.ws, c.L.revA)));
+             hipLaunchKernelGGL(k_reverse, dim3(grid1(N), c.m->cap_ang), dim3(256), 0, c.st, N, nb->idx_ang,
+                                nb->cnt_ang, c.m->cap_ang, at<int>(c.ws, c.L.revA)));
   int* order = at<int>(c.ws, c.L.order);
   int* blk = at<int>(c.ws, c.L.blk);
   int* seg = at<int>(c.ws, c.L.seg);
@@ -1520,8 +1561,8 @@ void run_adjoint(const Ctx& c, const nep_neighbors* nb, const float* params, con
     g.wspecies = a.wave_species;
     g.w0part = at<float>(c.ws, c.L.w0part);
     g.grad = grad;
-    NEP_LAUNCH(pr, "grad_final",
-               hipLaunchKernelGGL(k_grad_final, dim3(grid1((int)param_count(m))), dim3(256), 0, c.st, g));
+    const int nblk_gf = T * c.L.PW + grid1(T * m->hidden * c.o->D);
+    NEP_LAUNCH(pr, "grad_final", hipLaunchKernelGGL(k_grad_final, dim3(nblk_gf), dim3(256), 0, c.st, g));
   } else {
     const int64_t P = param_count(m);
     hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, c.st, grad, P, 0.f);
