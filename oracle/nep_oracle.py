@@ -260,7 +260,7 @@ class NEPOracle:
     def predict(self, theta_np, structures, nbr_cache=None):
         """E(n), F (per structure [n,3]), W(n) in (xx,yy,zz,xy,yz,zx), per-atom
         energies and descriptors, all float64 numpy."""
-        theta = torch.tensor(np.asarray(theta_np, np.float32).astype(np.float64), dtype=DT)
+        theta = torch.tensor(np.asarray(theta_np).astype(np.float64), dtype=DT)
         out = dict(E=[], F=[], W=[], Ei=[], G=[])
         for k, st in enumerate(structures):
             nb = nbr_cache[k] if nbr_cache is not None else None
@@ -282,7 +282,7 @@ class NEPOracle:
             Lv = 1/(6 N_str) sum_n sum_c ((W_c(n) - W_tar_c(n)) / N_n)^2 (Eq. 12)
         and its exact gradient.  labels: 'energy' [S] totals, 'force' list of
         [n,3] (or [N,3]), 'virial' [S,6] totals."""
-        theta = torch.tensor(np.asarray(theta_np, np.float32).astype(np.float64), dtype=DT,
+        theta = torch.tensor(np.asarray(theta_np).astype(np.float64), dtype=DT,
                              requires_grad=need_grad)
         S = len(structures)
         N = sum(st.n for st in structures)
@@ -318,7 +318,7 @@ class NEPOracle:
         """Gradient of sum_n e_bar[n] E(n) + sum_i f_bar_i . F_i + sum_n v_bar[n] . W(n)
         with respect to the parameters (a vector-Jacobian product written as the
         derivative of that contraction).  f_bar: list of [n,3] or [N,3]."""
-        theta = torch.tensor(np.asarray(theta_np, np.float32).astype(np.float64), dtype=DT, requires_grad=True)
+        theta = torch.tensor(np.asarray(theta_np).astype(np.float64), dtype=DT, requires_grad=True)
         S = len(structures)
         e_bar = np.asarray(e_bar, np.float64)
         v_bar = np.asarray(v_bar, np.float64).reshape(S, 6)

@@ -240,6 +240,39 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
+// ----------------------------------------- groups of 8 lanes (one atom)
+// Lane l of a wavefront works on atom l/8; DPP moves data inside the group
+// without touching LDS.  DPP reads return 0 from inactive lanes, so these
+// helpers are only called where every lane of the wavefront is active.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+constexpr int kDppXor1 = 0xB1;       // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;       // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppRowRor8 = 0x128;   // within 16-lane rows: lane l takes lane l^8
+
+// sum over the 4 lanes of a quad
+__device__ __forceinline__ float quad_sum(float v) {
+  v += dpp<kDppXor1>(v);
+  v += dpp<kDppXor2>(v);
+  return v;
+}
+// sum over the 8 lanes of an atom group
+__device__ __forceinline__ float grp8_sum(float v) {
+  v = quad_sum(v);
+  v += dpp<kDppHalfMirror>(v);
+  return v;
+}
+// sum over the 8 lanes of the wavefront with the same (l & 7)
+__device__ __forceinline__ float atoms8_sum(float v) {
+  v += dpp<kDppRowRor8>(v);
+  v += __shfl_xor(v, 16, kWave);
+  v += __shfl_xor(v, 32, kWave);
+  return v;
+}
+
 // Image shift of a neighbor code: code = 9(sx+1) + 3(sy+1) + (sz+1).
 __device__ __forceinline__ void decode_shift(uint32_t code, float& sx, float& sy, float& sz) {
   const int c = (int)code;

@@ -6,9 +6,9 @@
 //   pass, network adjoint, parameter partials) -> W0 reduction -> final gradient
 //   reduction -> Adam.
 // Per-atom kernels run in "species order": atoms grouped by species, each
-// group padded to a multiple of 64, so every wavefront evaluates one species'
-// network with wave-uniform weights.  Padding lanes act as atoms without
-// neighbors and write nothing.
+// group padded to a multiple of 8 atoms, and 8 lanes per atom, so every
+// wavefront evaluates one species' network.  Padding atoms have no neighbors
+// and write nothing.
 #pragma once
 #include "nep_device.h"
 
@@ -88,7 +88,9 @@ struct AdjArgs {
   const float* fbar;  // [3][N] dL/dF
   const float* wbar;  // [S][6] dL/dW(n)
   float* Gd;          // [D][Npad]
-  float* Sd;          // [NA*Y][Npad]
+  float* FRst;        // [T*KR][Npad] radial sums F[J][k]
+  float* FPst;        // [T*KR][Npad] tangent sums Fp[J][k]
+  float* Gbr;         // [NR][Npad] Gbar of the radial descriptors
   float* beta;        // [H][Npad]
   float* w1s;         // [H][Npad]
   float* part;        // [n_waves][PW] wave partial sums

@@ -77,6 +77,9 @@ __global__ __launch_bounds__(kNbrBlk) void k_neighbors(NbrArgs a) {
   const double rcR = (double)a.rcR, rcA = (double)a.rcA;
   const double rcR2 = rcR * rcR, rcA2 = rcA * rcA;  // exact: float squared in double
   const double Lx = Lxf, Ly = Lyf, Lz = Lzf;
+  const float xif = (float)xi, yif = (float)yi, zif = (float)zi;
+  const float invLx = ok ? 1.0f / Lxf : 0.f, invLy = ok ? 1.0f / Lyf : 0.f, invLz = ok ? 1.0f / Lzf : 0.f;
+  const float rpad2 = (a.rcR + 0.01f) * (a.rcR + 0.01f);
   int nR = 0, nA = 0;
   for (int t0 = j_lo; t0 < j_hi; t0 += kNbrBlk) {
     const int jt = t0 + threadIdx.x;
@@ -89,6 +92,15 @@ __global__ __launch_bounds__(kNbrBlk) void k_neighbors(NbrArgs a) {
     const int jb = ok ? max(a0, t0) : 0, je = ok ? min(a1, t0 + kNbrBlk) : 0;
     for (int j = jb; j < je; ++j) {
       const int q = j - t0;
+      // single-precision minimum-image distance with a 0.01 A margin: rounding
+      // here is below 1e-4 A, so rejected j are certainly outside rc
+      {
+        float ex = tx[q] - xif, ey = ty[q] - yif, ez = tz[q] - zif;
+        ex -= Lxf * rintf(ex * invLx);
+        ey -= Lyf * rintf(ey * invLy);
+        ez -= Lzf * rintf(ez * invLz);
+        if (ex * ex + ey * ey + ez * ez >= rpad2) continue;
+      }
       const double x0 = __dadd_rn((double)tx[q], -xi);
       const unsigned mx = axis_candidates(x0, Lx, rcR);
       if (!mx) continue;
@@ -157,6 +169,7 @@ __global__ __launch_bounds__(256) void k_reverse(int N, const uint32_t* __restri
 
 // ============================================================ species order
 constexpr int kOrdBlk = 1024;
+constexpr int kSegAlign = 8;   // species segments start on multiples of the atoms per wavefront
 
 __global__ __launch_bounds__(kOrdBlk) void k_order_count(int N, int Npad, int T, const int* __restrict__ type,
                                                          int* __restrict__ blkcnt, int* __restrict__ order) {
@@ -174,7 +187,7 @@ __global__ __launch_bounds__(kOrdBlk) void k_order_count(int N, int Npad, int T,
 }
 
 // Exclusive scan of the per-block counts; species segments start on
-// multiples of 64 so that no wavefront mixes species.  seg[2t], seg[2t+1] =
+// multiples of 8 atoms so that no wavefront mixes species.  seg[2t], seg[2t+1] =
 // start and count of species t.
 __global__ void k_order_scan(int nblk, int T, int* __restrict__ blk, int* __restrict__ seg) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -188,7 +201,7 @@ __global__ void k_order_scan(int nblk, int T, int* __restrict__ blk, int* __rest
     }
     seg[2 * t] = start;
     seg[2 * t + 1] = run - start;
-    start += ((run - start) + kWave - 1) / kWave * kWave;
+    start += ((run - start) + kSegAlign - 1) / kSegAlign * kSegAlign;
   }
 }
 
@@ -266,39 +279,144 @@ __device__ __forceinline__ WaveCtx wave_ctx(const int* __restrict__ order, const
   return c;
 }
 
+// ========================================================= atom groups
+// Per-atom kernels run 8 lanes per atom, 8 atoms per wavefront and 32 atoms
+// per block.  Lane s = l & 7 of an atom's group splits the radial pairs
+// (pairs k = s, s+8, ...); for the angular sums the group is 2 harmonic
+// groups x 4 pair slots: g = s >> 2 picks the harmonics (l = 1 and 4, or
+// l = 2 and 3; 12 each for l <= 4) and p = s & 3 the pairs k = p, p+4, ....
+// The hidden layer is split over hidden units mu = s, s+8, ....
+// Atoms are in species order with species segments aligned to 8, so every
+// wavefront evaluates a single species' network.
+constexpr int kLPA = 8;                    // lanes per atom
+constexpr int kAPB = 256 / kLPA;           // atoms per block
+constexpr int kAPW = kWave / kLPA;         // atoms per wavefront
+static_assert(kAPW == kSegAlign, "species segments must align to wavefronts");
+
+template <int LM>
+struct HSplit {
+  static constexpr int nA0 = LM >= 1 ? 3 : 0;   // group 0: l = 1 ...
+  static constexpr int nB0 = LM >= 4 ? 9 : 0;   // ... and l = 4
+  static constexpr int nA1 = LM >= 2 ? 5 : 0;   // group 1: l = 2 ...
+  static constexpr int nB1 = LM >= 3 ? 7 : 0;   // ... and l = 3
+  static constexpr int YG = (nA0 + nB0 > nA1 + nB1) ? nA0 + nB0 : nA1 + nB1;
+  // harmonic index of compact entry i of group g, -1 for padding
+  static constexpr int q(int g, int i) {
+    return g == 0 ? (i < nA0 ? i : (i - nA0 < nB0 ? 15 + (i - nA0) : -1))
+                  : (i < nA1 ? 3 + i : (i - nA1 < nB1 ? 8 + (i - nA1) : -1));
+  }
+};
+
+// B_q of compact entry i for this lane's harmonic group
+template <class HS, int Y>
+__device__ __forceinline__ float hsel(int g, int i, const float (&B)[Y]) {
+  const int q0 = HS::q(0, i), q1 = HS::q(1, i);
+  const float b0 = q0 >= 0 ? B[q0] : 0.f;
+  const float b1 = q1 >= 0 ? B[q1] : 0.f;
+  return g ? b1 : b0;
+}
+template <class HS>
+__device__ __forceinline__ float csel(int g, int i) {
+  const int q0 = HS::q(0, i), q1 = HS::q(1, i);
+  return g ? (q1 >= 0 ? clm(q1) : 0.f) : (q0 >= 0 ? clm(q0) : 0.f);
+}
+
+// E' of q_nl for the two l blocks of harmonic group g (l = 1, 4 or l = 2, 3)
+template <int NR, int NA, int L3, int D>
+__device__ __forceinline__ void ep_blocks(const float (&Ep)[D], int n, int g, float& eA, float& eB) {
+  float e1 = 0.f, e2 = 0.f, e3 = 0.f, e4 = 0.f;
+  if constexpr (L3 >= 1) e1 = Ep[NR + n];
+  if constexpr (L3 >= 2) e2 = Ep[NR + NA + n];
+  if constexpr (L3 >= 3) e3 = Ep[NR + 2 * NA + n];
+  if constexpr (L3 >= 4) e4 = Ep[NR + 3 * NA + n];
+  eA = g ? e2 : e1;
+  eB = g ? e3 : e4;
+}
+
+struct GroupCtx {
+  int s, g, p, al, pa, i, I;
+  bool valid;
+};
+
+// lane roles and the atom of this lane; every lane of the block stays alive
+__device__ __forceinline__ GroupCtx group_ctx(const int* __restrict__ order, const int* __restrict__ type, int Npad) {
+  GroupCtx c;
+  c.s = threadIdx.x & (kLPA - 1);
+  c.g = c.s >> 2;
+  c.p = c.s & 3;
+  c.al = threadIdx.x / kLPA;
+  c.pa = blockIdx.x * kAPB + c.al;
+  const int iraw = c.pa < Npad ? order[c.pa] : -1;
+  c.valid = iraw >= 0;
+  const unsigned long long vm = __ballot(c.valid);
+  const int lead = vm ? __ffsll(vm) - 1 : 0;
+  const int ilead = vm ? __shfl(iraw, lead, kWave) : 0;
+  c.i = c.valid ? iraw : ilead;
+  c.I = __builtin_amdgcn_readfirstlane(vm ? type[ilead] : 0);
+  return c;
+}
+
+// stage every species' W0 (rows padded to DP floats), b0 and w1 into LDS
+__device__ __forceinline__ void stage_weights(float* wl, const float* __restrict__ nn, int nn_stride, int T, int H,
+                                              int D, int DP) {
+  const int WS = H * DP + 2 * H;
+  for (int q = threadIdx.x; q < T * WS; q += blockDim.x) {
+    const int I = q / WS, o = q % WS;
+    float v = 0.f;
+    if (o < H * DP) {
+      const int mu = o / DP, d = o % DP;
+      if (d < D) v = nn[(size_t)I * nn_stride + mu * D + d];
+    } else {
+      v = nn[(size_t)I * nn_stride + H * D + (o - H * DP)];
+    }
+    wl[q] = v;
+  }
+}
+
 // ================================================================= forward
-// Per atom (species order): radial sums F[J][k] = sum_{j of type J} f_k(r_ij)
-// give q_n = sum_{J,k} c^R_{IJnk} F[J][k] (Eqs. 5-6); angular sums S_nlm
-// (Eq. 8) give q_nl (Eq. 7) and the 4-/5-body invariants; the per-species
-// network gives E_i and E' = dE_i/dG (D1.1-D1.5).  With forces on, the partial
-// force f_ij = dE_i/dr_ij of every listed pair is stored (C3.6) together with
-// this atom's share -sum_j f_ij (x) r_ij of the virial.
+// Per atom: radial sums F[J][k] = sum_{j of type J} f_k(r_ij) give
+// q_n = sum_{J,k} c^R_{IJnk} F[J][k] (Eqs. 5-6); angular sums S_nlm (Eq. 8)
+// give q_nl (Eq. 7) and the 4-/5-body invariants; the per-species network
+// gives E_i and E' = dE_i/dG (D1.1-D1.5).  With forces on, every listed
+// pair's partial force f_ij = dE_i/dr_ij is stored (C3.6) with this atom's
+// share -sum_j f_ij (x) r_ij of the virial.
 template <class C>
-__global__ __launch_bounds__(256) void k_forward(FwdArgs a) {
+__global__ __launch_bounds__(256, 2) void k_forward(FwdArgs a) {
   constexpr int T = C::T, NR = C::NR, NA = C::NA, KR = C::KR, KA = C::KA, Y = C::Y, D = C::D, LM = C::LMAX;
   constexpr int L3 = C::L3, L4 = C::L4, L5 = C::L5;
-  const WaveCtx w = wave_ctx(a.order, a.type, a.Npad);
-  if (!w.any) return;
-  const int N = a.N, i = w.i, I = w.I, p = w.p;
-  const int s = a.astruct[i];
-  const float Lx = a.box[3 * s], Ly = a.box[3 * s + 1], Lz = a.box[3 * s + 2];
+  using HS = HSplit<LM>;
+  constexpr int YG = HS::YG;
+  constexpr int DP = (D + 3) & ~3;
+  extern __shared__ float lds[];
+  const int H = a.H;
+  const int WS = H * DP + 2 * H;
+  constexpr int RW = DP + NA * Y;         // LDS row per atom: G, S
+  float* wl = lds;                       // [T][WS]
+  float* rows = lds + T * WS;            // [kAPB][RW]
+  if (a.do_mlp) stage_weights(wl, a.nn, a.nn_stride, T, H, D, DP);
+  const GroupCtx w = group_ctx(a.order, a.type, a.Npad);
+  const int N = a.N, i = w.i, I = w.I, pa = w.pa, s = w.s, g = w.g;
+  float* row = rows + w.al * RW;
+  float* rowS = row + DP;
+  const int st = a.astruct[i];
+  const float Lx = a.box[3 * st], Ly = a.box[3 * st + 1], Lz = a.box[3 * st + 2];
   const float xi = a.pos[i], yi = a.pos[N + i], zi = a.pos[2 * N + i];
   const int nR = w.valid ? min(a.nb.cntR[i], a.nb.capR) : 0;
   const int nA = w.valid ? min(a.nb.cntA[i], a.nb.capA) : 0;
   const cptr<float> cRI = as_const(a.cR) + (size_t)I * T * NR * KR;
   const cptr<float> cAI = as_const(a.cA) + (size_t)I * T * NA * KA;
 
-  // ---- radial descriptors
+  // ---- radial sums, pairs split over the 8 lanes
   float FR[T][KR];
 #pragma unroll
   for (int t = 0; t < T; ++t)
 #pragma unroll
     for (int k = 0; k < KR; ++k) FR[t][k] = 0.f;
-  for (int k = 0; k < nR; ++k) {
-    const PairGeom g = pair_geom(a.nb.idxR[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+  for (int k = s; k < nR; k += kLPA) {
+    const PairGeom q = pair_geom(a.nb.idxR[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
     float f[KR];
-    radial_basis<KR>(g.r, a.inv_rcR, f);
-    const int J = a.type[g.j];
+    radial_basis<KR>(q.r, a.inv_rcR, f);
+    const int J = a.type[q.j];
 #pragma unroll
     for (int t = 0; t < T; ++t) {
       const float m = (T == 1 || J == t) ? 1.f : 0.f;
@@ -306,28 +424,32 @@ __global__ __launch_bounds__(256) void k_forward(FwdArgs a) {
       for (int kk = 0; kk < KR; ++kk) FR[t][kk] = fmaf(m, f[kk], FR[t][kk]);
     }
   }
-  float G[D];
 #pragma unroll
-  for (int n = 0; n < NR; ++n) {
-    float acc = 0.f;
+  for (int t = 0; t < T; ++t)
 #pragma unroll
-    for (int t = 0; t < T; ++t)
+    for (int k = 0; k < KR; ++k) FR[t][k] = grp8_sum(FR[t][k]);
 #pragma unroll
-      for (int k = 0; k < KR; ++k) acc = fmaf(cRI[(t * NR + n) * KR + k], FR[t][k], acc);
-    G[n] = acc;
-  }
+  for (int n = 0; n < NR; ++n)
+    if (s == (n & 7)) {
+      float acc = 0.f;
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int k = 0; k < KR; ++k) acc = fmaf(cRI[(t * NR + n) * KR + k], FR[t][k], acc);
+      row[n] = acc;
+    }
 
-  // ---- angular sums S_nlm
-  float S[NA][Y];
+  // ---- angular sums S_nlm: harmonic group g, pairs p, p+4, ...
+  float Sg[NA][YG];
 #pragma unroll
   for (int n = 0; n < NA; ++n)
 #pragma unroll
-    for (int q = 0; q < Y; ++q) S[n][q] = 0.f;
-  for (int k = 0; k < nA; ++k) {
-    const PairGeom g = pair_geom(a.nb.idxA[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+    for (int e = 0; e < YG; ++e) Sg[n][e] = 0.f;
+  for (int k = w.p; k < nA; k += 4) {
+    const PairGeom q = pair_geom(a.nb.idxA[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
     float f[KA];
-    radial_basis<KA>(g.r, a.inv_rcA, f);
-    const int J = a.type[g.j];
+    radial_basis<KA>(q.r, a.inv_rcA, f);
+    const int J = a.type[q.j];
     float gn[NA];
 #pragma unroll
     for (int n = 0; n < NA; ++n) {
@@ -337,87 +459,113 @@ __global__ __launch_bounds__(256) void k_forward(FwdArgs a) {
       gn[n] = acc;
     }
     float B[Y];
-    harm_val<LM>(g.dx * g.inv_r, g.dy * g.inv_r, g.dz * g.inv_r, B);
+    harm_val<LM>(q.dx * q.inv_r, q.dy * q.inv_r, q.dz * q.inv_r, B);
+#pragma unroll
+    for (int e = 0; e < YG; ++e) {
+      const float b = hsel<HS, Y>(g, e, B);
+#pragma unroll
+      for (int n = 0; n < NA; ++n) Sg[n][e] = fmaf(gn[n], b, Sg[n][e]);
+    }
+  }
+#pragma unroll
+  for (int n = 0; n < NA; ++n)
+#pragma unroll
+    for (int e = 0; e < YG; ++e) Sg[n][e] = quad_sum(Sg[n][e]);
+
+  // ---- angular descriptors of this lane's harmonic group
+  {
+    const int nAg = g ? HS::nA1 : HS::nA0;     // size of the first l block
+    const int lA = g ? 2 : 1, lB = g ? 3 : 4;
+#pragma unroll
+    for (int n = 0; n < NA; ++n) {
+      float qa = 0.f, qb = 0.f;
+#pragma unroll
+      for (int e = 0; e < YG; ++e) {
+        const float v = csel<HS>(g, e) * Sg[n][e] * Sg[n][e];
+        if (e < nAg) qa += v; else qb += v;
+      }
+      if (w.p == 0) {
+        if (lA <= L3) row[NR + (lA - 1) * NA + n] = qa;
+        if (lB <= L3) row[NR + (lB - 1) * NA + n] = qb;
+      }
+    }
+    if constexpr (L4 != 0) {
+#pragma unroll
+      for (int n = 0; n < NA; ++n) {
+        const Sym3 M = sym_of(Sg[n][0], Sg[n][1], Sg[n][2], Sg[n][3], Sg[n][4]);
+        const float q4 = sym_dot(sym_mul(M, M), M);
+        if (g == 1 && w.p == 0) row[NR + L3 * NA + n] = q4;
+      }
+    }
+    if constexpr (L5 != 0) {
+#pragma unroll
+      for (int n = 0; n < NA; ++n) {
+        const float P = Sg[n][0] * Sg[n][0] + Sg[n][1] * Sg[n][1] + Sg[n][2] * Sg[n][2];
+        if (g == 0 && w.p == 0) row[NR + L3 * NA + (L4 ? NA : 0) + n] = P * P;
+      }
+    }
+  }
+  if (w.p == 0) {
 #pragma unroll
     for (int n = 0; n < NA; ++n)
 #pragma unroll
-      for (int q = 0; q < Y; ++q) S[n][q] = fmaf(gn[n], B[q], S[n][q]);
-  }
-
-  // ---- angular descriptors
-#pragma unroll
-  for (int l = 1; l <= L3; ++l)
-#pragma unroll
-    for (int n = 0; n < NA; ++n) {
-      float acc = 0.f;
-#pragma unroll
-      for (int m = 0; m < 2 * l + 1; ++m) {
-        const int q = (l - 1) * (l + 1) + m;
-        acc = fmaf(clm(q) * S[n][q], S[n][q], acc);
+      for (int e = 0; e < YG; ++e) {
+        const int q = g ? HS::q(1, e) : HS::q(0, e);
+        if (q >= 0) {
+          rowS[n * Y + q] = Sg[n][e];
+          if (w.valid && a.Sst) a.Sst[(size_t)(n * Y + q) * a.Npad + pa] = Sg[n][e];
+        }
       }
-      G[NR + (l - 1) * NA + n] = acc;
-    }
-  if constexpr (L4 != 0) {
-#pragma unroll
-    for (int n = 0; n < NA; ++n) {
-      const Sym3 M = sym_of(S[n][3], S[n][4], S[n][5], S[n][6], S[n][7]);
-      G[NR + L3 * NA + n] = sym_dot(sym_mul(M, M), M);
-    }
   }
-  if constexpr (L5 != 0) {
+  __syncthreads();
+  float G[D];
 #pragma unroll
-    for (int n = 0; n < NA; ++n) {
-      const float P = S[n][0] * S[n][0] + S[n][1] * S[n][1] + S[n][2] * S[n][2];
-      G[NR + L3 * NA + (L4 ? NA : 0) + n] = P * P;
-    }
-  }
+  for (int v = 0; v < D; ++v) G[v] = row[v];
   if (w.valid) {
-    if (a.G)
 #pragma unroll
-      for (int v = 0; v < D; ++v) a.G[(size_t)v * a.Npad + p] = G[v];
-    if (a.Guser)
-#pragma unroll
-      for (int v = 0; v < D; ++v) a.Guser[(size_t)v * N + i] = G[v];
-    if (a.Sst)
-#pragma unroll
-      for (int n = 0; n < NA; ++n)
-#pragma unroll
-        for (int q = 0; q < Y; ++q) a.Sst[(size_t)(n * Y + q) * a.Npad + p] = S[n][q];
+    for (int v = 0; v < D; ++v)
+      if (s == (v & 7)) {
+        if (a.G) a.G[(size_t)v * a.Npad + pa] = G[v];
+        if (a.Guser) a.Guser[(size_t)v * N + i] = G[v];
+      }
   }
   if (!a.do_mlp) return;
 
-  // ---- network: E_i and E' (wave-uniform species weights)
-  const int H = a.H;
-  const cptr<float> W = as_const(a.nn) + (size_t)I * a.nn_stride;
-  const cptr<float> b0 = W + (size_t)H * D;
-  const cptr<float> w1 = b0 + H;
+  // ---- network: hidden units mu = s, s+8, ... (weights from LDS)
+  const float* Wl = wl + I * WS;
   float Ep[D];
 #pragma unroll
   for (int v = 0; v < D; ++v) Ep[v] = 0.f;
-  float E = w1[H];
-  for (int mu = 0; mu < H; ++mu) {
-    const cptr<float> wr = W + (size_t)mu * D;
-    float z = b0[mu];
+  float E = 0.f;
+  for (int mu = s; mu < H; mu += kLPA) {
+    const float* wr = Wl + mu * DP;
+    float z = Wl[H * DP + mu];
 #pragma unroll
     for (int v = 0; v < D; ++v) z = fmaf(wr[v], G[v], z);
     const float x = tanhf(z);
-    E = fmaf(w1[mu], x, E);
-    const float sg = w1[mu] * (1.0f - x * x);
+    const float w1 = Wl[H * DP + H + mu];
+    E = fmaf(w1, x, E);
+    const float sg = w1 * (1.0f - x * x);
 #pragma unroll
     for (int v = 0; v < D; ++v) Ep[v] = fmaf(sg, wr[v], Ep[v]);
-    if (w.valid && a.X) a.X[(size_t)mu * a.Npad + p] = x;
+    if (w.valid && a.X) a.X[(size_t)mu * a.Npad + pa] = x;
   }
+#pragma unroll
+  for (int v = 0; v < D; ++v) Ep[v] = grp8_sum(Ep[v]);
+  E = grp8_sum(E) + a.nn[(size_t)I * a.nn_stride + H * D + 2 * H];
   if (w.valid) {
     if (a.Ep)
 #pragma unroll
-      for (int v = 0; v < D; ++v) a.Ep[(size_t)v * a.Npad + p] = Ep[v];
-    if (a.eatom) a.eatom[i] = E;
-    if (a.eatom2) a.eatom2[i] = E;
+      for (int v = 0; v < D; ++v)
+        if (s == (v & 7)) a.Ep[(size_t)v * a.Npad + pa] = Ep[v];
+    if (s == 0) {
+      if (a.eatom) a.eatom[i] = E;
+      if (a.eatom2) a.eatom2[i] = E;
+    }
   }
   if (!a.do_force) return;
 
-  // ---- radial partial forces: f_ij = (sum_k h_Jk f'_k(r)) r_hat,
-  //      h_Jk = sum_n E'_n c^R_{IJnk}
+  // ---- radial partial forces: f_ij = (sum_k h_Jk f'_k(r)) r_hat, h_Jk = sum_n E'_n c^R_{IJnk}
   float hR[T][KR];
 #pragma unroll
   for (int t = 0; t < T; ++t)
@@ -430,11 +578,11 @@ __global__ __launch_bounds__(256) void k_forward(FwdArgs a) {
     }
   float vxx = 0.f, vyy = 0.f, vzz = 0.f, vxy = 0.f, vyz = 0.f, vzx = 0.f;
   const size_t capN_R = (size_t)a.nb.capR * N, capN_A = (size_t)a.nb.capA * N;
-  for (int k = 0; k < nR; ++k) {
-    const PairGeom g = pair_geom(a.nb.idxR[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+  for (int k = s; k < nR; k += kLPA) {
+    const PairGeom q = pair_geom(a.nb.idxR[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
     float f[KR], fp[KR];
-    radial_basis_d<KR>(g.r, a.inv_rcR, f, fp);
-    const int J = a.type[g.j];
+    radial_basis_d<KR>(q.r, a.inv_rcR, f, fp);
+    const int J = a.type[q.j];
     float sc = 0.f;
 #pragma unroll
     for (int kk = 0; kk < KR; ++kk) {
@@ -443,51 +591,62 @@ __global__ __launch_bounds__(256) void k_forward(FwdArgs a) {
       for (int t = 1; t < T; ++t) h = (J == t) ? hR[t][kk] : h;
       sc = fmaf(h, fp[kk], sc);
     }
-    sc *= g.inv_r;
-    const float fx = sc * g.dx, fy = sc * g.dy, fz = sc * g.dz;
+    sc *= q.inv_r;
+    const float fx = sc * q.dx, fy = sc * q.dy, fz = sc * q.dz;
     a.fR[(size_t)k * N + i] = fx;
     a.fR[capN_R + (size_t)k * N + i] = fy;
     a.fR[2 * capN_R + (size_t)k * N + i] = fz;
-    vxx -= fx * g.dx; vyy -= fy * g.dy; vzz -= fz * g.dz;
-    vxy -= fx * g.dy; vyz -= fy * g.dz; vzx -= fz * g.dx;
+    vxx -= fx * q.dx; vyy -= fy * q.dy; vzz -= fz * q.dz;
+    vxy -= fx * q.dy; vyz -= fy * q.dz; vzx -= fz * q.dx;
   }
 
-  // ---- A_nlm = sum_v E'_v dG_v/dS_nlm (overwrites S)
+  // ---- A_nlm = sum_v E'_v dG_v/dS_nlm for this lane's harmonics
+  float Ag[NA][YG];
+  {
+    const int nAg = g ? HS::nA1 : HS::nA0;
 #pragma unroll
-  for (int n = 0; n < NA; ++n) {
-    float a4[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, a5[3] = {0.f, 0.f, 0.f};
-    if constexpr (L4 != 0) {
-      const Sym3 M = sym_of(S[n][3], S[n][4], S[n][5], S[n][6], S[n][7]);
-      float o[5];
-      sym_proj(sym_mul(M, M), o);
-      const float e4 = 3.0f * Ep[NR + L3 * NA + n];
+    for (int n = 0; n < NA; ++n) {
+      float Sn[YG];
 #pragma unroll
-      for (int m = 0; m < 5; ++m) a4[m] = e4 * o[m];
-    }
-    if constexpr (L5 != 0) {
-      const float P = S[n][0] * S[n][0] + S[n][1] * S[n][1] + S[n][2] * S[n][2];
-      const float e5 = 4.0f * Ep[NR + L3 * NA + (L4 ? NA : 0) + n] * P;
+      for (int e = 0; e < YG; ++e) {
+        const int q = g ? HS::q(1, e) : HS::q(0, e);
+        Sn[e] = q >= 0 ? rowS[n * Y + q] : 0.f;
+      }
+      float eA, eBv;
+      ep_blocks<NR, NA, L3, D>(Ep, n, g, eA, eBv);
+      float a4[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, a5[3] = {0.f, 0.f, 0.f};
+      if constexpr (L4 != 0) {
+        const Sym3 M = sym_of(Sn[0], Sn[1], Sn[2], Sn[3], Sn[4]);
+        float o[5];
+        sym_proj(sym_mul(M, M), o);
+        const float e4 = g == 1 ? 3.0f * Ep[NR + L3 * NA + n] : 0.f;
 #pragma unroll
-      for (int m = 0; m < 3; ++m) a5[m] = e5 * S[n][m];
-    }
+        for (int m = 0; m < 5; ++m) a4[m] = e4 * o[m];
+      }
+      if constexpr (L5 != 0) {
+        const float P = Sn[0] * Sn[0] + Sn[1] * Sn[1] + Sn[2] * Sn[2];
+        const float e5 = g == 0 ? 4.0f * Ep[NR + L3 * NA + (L4 ? NA : 0) + n] * P : 0.f;
 #pragma unroll
-    for (int q = 0; q < Y; ++q) {
-      int l = 1;
-      while ((l) * (l + 2) <= q) ++l;  // q in [(l-1)(l+1), l(l+2))
-      float v = (l <= L3) ? 2.0f * clm(q) * Ep[NR + (l - 1) * NA + n] * S[n][q] : 0.f;
-      if (L4 && q >= 3 && q < 8) v += a4[q - 3];
-      if (L5 && q < 3) v += a5[q];
-      S[n][q] = v;
+        for (int m = 0; m < 3; ++m) a5[m] = e5 * Sn[m];
+      }
+#pragma unroll
+      for (int e = 0; e < YG; ++e) {
+        float v = 2.0f * csel<HS>(g, e) * (e < nAg ? eA : eBv) * Sn[e];
+        if (e < 5) v += a4[e];
+        if (e < 3) v += a5[e];
+        Ag[n][e] = v;
+      }
     }
   }
 
-  // ---- angular partial forces: f_ij = sum_nlm A_nlm (g'_n r_hat B_lm + g_n grad B_lm)
-  for (int k = 0; k < nA; ++k) {
-    const PairGeom g = pair_geom(a.nb.idxA[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
-    const float ux = g.dx * g.inv_r, uy = g.dy * g.inv_r, uz = g.dz * g.inv_r;
+  // ---- angular partial forces: f_ij = sum_nlm A_nlm (g'_n r_hat B_lm + g_n grad B_lm);
+  //      each harmonic group adds its half, the two halves are summed across lanes
+  for (int k = w.p; k < nA; k += 4) {
+    const PairGeom q = pair_geom(a.nb.idxA[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+    const float ux = q.dx * q.inv_r, uy = q.dy * q.inv_r, uz = q.dz * q.inv_r;
     float f[KA], fp[KA];
-    radial_basis_d<KA>(g.r, a.inv_rcA, f, fp);
-    const int J = a.type[g.j];
+    radial_basis_d<KA>(q.r, a.inv_rcA, f, fp);
+    const int J = a.type[q.j];
     float gn[NA], gp[NA];
 #pragma unroll
     for (int n = 0; n < NA; ++n) {
@@ -504,35 +663,48 @@ __global__ __launch_bounds__(256) void k_forward(FwdArgs a) {
     float B[Y];
     harm_val<LM>(ux, uy, uz, B);
     float vv = 0.f;
-    float uu[Y];
+    float uf[Y];
 #pragma unroll
-    for (int q = 0; q < Y; ++q) {
+    for (int qq = 0; qq < Y; ++qq) uf[qq] = 0.f;
+#pragma unroll
+    for (int e = 0; e < YG; ++e) {
       float su = 0.f, sv = 0.f;
 #pragma unroll
       for (int n = 0; n < NA; ++n) {
-        su = fmaf(S[n][q], gn[n], su);
-        sv = fmaf(S[n][q], gp[n], sv);
+        su = fmaf(Ag[n][e], gn[n], su);
+        sv = fmaf(Ag[n][e], gp[n], sv);
       }
-      uu[q] = su;
-      vv = fmaf(sv, B[q], vv);
+      vv = fmaf(sv, hsel<HS, Y>(g, e, B), vv);
+      const int q0 = HS::q(0, e), q1 = HS::q(1, e);
+      if (q0 >= 0) uf[q0] = g ? uf[q0] : su;
+      if (q1 >= 0) uf[q1] = g ? su : uf[q1];
     }
     float gx = 0.f, gy = 0.f, gz = 0.f;
-    harm_grad<LM>(ux, uy, uz, [&](int q, float ax, float ay, float az) {
-      gx = fmaf(uu[q], ax, gx);
-      gy = fmaf(uu[q], ay, gy);
-      gz = fmaf(uu[q], az, gz);
+    harm_grad<LM>(ux, uy, uz, [&](int qq, float ax, float ay, float az) {
+      gx = fmaf(uf[qq], ax, gx);
+      gy = fmaf(uf[qq], ay, gy);
+      gz = fmaf(uf[qq], az, gz);
     });
     const float rad = ux * gx + uy * gy + uz * gz;
-    const float fx = vv * ux + (gx - rad * ux) * g.inv_r;
-    const float fy = vv * uy + (gy - rad * uy) * g.inv_r;
-    const float fz = vv * uz + (gz - rad * uz) * g.inv_r;
-    a.fA[(size_t)k * N + i] = fx;
-    a.fA[capN_A + (size_t)k * N + i] = fy;
-    a.fA[2 * capN_A + (size_t)k * N + i] = fz;
-    vxx -= fx * g.dx; vyy -= fy * g.dy; vzz -= fz * g.dz;
-    vxy -= fx * g.dy; vyz -= fy * g.dz; vzx -= fz * g.dx;
+    float fx = vv * ux + (gx - rad * ux) * q.inv_r;
+    float fy = vv * uy + (gy - rad * uy) * q.inv_r;
+    float fz = vv * uz + (gz - rad * uz) * q.inv_r;
+    // the partner lane (other harmonic group, same pair) runs the same
+    // iterations; a single-hop permute reads it while other lanes idle
+    fx += __shfl_xor(fx, 4, kWave);
+    fy += __shfl_xor(fy, 4, kWave);
+    fz += __shfl_xor(fz, 4, kWave);
+    if (g == 0) {
+      a.fA[(size_t)k * N + i] = fx;
+      a.fA[capN_A + (size_t)k * N + i] = fy;
+      a.fA[2 * capN_A + (size_t)k * N + i] = fz;
+      vxx -= fx * q.dx; vyy -= fy * q.dy; vzz -= fz * q.dz;
+      vxy -= fx * q.dy; vyz -= fy * q.dz; vzx -= fz * q.dx;
+    }
   }
-  if (w.valid) {
+  vxx = grp8_sum(vxx); vyy = grp8_sum(vyy); vzz = grp8_sum(vzz);
+  vxy = grp8_sum(vxy); vyz = grp8_sum(vyz); vzx = grp8_sum(vzx);
+  if (w.valid && s == 0) {
     a.wv[i] = vxx;
     a.wv[(size_t)N + i] = vyy;
     a.wv[(size_t)2 * N + i] = vzz;
@@ -710,60 +882,79 @@ __global__ __launch_bounds__(kRedBlk) void k_loss_final(int S, int N, float le, 
 }
 
 // ================================================================= adjoint
-// Per atom (species order), with the cotangents eps = dL/dE(n),
-// Fbar = dL/dF and Gamma = dL/dW(n) frozen, the parameter gradient is the
-// gradient of  Phi_i = eps E_i - E'_i . Gdot_i,  Gdot_i = sum_j dG_i/dr_ij t_ij,
-// t_ij = Fbar_j - Fbar_i + Gamma r_ij  (the E, F and V terms of Eqs. 13-16
-// contracted with the residuals; the force and virial parts are the mixed
-// second derivatives of C1.4-C3.20 and D1.11-D1.17 applied to t).
-//   network:  a = W0 Gdot, beta = w1 sigma (eps + 2 x a):
-//             dPhi/dW0 = beta G^T - (w1 sigma) Gdot^T, dPhi/db0 = beta,
-//             dPhi/dw1 = eps x - sigma a, dPhi/db1 = eps, Gbar = W0^T beta
-//   radial:   dPhi/dc^R_{IJnk} = Gbar_n F[J][k] - E'_n Fp[J][k],
-//             Fp[J][k] = sum_{j of type J} f'_k(r_ij) (r_hat . t)
-//   angular:  dPhi/dc^A_{IJnk} = sum_{j of type J} f_k X_n - f'_k (r_hat . t) Y_n,
-//             X_n = sum_lm Sbar_nlm B_lm - A_nlm grad B_lm . t, Y_n = sum_lm A_nlm B_lm
-//   with Sbar = Gbar . dG/dS - E' . d2G/dS2 Sdot (the pairwise coupling that
-//   Algorithm 1 enumerates).
-// Sums over the atoms of a wavefront are reduced with shuffles and written
-// as one partial per wavefront; W0 partials go through k_w0_grad.
+// Per atom, with the cotangents eps = dL/dE(n), Fbar = dL/dF and
+// Gamma = dL/dW(n) frozen, the parameter gradient is the gradient of
+//   Phi_i = eps E_i - E'_i . Gdot_i,  Gdot_i = sum_j dG_i/dr_ij t_ij,
+//   t_ij = Fbar_j - Fbar_i + Gamma r_ij
+// (the E, F and V terms of Eqs. 13-16 contracted with the residuals; the
+// force and virial parts are the mixed second derivatives of C1.4-C3.20 and
+// D1.11-D1.17 applied to t).
+//   network: a = W0 Gdot, beta = w1 sigma (eps + 2 x a): dPhi/dW0 =
+//            beta G^T - (w1 sigma) Gdot^T, dPhi/db0 = beta, dPhi/dw1 =
+//            eps x - sigma a, dPhi/db1 = eps, Gbar = W0^T beta
+//   radial:  dPhi/dc^R_{IJnk} = Gbar_n F[J][k] - E'_n Fp[J][k],
+//            Fp[J][k] = sum_{j of type J} f'_k(r_ij) (r_hat . t)
+//   angular: dPhi/dc^A_{IJnk} = sum_{j of type J} f_k X_n - f'_k (r_hat.t) Y_n,
+//            X_n = sum_lm Sbar_nlm B_lm - A_nlm grad B_lm . t,
+//            Y_n = sum_lm A_nlm B_lm,
+//            Sbar = Gbar . dG/dS - E' . (d2G/dS2) Sdot  (the pairwise
+//            coupling that Algorithm 1 enumerates).
+// Outputs: per-atom vectors for the outer-product sums (W0, c^R) and, per
+// wavefront, the sums of the c^A, b0, w1, b1 partials over its 8 atoms.
 template <class C>
 __global__ __launch_bounds__(256) void k_adjoint(AdjArgs a) {
   constexpr int T = C::T, NR = C::NR, NA = C::NA, KR = C::KR, KA = C::KA, Y = C::Y, D = C::D, LM = C::LMAX;
-  constexpr int L3 = C::L3, L4 = C::L4, L5 = C::L5, PS = C::PS;
-  const WaveCtx w = wave_ctx(a.order, a.type, a.Npad);
-  const int nwaves = a.Npad / kWave;
-  if (w.lane == 0 && w.wave < nwaves) a.wave_species[w.wave] = w.any ? w.I : -1;
-  if (!w.any) return;
-  const int N = a.N, i = w.i, I = w.I, p = w.p, H = a.H;
-  const int s = a.astruct[i];
-  const float Lx = a.box[3 * s], Ly = a.box[3 * s + 1], Lz = a.box[3 * s + 2];
+  constexpr int L3 = C::L3, L4 = C::L4, L5 = C::L5;
+  using HS = HSplit<LM>;
+  constexpr int YG = HS::YG;
+  constexpr int DP = (D + 3) & ~3;
+  constexpr int NAH = (NA + 1) / 2;          // channels per lane in the coefficient pass
+  constexpr int RW = DP + 2 * NA * Y;        // LDS row per atom: Gdot, Sbar, A
+  constexpr int PSA = T * NA * KA;
+  extern __shared__ float lds[];
+  const int H = a.H;
+  const int WS = H * DP + 2 * H;
+  float* wl = lds;
+  float* rows = lds + T * WS;
+  stage_weights(wl, a.nn, a.nn_stride, T, H, D, DP);
+  const GroupCtx w = group_ctx(a.order, a.type, a.Npad);
+  const int N = a.N, i = w.i, I = w.I, pa = w.pa, s = w.s, g = w.g;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const bool wave_any = __ballot(w.valid) != 0ull;
+  if (lane == 0 && wave < a.Npad / kAPW) a.wave_species[wave] = wave_any ? I : -1;
+  const bool first_atom = (lane >> 3) == 0;   // atom slot 0 of the wavefront writes the sums
+  float* part = a.part + (size_t)wave * a.PW;
+  float* row = rows + w.al * RW;
+  float* rowSb = row + DP;
+  float* rowA = rowSb + NA * Y;
+  const int st = a.astruct[i];
+  const float Lx = a.box[3 * st], Ly = a.box[3 * st + 1], Lz = a.box[3 * st + 2];
   const float xi = a.pos[i], yi = a.pos[N + i], zi = a.pos[2 * N + i];
   const int nR = w.valid ? min(a.nb.cntR[i], a.nb.capR) : 0;
   const int nA = w.valid ? min(a.nb.cntA[i], a.nb.capA) : 0;
   const cptr<float> cRI = as_const(a.cR) + (size_t)I * T * NR * KR;
   const cptr<float> cAI = as_const(a.cA) + (size_t)I * T * NA * KA;
-  const float eps = w.valid ? a.eps[s] : 0.f;
-  const float* wb = a.wbar + 6 * s;
+  const float eps = w.valid ? a.eps[st] : 0.f;
+  const float* wb = a.wbar + 6 * st;
   const float gxx = wb[0], gyy = wb[1], gzz = wb[2], gxy = wb[3], gyz = wb[4], gzx = wb[5];
   const float fbx = a.fbar[i], fby = a.fbar[N + i], fbz = a.fbar[2 * N + i];
-  float* part = a.part + (size_t)w.wave * a.PW;
 
-  // ---- radial tangent pass
+  // ---- radial tangent pass, pairs split over the 8 lanes
   float FR[T][KR], FP[T][KR];
 #pragma unroll
   for (int t = 0; t < T; ++t)
 #pragma unroll
     for (int k = 0; k < KR; ++k) FR[t][k] = FP[t][k] = 0.f;
-  for (int k = 0; k < nR; ++k) {
-    const PairGeom g = pair_geom(a.nb.idxR[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
-    const float tx = (a.fbar[g.j] - fbx) + gxx * g.dx + gxy * g.dy;
-    const float ty = (a.fbar[N + g.j] - fby) + gyy * g.dy + gyz * g.dz;
-    const float tz = (a.fbar[2 * N + g.j] - fbz) + gzz * g.dz + gzx * g.dx;
-    const float dt = (g.dx * tx + g.dy * ty + g.dz * tz) * g.inv_r;
+  for (int k = s; k < nR; k += kLPA) {
+    const PairGeom q = pair_geom(a.nb.idxR[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+    const float tx = (a.fbar[q.j] - fbx) + gxx * q.dx + gxy * q.dy;
+    const float ty = (a.fbar[N + q.j] - fby) + gyy * q.dy + gyz * q.dz;
+    const float tz = (a.fbar[2 * N + q.j] - fbz) + gzz * q.dz + gzx * q.dx;
+    const float dt = (q.dx * tx + q.dy * ty + q.dz * tz) * q.inv_r;
     float f[KR], fp[KR];
-    radial_basis_d<KR>(g.r, a.inv_rcR, f, fp);
-    const int J = a.type[g.j];
+    radial_basis_d<KR>(q.r, a.inv_rcR, f, fp);
+    const int J = a.type[q.j];
 #pragma unroll
     for (int t = 0; t < T; ++t) {
       const float m = (T == 1 || J == t) ? 1.f : 0.f;
@@ -775,253 +966,321 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs a) {
       }
     }
   }
-  float Gd[D];
 #pragma unroll
-  for (int n = 0; n < NR; ++n) {
-    float acc = 0.f;
+  for (int t = 0; t < T; ++t)
 #pragma unroll
-    for (int t = 0; t < T; ++t)
+    for (int k = 0; k < KR; ++k) {
+      FR[t][k] = grp8_sum(FR[t][k]);
+      FP[t][k] = grp8_sum(FP[t][k]);
+      const int e = t * KR + k;
+      if (w.valid && s == (e & 7)) {
+        a.FRst[(size_t)e * a.Npad + pa] = FR[t][k];
+        a.FPst[(size_t)e * a.Npad + pa] = FP[t][k];
+      }
+    }
 #pragma unroll
-      for (int k = 0; k < KR; ++k) acc = fmaf(cRI[(t * NR + n) * KR + k], FP[t][k], acc);
-    Gd[n] = acc;
-  }
+  for (int n = 0; n < NR; ++n)
+    if (s == (n & 7)) {
+      float acc = 0.f;
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int k = 0; k < KR; ++k) acc = fmaf(cRI[(t * NR + n) * KR + k], FP[t][k], acc);
+      row[n] = acc;
+    }
 
   // ---- angular tangent pass: Sdot_nlm = sum_j g'_n (r_hat.t) B_lm + g_n grad B_lm . t
-  {
-    float Sd[NA][Y];
+  float Sd[NA][YG];
 #pragma unroll
-    for (int n = 0; n < NA; ++n)
+  for (int n = 0; n < NA; ++n)
 #pragma unroll
-      for (int q = 0; q < Y; ++q) Sd[n][q] = 0.f;
-    for (int k = 0; k < nA; ++k) {
-      const PairGeom g = pair_geom(a.nb.idxA[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
-      const float ux = g.dx * g.inv_r, uy = g.dy * g.inv_r, uz = g.dz * g.inv_r;
-      const float tx = (a.fbar[g.j] - fbx) + gxx * g.dx + gxy * g.dy;
-      const float ty = (a.fbar[N + g.j] - fby) + gyy * g.dy + gyz * g.dz;
-      const float tz = (a.fbar[2 * N + g.j] - fbz) + gzz * g.dz + gzx * g.dx;
-      const float dt = ux * tx + uy * ty + uz * tz;
-      float f[KA], fp[KA];
-      radial_basis_d<KA>(g.r, a.inv_rcA, f, fp);
-      const int J = a.type[g.j];
-      float gn[NA], gpd[NA];
-#pragma unroll
-      for (int n = 0; n < NA; ++n) {
-        float s0 = 0.f, s1 = 0.f;
-#pragma unroll
-        for (int kk = 0; kk < KA; ++kk) {
-          const float c = coef_sel<T, NA, KA>(cAI, J, n, kk);
-          s0 = fmaf(c, f[kk], s0);
-          s1 = fmaf(c, fp[kk], s1);
-        }
-        gn[n] = s0;
-        gpd[n] = s1 * dt;
-      }
-      float B[Y];
-      harm_val<LM>(ux, uy, uz, B);
-#pragma unroll
-      for (int n = 0; n < NA; ++n)
-#pragma unroll
-        for (int q = 0; q < Y; ++q) Sd[n][q] = fmaf(gpd[n], B[q], Sd[n][q]);
-      harm_grad<LM>(ux, uy, uz, [&](int q, float ax, float ay, float az) {
-        const float gbt = ((ax * tx + ay * ty + az * tz) - (ax * ux + ay * uy + az * uz) * dt) * g.inv_r;
-#pragma unroll
-        for (int n = 0; n < NA; ++n) Sd[n][q] = fmaf(gn[n], gbt, Sd[n][q]);
-      });
-    }
-    // Gdot of the angular descriptors, using the stored S
+    for (int e = 0; e < YG; ++e) Sd[n][e] = 0.f;
+  for (int k = w.p; k < nA; k += 4) {
+    const PairGeom q = pair_geom(a.nb.idxA[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+    const float ux = q.dx * q.inv_r, uy = q.dy * q.inv_r, uz = q.dz * q.inv_r;
+    const float tx = (a.fbar[q.j] - fbx) + gxx * q.dx + gxy * q.dy;
+    const float ty = (a.fbar[N + q.j] - fby) + gyy * q.dy + gyz * q.dz;
+    const float tz = (a.fbar[2 * N + q.j] - fbz) + gzz * q.dz + gzx * q.dx;
+    const float dt = ux * tx + uy * ty + uz * tz;
+    float f[KA], fp[KA];
+    radial_basis_d<KA>(q.r, a.inv_rcA, f, fp);
+    const int J = a.type[q.j];
+    float gn[NA], gpd[NA];
 #pragma unroll
     for (int n = 0; n < NA; ++n) {
-      float Sn[Y];
+      float s0 = 0.f, s1 = 0.f;
 #pragma unroll
-      for (int q = 0; q < Y; ++q) Sn[q] = a.Sst[(size_t)(n * Y + q) * a.Npad + p];
+      for (int kk = 0; kk < KA; ++kk) {
+        const float c = coef_sel<T, NA, KA>(cAI, J, n, kk);
+        s0 = fmaf(c, f[kk], s0);
+        s1 = fmaf(c, fp[kk], s1);
+      }
+      gn[n] = s0;
+      gpd[n] = s1 * dt;
+    }
+    float B[Y], gbt[Y];
+    harm_val<LM>(ux, uy, uz, B);
+    harm_grad<LM>(ux, uy, uz, [&](int qq, float ax, float ay, float az) {
+      gbt[qq] = ((ax * tx + ay * ty + az * tz) - (ax * ux + ay * uy + az * uz) * dt) * q.inv_r;
+    });
 #pragma unroll
-      for (int l = 1; l <= L3; ++l) {
-        float acc = 0.f;
+    for (int e = 0; e < YG; ++e) {
+      const float b = hsel<HS, Y>(g, e, B), c = hsel<HS, Y>(g, e, gbt);
 #pragma unroll
-        for (int m = 0; m < 2 * l + 1; ++m) {
-          const int q = (l - 1) * (l + 1) + m;
-          acc = fmaf(2.0f * clm(q) * Sn[q], Sd[n][q], acc);
-        }
-        Gd[NR + (l - 1) * NA + n] = acc;
+      for (int n = 0; n < NA; ++n) Sd[n][e] = fmaf(gpd[n], b, fmaf(gn[n], c, Sd[n][e]));
+    }
+  }
+#pragma unroll
+  for (int n = 0; n < NA; ++n)
+#pragma unroll
+    for (int e = 0; e < YG; ++e) Sd[n][e] = quad_sum(Sd[n][e]);
+
+  // ---- Gdot of the angular descriptors, one channel at a time; S (stored by
+  //      the forward pass) and Sdot are parked in the atom's LDS row
+  {
+    const int nAg = g ? HS::nA1 : HS::nA0;
+    const int lA = g ? 2 : 1, lB = g ? 3 : 4;
+#pragma unroll
+    for (int n = 0; n < NA; ++n) {
+      float Sn[YG];
+#pragma unroll
+      for (int e = 0; e < YG; ++e) {
+        const int q = g ? HS::q(1, e) : HS::q(0, e);
+        Sn[e] = (w.valid && q >= 0) ? a.Sst[(size_t)(n * Y + q) * a.Npad + pa] : 0.f;
+      }
+      float qa = 0.f, qb = 0.f;
+#pragma unroll
+      for (int e = 0; e < YG; ++e) {
+        const float v = 2.0f * csel<HS>(g, e) * Sn[e] * Sd[n][e];
+        if (e < nAg) qa += v; else qb += v;
+      }
+      if (w.p == 0) {
+        if (lA <= L3) row[NR + (lA - 1) * NA + n] = qa;
+        if (lB <= L3) row[NR + (lB - 1) * NA + n] = qb;
       }
       if constexpr (L4 != 0) {
-        const Sym3 M = sym_of(Sn[3], Sn[4], Sn[5], Sn[6], Sn[7]);
-        const Sym3 Md = sym_of(Sd[n][3], Sd[n][4], Sd[n][5], Sd[n][6], Sd[n][7]);
-        Gd[NR + L3 * NA + n] = 3.0f * sym_dot(sym_mul(M, M), Md);
+        const Sym3 M = sym_of(Sn[0], Sn[1], Sn[2], Sn[3], Sn[4]);
+        const Sym3 Md = sym_of(Sd[n][0], Sd[n][1], Sd[n][2], Sd[n][3], Sd[n][4]);
+        const float v = 3.0f * sym_dot(sym_mul(M, M), Md);
+        if (g == 1 && w.p == 0) row[NR + L3 * NA + n] = v;
       }
       if constexpr (L5 != 0) {
         const float P = Sn[0] * Sn[0] + Sn[1] * Sn[1] + Sn[2] * Sn[2];
         const float SS = Sn[0] * Sd[n][0] + Sn[1] * Sd[n][1] + Sn[2] * Sd[n][2];
-        Gd[NR + L3 * NA + (L4 ? NA : 0) + n] = 4.0f * P * SS;
+        if (g == 0 && w.p == 0) row[NR + L3 * NA + (L4 ? NA : 0) + n] = 4.0f * P * SS;
       }
-      if (w.valid)
+      if (w.p == 0) {
 #pragma unroll
-        for (int q = 0; q < Y; ++q) a.Sd[(size_t)(n * Y + q) * a.Npad + p] = Sd[n][q];
+        for (int e = 0; e < YG; ++e) {
+          const int q = g ? HS::q(1, e) : HS::q(0, e);
+          if (q >= 0) {
+            rowA[n * Y + q] = Sn[e];
+            rowSb[n * Y + q] = Sd[n][e];
+          }
+        }
+      }
     }
   }
-  if (w.valid)
+  __syncthreads();
+  float Gd[D];
 #pragma unroll
-    for (int v = 0; v < D; ++v) a.Gd[(size_t)v * a.Npad + p] = Gd[v];
+  for (int v = 0; v < D; ++v) {
+    Gd[v] = row[v];
+    if (w.valid && s == (v & 7)) a.Gd[(size_t)v * a.Npad + pa] = Gd[v];
+  }
 
-  // ---- network adjoint
-  const cptr<float> W = as_const(a.nn) + (size_t)I * a.nn_stride;
-  const cptr<float> w1 = W + (size_t)H * D + H;
+  // ---- network adjoint, hidden units mu = s, s+8, ...
+  const float* Wl = wl + I * WS;
   float Gb[D];
 #pragma unroll
   for (int v = 0; v < D; ++v) Gb[v] = 0.f;
-  for (int mu = 0; mu < H; ++mu) {
-    const cptr<float> wr = W + (size_t)mu * D;
+  const int RH = (H + kLPA - 1) / kLPA;
+  for (int r = 0; r < RH; ++r) {
+    const int mu = r * kLPA + s;
+    const bool act = mu < H;
+    const int mm = act ? mu : H - 1;
+    const float* wr = Wl + mm * DP;
     float aa = 0.f;
 #pragma unroll
     for (int v = 0; v < D; ++v) aa = fmaf(wr[v], Gd[v], aa);
-    const float x = a.X[(size_t)mu * a.Npad + p];
+    const bool live = act && w.valid;
+    const float x = live ? a.X[(size_t)mu * a.Npad + pa] : 0.f;
     const float sg = 1.0f - x * x;
-    const float ws = w1[mu] * sg;
-    const float be = w.valid ? ws * (eps + 2.0f * x * aa) : 0.f;
+    const float ws = Wl[H * DP + H + mm] * sg;
+    const float be = live ? ws * (eps + 2.0f * x * aa) : 0.f;
 #pragma unroll
     for (int v = 0; v < D; ++v) Gb[v] = fmaf(be, wr[v], Gb[v]);
-    a.beta[(size_t)mu * a.Npad + p] = be;
-    a.w1s[(size_t)mu * a.Npad + p] = w.valid ? ws : 0.f;
-    const float r0 = wave_sum(be);
-    const float r1 = wave_sum(w.valid ? eps * x - sg * aa : 0.f);
-    if (w.lane == 0) {
-      part[PS + mu] = r0;
-      part[PS + H + mu] = r1;
+    if (live) {
+      a.beta[(size_t)mu * a.Npad + pa] = be;
+      a.w1s[(size_t)mu * a.Npad + pa] = ws;
+    }
+    const float r0 = atoms8_sum(be);
+    const float r1 = atoms8_sum(live ? eps * x - sg * aa : 0.f);
+    if (act && first_atom) {
+      part[PSA + mu] = r0;
+      part[PSA + H + mu] = r1;
     }
   }
-  {
-    const float r = wave_sum(eps);
-    if (w.lane == 0) part[PS + 2 * H] = r;
-  }
-
-  // ---- radial coefficient gradient
-  float Ep[D];
 #pragma unroll
-  for (int v = 0; v < D; ++v) Ep[v] = a.Ep[(size_t)v * a.Npad + p];
+  for (int v = 0; v < D; ++v) Gb[v] = grp8_sum(Gb[v]);
+  {
+    const float r = atoms8_sum(s == 0 ? eps : 0.f);
+    if (lane == 0) part[PSA + 2 * H] = r;
+  }
+#pragma unroll
+  for (int n = 0; n < NR; ++n)
+    if (w.valid && s == (n & 7)) a.Gbr[(size_t)n * a.Npad + pa] = Gb[n];
+
+  // ---- Sbar and A of this lane's harmonic group, in place in the atom's LDS row
+  {
+    const int nAg = g ? HS::nA1 : HS::nA0;
+    const int lA = g ? 2 : 1, lB = g ? 3 : 4;
+    const size_t Np = a.Npad;
+#pragma unroll
+    for (int n = 0; n < NA; ++n) {
+      float Sn[YG], Sdn[YG];
+#pragma unroll
+      for (int e = 0; e < YG; ++e) {
+        const int q = g ? HS::q(1, e) : HS::q(0, e);
+        Sn[e] = q >= 0 ? rowA[n * Y + q] : 0.f;
+        Sdn[e] = q >= 0 ? rowSb[n * Y + q] : 0.f;
+      }
+      // E' and Gbar of the descriptors built from these sums
+      const float eA = (w.valid && lA <= L3) ? a.Ep[(size_t)(NR + (lA - 1) * NA + n) * Np + pa] : 0.f;
+      const float eB = (w.valid && lB <= L3) ? a.Ep[(size_t)(NR + (lB - 1) * NA + n) * Np + pa] : 0.f;
+      float gA, gB;
+      ep_blocks<NR, NA, L3, D>(Gb, n, g, gA, gB);
+      float o[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, od[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+      float e4 = 0.f, g4 = 0.f, e5 = 0.f, g5 = 0.f, P = 0.f, SS = 0.f;
+      if constexpr (L4 != 0) {
+        const Sym3 M = sym_of(Sn[0], Sn[1], Sn[2], Sn[3], Sn[4]);
+        const Sym3 Md = sym_of(Sdn[0], Sdn[1], Sdn[2], Sdn[3], Sdn[4]);
+        sym_proj(sym_mul(M, M), o);
+        sym_proj(sym_mul(Md, M), od);
+        const int v4 = NR + L3 * NA + n;
+        e4 = (w.valid && g == 1) ? a.Ep[(size_t)v4 * Np + pa] : 0.f;
+        g4 = g == 1 ? Gb[v4] : 0.f;
+      }
+      if constexpr (L5 != 0) {
+        P = Sn[0] * Sn[0] + Sn[1] * Sn[1] + Sn[2] * Sn[2];
+        SS = Sn[0] * Sdn[0] + Sn[1] * Sdn[1] + Sn[2] * Sdn[2];
+        const int v5 = NR + L3 * NA + (L4 ? NA : 0) + n;
+        e5 = (w.valid && g == 0) ? a.Ep[(size_t)v5 * Np + pa] : 0.f;
+        g5 = g == 0 ? Gb[v5] : 0.f;
+      }
+#pragma unroll
+      for (int e = 0; e < YG; ++e) {
+        const int q = g ? HS::q(1, e) : HS::q(0, e);
+        const float c2 = 2.0f * csel<HS>(g, e);
+        const float eL = e < nAg ? eA : eB, gL = e < nAg ? gA : gB;
+        float Av = c2 * eL * Sn[e];
+        float Sb = c2 * (gL * Sn[e] - eL * Sdn[e]);
+        if (e < 5) {
+          Av += 3.0f * e4 * o[e];
+          Sb += 3.0f * g4 * o[e] - 6.0f * e4 * od[e];
+        }
+        if (e < 3) {
+          Av += 4.0f * e5 * P * Sn[e];
+          Sb += 4.0f * g5 * P * Sn[e] - e5 * (8.0f * SS * Sn[e] + 4.0f * P * Sdn[e]);
+        }
+        if (w.p == 0 && q >= 0) {
+          rowA[n * Y + q] = Av;
+          rowSb[n * Y + q] = Sb;
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- angular coefficient gradient: channels g*NAH + j, pairs p, p+4, ...
+  float cb[T][NAH][KA];
 #pragma unroll
   for (int t = 0; t < T; ++t)
 #pragma unroll
-    for (int n = 0; n < NR; ++n)
+    for (int j = 0; j < NAH; ++j)
 #pragma unroll
-      for (int k = 0; k < KR; ++k) {
-        const float v = w.valid ? Gb[n] * FR[t][k] - Ep[n] * FP[t][k] : 0.f;
-        const float r = wave_sum(v);
-        if (w.lane == 0) part[(t * NR + n) * KR + k] = r;
-      }
-
-  // ---- angular coefficient gradient, one radial channel n at a time
-  for (int n = 0; n < NA; ++n) {
-    float Sn[Y], Sdn[Y], An[Y], Sb[Y];
+      for (int k = 0; k < KA; ++k) cb[t][j][k] = 0.f;
+  for (int k = w.p; k < nA; k += 4) {
+    const PairGeom q = pair_geom(a.nb.idxA[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+    const float ux = q.dx * q.inv_r, uy = q.dy * q.inv_r, uz = q.dz * q.inv_r;
+    const float tx = (a.fbar[q.j] - fbx) + gxx * q.dx + gxy * q.dy;
+    const float ty = (a.fbar[N + q.j] - fby) + gyy * q.dy + gyz * q.dz;
+    const float tz = (a.fbar[2 * N + q.j] - fbz) + gzz * q.dz + gzx * q.dx;
+    const float dt = ux * tx + uy * ty + uz * tz;
+    float f[KA], fp[KA];
+    radial_basis_d<KA>(q.r, a.inv_rcA, f, fp);
+    const int J = a.type[q.j];
+    float B[Y], gbt[Y];
+    harm_val<LM>(ux, uy, uz, B);
+    harm_grad<LM>(ux, uy, uz, [&](int qq, float ax, float ay, float az) {
+      gbt[qq] = ((ax * tx + ay * ty + az * tz) - (ax * ux + ay * uy + az * uz) * dt) * q.inv_r;
+    });
 #pragma unroll
-    for (int q = 0; q < Y; ++q) {
-      Sn[q] = a.Sst[(size_t)(n * Y + q) * a.Npad + p];
-      Sdn[q] = a.Sd[(size_t)(n * Y + q) * a.Npad + p];
-    }
-#pragma unroll
-    for (int q = 0; q < Y; ++q) {
-      int l = 1;
-      while (l * (l + 2) <= q) ++l;
-      if (l <= L3) {
-        const int v = NR + (l - 1) * NA + n;
-        const float c2 = 2.0f * clm(q);
-        An[q] = c2 * Ep[v] * Sn[q];
-        Sb[q] = c2 * (Gb[v] * Sn[q] - Ep[v] * Sdn[q]);
-      } else {
-        An[q] = 0.f;
-        Sb[q] = 0.f;
-      }
-    }
-    if constexpr (L4 != 0) {
-      const int v = NR + L3 * NA + n;
-      const Sym3 M = sym_of(Sn[3], Sn[4], Sn[5], Sn[6], Sn[7]);
-      const Sym3 Md = sym_of(Sdn[3], Sdn[4], Sdn[5], Sdn[6], Sdn[7]);
-      float o[5], od[5];
-      sym_proj(sym_mul(M, M), o);
-      sym_proj(sym_mul(Md, M), od);
-#pragma unroll
-      for (int m = 0; m < 5; ++m) {
-        An[3 + m] += 3.0f * Ep[v] * o[m];
-        Sb[3 + m] += 3.0f * Gb[v] * o[m] - 6.0f * Ep[v] * od[m];
-      }
-    }
-    if constexpr (L5 != 0) {
-      const int v = NR + L3 * NA + (L4 ? NA : 0) + n;
-      const float P = Sn[0] * Sn[0] + Sn[1] * Sn[1] + Sn[2] * Sn[2];
-      const float SS = Sn[0] * Sdn[0] + Sn[1] * Sdn[1] + Sn[2] * Sdn[2];
-#pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        An[m] += 4.0f * Ep[v] * P * Sn[m];
-        Sb[m] += 4.0f * Gb[v] * P * Sn[m] - Ep[v] * (8.0f * SS * Sn[m] + 4.0f * P * Sdn[m]);
-      }
-    }
-    float cb[T][KA];
-#pragma unroll
-    for (int t = 0; t < T; ++t)
-#pragma unroll
-      for (int k = 0; k < KA; ++k) cb[t][k] = 0.f;
-    for (int k = 0; k < nA; ++k) {
-      const PairGeom g = pair_geom(a.nb.idxA[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
-      const float ux = g.dx * g.inv_r, uy = g.dy * g.inv_r, uz = g.dz * g.inv_r;
-      const float tx = (a.fbar[g.j] - fbx) + gxx * g.dx + gxy * g.dy;
-      const float ty = (a.fbar[N + g.j] - fby) + gyy * g.dy + gyz * g.dz;
-      const float tz = (a.fbar[2 * N + g.j] - fbz) + gzz * g.dz + gzx * g.dx;
-      const float dt = ux * tx + uy * ty + uz * tz;
-      float f[KA], fp[KA];
-      radial_basis_d<KA>(g.r, a.inv_rcA, f, fp);
-      const int J = a.type[g.j];
-      float B[Y];
-      harm_val<LM>(ux, uy, uz, B);
+    for (int j = 0; j < NAH; ++j) {
+      const int n = g * NAH + j;
+      const bool on = n < NA;
+      const float* sb = rowSb + (on ? n : 0) * Y;
+      const float* av = rowA + (on ? n : 0) * Y;
       float X = 0.f, Yv = 0.f;
 #pragma unroll
-      for (int q = 0; q < Y; ++q) {
-        X = fmaf(Sb[q], B[q], X);
-        Yv = fmaf(An[q], B[q], Yv);
+      for (int qq = 0; qq < Y; ++qq) {
+        X = fmaf(sb[qq], B[qq], fmaf(-av[qq], gbt[qq], X));
+        Yv = fmaf(av[qq], B[qq], Yv);
       }
-      float at = 0.f, au = 0.f;
-      harm_grad<LM>(ux, uy, uz, [&](int q, float ax, float ay, float az) {
-        at = fmaf(An[q], ax * tx + ay * ty + az * tz, at);
-        au = fmaf(An[q], ax * ux + ay * uy + az * uz, au);
-      });
-      X -= (at - au * dt) * g.inv_r;
-      const float Yd = Yv * dt;
+      X = on ? X : 0.f;
+      const float Yd = on ? Yv * dt : 0.f;
 #pragma unroll
       for (int t = 0; t < T; ++t) {
         const float m = (T == 1 || J == t) ? 1.f : 0.f;
         const float mX = m * X, mY = m * Yd;
 #pragma unroll
-        for (int kk = 0; kk < KA; ++kk) cb[t][kk] = fmaf(mX, f[kk], fmaf(-mY, fp[kk], cb[t][kk]));
+        for (int kk = 0; kk < KA; ++kk) cb[t][j][kk] = fmaf(mX, f[kk], fmaf(-mY, fp[kk], cb[t][j][kk]));
       }
     }
+  }
 #pragma unroll
-    for (int t = 0; t < T; ++t)
+  for (int t = 0; t < T; ++t)
+#pragma unroll
+    for (int j = 0; j < NAH; ++j)
 #pragma unroll
       for (int k = 0; k < KA; ++k) {
-        const float r = wave_sum(cb[t][k]);
-        if (w.lane == 0) part[T * NR * KR + (t * NA + n) * KA + k] = r;
+        const float r = atoms8_sum(quad_sum(cb[t][j][k]));
+        const int n = g * NAH + j;
+        if (first_atom && w.p == 0 && n < NA) part[(t * NA + n) * KA + k] = r;
       }
-  }
 }
 
-// sum over the atoms of species I of beta G^T - (w1 sigma) Gdot^T, tiled
-// 4 x 4 per thread over (hidden unit, descriptor) with atom tiles in LDS.
-constexpr int kW0Atoms = 64;
+// Sums over the atoms of each species of an outer product,
+//   out[I][b][m][v] = sum_p A1[m][p] B1[v][p] - A2[m][p] B2[v][p],
+// for block b of species I's atoms (species order).  Used for
+// dL/dW0 = sum beta G^T - (w1 sigma) Gdot^T and for
+// dL/dc^R = sum Gbar_n F[J][k] - E'_n Fp[J][k].  4 x 4 register tiles per
+// thread over (m, v), atom tiles staged in LDS.
+constexpr int kOSAtoms = 64;
 
-__global__ __launch_bounds__(256) void k_w0_grad(int Npad, int H, int D, int NB, const int* __restrict__ seg,
-                                                 const float* __restrict__ beta, const float* __restrict__ w1s,
-                                                 const float* __restrict__ G, const float* __restrict__ Gd,
-                                                 float* __restrict__ w0part) {
+struct OuterArgs {
+  int Npad, M, V, NB;
+  const int* seg;
+  const float* A1;
+  const float* B1;
+  const float* A2;
+  const float* B2;
+  float* out;
+};
+
+__global__ __launch_bounds__(256) void k_outer_sum(OuterArgs o) {
   extern __shared__ float lds[];
-  const int HP = (H + 3) & ~3, DP = (D + 3) & ~3;
-  float* bl = lds;                       // [kW0Atoms][HP]
-  float* sl = bl + kW0Atoms * HP;        // [kW0Atoms][HP]
-  float* gl = sl + kW0Atoms * HP;        // [kW0Atoms][DP]
-  float* dl = gl + kW0Atoms * DP;        // [kW0Atoms][DP]
+  const int MP = (o.M + 3) & ~3, VP = (o.V + 3) & ~3;
+  float* al = lds;                        // [kOSAtoms][MP]
+  float* sl = al + kOSAtoms * MP;         // [kOSAtoms][MP]
+  float* bl = sl + kOSAtoms * MP;         // [kOSAtoms][VP]
+  float* dl = bl + kOSAtoms * VP;         // [kOSAtoms][VP]
   const int I = blockIdx.y, b = blockIdx.x;
-  const int start = seg[2 * I], count = seg[2 * I + 1];
-  const int chunk = (count + NB - 1) / NB;
+  const int start = o.seg[2 * I], count = o.seg[2 * I + 1];
+  const int chunk = (count + o.NB - 1) / o.NB;
   const int p0 = start + b * chunk;
   const int p1 = min(start + count, p0 + chunk);
-  const int ntm = HP / 4, ntv = DP / 4, ntile = ntm * ntv;
+  const int ntv = VP / 4, ntile = (MP / 4) * ntv;
   constexpr int kMaxTiles = 4;
   float acc[kMaxTiles][4][4];
 #pragma unroll
@@ -1030,19 +1289,19 @@ __global__ __launch_bounds__(256) void k_w0_grad(int Npad, int H, int D, int NB,
     for (int x = 0; x < 4; ++x)
 #pragma unroll
       for (int y = 0; y < 4; ++y) acc[u][x][y] = 0.f;
-  for (int base = p0; base < p1; base += kW0Atoms) {
-    const int na = min(kW0Atoms, p1 - base);
-    for (int q = threadIdx.x; q < kW0Atoms * HP; q += blockDim.x) {
-      const int u = q / kW0Atoms, at = q % kW0Atoms;
-      const bool ok = u < H && at < na;
-      bl[at * HP + u] = ok ? beta[(size_t)u * Npad + base + at] : 0.f;
-      sl[at * HP + u] = ok ? w1s[(size_t)u * Npad + base + at] : 0.f;
+  for (int base = p0; base < p1; base += kOSAtoms) {
+    const int na = min(kOSAtoms, p1 - base);
+    for (int q = threadIdx.x; q < kOSAtoms * MP; q += blockDim.x) {
+      const int m = q / kOSAtoms, at = q % kOSAtoms;
+      const bool ok = m < o.M && at < na;
+      al[at * MP + m] = ok ? o.A1[(size_t)m * o.Npad + base + at] : 0.f;
+      sl[at * MP + m] = ok ? o.A2[(size_t)m * o.Npad + base + at] : 0.f;
     }
-    for (int q = threadIdx.x; q < kW0Atoms * DP; q += blockDim.x) {
-      const int v = q / kW0Atoms, at = q % kW0Atoms;
-      const bool ok = v < D && at < na;
-      gl[at * DP + v] = ok ? G[(size_t)v * Npad + base + at] : 0.f;
-      dl[at * DP + v] = ok ? Gd[(size_t)v * Npad + base + at] : 0.f;
+    for (int q = threadIdx.x; q < kOSAtoms * VP; q += blockDim.x) {
+      const int v = q / kOSAtoms, at = q % kOSAtoms;
+      const bool ok = v < o.V && at < na;
+      bl[at * VP + v] = ok ? o.B1[(size_t)v * o.Npad + base + at] : 0.f;
+      dl[at * VP + v] = ok ? o.B2[(size_t)v * o.Npad + base + at] : 0.f;
     }
     __syncthreads();
 #pragma unroll
@@ -1051,21 +1310,21 @@ __global__ __launch_bounds__(256) void k_w0_grad(int Npad, int H, int D, int NB,
       if (tile >= ntile) break;
       const int m0 = (tile / ntv) * 4, v0 = (tile % ntv) * 4;
       for (int at = 0; at < na; ++at) {
-        const float4 bb = *reinterpret_cast<const float4*>(bl + at * HP + m0);
-        const float4 ss = *reinterpret_cast<const float4*>(sl + at * HP + m0);
-        const float4 gg = *reinterpret_cast<const float4*>(gl + at * DP + v0);
-        const float4 dd = *reinterpret_cast<const float4*>(dl + at * DP + v0);
-        const float bv[4] = {bb.x, bb.y, bb.z, bb.w}, sv[4] = {ss.x, ss.y, ss.z, ss.w};
-        const float gv[4] = {gg.x, gg.y, gg.z, gg.w}, dv[4] = {dd.x, dd.y, dd.z, dd.w};
+        const float4 aa = *reinterpret_cast<const float4*>(al + at * MP + m0);
+        const float4 ss = *reinterpret_cast<const float4*>(sl + at * MP + m0);
+        const float4 bb = *reinterpret_cast<const float4*>(bl + at * VP + v0);
+        const float4 dd = *reinterpret_cast<const float4*>(dl + at * VP + v0);
+        const float av[4] = {aa.x, aa.y, aa.z, aa.w}, sv[4] = {ss.x, ss.y, ss.z, ss.w};
+        const float bv[4] = {bb.x, bb.y, bb.z, bb.w}, dv[4] = {dd.x, dd.y, dd.z, dd.w};
 #pragma unroll
         for (int x = 0; x < 4; ++x)
 #pragma unroll
-          for (int y = 0; y < 4; ++y) acc[u][x][y] = fmaf(bv[x], gv[y], fmaf(-sv[x], dv[y], acc[u][x][y]));
+          for (int y = 0; y < 4; ++y) acc[u][x][y] = fmaf(av[x], bv[y], fmaf(-sv[x], dv[y], acc[u][x][y]));
       }
     }
     __syncthreads();
   }
-  float* out = w0part + ((size_t)I * NB + b) * H * D;
+  float* out = o.out + ((size_t)I * o.NB + b) * o.M * o.V;
 #pragma unroll
   for (int u = 0; u < kMaxTiles; ++u) {
     const int tile = threadIdx.x + u * blockDim.x;
@@ -1073,18 +1332,20 @@ __global__ __launch_bounds__(256) void k_w0_grad(int Npad, int H, int D, int NB,
     const int m0 = (tile / ntv) * 4, v0 = (tile % ntv) * 4;
     for (int x = 0; x < 4; ++x)
       for (int y = 0; y < 4; ++y)
-        if (m0 + x < H && v0 + y < D) out[(m0 + x) * D + v0 + y] = acc[u][x][y];
+        if (m0 + x < o.M && v0 + y < o.V) out[(m0 + x) * o.V + v0 + y] = acc[u][x][y];
   }
 }
 
-// Final gradient: float64 sums of the per-wavefront and per-block partials in
-// a fixed order.  Blocks [0, T*PW) each reduce one (species, slot) column of
-// the wavefront partials; the remaining blocks sum the W0 block partials.
+// Final gradient: float64 sums in a fixed order.  Blocks [0, T*PW) each
+// reduce one (species, slot) column of the wavefront partials (c^A, b0, w1,
+// b1); the remaining threads sum the outer-product block partials of W0 and
+// c^R.
 struct GradArgs {
   int T, NR, NA, KR, KA, H, D, nwaves, PW, NB;
   const float* part;
   const int* wspecies;
   const float* w0part;
+  const float* crpart;
   float* grad;
 };
 
@@ -1092,38 +1353,43 @@ __global__ __launch_bounds__(256) void k_grad_final(GradArgs a) {
   __shared__ double red[256];
   const int P_R = a.T * a.T * a.NR * a.KR, P_A = a.T * a.T * a.NA * a.KA;
   const int blk = a.H * a.D + 2 * a.H + 1;
-  const int PSR = a.T * a.NR * a.KR, PSA = a.T * a.NA * a.KA;
+  const int PSA = a.T * a.NA * a.KA;
   const int ncol = a.T * a.PW;
   if ((int)blockIdx.x < ncol) {
     const int I = blockIdx.x / a.PW, slot = blockIdx.x % a.PW;
-    double s = 0.0;
+    double sum = 0.0;
     for (int w = threadIdx.x; w < a.nwaves; w += blockDim.x)
-      if (a.wspecies[w] == I) s += a.part[(size_t)w * a.PW + slot];
-    red[threadIdx.x] = s;
+      if (a.wspecies[w] == I) sum += a.part[(size_t)w * a.PW + slot];
+    red[threadIdx.x] = sum;
     __syncthreads();
     for (int st = blockDim.x / 2; st > 0; st >>= 1) {
       if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
       __syncthreads();
     }
     if (threadIdx.x != 0) return;
-    int q;
-    if (slot < PSR) {
-      q = I * PSR + slot;                          // c^R[I][J][n][k]
-    } else if (slot < PSR + PSA) {
-      q = P_R + I * PSA + (slot - PSR);            // c^A[I][J][n][k]
-    } else {
-      const int o = slot - PSR - PSA;              // b0, w1, b1
-      q = P_R + P_A + I * blk + a.H * a.D + o;
-    }
+    const int q = slot < PSA ? P_R + I * PSA + slot                   // c^A[I][J][n][k]
+                             : P_R + P_A + I * blk + a.H * a.D + (slot - PSA);  // b0, w1, b1
     a.grad[q] = (float)red[0];
     return;
   }
-  const int q = (blockIdx.x - ncol) * blockDim.x + threadIdx.x;
-  if (q >= a.T * a.H * a.D) return;
-  const int I = q / (a.H * a.D), o = q % (a.H * a.D);
-  double s = 0.0;
-  for (int b = 0; b < a.NB; ++b) s += a.w0part[((size_t)I * a.NB + b) * a.H * a.D + o];
-  a.grad[P_R + P_A + I * blk + o] = (float)s;
+  int q = (blockIdx.x - ncol) * blockDim.x + threadIdx.x;
+  const int nW = a.T * a.H * a.D;
+  if (q < nW) {
+    const int I = q / (a.H * a.D), o = q % (a.H * a.D);
+    double sum = 0.0;
+    for (int b = 0; b < a.NB; ++b) sum += a.w0part[((size_t)I * a.NB + b) * a.H * a.D + o];
+    a.grad[P_R + P_A + I * blk + o] = (float)sum;
+    return;
+  }
+  q -= nW;
+  const int VR = a.T * a.KR, MR = a.NR;
+  if (q < a.T * MR * VR) {
+    const int I = q / (MR * VR), o = q % (MR * VR);
+    const int n = o / VR, t = (o % VR) / a.KR, k = o % a.KR;
+    double sum = 0.0;
+    for (int b = 0; b < a.NB; ++b) sum += a.crpart[((size_t)I * a.NB + b) * MR * VR + o];
+    a.grad[((I * a.T + t) * a.NR + n) * a.KR + k] = (float)sum;
+  }
 }
 
 // ==================================================================== Adam
@@ -1189,20 +1455,32 @@ struct Ops {
   int T, NR, NA, KR, KA, L3, L4, L5, D, Y, PS;
   void (*forward)(const FwdArgs&, dim3, hipStream_t);
   void (*adjoint)(const AdjArgs&, dim3, hipStream_t);
+  size_t (*lds_fwd)(int);
+  size_t (*lds_adj)(int);
 };
 
 template <class C>
+static size_t lds_forward(int H) {
+  const int DP = (C::D + 3) & ~3;
+  return sizeof(float) * ((size_t)C::T * (H * DP + 2 * H) + (size_t)kAPB * (DP + C::NA * C::Y));
+}
+template <class C>
+static size_t lds_adjoint(int H) {
+  const int DP = (C::D + 3) & ~3;
+  return sizeof(float) * ((size_t)C::T * (H * DP + 2 * H) + (size_t)kAPB * (DP + 2 * C::NA * C::Y));
+}
+template <class C>
 static void launch_forward(const FwdArgs& a, dim3 grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_forward<C>, grid, dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_forward<C>, grid, dim3(256), lds_forward<C>(a.H), st, a);
 }
 template <class C>
 static void launch_adjoint(const AdjArgs& a, dim3 grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_adjoint<C>, grid, dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_adjoint<C>, grid, dim3(256), lds_adjoint<C>(a.H), st, a);
 }
 template <class C>
 static Ops make_ops() {
   return Ops{C::T, C::NR, C::NA, C::KR, C::KA, C::L3, C::L4, C::L5, C::D, C::Y, C::PS,
-             &launch_forward<C>, &launch_adjoint<C>};
+             &launch_forward<C>, &launch_adjoint<C>, &lds_forward<C>, &lds_adjoint<C>};
 }
 
 // Compiled-in model sizes (n_types, n_rad, n_ang, k_rad, k_ang, l3, l4, l5).
@@ -1249,12 +1527,12 @@ int64_t param_count(const nep_model* m) {
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
-constexpr int kW0Blocks = 256;
+constexpr int kOSBlocks = 256;   // outer-sum blocks per species
 
 struct Layout {
-  int N, S, T, D, Y, H, Npad, nwaves, nblk, PW, NA, capR, capA;
+  int N, S, T, D, Y, H, NR, TKR, Npad, nwaves, nblk, PW, NA, capR, capA;
   size_t order, seg, blk, astruct, revR, revA, G, Sst, Ep, X, eatom, fR, fA, wv, F, fbar, Es, Ws, eps, wbar, lpart,
-      Gd, Sd, beta, w1s, part, wsp, w0part, total;
+      Gd, FRst, FPst, Gbr, beta, w1s, part, wsp, w0part, crpart, total;
 };
 
 Layout make_layout(const nep_model* m, const Ops* o, int S, int N) {
@@ -1266,12 +1544,15 @@ Layout make_layout(const nep_model* m, const Ops* o, int S, int N) {
   L.Y = o->Y;
   L.H = m->hidden;
   L.NA = m->n_ang;
+  L.NR = m->n_rad;
+  L.TKR = m->n_types * m->k_rad;
   L.capR = m->cap_rad;
   L.capA = m->cap_ang;
-  L.Npad = ((N + kWave - 1) / kWave) * kWave + L.T * kWave;
-  L.nwaves = L.Npad / kWave;
+  const int n8 = ((N + kSegAlign - 1) / kSegAlign) * kSegAlign + L.T * kSegAlign;
+  L.Npad = ((n8 + kAPB - 1) / kAPB) * kAPB;
+  L.nwaves = L.Npad / kAPW;
   L.nblk = N > 0 ? (N + kOrdBlk - 1) / kOrdBlk : 1;
-  L.PW = o->PS + 2 * L.H + 1;
+  L.PW = L.T * m->n_ang * m->k_ang + 2 * L.H + 1;
   const size_t Np = L.Npad, Nn = (size_t)(N > 0 ? N : 1), Ss = (size_t)(S > 0 ? S : 1);
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -1301,12 +1582,15 @@ Layout make_layout(const nep_model* m, const Ops* o, int S, int N) {
   L.wbar = take(4 * 6 * Ss);
   L.lpart = take(8 * 3 * Ss);
   L.Gd = take(4 * (size_t)L.D * Np);
-  L.Sd = take(4 * (size_t)L.NA * L.Y * Np);
+  L.FRst = take(4 * (size_t)L.TKR * Np);
+  L.FPst = take(4 * (size_t)L.TKR * Np);
+  L.Gbr = take(4 * (size_t)L.NR * Np);
   L.beta = take(4 * (size_t)L.H * Np);
   L.w1s = take(4 * (size_t)L.H * Np);
   L.part = take(4 * (size_t)L.nwaves * L.PW);
   L.wsp = take(4 * (size_t)L.nwaves);
-  L.w0part = take(4 * (size_t)L.T * kW0Blocks * L.H * L.D);
+  L.w0part = take(4 * (size_t)L.T * kOSBlocks * L.H * L.D);
+  L.crpart = take(4 * (size_t)L.T * kOSBlocks * L.NR * L.TKR);
   L.total = off;
   return L;
 }
@@ -1467,7 +1751,7 @@ void run_forward(const Ctx& c, const nep_neighbors* nb, const float* params, flo
   if (N > 0) {
     FwdArgs a = fwd_args(c, nb, params);
     a.eatom2 = e_atom;
-    NEP_LAUNCH(pr, "forward", c.o->forward(a, dim3(grid1(c.L.Npad)), c.st));
+    NEP_LAUNCH(pr, "forward", c.o->forward(a, dim3(c.L.Npad / kAPB), c.st));
     NEP_LAUNCH(pr, "force_gather",
                hipLaunchKernelGGL(k_force_gather, dim3(grid1(N)), dim3(256), 0, c.st, N, a.nb, a.fR, a.fA,
                                   at<float>(c.ws, c.L.F), force));
@@ -1533,19 +1817,30 @@ void run_adjoint(const Ctx& c, const nep_neighbors* nb, const float* params, con
     a.fbar = fbar;
     a.wbar = wbar;
     a.Gd = at<float>(c.ws, c.L.Gd);
-    a.Sd = at<float>(c.ws, c.L.Sd);
+    a.FRst = at<float>(c.ws, c.L.FRst);
+    a.FPst = at<float>(c.ws, c.L.FPst);
+    a.Gbr = at<float>(c.ws, c.L.Gbr);
     a.beta = at<float>(c.ws, c.L.beta);
     a.w1s = at<float>(c.ws, c.L.w1s);
     a.part = at<float>(c.ws, c.L.part);
     a.wave_species = at<int>(c.ws, c.L.wsp);
     a.PW = c.L.PW;
-    NEP_LAUNCH(pr, "adjoint", c.o->adjoint(a, dim3(grid1(c.L.Npad)), c.st));
-    const int HP = (m->hidden + 3) & ~3, DP = (c.o->D + 3) & ~3;
-    const size_t lds = sizeof(float) * kW0Atoms * 2 * (HP + DP);
-    NEP_LAUNCH(pr, "w0_grad",
-               hipLaunchKernelGGL(k_w0_grad, dim3(kW0Blocks, T), dim3(256), lds, c.st, c.L.Npad, m->hidden, c.o->D,
-                                  kW0Blocks, at<int>(c.ws, c.L.seg), a.beta, a.w1s, at<float>(c.ws, c.L.G), a.Gd,
-                                  at<float>(c.ws, c.L.w0part)));
+    NEP_LAUNCH(pr, "adjoint", c.o->adjoint(a, dim3(c.L.Npad / kAPB), c.st));
+    const int* seg = at<int>(c.ws, c.L.seg);
+    {
+      OuterArgs o{c.L.Npad, m->hidden, c.o->D, kOSBlocks, seg, a.beta, at<float>(c.ws, c.L.G), a.w1s, a.Gd,
+                  at<float>(c.ws, c.L.w0part)};
+      const size_t lds = sizeof(float) * kOSAtoms * 2 * (((o.M + 3) & ~3) + ((o.V + 3) & ~3));
+      NEP_LAUNCH(pr, "w0_grad",
+                 hipLaunchKernelGGL(k_outer_sum, dim3(kOSBlocks, T), dim3(256), lds, c.st, o));
+    }
+    {
+      OuterArgs o{c.L.Npad, m->n_rad, c.L.TKR, kOSBlocks, seg, a.Gbr, a.FRst, at<float>(c.ws, c.L.Ep), a.FPst,
+                  at<float>(c.ws, c.L.crpart)};
+      const size_t lds = sizeof(float) * kOSAtoms * 2 * (((o.M + 3) & ~3) + ((o.V + 3) & ~3));
+      NEP_LAUNCH(pr, "crad_grad",
+                 hipLaunchKernelGGL(k_outer_sum, dim3(kOSBlocks, T), dim3(256), lds, c.st, o));
+    }
     GradArgs g;
     g.T = T;
     g.NR = m->n_rad;
@@ -1556,12 +1851,13 @@ void run_adjoint(const Ctx& c, const nep_neighbors* nb, const float* params, con
     g.D = c.o->D;
     g.nwaves = c.L.nwaves;
     g.PW = c.L.PW;
-    g.NB = kW0Blocks;
+    g.NB = kOSBlocks;
     g.part = a.part;
     g.wspecies = a.wave_species;
     g.w0part = at<float>(c.ws, c.L.w0part);
+    g.crpart = at<float>(c.ws, c.L.crpart);
     g.grad = grad;
-    const int nblk_gf = T * c.L.PW + grid1(T * m->hidden * c.o->D);
+    const int nblk_gf = T * c.L.PW + grid1(T * m->hidden * c.o->D + T * m->n_rad * c.L.TKR);
     NEP_LAUNCH(pr, "grad_final", hipLaunchKernelGGL(k_grad_final, dim3(nblk_gf), dim3(256), 0, c.st, g));
   } else {
     const int64_t P = param_count(m);
@@ -1575,6 +1871,7 @@ int setup(Ctx& c, const nep_model* m, const nep_batch* b, void* ws, void* stream
   c.o = find_ops(m);
   if (!c.o) return NEP_ERR_ARG;
   if (((m->hidden + 3) / 4) * ((c.o->D + 3) / 4) > 4 * 256) return NEP_ERR_ARG;  // W0 tiles per block
+  if (c.o->lds_adj(m->hidden) > 64 * 1024 || c.o->lds_fwd(m->hidden) > 64 * 1024) return NEP_ERR_ARG;
   if ((rc = check_batch(b))) return rc;
   if ((rc = check_ws(ws))) return rc;
   c.m = m;
@@ -1651,7 +1948,7 @@ int nep_descriptors(const nep_model* m, const nep_batch* b, const nep_neighbors*
   a.Guser = G;
   a.do_mlp = 0;
   a.do_force = 0;
-  c.o->forward(a, dim3(grid1(c.L.Npad)), c.st);
+  c.o->forward(a, dim3(c.L.Npad / kAPB), c.st);
   return hip_ok();
 }
 
@@ -1677,7 +1974,7 @@ int nep_vjp(const nep_model* m, const nep_batch* b, const nep_neighbors* nb, con
   if (b->n_atom > 0) {
     FwdArgs a = fwd_args(c, nb, params);
     a.do_force = 0;
-    c.o->forward(a, dim3(grid1(c.L.Npad)), c.st);
+    c.o->forward(a, dim3(c.L.Npad / kAPB), c.st);
   }
   run_adjoint(c, nb, params, e_bar, f_bar, v_bar, grad, nullptr);
   return hip_ok();

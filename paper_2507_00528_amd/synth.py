@@ -345,4 +345,17 @@ def label_noise(batch: Batch, seed: int, e_sigma: float = 1e-3, f_sigma: float =
     return de, df
 
 
-SEEDS = {"data": 1234, "student": 11, "teacher": 22, "noise": 33, "fd": 44}
+def random_labels(batch: Batch, seed: int):
+    """Seeded labels of Sb-Te-like magnitude without a teacher model: total
+    energies -0.35 eV/atom with 0.05 eV/atom spread, force components N(0, 0.5)
+    eV/A, virial components N_n * N(0, 0.05) eV.  Returns float32 arrays
+    (energy [S], force SoA [3N], virial [S*6])."""
+    rng = np.random.default_rng(seed)
+    sizes = np.diff(batch.atom_offset).astype(np.float64)
+    e = sizes * (-0.35 + rng.normal(0.0, 0.05, batch.n_struct))
+    f = rng.normal(0.0, 0.5, 3 * batch.n_atom)
+    w = (sizes[:, None] * rng.normal(0.0, 0.05, (batch.n_struct, 6))).reshape(-1)
+    return e.astype(np.float32), f.astype(np.float32), w.astype(np.float32)
+
+
+SEEDS = {"data": 1234, "student": 11, "teacher": 22, "noise": 33, "fd": 44, "labels": 55}
