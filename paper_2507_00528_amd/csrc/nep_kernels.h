@@ -94,7 +94,6 @@ struct AdjArgs {
   float* beta;        // [H][Npad]
   float* w1s;         // [H][Npad]
   float* part;        // [n_waves][PW] wave partial sums
-  int* wave_species;  // [n_waves]
   int PW;
 };
 

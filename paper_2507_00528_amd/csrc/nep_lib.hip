@@ -28,124 +28,183 @@ __device__ __forceinline__ unsigned axis_candidates(double d0, double L, double 
   return m;
 }
 
-constexpr int kNbrBlk = 256;
+// One atom per group of 8 lanes; lane s scans the s-th contiguous eighth of
+// the atom's structure, so concatenating the lanes' entries in lane order
+// keeps the canonical (j, code) order.  A count pass and an exclusive scan
+// over the group give each lane its write offset; a second pass writes.
+//
+// Fast decision.  When every cell edge is at least 2(rc + delta) and at most
+// kNbrFastL, at most one image of j lies within rc + delta, and the single
+// precision minimum image finds it.  Its squared distance is then within
+// 3e-3 A^2 of the float64 value, far inside the margins of the shell
+// |r - rc| < delta = 0.01 A (at least 0.0199 A^2 for rc >= 1 A), so pairs
+// outside the shell are decided in single precision and only pairs in the
+// shell, and every pair of smaller or larger cells, take the float64 test.
+constexpr int kNbrAPB = 256 / 8;   // atoms per block
+constexpr float kNbrDelta = 0.01f;
+constexpr float kNbrFastL = 512.0f;
 
-__global__ __launch_bounds__(kNbrBlk) void k_neighbors(NbrArgs a) {
-  __shared__ float tx[kNbrBlk], ty[kNbrBlk], tz[kNbrBlk];
-  __shared__ int srange[2];
-  const int b0 = blockIdx.x * kNbrBlk;
-  const int i = b0 + threadIdx.x;
-  const bool live = i < a.N;
-  // structure of this atom (binary search over atom_offset)
-  int s = 0;
-  {
-    const int q = live ? i : a.N - 1;
-    int lo = 0, hi = a.S;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (a.aoff[mid] <= q) lo = mid; else hi = mid;
+struct ScanCtx {
+  int i, N;
+  const float* pos;
+  double xi, yi, zi, Lx, Ly, Lz, rcR, rcR2, rcA2;
+  float xf, yf, zf, Lxf, Lyf, Lzf, ilx, ily, ilz;
+  float inR2, outR2, inA2, outA2;
+  bool fast;
+};
+
+// float64 predicate of Eq. 2 for the pair (i, j) over the candidate shifts;
+// calls emit(j, code, is_angular) in ascending code order
+template <class Emit>
+__device__ __forceinline__ void exact_pair(const ScanCtx& c, int j, Emit& emit) {
+  const double x0 = __dadd_rn((double)c.pos[j], -c.xi);
+  const unsigned mx = axis_candidates(x0, c.Lx, c.rcR);
+  if (!mx) return;
+  const double y0 = __dadd_rn((double)c.pos[c.N + j], -c.yi);
+  const unsigned my = axis_candidates(y0, c.Ly, c.rcR);
+  if (!my) return;
+  const double z0 = __dadd_rn((double)c.pos[2 * c.N + j], -c.zi);
+  const unsigned mz = axis_candidates(z0, c.Lz, c.rcR);
+  if (!mz) return;
+  for (unsigned bx = mx; bx; bx &= bx - 1u) {
+    const int sx = __builtin_ctz(bx);
+    const double dx = sx == 1 ? x0 : __dadd_rn(x0, sx == 0 ? -c.Lx : c.Lx);
+    const double dx2 = __dmul_rn(dx, dx);
+    for (unsigned by = my; by; by &= by - 1u) {
+      const int sy = __builtin_ctz(by);
+      const double dy = sy == 1 ? y0 : __dadd_rn(y0, sy == 0 ? -c.Ly : c.Ly);
+      const double dxy = __dadd_rn(dx2, __dmul_rn(dy, dy));
+      for (unsigned bz = mz; bz; bz &= bz - 1u) {
+        const int sz = __builtin_ctz(bz);
+        const int code = 9 * sx + 3 * sy + sz;
+        const double dz = sz == 1 ? z0 : __dadd_rn(z0, sz == 0 ? -c.Lz : c.Lz);
+        const double d2 = __dadd_rn(dxy, __dmul_rn(dz, dz));
+        if (d2 < c.rcR2 && !(j == c.i && code == 13)) emit(j, code, d2 < c.rcA2);
+      }
     }
-    s = lo;
   }
-  if (threadIdx.x == 0) srange[0] = s;
-  if (threadIdx.x == kNbrBlk - 1 || i == a.N - 1) srange[1] = s;
-  const int a0 = max(a.aoff[s], 0), a1 = min(a.aoff[s + 1], a.N);
-  __syncthreads();
-  const int j_lo = max(a.aoff[srange[0]], 0), j_hi = min(a.aoff[srange[1] + 1], a.N);
+}
 
+template <class Emit>
+__device__ __forceinline__ void scan_range(const ScanCtx& c, int jb, int je, Emit& emit) {
+  for (int j = jb; j < je; ++j) {
+    if (c.fast) {
+      float ex = c.pos[j] - c.xf, ey = c.pos[c.N + j] - c.yf, ez = c.pos[2 * c.N + j] - c.zf;
+      const float kx = rintf(ex * c.ilx), ky = rintf(ey * c.ily), kz = rintf(ez * c.ilz);
+      ex -= c.Lxf * kx;
+      ey -= c.Lyf * ky;
+      ez -= c.Lzf * kz;
+      const float r2 = ex * ex + ey * ey + ez * ez;
+      if (r2 >= c.outR2) continue;
+      if (r2 < c.inR2 && fabsf(kx) <= 1.f && fabsf(ky) <= 1.f && fabsf(kz) <= 1.f) {
+        // shift s = -k on each axis; code 9(sx+1) + 3(sy+1) + (sz+1)
+        const int code = 9 * (1 - (int)kx) + 3 * (1 - (int)ky) + (1 - (int)kz);
+        if (j == c.i && code == 13) continue;
+        bool ang = r2 < c.inA2;
+        if (!ang && r2 < c.outA2) {
+          const double dx = __dadd_rn(__dadd_rn((double)c.pos[j], -c.xi), -(double)kx * c.Lx);
+          const double dy = __dadd_rn(__dadd_rn((double)c.pos[c.N + j], -c.yi), -(double)ky * c.Ly);
+          const double dz = __dadd_rn(__dadd_rn((double)c.pos[2 * c.N + j], -c.zi), -(double)kz * c.Lz);
+          const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+          ang = d2 < c.rcA2;
+        }
+        emit(j, code, ang);
+        continue;
+      }
+    }
+    exact_pair(c, j, emit);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
+  const int s = threadIdx.x & 7;
+  const int i = blockIdx.x * kNbrAPB + (threadIdx.x >> 3);
+  const bool live = i < a.N;
+  ScanCtx c;
+  c.i = live ? i : a.N - 1;
+  c.N = a.N;
+  c.pos = a.pos;
+  int lo = 0, hi = a.S;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (a.aoff[mid] <= c.i) lo = mid; else hi = mid;
+  }
+  const int st = lo;
+  const int a0 = max(a.aoff[st], 0), a1 = min(a.aoff[st + 1], a.N);
+  c.Lxf = a.box[3 * st];
+  c.Lyf = a.box[3 * st + 1];
+  c.Lzf = a.box[3 * st + 2];
+  c.xf = a.pos[c.i];
+  c.yf = a.pos[a.N + c.i];
+  c.zf = a.pos[2 * a.N + c.i];
   int fl = 0;
+  if (!(c.xf >= 0.f && c.xf < c.Lxf && c.yf >= 0.f && c.yf < c.Lyf && c.zf >= 0.f && c.zf < c.Lzf)) fl |= FL_POS;
   bool ok = live;
-  float Lxf = 0.f, Lyf = 0.f, Lzf = 0.f;
-  double xi = 0.0, yi = 0.0, zi = 0.0;
-  if (live) {
-    a.astruct[i] = s;
-    Lxf = a.box[3 * s];
-    Lyf = a.box[3 * s + 1];
-    Lzf = a.box[3 * s + 2];
+  if (!(c.Lxf >= a.rcR && c.Lyf >= a.rcR && c.Lzf >= a.rcR)) {
+    fl |= FL_BOX;
+    ok = false;
+  }
+  if (live && s == 0) {
+    a.astruct[i] = st;
     const int ti = a.type[i];
     if (ti < 0 || ti >= a.T) fl |= FL_TYPE;
-    const float xf = a.pos[i], yf = a.pos[a.N + i], zf = a.pos[2 * a.N + i];
-    if (!(xf >= 0.f && xf < Lxf && yf >= 0.f && yf < Lyf && zf >= 0.f && zf < Lzf)) fl |= FL_POS;
-    if (!(Lxf >= a.rcR && Lyf >= a.rcR && Lzf >= a.rcR)) {
-      fl |= FL_BOX;
-      ok = false;
-    }
-    xi = xf;
-    yi = yf;
-    zi = zf;
   }
-  const double rcR = (double)a.rcR, rcA = (double)a.rcA;
-  const double rcR2 = rcR * rcR, rcA2 = rcA * rcA;  // exact: float squared in double
-  const double Lx = Lxf, Ly = Lyf, Lz = Lzf;
-  const float xif = (float)xi, yif = (float)yi, zif = (float)zi;
-  const float invLx = ok ? 1.0f / Lxf : 0.f, invLy = ok ? 1.0f / Lyf : 0.f, invLz = ok ? 1.0f / Lzf : 0.f;
-  const float rpad2 = (a.rcR + 0.01f) * (a.rcR + 0.01f);
+  c.xi = c.xf;
+  c.yi = c.yf;
+  c.zi = c.zf;
+  c.Lx = c.Lxf;
+  c.Ly = c.Lyf;
+  c.Lz = c.Lzf;
+  c.rcR = (double)a.rcR;
+  c.rcR2 = c.rcR * c.rcR;  // exact: a float squared in double
+  c.rcA2 = (double)a.rcA * (double)a.rcA;
+  c.ilx = 1.0f / c.Lxf;
+  c.ily = 1.0f / c.Lyf;
+  c.ilz = 1.0f / c.Lzf;
+  const float wide = 2.0f * (a.rcR + kNbrDelta);
+  c.fast = c.Lxf >= wide && c.Lyf >= wide && c.Lzf >= wide &&
+           c.Lxf <= kNbrFastL && c.Lyf <= kNbrFastL && c.Lzf <= kNbrFastL && a.rcA >= 1.0f;
+  c.inR2 = (a.rcR - kNbrDelta) * (a.rcR - kNbrDelta);
+  c.outR2 = (a.rcR + kNbrDelta) * (a.rcR + kNbrDelta);
+  c.inA2 = (a.rcA - kNbrDelta) * (a.rcA - kNbrDelta);
+  c.outA2 = (a.rcA + kNbrDelta) * (a.rcA + kNbrDelta);
+  const int len = ok ? a1 - a0 : 0;
+  const int jb = a0 + (len * s) / 8, je = a0 + (len * (s + 1)) / 8;
   int nR = 0, nA = 0;
-  for (int t0 = j_lo; t0 < j_hi; t0 += kNbrBlk) {
-    const int jt = t0 + threadIdx.x;
-    if (jt < j_hi) {
-      tx[threadIdx.x] = a.pos[jt];
-      ty[threadIdx.x] = a.pos[a.N + jt];
-      tz[threadIdx.x] = a.pos[2 * a.N + jt];
+  auto count = [&](int, int, bool ang) {
+    ++nR;
+    nA += ang ? 1 : 0;
+  };
+  scan_range(c, jb, je, count);
+  // inclusive prefix over the 8 lanes of the atom
+  int pR = nR, pA = nA;
+#pragma unroll
+  for (int d = 1; d < 8; d <<= 1) {
+    const int uR = __shfl_up(pR, d, 8), uA = __shfl_up(pA, d, 8);
+    if (s >= d) {
+      pR += uR;
+      pA += uA;
     }
-    __syncthreads();
-    const int jb = ok ? max(a0, t0) : 0, je = ok ? min(a1, t0 + kNbrBlk) : 0;
-    for (int j = jb; j < je; ++j) {
-      const int q = j - t0;
-      // single-precision minimum-image distance with a 0.01 A margin: rounding
-      // here is below 1e-4 A, so rejected j are certainly outside rc
-      {
-        float ex = tx[q] - xif, ey = ty[q] - yif, ez = tz[q] - zif;
-        ex -= Lxf * rintf(ex * invLx);
-        ey -= Lyf * rintf(ey * invLy);
-        ez -= Lzf * rintf(ez * invLz);
-        if (ex * ex + ey * ey + ez * ez >= rpad2) continue;
-      }
-      const double x0 = __dadd_rn((double)tx[q], -xi);
-      const unsigned mx = axis_candidates(x0, Lx, rcR);
-      if (!mx) continue;
-      const double y0 = __dadd_rn((double)ty[q], -yi);
-      const unsigned my = axis_candidates(y0, Ly, rcR);
-      if (!my) continue;
-      const double z0 = __dadd_rn((double)tz[q], -zi);
-      const unsigned mz = axis_candidates(z0, Lz, rcR);
-      if (!mz) continue;
-      // candidate shifts per axis are the set bits of mx, my, mz (one bit
-      // each unless the cell edge is shorter than 2 rc); codes stay ascending
-      for (unsigned bx = mx; bx; bx &= bx - 1u) {
-        const int sx = __builtin_ctz(bx);
-        const double dx = sx == 1 ? x0 : __dadd_rn(x0, sx == 0 ? -Lx : Lx);
-        const double dx2 = __dmul_rn(dx, dx);
-        for (unsigned by = my; by; by &= by - 1u) {
-          const int sy = __builtin_ctz(by);
-          const double dy = sy == 1 ? y0 : __dadd_rn(y0, sy == 0 ? -Ly : Ly);
-          const double dxy = __dadd_rn(dx2, __dmul_rn(dy, dy));
-          for (unsigned bz = mz; bz; bz &= bz - 1u) {
-            const int sz = __builtin_ctz(bz);
-            const int code = 9 * sx + 3 * sy + sz;
-            const double dz = sz == 1 ? z0 : __dadd_rn(z0, sz == 0 ? -Lz : Lz);
-            const double d2 = __dadd_rn(dxy, __dmul_rn(dz, dz));
-            if (d2 < rcR2 && !(j == i && code == 13)) {
-              const uint32_t e = ((uint32_t)j << 5) | (uint32_t)code;
-              if (nR < a.capR) a.idxR[(size_t)nR * a.N + i] = e;
-              ++nR;
-              if (d2 < rcA2) {
-                if (nA < a.capA) a.idxA[(size_t)nA * a.N + i] = e;
-                ++nA;
-              }
-            }
-          }
-        }
-      }
+  }
+  const int totR = __shfl(pR, 7, 8), totA = __shfl(pA, 7, 8);
+  int wR = pR - nR, wA = pA - nA;
+  const size_t col = (size_t)c.i;
+  auto write = [&](int j, int code, bool ang) {
+    const uint32_t e = ((uint32_t)j << 5) | (uint32_t)code;
+    if (wR < a.capR) a.idxR[(size_t)wR * a.N + col] = e;
+    ++wR;
+    if (ang) {
+      if (wA < a.capA) a.idxA[(size_t)wA * a.N + col] = e;
+      ++wA;
     }
-    __syncthreads();
+  };
+  if (live && nR > 0 && wR < a.capR) scan_range(c, jb, je, write);
+  if (live && s == 0) {
+    a.cntR[i] = totR;
+    a.cntA[i] = totA;
+    if (totR > a.capR || totA > a.capA) fl |= FL_OVERFLOW;
   }
-  if (live) {
-    a.cntR[i] = nR;
-    a.cntA[i] = nA;
-    if (nR > a.capR || nA > a.capA) fl |= FL_OVERFLOW;
-    if (fl) atomicOr(a.flags, fl);
-  }
+  if (live && s == 0 && fl) atomicOr(a.flags, fl);
 }
 
 // Position of the reverse entry (i, -s) in j's list, by binary search over
@@ -168,60 +227,121 @@ __global__ __launch_bounds__(256) void k_reverse(int N, const uint32_t* __restri
 }
 
 // ============================================================ species order
+// Atoms are laid out by (species, angular neighbor count descending), with
+// ties in atom order: every wavefront then holds one species and atoms of
+// similar pair counts, so the pair loops of its 8 atoms end together.  The
+// key of atom i is t * kOrdBuckets + (kOrdBuckets - 1 - min(nA_i, kOrdBuckets - 1)),
+// and a counting sort over keys keeps the layout deterministic.
 constexpr int kOrdBlk = 1024;
+constexpr int kOrdBuckets = 64;
 constexpr int kSegAlign = 8;   // species segments start on multiples of the atoms per wavefront
 
+__device__ __forceinline__ int order_key(int t, int T, int nA) {
+  if (t < 0 || t >= T) return -1;
+  return t * kOrdBuckets + (kOrdBuckets - 1 - min(max(nA, 0), kOrdBuckets - 1));
+}
+
 __global__ __launch_bounds__(kOrdBlk) void k_order_count(int N, int Npad, int T, const int* __restrict__ type,
-                                                         int* __restrict__ blkcnt, int* __restrict__ order) {
+                                                         const int* __restrict__ cntA, int* __restrict__ blkcnt,
+                                                         int* __restrict__ order) {
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < Npad; q += gridDim.x * blockDim.x) order[q] = -1;
-  __shared__ int cnt[8];
-  if (threadIdx.x < T) cnt[threadIdx.x] = 0;
+  const int K = T * kOrdBuckets;
+  __shared__ int cnt[8 * kOrdBuckets];
+  for (int q = threadIdx.x; q < K; q += blockDim.x) cnt[q] = 0;
   __syncthreads();
   const int i = blockIdx.x * kOrdBlk + threadIdx.x;
   if (i < N) {
-    const int t = type[i];
-    if (t >= 0 && t < T) atomicAdd(&cnt[t], 1);
+    const int key = order_key(type[i], T, cntA[i]);
+    if (key >= 0) atomicAdd(&cnt[key], 1);
   }
   __syncthreads();
-  if (threadIdx.x < T) blkcnt[blockIdx.x * T + threadIdx.x] = cnt[threadIdx.x];
+  for (int q = threadIdx.x; q < K; q += blockDim.x) blkcnt[(size_t)blockIdx.x * K + q] = cnt[q];
 }
 
-// Exclusive scan of the per-block counts; species segments start on
-// multiples of 8 atoms so that no wavefront mixes species.  seg[2t], seg[2t+1] =
-// start and count of species t.
-__global__ void k_order_scan(int nblk, int T, int* __restrict__ blk, int* __restrict__ seg) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int start = 0;
-  for (int t = 0; t < T; ++t) {
-    int run = start;
-    for (int b = 0; b < nblk; ++b) {
-      const int c = blk[b * T + t];
-      blk[b * T + t] = run;
-      run += c;
+// One block, one thread per key: key totals, their exclusive scan in key
+// order with each species segment starting on a multiple of 8 atoms, then
+// the per-block offsets.  seg[2t], seg[2t+1] = start and count of species t.
+__global__ __launch_bounds__(8 * kOrdBuckets) void k_order_scan(int nblk, int T, int* __restrict__ blk,
+                                                               int* __restrict__ seg) {
+  const int K = T * kOrdBuckets;
+  const int k = threadIdx.x;
+  __shared__ int sc[8 * kOrdBuckets];
+  __shared__ int sstart[9];
+  int tot = 0;
+  if (k < K)
+    for (int b0 = 0; b0 < nblk; b0 += 8) {
+      int v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = b0 + u < nblk ? blk[(size_t)(b0 + u) * K + k] : 0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) tot += v[u];
     }
-    seg[2 * t] = start;
-    seg[2 * t + 1] = run - start;
-    start += ((run - start) + kSegAlign - 1) / kSegAlign * kSegAlign;
+  sc[k] = k < K ? tot : 0;
+  __syncthreads();
+  // inclusive scan (Hillis-Steele)
+  for (int d = 1; d < 8 * kOrdBuckets; d <<= 1) {
+    const int v = k >= d ? sc[k - d] : 0;
+    __syncthreads();
+    sc[k] += v;
+    __syncthreads();
+  }
+  if (k == 0) {
+    int start = 0;
+    for (int t = 0; t < T; ++t) {
+      const int lo = t == 0 ? 0 : sc[t * kOrdBuckets - 1];
+      const int cnt = sc[(t + 1) * kOrdBuckets - 1] - lo;
+      sstart[t] = start - lo;   // aligned start minus the unaligned prefix
+      seg[2 * t] = start;
+      seg[2 * t + 1] = cnt;
+      start += (cnt + kSegAlign - 1) / kSegAlign * kSegAlign;
+    }
+  }
+  __syncthreads();
+  if (k < K) {
+    int off = sstart[k / kOrdBuckets] + sc[k] - tot;
+    for (int b0 = 0; b0 < nblk; b0 += 8) {
+      int v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = b0 + u < nblk ? blk[(size_t)(b0 + u) * K + k] : 0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (b0 + u < nblk) blk[(size_t)(b0 + u) * K + k] = off;
+        off += v[u];
+      }
+    }
   }
 }
 
+// Rank of each atom among the atoms of its key: lanes before it in its
+// wavefront (one ballot per distinct key in the wavefront), then the
+// wavefronts before it in the block.
 __global__ __launch_bounds__(kOrdBlk) void k_order_scatter(int N, int T, const int* __restrict__ type,
+                                                           const int* __restrict__ cntA,
                                                            const int* __restrict__ blkoff, int* __restrict__ order) {
-  __shared__ int wcnt[kOrdBlk / kWave][8];
+  constexpr int NW = kOrdBlk / kWave;
+  __shared__ int wcnt[NW][8 * kOrdBuckets];
+  const int K = T * kOrdBuckets;
   const int i = blockIdx.x * kOrdBlk + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  const int t = i < N ? type[i] : -1;
+  for (int q = threadIdx.x; q < NW * 8 * kOrdBuckets; q += blockDim.x) (&wcnt[0][0])[q] = 0;
+  __syncthreads();
+  const int key = i < N ? order_key(type[i], T, cntA[i]) : -1;
+  const unsigned long long below = (1ull << lane) - 1ull;
   int rank = 0;
-  for (int tt = 0; tt < T; ++tt) {
-    const unsigned long long m = __ballot(t == tt);
-    if (t == tt) rank = __popcll(m & ((1ull << lane) - 1ull));
-    if (lane == 0) wcnt[wid][tt] = __popcll(m);
+  unsigned long long rem = __ballot(key >= 0);
+  while (rem) {
+    const int leader = __ffsll(rem) - 1;
+    const int kk = __shfl(key, leader, kWave);
+    const unsigned long long m = __ballot(key == kk);
+    if (key == kk) rank = __popcll(m & below);
+    if (lane == leader) wcnt[wid][kk] = __popcll(m);
+    rem &= ~m;
   }
   __syncthreads();
-  if (i < N && t >= 0 && t < T) {
+  if (key >= 0) {
     int before = 0;
-    for (int w = 0; w < wid; ++w) before += wcnt[w][t];
-    order[blkoff[blockIdx.x * T + t] + before + rank] = i;
+    for (int w = 0; w < wid; ++w) before += wcnt[w][key];
+    order[blkoff[(size_t)blockIdx.x * K + key] + before + rank] = i;
   }
 }
 
@@ -921,8 +1041,6 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs a) {
   const int N = a.N, i = w.i, I = w.I, pa = w.pa, s = w.s, g = w.g;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const bool wave_any = __ballot(w.valid) != 0ull;
-  if (lane == 0 && wave < a.Npad / kAPW) a.wave_species[wave] = wave_any ? I : -1;
   const bool first_atom = (lane >> 3) == 0;   // atom slot 0 of the wavefront writes the sums
   float* part = a.part + (size_t)wave * a.PW;
   float* row = rows + w.al * RW;
@@ -1201,6 +1319,9 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs a) {
 #pragma unroll
       for (int k = 0; k < KA; ++k) cb[t][j][k] = 0.f;
   for (int k = w.p; k < nA; k += 4) {
+    // reload Sbar and A from LDS every pair: hoisted out of the loop they
+    // would take 2 NAH Y registers and halve the occupancy
+    asm volatile("" ::: "memory");
     const PairGeom q = pair_geom(a.nb.idxA[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
     const float ux = q.dx * q.inv_r, uy = q.dy * q.inv_r, uz = q.dz * q.inv_r;
     const float tx = (a.fbar[q.j] - fbx) + gxx * q.dx + gxy * q.dy;
@@ -1252,11 +1373,20 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs a) {
 
 // Sums over the atoms of each species of an outer product,
 //   out[I][b][m][v] = sum_p A1[m][p] B1[v][p] - A2[m][p] B2[v][p],
-// for block b of species I's atoms (species order).  Used for
+// over block b's share of species I's atoms (species order).  Used for
 // dL/dW0 = sum beta G^T - (w1 sigma) Gdot^T and for
-// dL/dc^R = sum Gbar_n F[J][k] - E'_n Fp[J][k].  4 x 4 register tiles per
-// thread over (m, v), atom tiles staged in LDS.
-constexpr int kOSAtoms = 64;
+// dL/dc^R = sum Gbar_n F[J][k] - E'_n Fp[J][k].
+// This is a product contracted over atoms, so it runs on the fp32 matrix
+// cores: v_mfma_f32_16x16x4f32 takes a 16 x 4 slice of A (lane l: row l % 16,
+// atom slot l / 16) and a 4 x 16 slice of B, and accumulates a 16 x 16 tile
+// of which lane l holds rows 4 (l / 16) + r, column l % 16.  Each lane loads
+// float4 runs of 4 consecutive atoms and feeds component j to the j-th of 4
+// MFMAs, so atom slot l / 16 of MFMA j is atom 4 (l / 16) + j of the 16-atom
+// group.  A block covers a 4 x 3 grid of 16 x 16 output tiles (blockIdx.z
+// picks the grid cell for larger products); its 4 wavefronts take
+// consecutive 16-atom groups and are summed through LDS at the end.
+constexpr int kOSBlocks = 128;   // blocks per species
+constexpr int kOSTM = 4, kOSTV = 3;
 
 struct OuterArgs {
   int Npad, M, V, NB;
@@ -1268,128 +1398,198 @@ struct OuterArgs {
   float* out;
 };
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 ld_atoms4(const float* row, int p, int p1) {
+  // atoms p .. p + 3 of a row (p a multiple of 4, row padded to 32 atoms); zero past p1
+  const float4 v = *reinterpret_cast<const float4*>(row + p);
+  f32x4 r;
+  r[0] = p < p1 ? v.x : 0.f;
+  r[1] = p + 1 < p1 ? v.y : 0.f;
+  r[2] = p + 2 < p1 ? v.z : 0.f;
+  r[3] = p + 3 < p1 ? v.w : 0.f;
+  return r;
+}
+
 __global__ __launch_bounds__(256) void k_outer_sum(OuterArgs o) {
-  extern __shared__ float lds[];
-  const int MP = (o.M + 3) & ~3, VP = (o.V + 3) & ~3;
-  float* al = lds;                        // [kOSAtoms][MP]
-  float* sl = al + kOSAtoms * MP;         // [kOSAtoms][MP]
-  float* bl = sl + kOSAtoms * MP;         // [kOSAtoms][VP]
-  float* dl = bl + kOSAtoms * VP;         // [kOSAtoms][VP]
+  __shared__ f32x4 red[3][kOSTM * kOSTV][kWave];
   const int I = blockIdx.y, b = blockIdx.x;
+  const int nzv = (o.V + 16 * kOSTV - 1) / (16 * kOSTV);
+  const int mz = blockIdx.z / nzv, vz = blockIdx.z % nzv;
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const int start = o.seg[2 * I], count = o.seg[2 * I + 1];
-  const int chunk = (count + o.NB - 1) / o.NB;
-  const int p0 = start + b * chunk;
-  const int p1 = min(start + count, p0 + chunk);
-  const int ntv = VP / 4, ntile = (MP / 4) * ntv;
-  constexpr int kMaxTiles = 4;
-  float acc[kMaxTiles][4][4];
+  const int per = ((count + o.NB - 1) / o.NB + 15) & ~15;   // multiple of 16 atoms
+  const int p0 = start + b * per;
+  const int p1 = min(start + count, p0 + per);
+  const int row = lane & 15, slot = lane >> 4;
+  const float* a1[kOSTM];
+  const float* a2[kOSTM];
+  const float* b1[kOSTV];
+  const float* b2[kOSTV];
+  bool am[kOSTM], bm[kOSTV];
 #pragma unroll
-  for (int u = 0; u < kMaxTiles; ++u)
+  for (int t = 0; t < kOSTM; ++t) {
+    const int m = (mz * kOSTM + t) * 16 + row;
+    am[t] = m < o.M;
+    a1[t] = o.A1 + (size_t)(am[t] ? m : 0) * o.Npad;
+    a2[t] = o.A2 + (size_t)(am[t] ? m : 0) * o.Npad;
+  }
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+  for (int t = 0; t < kOSTV; ++t) {
+    const int v = (vz * kOSTV + t) * 16 + row;
+    bm[t] = v < o.V;
+    b1[t] = o.B1 + (size_t)(bm[t] ? v : 0) * o.Npad;
+    b2[t] = o.B2 + (size_t)(bm[t] ? v : 0) * o.Npad;
+  }
+  // tiles with no row or no column inside the product are skipped (uniform)
+  const int tm_live = min(kOSTM, (o.M - mz * kOSTM * 16 + 15) / 16);
+  const int tv_live = min(kOSTV, (o.V - vz * kOSTV * 16 + 15) / 16);
+  f32x4 acc[kOSTM][kOSTV];
 #pragma unroll
-      for (int y = 0; y < 4; ++y) acc[u][x][y] = 0.f;
-  for (int base = p0; base < p1; base += kOSAtoms) {
-    const int na = min(kOSAtoms, p1 - base);
-    for (int q = threadIdx.x; q < kOSAtoms * MP; q += blockDim.x) {
-      const int m = q / kOSAtoms, at = q % kOSAtoms;
-      const bool ok = m < o.M && at < na;
-      al[at * MP + m] = ok ? o.A1[(size_t)m * o.Npad + base + at] : 0.f;
-      sl[at * MP + m] = ok ? o.A2[(size_t)m * o.Npad + base + at] : 0.f;
+  for (int x = 0; x < kOSTM; ++x)
+#pragma unroll
+    for (int y = 0; y < kOSTV; ++y) acc[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int g = p0 + 16 * wv; g < p1; g += 64) {
+    const int p = g + 4 * slot;
+    f32x4 va1[kOSTM], va2[kOSTM], vb1[kOSTV], vb2[kOSTV];
+#pragma unroll
+    for (int t = 0; t < kOSTM; ++t) {
+      va1[t] = am[t] ? ld_atoms4(a1[t], p, p1) : f32x4{0.f, 0.f, 0.f, 0.f};
+      va2[t] = am[t] ? -ld_atoms4(a2[t], p, p1) : f32x4{0.f, 0.f, 0.f, 0.f};
     }
-    for (int q = threadIdx.x; q < kOSAtoms * VP; q += blockDim.x) {
-      const int v = q / kOSAtoms, at = q % kOSAtoms;
-      const bool ok = v < o.V && at < na;
-      bl[at * VP + v] = ok ? o.B1[(size_t)v * o.Npad + base + at] : 0.f;
-      dl[at * VP + v] = ok ? o.B2[(size_t)v * o.Npad + base + at] : 0.f;
+#pragma unroll
+    for (int t = 0; t < kOSTV; ++t) {
+      vb1[t] = bm[t] ? ld_atoms4(b1[t], p, p1) : f32x4{0.f, 0.f, 0.f, 0.f};
+      vb2[t] = bm[t] ? ld_atoms4(b2[t], p, p1) : f32x4{0.f, 0.f, 0.f, 0.f};
     }
-    __syncthreads();
 #pragma unroll
-    for (int u = 0; u < kMaxTiles; ++u) {
-      const int tile = threadIdx.x + u * blockDim.x;
-      if (tile >= ntile) break;
-      const int m0 = (tile / ntv) * 4, v0 = (tile % ntv) * 4;
-      for (int at = 0; at < na; ++at) {
-        const float4 aa = *reinterpret_cast<const float4*>(al + at * MP + m0);
-        const float4 ss = *reinterpret_cast<const float4*>(sl + at * MP + m0);
-        const float4 bb = *reinterpret_cast<const float4*>(bl + at * VP + v0);
-        const float4 dd = *reinterpret_cast<const float4*>(dl + at * VP + v0);
-        const float av[4] = {aa.x, aa.y, aa.z, aa.w}, sv[4] = {ss.x, ss.y, ss.z, ss.w};
-        const float bv[4] = {bb.x, bb.y, bb.z, bb.w}, dv[4] = {dd.x, dd.y, dd.z, dd.w};
+    for (int x = 0; x < kOSTM; ++x) {
+      if (x >= tm_live) break;
 #pragma unroll
-        for (int x = 0; x < 4; ++x)
+      for (int y = 0; y < kOSTV; ++y) {
+        if (y >= tv_live) break;
 #pragma unroll
-          for (int y = 0; y < 4; ++y) acc[u][x][y] = fmaf(av[x], bv[y], fmaf(-sv[x], dv[y], acc[u][x][y]));
+        for (int j = 0; j < 4; ++j) {
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(va1[x][j], vb1[y][j], acc[x][y], 0, 0, 0);
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(va2[x][j], vb2[y][j], acc[x][y], 0, 0, 0);
+        }
       }
     }
-    __syncthreads();
   }
+  if (wv > 0) {
+#pragma unroll
+    for (int x = 0; x < kOSTM; ++x)
+#pragma unroll
+      for (int y = 0; y < kOSTV; ++y) red[wv - 1][x * kOSTV + y][lane] = acc[x][y];
+  }
+  __syncthreads();
+  if (wv != 0) return;
   float* out = o.out + ((size_t)I * o.NB + b) * o.M * o.V;
 #pragma unroll
-  for (int u = 0; u < kMaxTiles; ++u) {
-    const int tile = threadIdx.x + u * blockDim.x;
-    if (tile >= ntile) break;
-    const int m0 = (tile / ntv) * 4, v0 = (tile % ntv) * 4;
-    for (int x = 0; x < 4; ++x)
-      for (int y = 0; y < 4; ++y)
-        if (m0 + x < o.M && v0 + y < o.V) out[(m0 + x) * o.V + v0 + y] = acc[u][x][y];
+  for (int x = 0; x < kOSTM; ++x)
+#pragma unroll
+    for (int y = 0; y < kOSTV; ++y) {
+      f32x4 s4 = acc[x][y];
+#pragma unroll
+      for (int w = 0; w < 3; ++w) s4 += red[w][x * kOSTV + y][lane];
+      const int v = (vz * kOSTV + y) * 16 + row;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = (mz * kOSTM + x) * 16 + 4 * slot + r;
+        if (m < o.M && v < o.V) out[m * o.V + v] = s4[r];
+      }
+    }
+}
+
+dim3 outer_grid(int M, int V, int T) {
+  const int nzm = (M + 16 * kOSTM - 1) / (16 * kOSTM), nzv = (V + 16 * kOSTV - 1) / (16 * kOSTV);
+  return dim3(kOSBlocks, T, nzm * nzv);
+}
+
+// First stage of the final reduction for the wavefront partials (c^A, b0,
+// w1, b1): block (b, I) sums, in float64 and in wave order, chunk b of the
+// wavefronts of species I; one thread per slot, so reads run along rows.
+constexpr int kPRChunks = 128;
+
+__global__ __launch_bounds__(256) void k_part_reduce(int PW, const int* seg, const float* part, double* pp) {
+  const int I = blockIdx.y, b = blockIdx.x;
+  const int start = seg[2 * I], count = seg[2 * I + 1];
+  const int w0 = start / kAPW, w1 = count > 0 ? (start + count + kAPW - 1) / kAPW : w0;
+  const int per = (w1 - w0 + kPRChunks - 1) / kPRChunks;
+  const int r0 = w0 + b * per, r1 = min(w1, r0 + per);
+  for (int slot = threadIdx.x; slot < PW; slot += blockDim.x) {
+    double sum = 0.0;
+    int r = r0;
+    for (; r + 4 <= r1; r += 4) {
+      float v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = part[(size_t)(r + u) * PW + slot];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sum += (double)v[u];
+    }
+    for (; r < r1; ++r) sum += (double)part[(size_t)r * PW + slot];
+    pp[((size_t)I * kPRChunks + b) * PW + slot] = sum;
   }
 }
 
-// Final gradient: float64 sums in a fixed order.  Blocks [0, T*PW) each
-// reduce one (species, slot) column of the wavefront partials (c^A, b0, w1,
-// b1); the remaining threads sum the outer-product block partials of W0 and
-// c^R.
+// Final gradient: 16 lanes per parameter; lane l sums rows l, l + 16, ... of
+// that parameter's partials in float64, then a fixed xor tree adds the 16
+// lane sums.  Parameter layout: c^R [T][T][NR][KR], c^A [T][T][NA][KA], then
+// per species W0 [H][D], b0 [H], w1 [H], b1.
 struct GradArgs {
-  int T, NR, NA, KR, KA, H, D, nwaves, PW, NB;
-  const float* part;
-  const int* wspecies;
-  const float* w0part;
-  const float* crpart;
+  int T, NR, NA, KR, KA, H, D, PW, NB;
+  int64_t P;
+  const double* pp;      // [T][kPRChunks][PW]
+  const float* w0part;   // [T][NB][H*D]
+  const float* crpart;   // [T][NB][NR*T*KR]
   float* grad;
 };
 
 __global__ __launch_bounds__(256) void k_grad_final(GradArgs a) {
-  __shared__ double red[256];
+  const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const int l = threadIdx.x & 15;
   const int P_R = a.T * a.T * a.NR * a.KR, P_A = a.T * a.T * a.NA * a.KA;
   const int blk = a.H * a.D + 2 * a.H + 1;
   const int PSA = a.T * a.NA * a.KA;
-  const int ncol = a.T * a.PW;
-  if ((int)blockIdx.x < ncol) {
-    const int I = blockIdx.x / a.PW, slot = blockIdx.x % a.PW;
-    double sum = 0.0;
-    for (int w = threadIdx.x; w < a.nwaves; w += blockDim.x)
-      if (a.wspecies[w] == I) sum += a.part[(size_t)w * a.PW + slot];
-    red[threadIdx.x] = sum;
-    __syncthreads();
-    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-      if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-      __syncthreads();
+  const int HD = a.H * a.D, CR = a.NR * a.T * a.KR;
+  double sum = 0.0;
+  if (q < a.P) {
+    const int qi = (int)q;
+    const float* fsrc = nullptr;
+    const double* dsrc = nullptr;
+    int stride = 0, rows = 0;
+    if (qi < P_R) {
+      const int I = qi / (a.T * a.NR * a.KR), rem = qi % (a.T * a.NR * a.KR);
+      const int t = rem / (a.NR * a.KR), n = (rem / a.KR) % a.NR, k = rem % a.KR;
+      fsrc = a.crpart + (size_t)I * a.NB * CR + n * (a.T * a.KR) + t * a.KR + k;
+      stride = CR;
+      rows = a.NB;
+    } else if (qi < P_R + P_A) {
+      const int I = (qi - P_R) / PSA, slot = (qi - P_R) % PSA;
+      dsrc = a.pp + (size_t)I * kPRChunks * a.PW + slot;
+      stride = a.PW;
+      rows = kPRChunks;
+    } else {
+      const int I = (qi - P_R - P_A) / blk, o = (qi - P_R - P_A) % blk;
+      if (o < HD) {
+        fsrc = a.w0part + (size_t)I * a.NB * HD + o;
+        stride = HD;
+        rows = a.NB;
+      } else {
+        dsrc = a.pp + (size_t)I * kPRChunks * a.PW + PSA + (o - HD);
+        stride = a.PW;
+        rows = kPRChunks;
+      }
     }
-    if (threadIdx.x != 0) return;
-    const int q = slot < PSA ? P_R + I * PSA + slot                   // c^A[I][J][n][k]
-                             : P_R + P_A + I * blk + a.H * a.D + (slot - PSA);  // b0, w1, b1
-    a.grad[q] = (float)red[0];
-    return;
+    if (fsrc) {
+      for (int r = l; r < rows; r += 16) sum += (double)fsrc[(size_t)r * stride];
+    } else {
+      for (int r = l; r < rows; r += 16) sum += dsrc[(size_t)r * stride];
+    }
   }
-  int q = (blockIdx.x - ncol) * blockDim.x + threadIdx.x;
-  const int nW = a.T * a.H * a.D;
-  if (q < nW) {
-    const int I = q / (a.H * a.D), o = q % (a.H * a.D);
-    double sum = 0.0;
-    for (int b = 0; b < a.NB; ++b) sum += a.w0part[((size_t)I * a.NB + b) * a.H * a.D + o];
-    a.grad[P_R + P_A + I * blk + o] = (float)sum;
-    return;
-  }
-  q -= nW;
-  const int VR = a.T * a.KR, MR = a.NR;
-  if (q < a.T * MR * VR) {
-    const int I = q / (MR * VR), o = q % (MR * VR);
-    const int n = o / VR, t = (o % VR) / a.KR, k = o % a.KR;
-    double sum = 0.0;
-    for (int b = 0; b < a.NB; ++b) sum += a.crpart[((size_t)I * a.NB + b) * MR * VR + o];
-    a.grad[((I * a.T + t) * a.NR + n) * a.KR + k] = (float)sum;
-  }
+#pragma unroll
+  for (int d = 8; d >= 1; d >>= 1) sum += __shfl_xor(sum, d, 16);
+  if (q < a.P && l == 0) a.grad[q] = (float)sum;
 }
 
 // ==================================================================== Adam
@@ -1527,12 +1727,10 @@ int64_t param_count(const nep_model* m) {
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
-constexpr int kOSBlocks = 256;   // outer-sum blocks per species
-
 struct Layout {
   int N, S, T, D, Y, H, NR, TKR, Npad, nwaves, nblk, PW, NA, capR, capA;
   size_t order, seg, blk, astruct, revR, revA, G, Sst, Ep, X, eatom, fR, fA, wv, F, fbar, Es, Ws, eps, wbar, lpart,
-      Gd, FRst, FPst, Gbr, beta, w1s, part, wsp, w0part, crpart, total;
+      Gd, FRst, FPst, Gbr, beta, w1s, part, pp, w0part, crpart, total;
 };
 
 Layout make_layout(const nep_model* m, const Ops* o, int S, int N) {
@@ -1548,7 +1746,9 @@ Layout make_layout(const nep_model* m, const Ops* o, int S, int N) {
   L.TKR = m->n_types * m->k_rad;
   L.capR = m->cap_rad;
   L.capA = m->cap_ang;
-  const int n8 = ((N + kSegAlign - 1) / kSegAlign) * kSegAlign + L.T * kSegAlign;
+  // species segments (each rounded up to 8 atoms) plus 16 atoms of slack for
+  // the 16-atom groups of the outer-product sums
+  const int n8 = ((N + kSegAlign - 1) / kSegAlign) * kSegAlign + L.T * kSegAlign + 16;
   L.Npad = ((n8 + kAPB - 1) / kAPB) * kAPB;
   L.nwaves = L.Npad / kAPW;
   L.nblk = N > 0 ? (N + kOrdBlk - 1) / kOrdBlk : 1;
@@ -1562,7 +1762,7 @@ Layout make_layout(const nep_model* m, const Ops* o, int S, int N) {
   };
   L.order = take(4 * Np);
   L.seg = take(4 * 2 * 8);
-  L.blk = take(4 * (size_t)L.nblk * L.T);
+  L.blk = take(4 * (size_t)L.nblk * L.T * kOrdBuckets);
   L.astruct = take(4 * Nn);
   L.revR = take(4 * (size_t)L.capR * Nn);
   L.revA = take(4 * (size_t)L.capA * Nn);
@@ -1588,7 +1788,7 @@ Layout make_layout(const nep_model* m, const Ops* o, int S, int N) {
   L.beta = take(4 * (size_t)L.H * Np);
   L.w1s = take(4 * (size_t)L.H * Np);
   L.part = take(4 * (size_t)L.nwaves * L.PW);
-  L.wsp = take(4 * (size_t)L.nwaves);
+  L.pp = take(8 * (size_t)L.T * kPRChunks * L.PW);
   L.w0part = take(4 * (size_t)L.T * kOSBlocks * L.H * L.D);
   L.crpart = take(4 * (size_t)L.T * kOSBlocks * L.NR * L.TKR);
   L.total = off;
@@ -1690,7 +1890,7 @@ void run_neighbors(const Ctx& c, nep_neighbors* nb, int32_t* flags, Prof* pr) {
   a.cntA = nb->cnt_ang;
   a.astruct = at<int>(c.ws, c.L.astruct);
   a.flags = flags;
-  NEP_LAUNCH(pr, "neighbors", hipLaunchKernelGGL(k_neighbors, dim3(grid1(N, kNbrBlk)), dim3(kNbrBlk), 0, c.st, a));
+  NEP_LAUNCH(pr, "neighbors", hipLaunchKernelGGL(k_neighbors, dim3(grid1(N, kNbrAPB)), dim3(256), 0, c.st, a));
   NEP_LAUNCH(pr, "reverse_rad",
              hipLaunchKernelGGL(k_reverse, dim3(grid1(N), c.m->cap_rad), dim3(256), 0, c.st, N, nb->idx_rad,
                                 nb->cnt_rad, c.m->cap_rad, at<int>(c.ws, c.L.revR)));
@@ -1702,11 +1902,12 @@ void run_neighbors(const Ctx& c, nep_neighbors* nb, int32_t* flags, Prof* pr) {
   int* seg = at<int>(c.ws, c.L.seg);
   NEP_LAUNCH(pr, "order_count",
              hipLaunchKernelGGL(k_order_count, dim3(c.L.nblk), dim3(kOrdBlk), 0, c.st, N, c.L.Npad, c.L.T, c.b->type,
-                                blk, order));
-  NEP_LAUNCH(pr, "order_scan", hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, c.st, c.L.nblk, c.L.T, blk, seg));
+                                nb->cnt_ang, blk, order));
+  NEP_LAUNCH(pr, "order_scan",
+             hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(8 * kOrdBuckets), 0, c.st, c.L.nblk, c.L.T, blk, seg));
   NEP_LAUNCH(pr, "order_scatter",
-             hipLaunchKernelGGL(k_order_scatter, dim3(c.L.nblk), dim3(kOrdBlk), 0, c.st, N, c.L.T, c.b->type, blk,
-                                order));
+             hipLaunchKernelGGL(k_order_scatter, dim3(c.L.nblk), dim3(kOrdBlk), 0, c.st, N, c.L.T, c.b->type,
+                                nb->cnt_ang, blk, order));
 }
 
 FwdArgs fwd_args(const Ctx& c, const nep_neighbors* nb, const float* params) {
@@ -1823,24 +2024,24 @@ void run_adjoint(const Ctx& c, const nep_neighbors* nb, const float* params, con
     a.beta = at<float>(c.ws, c.L.beta);
     a.w1s = at<float>(c.ws, c.L.w1s);
     a.part = at<float>(c.ws, c.L.part);
-    a.wave_species = at<int>(c.ws, c.L.wsp);
     a.PW = c.L.PW;
     NEP_LAUNCH(pr, "adjoint", c.o->adjoint(a, dim3(c.L.Npad / kAPB), c.st));
     const int* seg = at<int>(c.ws, c.L.seg);
     {
       OuterArgs o{c.L.Npad, m->hidden, c.o->D, kOSBlocks, seg, a.beta, at<float>(c.ws, c.L.G), a.w1s, a.Gd,
                   at<float>(c.ws, c.L.w0part)};
-      const size_t lds = sizeof(float) * kOSAtoms * 2 * (((o.M + 3) & ~3) + ((o.V + 3) & ~3));
       NEP_LAUNCH(pr, "w0_grad",
-                 hipLaunchKernelGGL(k_outer_sum, dim3(kOSBlocks, T), dim3(256), lds, c.st, o));
+                 hipLaunchKernelGGL(k_outer_sum, outer_grid(o.M, o.V, T), dim3(256), 0, c.st, o));
     }
     {
       OuterArgs o{c.L.Npad, m->n_rad, c.L.TKR, kOSBlocks, seg, a.Gbr, a.FRst, at<float>(c.ws, c.L.Ep), a.FPst,
                   at<float>(c.ws, c.L.crpart)};
-      const size_t lds = sizeof(float) * kOSAtoms * 2 * (((o.M + 3) & ~3) + ((o.V + 3) & ~3));
       NEP_LAUNCH(pr, "crad_grad",
-                 hipLaunchKernelGGL(k_outer_sum, dim3(kOSBlocks, T), dim3(256), lds, c.st, o));
+                 hipLaunchKernelGGL(k_outer_sum, outer_grid(o.M, o.V, T), dim3(256), 0, c.st, o));
     }
+    double* pp = at<double>(c.ws, c.L.pp);
+    NEP_LAUNCH(pr, "part_reduce",
+               hipLaunchKernelGGL(k_part_reduce, dim3(kPRChunks, T), dim3(256), 0, c.st, c.L.PW, seg, a.part, pp));
     GradArgs g;
     g.T = T;
     g.NR = m->n_rad;
@@ -1849,15 +2050,14 @@ void run_adjoint(const Ctx& c, const nep_neighbors* nb, const float* params, con
     g.KA = m->k_ang;
     g.H = m->hidden;
     g.D = c.o->D;
-    g.nwaves = c.L.nwaves;
     g.PW = c.L.PW;
     g.NB = kOSBlocks;
-    g.part = a.part;
-    g.wspecies = a.wave_species;
+    g.P = param_count(m);
+    g.pp = pp;
     g.w0part = at<float>(c.ws, c.L.w0part);
     g.crpart = at<float>(c.ws, c.L.crpart);
     g.grad = grad;
-    const int nblk_gf = T * c.L.PW + grid1(T * m->hidden * c.o->D + T * m->n_rad * c.L.TKR);
+    const unsigned nblk_gf = (unsigned)((g.P * 16 + 255) / 256);
     NEP_LAUNCH(pr, "grad_final", hipLaunchKernelGGL(k_grad_final, dim3(nblk_gf), dim3(256), 0, c.st, g));
   } else {
     const int64_t P = param_count(m);
@@ -1870,7 +2070,6 @@ int setup(Ctx& c, const nep_model* m, const nep_batch* b, void* ws, void* stream
   if (rc) return rc;
   c.o = find_ops(m);
   if (!c.o) return NEP_ERR_ARG;
-  if (((m->hidden + 3) / 4) * ((c.o->D + 3) / 4) > 4 * 256) return NEP_ERR_ARG;  // W0 tiles per block
   if (c.o->lds_adj(m->hidden) > 64 * 1024 || c.o->lds_fwd(m->hidden) > 64 * 1024) return NEP_ERR_ARG;
   if ((rc = check_batch(b))) return rc;
   if ((rc = check_ws(ws))) return rc;
