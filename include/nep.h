@@ -89,7 +89,8 @@ typedef struct {
 } nep_batch;
 
 /* Neighbor lists (Eq. 2), one for rc_rad and one for rc_ang (device).
- *   idx_*  [cap*n_atom] uint32, entry k of atom i at [k*n_atom + i]:
+ *   idx_*  [n_atom*cap] uint32, entry k of atom i at [i*cap + k] (each atom's
+ *          list contiguous):
  *          (j << 5) | code, j the global atom index (< 2^27) and
  *          code = 9(sx+1) + 3(sy+1) + (sz+1) for the image shift s in {-1,0,1}^3
  *   cnt_*  [n_atom] int32, number of neighbors (may exceed cap: overflow)

@@ -40,30 +40,42 @@ __device__ __forceinline__ unsigned axis_candidates(double d0, double L, double 
 // |r - rc| < delta = 0.01 A (at least 0.0199 A^2 for rc >= 1 A), so pairs
 // outside the shell are decided in single precision and only pairs in the
 // shell, and every pair of smaller or larger cells, take the float64 test.
+//
+// Positions of the atoms j that a block's 32 atoms scan are staged in LDS in
+// tiles of kNbrTile atoms; every lane of the block walks the same tiles.
 constexpr int kNbrAPB = 256 / 8;   // atoms per block
+constexpr int kNbrTile = 1024;
 constexpr float kNbrDelta = 0.01f;
 constexpr float kNbrFastL = 512.0f;
 
 struct ScanCtx {
-  int i, N;
-  const float* pos;
+  int i;
   double xi, yi, zi, Lx, Ly, Lz, rcR, rcR2, rcA2;
   float xf, yf, zf, Lxf, Lyf, Lzf, ilx, ily, ilz;
   float inR2, outR2, inA2, outA2;
   bool fast;
 };
 
+// a tile of positions in LDS holding atoms [base, base + kNbrTile)
+struct PosTile {
+  const float* x;
+  const float* y;
+  const float* z;
+  int base;
+};
+
 // float64 predicate of Eq. 2 for the pair (i, j) over the candidate shifts;
 // calls emit(j, code, is_angular) in ascending code order
 template <class Emit>
-__device__ __forceinline__ void exact_pair(const ScanCtx& c, int j, Emit& emit) {
-  const double x0 = __dadd_rn((double)c.pos[j], -c.xi);
+__device__ __forceinline__ void exact_pair(const ScanCtx& c, const PosTile& t, int j, Emit& emit) {
+  const int q = j - t.base;
+  const double x0 = __dadd_rn((double)t.x[q], -c.xi);
   const unsigned mx = axis_candidates(x0, c.Lx, c.rcR);
   if (!mx) return;
-  const double y0 = __dadd_rn((double)c.pos[c.N + j], -c.yi);
+  const double y0 = __dadd_rn((double)t.y[q], -c.yi);
   const unsigned my = axis_candidates(y0, c.Ly, c.rcR);
   if (!my) return;
-  const double z0 = __dadd_rn((double)c.pos[2 * c.N + j], -c.zi);
+  const double z0 = __dadd_rn((double)t.z[q], -c.zi);
   const unsigned mz = axis_candidates(z0, c.Lz, c.rcR);
   if (!mz) return;
   for (unsigned bx = mx; bx; bx &= bx - 1u) {
@@ -86,10 +98,12 @@ __device__ __forceinline__ void exact_pair(const ScanCtx& c, int j, Emit& emit) 
 }
 
 template <class Emit>
-__device__ __forceinline__ void scan_range(const ScanCtx& c, int jb, int je, Emit& emit) {
+__device__ __forceinline__ void scan_range(const ScanCtx& c, const PosTile& t, int jb, int je, Emit& emit) {
   for (int j = jb; j < je; ++j) {
     if (c.fast) {
-      float ex = c.pos[j] - c.xf, ey = c.pos[c.N + j] - c.yf, ez = c.pos[2 * c.N + j] - c.zf;
+      const int q = j - t.base;
+      const float px = t.x[q], py = t.y[q], pz = t.z[q];
+      float ex = px - c.xf, ey = py - c.yf, ez = pz - c.zf;
       const float kx = rintf(ex * c.ilx), ky = rintf(ey * c.ily), kz = rintf(ez * c.ilz);
       ex -= c.Lxf * kx;
       ey -= c.Lyf * ky;
@@ -102,9 +116,9 @@ __device__ __forceinline__ void scan_range(const ScanCtx& c, int jb, int je, Emi
         if (j == c.i && code == 13) continue;
         bool ang = r2 < c.inA2;
         if (!ang && r2 < c.outA2) {
-          const double dx = __dadd_rn(__dadd_rn((double)c.pos[j], -c.xi), -(double)kx * c.Lx);
-          const double dy = __dadd_rn(__dadd_rn((double)c.pos[c.N + j], -c.yi), -(double)ky * c.Ly);
-          const double dz = __dadd_rn(__dadd_rn((double)c.pos[2 * c.N + j], -c.zi), -(double)kz * c.Lz);
+          const double dx = __dadd_rn(__dadd_rn((double)px, -c.xi), -(double)kx * c.Lx);
+          const double dy = __dadd_rn(__dadd_rn((double)py, -c.yi), -(double)ky * c.Ly);
+          const double dz = __dadd_rn(__dadd_rn((double)pz, -c.zi), -(double)kz * c.Lz);
           const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
           ang = d2 < c.rcA2;
         }
@@ -112,18 +126,19 @@ __device__ __forceinline__ void scan_range(const ScanCtx& c, int jb, int je, Emi
         continue;
       }
     }
-    exact_pair(c, j, emit);
+    exact_pair(c, t, j, emit);
   }
 }
 
 __global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
+  __shared__ float tx[kNbrTile], ty[kNbrTile], tz[kNbrTile];
+  __shared__ int jr[2];
   const int s = threadIdx.x & 7;
-  const int i = blockIdx.x * kNbrAPB + (threadIdx.x >> 3);
+  const int b0 = blockIdx.x * kNbrAPB;
+  const int i = b0 + (threadIdx.x >> 3);
   const bool live = i < a.N;
   ScanCtx c;
   c.i = live ? i : a.N - 1;
-  c.N = a.N;
-  c.pos = a.pos;
   int lo = 0, hi = a.S;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
@@ -131,6 +146,9 @@ __global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
   }
   const int st = lo;
   const int a0 = max(a.aoff[st], 0), a1 = min(a.aoff[st + 1], a.N);
+  // the block's atoms are consecutive, so their structures cover [jr[0], jr[1])
+  if (threadIdx.x == 0) jr[0] = a0;
+  if (i == min(b0 + kNbrAPB - 1, a.N - 1) && s == 0) jr[1] = a1;
   c.Lxf = a.box[3 * st];
   c.Lyf = a.box[3 * st + 1];
   c.Lzf = a.box[3 * st + 2];
@@ -170,12 +188,29 @@ __global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
   c.outA2 = (a.rcA + kNbrDelta) * (a.rcA + kNbrDelta);
   const int len = ok ? a1 - a0 : 0;
   const int jb = a0 + (len * s) / 8, je = a0 + (len * (s + 1)) / 8;
+  __syncthreads();
+  const int jlo = jr[0], jhi = jr[1];
+  // walks the tiles of [jlo, jhi); this lane scans [b, e) of each
+  auto sweep = [&](int b, int e, auto& emit) {
+    for (int t0 = jlo; t0 < jhi; t0 += kNbrTile) {
+      const int tn = min(kNbrTile, jhi - t0);
+      for (int q = threadIdx.x; q < tn; q += blockDim.x) {
+        tx[q] = a.pos[t0 + q];
+        ty[q] = a.pos[a.N + t0 + q];
+        tz[q] = a.pos[2 * a.N + t0 + q];
+      }
+      __syncthreads();
+      const PosTile t{tx, ty, tz, t0};
+      scan_range(c, t, max(b, t0), min(e, t0 + tn), emit);
+      __syncthreads();
+    }
+  };
   int nR = 0, nA = 0;
   auto count = [&](int, int, bool ang) {
     ++nR;
     nA += ang ? 1 : 0;
   };
-  scan_range(c, jb, je, count);
+  sweep(jb, je, count);
   // inclusive prefix over the 8 lanes of the atom
   int pR = nR, pA = nA;
 #pragma unroll
@@ -191,14 +226,15 @@ __global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
   const size_t col = (size_t)c.i;
   auto write = [&](int j, int code, bool ang) {
     const uint32_t e = ((uint32_t)j << 5) | (uint32_t)code;
-    if (wR < a.capR) a.idxR[(size_t)wR * a.N + col] = e;
+    if (wR < a.capR) a.idxR[col * a.capR + wR] = e;
     ++wR;
     if (ang) {
-      if (wA < a.capA) a.idxA[(size_t)wA * a.N + col] = e;
+      if (wA < a.capA) a.idxA[col * a.capA + wA] = e;
       ++wA;
     }
   };
-  if (live && nR > 0 && wR < a.capR) scan_range(c, jb, je, write);
+  const bool wr = live && nR > 0 && wR < a.capR;
+  sweep(wr ? jb : 0, wr ? je : 0, write);
   if (live && s == 0) {
     a.cntR[i] = totR;
     a.cntA[i] = totA;
@@ -208,22 +244,27 @@ __global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
 }
 
 // Position of the reverse entry (i, -s) in j's list, by binary search over
-// the canonically ordered entries.
+// j's canonically ordered entries; 8 lanes per atom take slots s, s + 8, ....
 __global__ __launch_bounds__(256) void k_reverse(int N, const uint32_t* __restrict__ idx,
                                                  const int* __restrict__ cnt, int cap, int* __restrict__ rev) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int k = blockIdx.y;
-  if (i >= N || k >= min(cnt[i], cap)) return;
-  const uint32_t e = idx[(size_t)k * N + i];
-  const int j = (int)(e >> 5);
-  const uint32_t key = ((uint32_t)i << 5) | (26u - (e & 31u));
-  const int m = min(cnt[j], cap);
-  int lo = 0, hi = m;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (idx[(size_t)mid * N + j] < key) lo = mid + 1; else hi = mid;
+  const int s = threadIdx.x & 7;
+  const int i = blockIdx.x * 32 + (threadIdx.x >> 3);
+  if (i >= N) return;
+  const int n = min(cnt[i], cap);
+  for (int k = s; k < n; k += 8) {
+    const size_t o = (size_t)i * cap + k;
+    const uint32_t e = idx[o];
+    const int j = (int)(e >> 5);
+    const uint32_t key = ((uint32_t)i << 5) | (26u - (e & 31u));
+    const uint32_t* lj = idx + (size_t)j * cap;
+    const int m = min(cnt[j], cap);
+    int lo = 0, hi = m;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (lj[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    rev[o] = (lo < m && lj[lo] == key) ? lo : -1;
   }
-  rev[(size_t)k * N + i] = (lo < m && idx[(size_t)lo * N + j] == key) ? lo : -1;
 }
 
 // ============================================================ species order
@@ -346,12 +387,22 @@ __global__ __launch_bounds__(kOrdBlk) void k_order_scatter(int N, int T, const i
 }
 
 // ================================================================= helpers
+// c^A of every species pair (I, J) staged in LDS with rows padded to KAP = 4k
+// floats: a pair reads its 4-aligned row with a few wide LDS reads instead of
+// selecting each coefficient by the neighbor's species
 template <int T, int NA, int KA>
-__device__ __forceinline__ float coef_sel(cptr<float> cI, int J, int n, int k) {
-  float c = cI[(0 * NA + n) * KA + k];
-#pragma unroll
-  for (int t = 1; t < T; ++t) c = (J == t) ? cI[(t * NA + n) * KA + k] : c;
-  return c;
+struct CTab {
+  static constexpr int KAP = (KA + 3) & ~3;
+  static constexpr int size = T * T * NA * KAP;
+};
+
+template <int T, int NA, int KA>
+__device__ __forceinline__ void stage_ctab(float* ct, const float* __restrict__ cA) {
+  constexpr int KAP = CTab<T, NA, KA>::KAP;
+  for (int q = threadIdx.x; q < CTab<T, NA, KA>::size; q += blockDim.x) {
+    const int k = q % KAP, r = q / KAP;
+    ct[q] = k < KA ? cA[r * KA + k] : 0.f;
+  }
 }
 
 struct PairGeom {
@@ -507,13 +558,17 @@ __global__ __launch_bounds__(256, 2) void k_forward(FwdArgs a) {
   using HS = HSplit<LM>;
   constexpr int YG = HS::YG;
   constexpr int DP = (D + 3) & ~3;
-  extern __shared__ float lds[];
+  extern __shared__ __align__(16) float lds[];
   const int H = a.H;
   const int WS = H * DP + 2 * H;
   constexpr int RW = DP + NA * Y;         // LDS row per atom: G, S
-  float* wl = lds;                       // [T][WS]
-  float* rows = lds + T * WS;            // [kAPB][RW]
+  using CT = CTab<T, NA, KA>;
+  float* ctab = lds;                     // [T][T][NA][KAP]
+  float* wl = lds + CT::size;            // [T][WS]
+  float* rows = wl + T * WS;             // [kAPB][RW]
+  stage_ctab<T, NA, KA>(ctab, a.cA);
   if (a.do_mlp) stage_weights(wl, a.nn, a.nn_stride, T, H, D, DP);
+  __syncthreads();
   const GroupCtx w = group_ctx(a.order, a.type, a.Npad);
   const int N = a.N, i = w.i, I = w.I, pa = w.pa, s = w.s, g = w.g;
   float* row = rows + w.al * RW;
@@ -524,7 +579,6 @@ __global__ __launch_bounds__(256, 2) void k_forward(FwdArgs a) {
   const int nR = w.valid ? min(a.nb.cntR[i], a.nb.capR) : 0;
   const int nA = w.valid ? min(a.nb.cntA[i], a.nb.capA) : 0;
   const cptr<float> cRI = as_const(a.cR) + (size_t)I * T * NR * KR;
-  const cptr<float> cAI = as_const(a.cA) + (size_t)I * T * NA * KA;
 
   // ---- radial sums, pairs split over the 8 lanes
   float FR[T][KR];
@@ -533,7 +587,7 @@ __global__ __launch_bounds__(256, 2) void k_forward(FwdArgs a) {
 #pragma unroll
     for (int k = 0; k < KR; ++k) FR[t][k] = 0.f;
   for (int k = s; k < nR; k += kLPA) {
-    const PairGeom q = pair_geom(a.nb.idxR[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+    const PairGeom q = pair_geom(a.nb.idxR[(size_t)i * a.nb.capR + k], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
     float f[KR];
     radial_basis<KR>(q.r, a.inv_rcR, f);
     const int J = a.type[q.j];
@@ -566,16 +620,17 @@ __global__ __launch_bounds__(256, 2) void k_forward(FwdArgs a) {
 #pragma unroll
     for (int e = 0; e < YG; ++e) Sg[n][e] = 0.f;
   for (int k = w.p; k < nA; k += 4) {
-    const PairGeom q = pair_geom(a.nb.idxA[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+    const PairGeom q = pair_geom(a.nb.idxA[(size_t)i * a.nb.capA + k], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
     float f[KA];
     radial_basis<KA>(q.r, a.inv_rcA, f);
     const int J = a.type[q.j];
+    const float* cJ = ctab + (I * T + J) * NA * CT::KAP;
     float gn[NA];
 #pragma unroll
     for (int n = 0; n < NA; ++n) {
       float acc = 0.f;
 #pragma unroll
-      for (int kk = 0; kk < KA; ++kk) acc = fmaf(coef_sel<T, NA, KA>(cAI, J, n, kk), f[kk], acc);
+      for (int kk = 0; kk < KA; ++kk) acc = fmaf(cJ[n * CT::KAP + kk], f[kk], acc);
       gn[n] = acc;
     }
     float B[Y];
@@ -697,9 +752,8 @@ __global__ __launch_bounds__(256, 2) void k_forward(FwdArgs a) {
       hR[t][k] = acc;
     }
   float vxx = 0.f, vyy = 0.f, vzz = 0.f, vxy = 0.f, vyz = 0.f, vzx = 0.f;
-  const size_t capN_R = (size_t)a.nb.capR * N, capN_A = (size_t)a.nb.capA * N;
   for (int k = s; k < nR; k += kLPA) {
-    const PairGeom q = pair_geom(a.nb.idxR[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+    const PairGeom q = pair_geom(a.nb.idxR[(size_t)i * a.nb.capR + k], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
     float f[KR], fp[KR];
     radial_basis_d<KR>(q.r, a.inv_rcR, f, fp);
     const int J = a.type[q.j];
@@ -713,9 +767,10 @@ __global__ __launch_bounds__(256, 2) void k_forward(FwdArgs a) {
     }
     sc *= q.inv_r;
     const float fx = sc * q.dx, fy = sc * q.dy, fz = sc * q.dz;
-    a.fR[(size_t)k * N + i] = fx;
-    a.fR[capN_R + (size_t)k * N + i] = fy;
-    a.fR[2 * capN_R + (size_t)k * N + i] = fz;
+    float* fo = a.fR + 3 * ((size_t)i * a.nb.capR + k);
+    fo[0] = fx;
+    fo[1] = fy;
+    fo[2] = fz;
     vxx -= fx * q.dx; vyy -= fy * q.dy; vzz -= fz * q.dz;
     vxy -= fx * q.dy; vyz -= fy * q.dz; vzx -= fz * q.dx;
   }
@@ -762,18 +817,19 @@ __global__ __launch_bounds__(256, 2) void k_forward(FwdArgs a) {
   // ---- angular partial forces: f_ij = sum_nlm A_nlm (g'_n r_hat B_lm + g_n grad B_lm);
   //      each harmonic group adds its half, the two halves are summed across lanes
   for (int k = w.p; k < nA; k += 4) {
-    const PairGeom q = pair_geom(a.nb.idxA[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+    const PairGeom q = pair_geom(a.nb.idxA[(size_t)i * a.nb.capA + k], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
     const float ux = q.dx * q.inv_r, uy = q.dy * q.inv_r, uz = q.dz * q.inv_r;
     float f[KA], fp[KA];
     radial_basis_d<KA>(q.r, a.inv_rcA, f, fp);
     const int J = a.type[q.j];
+    const float* cJ = ctab + (I * T + J) * NA * CT::KAP;
     float gn[NA], gp[NA];
 #pragma unroll
     for (int n = 0; n < NA; ++n) {
       float s0 = 0.f, s1 = 0.f;
 #pragma unroll
       for (int kk = 0; kk < KA; ++kk) {
-        const float c = coef_sel<T, NA, KA>(cAI, J, n, kk);
+        const float c = cJ[n * CT::KAP + kk];
         s0 = fmaf(c, f[kk], s0);
         s1 = fmaf(c, fp[kk], s1);
       }
@@ -815,9 +871,10 @@ __global__ __launch_bounds__(256, 2) void k_forward(FwdArgs a) {
     fy += __shfl_xor(fy, 4, kWave);
     fz += __shfl_xor(fz, 4, kWave);
     if (g == 0) {
-      a.fA[(size_t)k * N + i] = fx;
-      a.fA[capN_A + (size_t)k * N + i] = fy;
-      a.fA[2 * capN_A + (size_t)k * N + i] = fz;
+      float* fo = a.fA + 3 * ((size_t)i * a.nb.capA + k);
+      fo[0] = fx;
+      fo[1] = fy;
+      fo[2] = fz;
       vxx -= fx * q.dx; vyy -= fy * q.dy; vzz -= fz * q.dz;
       vxy -= fx * q.dy; vyz -= fy * q.dz; vzx -= fz * q.dx;
     }
@@ -834,56 +891,51 @@ __global__ __launch_bounds__(256, 2) void k_forward(FwdArgs a) {
   }
 }
 
-// F_i = sum_j f_ij - f_ji (Eq. 3), gathering f_ji through the reverse index.
+// F_i = sum_j f_ij - f_ji (Eq. 3), gathering f_ji through the reverse index;
+// 8 lanes per atom take list slots s, s + 8, ... and are summed by DPP.
+__device__ __forceinline__ void gather_list(int i, int s, const uint32_t* __restrict__ idx, const int* __restrict__ cnt,
+                                            const int* __restrict__ rev, int cap, const float* __restrict__ f,
+                                            float& fx, float& fy, float& fz) {
+  const int n = min(cnt[i], cap);
+  for (int k = s; k < n; k += 8) {
+    const size_t o = (size_t)i * cap + k;
+    const int j = (int)(idx[o] >> 5);
+    const int rk = rev[o];
+    const float* a = f + 3 * o;
+    fx += a[0];
+    fy += a[1];
+    fz += a[2];
+    if (rk >= 0) {
+      const float* b = f + 3 * ((size_t)j * cap + rk);
+      fx -= b[0];
+      fy -= b[1];
+      fz -= b[2];
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_force_gather(int N, PairLists nb, const float* __restrict__ fR,
                                                       const float* __restrict__ fA, float* __restrict__ F,
                                                       float* __restrict__ Fuser) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+  const int s = threadIdx.x & 7;
+  const int i = blockIdx.x * 32 + (threadIdx.x >> 3);
   float fx = 0.f, fy = 0.f, fz = 0.f;
-  {
-    const size_t cN = (size_t)nb.capR * N;
-    const int n = min(nb.cntR[i], nb.capR);
-    for (int k = 0; k < n; ++k) {
-      const int j = (int)(nb.idxR[(size_t)k * N + i] >> 5);
-      const size_t o = (size_t)k * N + i;
-      fx += fR[o];
-      fy += fR[cN + o];
-      fz += fR[2 * cN + o];
-      const int rk = nb.revR[o];
-      if (rk >= 0) {
-        const size_t q = (size_t)rk * N + j;
-        fx -= fR[q];
-        fy -= fR[cN + q];
-        fz -= fR[2 * cN + q];
-      }
-    }
+  if (i < N) {
+    gather_list(i, s, nb.idxR, nb.cntR, nb.revR, nb.capR, fR, fx, fy, fz);
+    gather_list(i, s, nb.idxA, nb.cntA, nb.revA, nb.capA, fA, fx, fy, fz);
   }
-  {
-    const size_t cN = (size_t)nb.capA * N;
-    const int n = min(nb.cntA[i], nb.capA);
-    for (int k = 0; k < n; ++k) {
-      const int j = (int)(nb.idxA[(size_t)k * N + i] >> 5);
-      const size_t o = (size_t)k * N + i;
-      fx += fA[o];
-      fy += fA[cN + o];
-      fz += fA[2 * cN + o];
-      const int rk = nb.revA[o];
-      if (rk >= 0) {
-        const size_t q = (size_t)rk * N + j;
-        fx -= fA[q];
-        fy -= fA[cN + q];
-        fz -= fA[2 * cN + q];
-      }
+  fx = grp8_sum(fx);
+  fy = grp8_sum(fy);
+  fz = grp8_sum(fz);
+  if (i < N && s == 0) {
+    F[i] = fx;
+    F[N + i] = fy;
+    F[2 * N + i] = fz;
+    if (Fuser) {
+      Fuser[i] = fx;
+      Fuser[N + i] = fy;
+      Fuser[2 * N + i] = fz;
     }
-  }
-  F[i] = fx;
-  F[N + i] = fy;
-  F[2 * N + i] = fz;
-  if (Fuser) {
-    Fuser[i] = fx;
-    Fuser[N + i] = fy;
-    Fuser[2 * N + i] = fz;
   }
 }
 
@@ -1022,7 +1074,7 @@ __global__ __launch_bounds__(kRedBlk) void k_loss_final(int S, int N, float le, 
 // Outputs: per-atom vectors for the outer-product sums (W0, c^R) and, per
 // wavefront, the sums of the c^A, b0, w1, b1 partials over its 8 atoms.
 template <class C>
-__global__ __launch_bounds__(256) void k_adjoint(AdjArgs a) {
+__global__ __launch_bounds__(256, 2) void k_adjoint(AdjArgs a) {
   constexpr int T = C::T, NR = C::NR, NA = C::NA, KR = C::KR, KA = C::KA, Y = C::Y, D = C::D, LM = C::LMAX;
   constexpr int L3 = C::L3, L4 = C::L4, L5 = C::L5;
   using HS = HSplit<LM>;
@@ -1031,12 +1083,16 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs a) {
   constexpr int NAH = (NA + 1) / 2;          // channels per lane in the coefficient pass
   constexpr int RW = DP + 2 * NA * Y;        // LDS row per atom: Gdot, Sbar, A
   constexpr int PSA = T * NA * KA;
-  extern __shared__ float lds[];
+  extern __shared__ __align__(16) float lds[];
   const int H = a.H;
   const int WS = H * DP + 2 * H;
-  float* wl = lds;
-  float* rows = lds + T * WS;
+  using CT = CTab<T, NA, KA>;
+  float* ctab = lds;                     // [T][T][NA][KAP]
+  float* wl = lds + CT::size;            // [T][WS]
+  float* rows = wl + T * WS;             // [kAPB][RW]
+  stage_ctab<T, NA, KA>(ctab, a.cA);
   stage_weights(wl, a.nn, a.nn_stride, T, H, D, DP);
+  __syncthreads();
   const GroupCtx w = group_ctx(a.order, a.type, a.Npad);
   const int N = a.N, i = w.i, I = w.I, pa = w.pa, s = w.s, g = w.g;
   const int lane = threadIdx.x & (kWave - 1);
@@ -1052,7 +1108,6 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs a) {
   const int nR = w.valid ? min(a.nb.cntR[i], a.nb.capR) : 0;
   const int nA = w.valid ? min(a.nb.cntA[i], a.nb.capA) : 0;
   const cptr<float> cRI = as_const(a.cR) + (size_t)I * T * NR * KR;
-  const cptr<float> cAI = as_const(a.cA) + (size_t)I * T * NA * KA;
   const float eps = w.valid ? a.eps[st] : 0.f;
   const float* wb = a.wbar + 6 * st;
   const float gxx = wb[0], gyy = wb[1], gzz = wb[2], gxy = wb[3], gyz = wb[4], gzx = wb[5];
@@ -1065,7 +1120,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs a) {
 #pragma unroll
     for (int k = 0; k < KR; ++k) FR[t][k] = FP[t][k] = 0.f;
   for (int k = s; k < nR; k += kLPA) {
-    const PairGeom q = pair_geom(a.nb.idxR[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+    const PairGeom q = pair_geom(a.nb.idxR[(size_t)i * a.nb.capR + k], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
     const float tx = (a.fbar[q.j] - fbx) + gxx * q.dx + gxy * q.dy;
     const float ty = (a.fbar[N + q.j] - fby) + gyy * q.dy + gyz * q.dz;
     const float tz = (a.fbar[2 * N + q.j] - fbz) + gzz * q.dz + gzx * q.dx;
@@ -1114,7 +1169,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs a) {
 #pragma unroll
     for (int e = 0; e < YG; ++e) Sd[n][e] = 0.f;
   for (int k = w.p; k < nA; k += 4) {
-    const PairGeom q = pair_geom(a.nb.idxA[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+    const PairGeom q = pair_geom(a.nb.idxA[(size_t)i * a.nb.capA + k], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
     const float ux = q.dx * q.inv_r, uy = q.dy * q.inv_r, uz = q.dz * q.inv_r;
     const float tx = (a.fbar[q.j] - fbx) + gxx * q.dx + gxy * q.dy;
     const float ty = (a.fbar[N + q.j] - fby) + gyy * q.dy + gyz * q.dz;
@@ -1123,13 +1178,14 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs a) {
     float f[KA], fp[KA];
     radial_basis_d<KA>(q.r, a.inv_rcA, f, fp);
     const int J = a.type[q.j];
+    const float* cJ = ctab + (I * T + J) * NA * CT::KAP;
     float gn[NA], gpd[NA];
 #pragma unroll
     for (int n = 0; n < NA; ++n) {
       float s0 = 0.f, s1 = 0.f;
 #pragma unroll
       for (int kk = 0; kk < KA; ++kk) {
-        const float c = coef_sel<T, NA, KA>(cAI, J, n, kk);
+        const float c = cJ[n * CT::KAP + kk];
         s0 = fmaf(c, f[kk], s0);
         s1 = fmaf(c, fp[kk], s1);
       }
@@ -1322,7 +1378,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs a) {
     // reload Sbar and A from LDS every pair: hoisted out of the loop they
     // would take 2 NAH Y registers and halve the occupancy
     asm volatile("" ::: "memory");
-    const PairGeom q = pair_geom(a.nb.idxA[(size_t)k * N + i], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+    const PairGeom q = pair_geom(a.nb.idxA[(size_t)i * a.nb.capA + k], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
     const float ux = q.dx * q.inv_r, uy = q.dy * q.inv_r, uz = q.dz * q.inv_r;
     const float tx = (a.fbar[q.j] - fbx) + gxx * q.dx + gxy * q.dy;
     const float ty = (a.fbar[N + q.j] - fby) + gyy * q.dy + gyz * q.dz;
@@ -1449,19 +1505,37 @@ __global__ __launch_bounds__(256) void k_outer_sum(OuterArgs o) {
   for (int x = 0; x < kOSTM; ++x)
 #pragma unroll
     for (int y = 0; y < kOSTV; ++y) acc[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int g = p0 + 16 * wv; g < p1; g += 64) {
+  // operands of one 16-atom group; the next group's loads are issued before
+  // the current group's MFMAs
+  f32x4 va1[kOSTM], va2[kOSTM], vb1[kOSTV], vb2[kOSTV];
+  auto load = [&](int g) {
     const int p = g + 4 * slot;
-    f32x4 va1[kOSTM], va2[kOSTM], vb1[kOSTV], vb2[kOSTV];
+    const bool in = g < p1;
 #pragma unroll
     for (int t = 0; t < kOSTM; ++t) {
-      va1[t] = am[t] ? ld_atoms4(a1[t], p, p1) : f32x4{0.f, 0.f, 0.f, 0.f};
-      va2[t] = am[t] ? -ld_atoms4(a2[t], p, p1) : f32x4{0.f, 0.f, 0.f, 0.f};
+      va1[t] = (in && am[t]) ? ld_atoms4(a1[t], p, p1) : f32x4{0.f, 0.f, 0.f, 0.f};
+      va2[t] = (in && am[t]) ? -ld_atoms4(a2[t], p, p1) : f32x4{0.f, 0.f, 0.f, 0.f};
     }
 #pragma unroll
     for (int t = 0; t < kOSTV; ++t) {
-      vb1[t] = bm[t] ? ld_atoms4(b1[t], p, p1) : f32x4{0.f, 0.f, 0.f, 0.f};
-      vb2[t] = bm[t] ? ld_atoms4(b2[t], p, p1) : f32x4{0.f, 0.f, 0.f, 0.f};
+      vb1[t] = (in && bm[t]) ? ld_atoms4(b1[t], p, p1) : f32x4{0.f, 0.f, 0.f, 0.f};
+      vb2[t] = (in && bm[t]) ? ld_atoms4(b2[t], p, p1) : f32x4{0.f, 0.f, 0.f, 0.f};
     }
+  };
+  load(p0 + 16 * wv);
+  for (int g = p0 + 16 * wv; g < p1; g += 64) {
+    f32x4 ca1[kOSTM], ca2[kOSTM], cb1[kOSTV], cb2[kOSTV];
+#pragma unroll
+    for (int t = 0; t < kOSTM; ++t) {
+      ca1[t] = va1[t];
+      ca2[t] = va2[t];
+    }
+#pragma unroll
+    for (int t = 0; t < kOSTV; ++t) {
+      cb1[t] = vb1[t];
+      cb2[t] = vb2[t];
+    }
+    load(g + 64);
 #pragma unroll
     for (int x = 0; x < kOSTM; ++x) {
       if (x >= tm_live) break;
@@ -1470,8 +1544,8 @@ __global__ __launch_bounds__(256) void k_outer_sum(OuterArgs o) {
         if (y >= tv_live) break;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(va1[x][j], vb1[y][j], acc[x][y], 0, 0, 0);
-          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(va2[x][j], vb2[y][j], acc[x][y], 0, 0, 0);
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(ca1[x][j], cb1[y][j], acc[x][y], 0, 0, 0);
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(ca2[x][j], cb2[y][j], acc[x][y], 0, 0, 0);
         }
       }
     }
@@ -1662,12 +1736,14 @@ struct Ops {
 template <class C>
 static size_t lds_forward(int H) {
   const int DP = (C::D + 3) & ~3;
-  return sizeof(float) * ((size_t)C::T * (H * DP + 2 * H) + (size_t)kAPB * (DP + C::NA * C::Y));
+  return sizeof(float) * ((size_t)CTab<C::T, C::NA, C::KA>::size + (size_t)C::T * (H * DP + 2 * H) +
+                          (size_t)kAPB * (DP + C::NA * C::Y));
 }
 template <class C>
 static size_t lds_adjoint(int H) {
   const int DP = (C::D + 3) & ~3;
-  return sizeof(float) * ((size_t)C::T * (H * DP + 2 * H) + (size_t)kAPB * (DP + 2 * C::NA * C::Y));
+  return sizeof(float) * ((size_t)CTab<C::T, C::NA, C::KA>::size + (size_t)C::T * (H * DP + 2 * H) +
+                          (size_t)kAPB * (DP + 2 * C::NA * C::Y));
 }
 template <class C>
 static void launch_forward(const FwdArgs& a, dim3 grid, hipStream_t st) {
@@ -1892,10 +1968,10 @@ void run_neighbors(const Ctx& c, nep_neighbors* nb, int32_t* flags, Prof* pr) {
   a.flags = flags;
   NEP_LAUNCH(pr, "neighbors", hipLaunchKernelGGL(k_neighbors, dim3(grid1(N, kNbrAPB)), dim3(256), 0, c.st, a));
   NEP_LAUNCH(pr, "reverse_rad",
-             hipLaunchKernelGGL(k_reverse, dim3(grid1(N), c.m->cap_rad), dim3(256), 0, c.st, N, nb->idx_rad,
+             hipLaunchKernelGGL(k_reverse, dim3(grid1(N, 32)), dim3(256), 0, c.st, N, nb->idx_rad,
                                 nb->cnt_rad, c.m->cap_rad, at<int>(c.ws, c.L.revR)));
   NEP_LAUNCH(pr, "reverse_ang",
-             hipLaunchKernelGGL(k_reverse, dim3(grid1(N), c.m->cap_ang), dim3(256), 0, c.st, N, nb->idx_ang,
+             hipLaunchKernelGGL(k_reverse, dim3(grid1(N, 32)), dim3(256), 0, c.st, N, nb->idx_ang,
                                 nb->cnt_ang, c.m->cap_ang, at<int>(c.ws, c.L.revA)));
   int* order = at<int>(c.ws, c.L.order);
   int* blk = at<int>(c.ws, c.L.blk);
@@ -1954,7 +2030,7 @@ void run_forward(const Ctx& c, const nep_neighbors* nb, const float* params, flo
     a.eatom2 = e_atom;
     NEP_LAUNCH(pr, "forward", c.o->forward(a, dim3(c.L.Npad / kAPB), c.st));
     NEP_LAUNCH(pr, "force_gather",
-               hipLaunchKernelGGL(k_force_gather, dim3(grid1(N)), dim3(256), 0, c.st, N, a.nb, a.fR, a.fA,
+               hipLaunchKernelGGL(k_force_gather, dim3(grid1(N, 32)), dim3(256), 0, c.st, N, a.nb, a.fR, a.fA,
                                   at<float>(c.ws, c.L.F), force));
   }
   if (S > 0) {

@@ -113,8 +113,8 @@ class GPURun:
         cap = self.model.cap_rad if which == "rad" else self.model.cap_ang
         idx = (self.nbrs.idx_rad if which == "rad" else self.nbrs.idx_ang).cpu().numpy().view(np.uint32)
         cnt = (self.nbrs.cnt_rad if which == "rad" else self.nbrs.cnt_ang).cpu().numpy()
-        idx = idx.reshape(cap, max(self.N, 1))
-        return [list(idx[:min(cnt[i], cap), i]) for i in range(self.N)], cnt
+        idx = idx.reshape(max(self.N, 1), cap)
+        return [list(idx[i, :min(cnt[i], cap)]) for i in range(self.N)], cnt
 
     def efw(self):
         import torch

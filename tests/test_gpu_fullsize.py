@@ -28,7 +28,7 @@ def golden(name):
 
 
 def digest(idx, cnt, cap, N):
-    idx = idx.reshape(cap, N).T.view(np.uint32)
+    idx = idx.reshape(N, cap).view(np.uint32)
     keep = np.arange(cap)[None, :] < cnt[:, None]
     e = idx[keep].astype(np.int64)
     i = np.repeat(np.arange(N, dtype=np.int64), cnt)
