@@ -35,20 +35,40 @@ struct Cfg {
   static constexpr int PS = T * NR * KR + T * NA * KA;  // c-grad slots of one center species
 };
 
+// --------------------------------------------------------- transcendentals
+// Hardware instructions: v_cos_f32 / v_sin_f32 take the angle in turns
+// (cos(2 pi t)), v_rsq_f32 is 1/sqrt, v_rcp_f32 is 1/x and v_exp_f32 is 2^x.
+// Their errors (a few ulp over these arguments) sit far below the FP32 path's
+// tolerances, and each is one instruction instead of a library sequence.
+__device__ __forceinline__ float cos_turns(float t) { return __builtin_amdgcn_cosf(t); }
+__device__ __forceinline__ float sin_turns(float t) { return __builtin_amdgcn_sinf(t); }
+__device__ __forceinline__ float rsq_hw(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float rcp_hw(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// tanh z = 1 - 2 / (e^{2z} + 1); saturates to +-1 through e^{2z} = inf or 0
+__device__ __forceinline__ float tanh_hw(float z) {
+  const float e = __builtin_amdgcn_exp2f(z * 2.8853900817779268f);   // 2 / ln 2
+  return fmaf(-2.0f, rcp_hw(e + 1.0f), 1.0f);
+}
+
 // ------------------------------------------------------------------ radial
-// f_k(r) = (T_k(xi) + 1)/2 * f_c(r), xi = 2 (r/rc - 1)^2 - 1, and df_k/dr.
+// f_k(r) = (T_k(xi) + 1)/2 * f_c(r), xi = 2 (r/rc - 1)^2 - 1, and df_k/dr;
+// f_c(r) = (1 + cos(pi r / rc)) / 2.  Written as two FMAs per order (four
+// with the derivative).
 template <int K>
 __device__ __forceinline__ void radial_basis(float r, float inv_rc, float (&f)[K]) {
-  const float x = r * inv_rc - 1.0f;
-  const float xi = 2.0f * x * x - 1.0f;
-  const float fc = 0.5f + 0.5f * cospif(r * inv_rc);
+  const float u = r * inv_rc;
+  const float x = u - 1.0f;
+  const float xi = fmaf(2.0f * x, x, -1.0f);
+  const float xi2 = 2.0f * xi;
+  const float hfc = fmaf(0.25f, cos_turns(0.5f * u), 0.25f);   // f_c / 2
   float t0 = 1.0f, t1 = xi;
-  f[0] = fc;
-  if (K > 1) f[1] = 0.5f * (xi + 1.0f) * fc;
+  f[0] = 2.0f * hfc;
+  if (K > 1) f[1] = fmaf(xi, hfc, hfc);
 #pragma unroll
   for (int k = 2; k < K; ++k) {
-    const float t2 = 2.0f * xi * t1 - t0;
-    f[k] = 0.5f * (t2 + 1.0f) * fc;
+    const float t2 = fmaf(xi2, t1, -t0);
+    f[k] = fmaf(t2, hfc, hfc);
     t0 = t1;
     t1 = t2;
   }
@@ -56,26 +76,27 @@ __device__ __forceinline__ void radial_basis(float r, float inv_rc, float (&f)[K
 
 template <int K>
 __device__ __forceinline__ void radial_basis_d(float r, float inv_rc, float (&f)[K], float (&fp)[K]) {
-  const float x = r * inv_rc - 1.0f;
-  const float xi = 2.0f * x * x - 1.0f;
+  const float u = r * inv_rc;
+  const float x = u - 1.0f;
+  const float xi = fmaf(2.0f * x, x, -1.0f);
+  const float xi2 = 2.0f * xi;
   const float dxi = 4.0f * x * inv_rc;
-  float s, c;
-  sincospif(r * inv_rc, &s, &c);
-  const float fc = 0.5f + 0.5f * c;
-  const float fcp = -0.5f * 3.14159265358979f * inv_rc * s;
+  const float hfc = fmaf(0.25f, cos_turns(0.5f * u), 0.25f);                     // f_c / 2
+  const float hfcp = -0.25f * 3.14159265358979f * inv_rc * sin_turns(0.5f * u);  // f_c' / 2
+  const float a = dxi * hfc;   // d(T_k)/dr coefficient of f_c / 2
   float t0 = 1.0f, t1 = xi, d0 = 0.0f, d1 = 1.0f;
-  f[0] = fc;
-  fp[0] = fcp;
+  f[0] = 2.0f * hfc;
+  fp[0] = 2.0f * hfcp;
   if (K > 1) {
-    f[1] = 0.5f * (xi + 1.0f) * fc;
-    fp[1] = 0.5f * dxi * fc + 0.5f * (xi + 1.0f) * fcp;
+    f[1] = fmaf(xi, hfc, hfc);
+    fp[1] = fmaf(xi, hfcp, fmaf(d1, a, hfcp));
   }
 #pragma unroll
   for (int k = 2; k < K; ++k) {
-    const float t2 = 2.0f * xi * t1 - t0;
-    const float d2 = 2.0f * t1 + 2.0f * xi * d1 - d0;
-    f[k] = 0.5f * (t2 + 1.0f) * fc;
-    fp[k] = 0.5f * d2 * dxi * fc + 0.5f * (t2 + 1.0f) * fcp;
+    const float t2 = fmaf(xi2, t1, -t0);
+    const float d2 = fmaf(xi2, d1, fmaf(2.0f, t1, -d0));
+    f[k] = fmaf(t2, hfc, hfc);
+    fp[k] = fmaf(t2, hfcp, fmaf(d2, a, hfcp));
     t0 = t1;
     t1 = t2;
     d0 = d1;

@@ -243,8 +243,11 @@ __global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
   if (live && s == 0 && fl) atomicOr(a.flags, fl);
 }
 
-// Position of the reverse entry (i, -s) in j's list, by binary search over
-// j's canonically ordered entries; 8 lanes per atom take slots s, s + 8, ....
+// Position of the reverse entry (i, -s) in j's list; 8 lanes per atom take
+// slots s, s + 8, ....  The search over j's sorted list takes two dependent
+// rounds instead of log2(cap): the last entry of every run of 8 (independent
+// loads) picks the run, then the run's 8 entries (two 16-byte loads) give the
+// position.  Entries past j's count are treated as larger than any key.
 __global__ __launch_bounds__(256) void k_reverse(int N, const uint32_t* __restrict__ idx,
                                                  const int* __restrict__ cnt, int cap, int* __restrict__ rev) {
   const int s = threadIdx.x & 7;
@@ -258,12 +261,37 @@ __global__ __launch_bounds__(256) void k_reverse(int N, const uint32_t* __restri
     const uint32_t key = ((uint32_t)i << 5) | (26u - (e & 31u));
     const uint32_t* lj = idx + (size_t)j * cap;
     const int m = min(cnt[j], cap);
-    int lo = 0, hi = m;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (lj[mid] < key) lo = mid + 1; else hi = mid;
+    // runs of 8 entries wholly below the key
+    const int nrun = (m + 7) >> 3;
+    int below = 0;
+    for (int r0 = 0; r0 < nrun; r0 += 8) {
+      uint32_t last[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int q = 8 * (r0 + u) + 7;
+        last[u] = (r0 + u < nrun && q < m) ? lj[q] : 0xFFFFFFFFu;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) below += (r0 + u < nrun && last[u] < key) ? 1 : 0;
     }
-    rev[o] = (lo < m && lj[lo] == key) ? lo : -1;
+    int pos = -1;
+    if (below < nrun) {
+      const int b = 8 * below;   // the key, if present, lies in entries b .. b + 7
+      uint32_t v[8];
+      if (b + 8 <= cap && (((uintptr_t)(lj + b)) & 15) == 0) {
+        const uint4 x = *reinterpret_cast<const uint4*>(lj + b);
+        const uint4 y = *reinterpret_cast<const uint4*>(lj + b + 4);
+        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+        v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
+      } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = b + u < cap ? lj[b + u] : 0xFFFFFFFFu;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (b + u < m && v[u] == key) pos = b + u;
+    }
+    rev[o] = pos;
   }
 }
 
@@ -419,8 +447,9 @@ __device__ __forceinline__ PairGeom pair_geom(uint32_t e, const float* __restric
   g.dx = (pos[g.j] - xi) + sx * Lx;
   g.dy = (pos[N + g.j] - yi) + sy * Ly;
   g.dz = (pos[2 * N + g.j] - zi) + sz * Lz;
-  g.r = sqrtf(g.dx * g.dx + g.dy * g.dy + g.dz * g.dz);
-  g.inv_r = 1.0f / g.r;
+  const float r2 = g.dx * g.dx + g.dy * g.dy + g.dz * g.dz;
+  g.inv_r = rsq_hw(r2);
+  g.r = r2 * g.inv_r;
   return g;
 }
 
@@ -576,8 +605,9 @@ __global__ __launch_bounds__(256, 2) void k_forward(FwdArgs a) {
   const int st = a.astruct[i];
   const float Lx = a.box[3 * st], Ly = a.box[3 * st + 1], Lz = a.box[3 * st + 2];
   const float xi = a.pos[i], yi = a.pos[N + i], zi = a.pos[2 * N + i];
-  const int nR = w.valid ? min(a.nb.cntR[i], a.nb.capR) : 0;
-  const int nA = w.valid ? min(a.nb.cntA[i], a.nb.capA) : 0;
+  const int cR_i = a.nb.cntR[i], cA_i = a.nb.cntA[i];
+  const int nR = w.valid ? min(cR_i, a.nb.capR) : 0;
+  const int nA = w.valid ? min(cA_i, a.nb.capA) : 0;
   const cptr<float> cRI = as_const(a.cR) + (size_t)I * T * NR * KR;
 
   // ---- radial sums, pairs split over the 8 lanes
@@ -717,7 +747,7 @@ __global__ __launch_bounds__(256, 2) void k_forward(FwdArgs a) {
     float z = Wl[H * DP + mu];
 #pragma unroll
     for (int v = 0; v < D; ++v) z = fmaf(wr[v], G[v], z);
-    const float x = tanhf(z);
+    const float x = tanh_hw(z);
     const float w1 = Wl[H * DP + H + mu];
     E = fmaf(w1, x, E);
     const float sg = w1 * (1.0f - x * x);
@@ -1105,10 +1135,12 @@ __global__ __launch_bounds__(256, 2) void k_adjoint(AdjArgs a) {
   const int st = a.astruct[i];
   const float Lx = a.box[3 * st], Ly = a.box[3 * st + 1], Lz = a.box[3 * st + 2];
   const float xi = a.pos[i], yi = a.pos[N + i], zi = a.pos[2 * N + i];
-  const int nR = w.valid ? min(a.nb.cntR[i], a.nb.capR) : 0;
-  const int nA = w.valid ? min(a.nb.cntA[i], a.nb.capA) : 0;
+  const int cR_i = a.nb.cntR[i], cA_i = a.nb.cntA[i];
+  const int nR = w.valid ? min(cR_i, a.nb.capR) : 0;
+  const int nA = w.valid ? min(cA_i, a.nb.capA) : 0;
   const cptr<float> cRI = as_const(a.cR) + (size_t)I * T * NR * KR;
-  const float eps = w.valid ? a.eps[st] : 0.f;
+  const float eps_v = a.eps[st];
+  const float eps = w.valid ? eps_v : 0.f;
   const float* wb = a.wbar + 6 * st;
   const float gxx = wb[0], gyy = wb[1], gzz = wb[2], gxy = wb[3], gyz = wb[4], gzx = wb[5];
   const float fbx = a.fbar[i], fby = a.fbar[N + i], fbz = a.fbar[2 * N + i];
@@ -1220,7 +1252,10 @@ __global__ __launch_bounds__(256, 2) void k_adjoint(AdjArgs a) {
 #pragma unroll
       for (int e = 0; e < YG; ++e) {
         const int q = g ? HS::q(1, e) : HS::q(0, e);
-        Sn[e] = (w.valid && q >= 0) ? a.Sst[(size_t)(n * Y + q) * a.Npad + pa] : 0.f;
+        // unconditional load from a valid address, then the mask: a guarded
+        // load would become a branch that waits for each value in turn
+        const float v = a.Sst[(size_t)(n * Y + (q >= 0 ? q : 0)) * a.Npad + pa];
+        Sn[e] = (w.valid && q >= 0) ? v : 0.f;
       }
       float qa = 0.f, qb = 0.f;
 #pragma unroll
@@ -1278,7 +1313,8 @@ __global__ __launch_bounds__(256, 2) void k_adjoint(AdjArgs a) {
 #pragma unroll
     for (int v = 0; v < D; ++v) aa = fmaf(wr[v], Gd[v], aa);
     const bool live = act && w.valid;
-    const float x = live ? a.X[(size_t)mu * a.Npad + pa] : 0.f;
+    const float xv = a.X[(size_t)mm * a.Npad + pa];
+    const float x = live ? xv : 0.f;
     const float sg = 1.0f - x * x;
     const float ws = Wl[H * DP + H + mm] * sg;
     const float be = live ? ws * (eps + 2.0f * x * aa) : 0.f;
@@ -1316,12 +1352,15 @@ __global__ __launch_bounds__(256, 2) void k_adjoint(AdjArgs a) {
 #pragma unroll
       for (int e = 0; e < YG; ++e) {
         const int q = g ? HS::q(1, e) : HS::q(0, e);
-        Sn[e] = q >= 0 ? rowA[n * Y + q] : 0.f;
-        Sdn[e] = q >= 0 ? rowSb[n * Y + q] : 0.f;
+        const float va = rowA[n * Y + (q >= 0 ? q : 0)], vb = rowSb[n * Y + (q >= 0 ? q : 0)];
+        Sn[e] = q >= 0 ? va : 0.f;
+        Sdn[e] = q >= 0 ? vb : 0.f;
       }
       // E' and Gbar of the descriptors built from these sums
-      const float eA = (w.valid && lA <= L3) ? a.Ep[(size_t)(NR + (lA - 1) * NA + n) * Np + pa] : 0.f;
-      const float eB = (w.valid && lB <= L3) ? a.Ep[(size_t)(NR + (lB - 1) * NA + n) * Np + pa] : 0.f;
+      const float vA = a.Ep[(size_t)(NR + ((lA <= L3 ? lA : 1) - 1) * NA + n) * Np + pa];
+      const float vB = a.Ep[(size_t)(NR + ((lB <= L3 ? lB : 1) - 1) * NA + n) * Np + pa];
+      const float eA = (w.valid && lA <= L3) ? vA : 0.f;
+      const float eB = (w.valid && lB <= L3) ? vB : 0.f;
       float gA, gB;
       ep_blocks<NR, NA, L3, D>(Gb, n, g, gA, gB);
       float o[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, od[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
@@ -1332,14 +1371,16 @@ __global__ __launch_bounds__(256, 2) void k_adjoint(AdjArgs a) {
         sym_proj(sym_mul(M, M), o);
         sym_proj(sym_mul(Md, M), od);
         const int v4 = NR + L3 * NA + n;
-        e4 = (w.valid && g == 1) ? a.Ep[(size_t)v4 * Np + pa] : 0.f;
+        const float v = a.Ep[(size_t)v4 * Np + pa];
+        e4 = (w.valid && g == 1) ? v : 0.f;
         g4 = g == 1 ? Gb[v4] : 0.f;
       }
       if constexpr (L5 != 0) {
         P = Sn[0] * Sn[0] + Sn[1] * Sn[1] + Sn[2] * Sn[2];
         SS = Sn[0] * Sdn[0] + Sn[1] * Sdn[1] + Sn[2] * Sdn[2];
         const int v5 = NR + L3 * NA + (L4 ? NA : 0) + n;
-        e5 = (w.valid && g == 0) ? a.Ep[(size_t)v5 * Np + pa] : 0.f;
+        const float v = a.Ep[(size_t)v5 * Np + pa];
+        e5 = (w.valid && g == 0) ? v : 0.f;
         g5 = g == 0 ? Gb[v5] : 0.f;
       }
 #pragma unroll
@@ -1456,14 +1497,16 @@ struct OuterArgs {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ f32x4 ld_atoms4(const float* row, int p, int p1) {
-  // atoms p .. p + 3 of a row (p a multiple of 4, row padded to 32 atoms); zero past p1
+// atoms p .. p + 3 of a row (p a multiple of 4 inside the padded row), zero
+// past p1 or when off; the load itself is unconditional so that a group's
+// loads issue back to back
+__device__ __forceinline__ f32x4 ld_atoms4(const float* row, int p, int p1, bool on) {
   const float4 v = *reinterpret_cast<const float4*>(row + p);
   f32x4 r;
-  r[0] = p < p1 ? v.x : 0.f;
-  r[1] = p + 1 < p1 ? v.y : 0.f;
-  r[2] = p + 2 < p1 ? v.z : 0.f;
-  r[3] = p + 3 < p1 ? v.w : 0.f;
+  r[0] = (on && p < p1) ? v.x : 0.f;
+  r[1] = (on && p + 1 < p1) ? v.y : 0.f;
+  r[2] = (on && p + 2 < p1) ? v.z : 0.f;
+  r[3] = (on && p + 3 < p1) ? v.w : 0.f;
   return r;
 }
 
@@ -1509,17 +1552,19 @@ __global__ __launch_bounds__(256) void k_outer_sum(OuterArgs o) {
   // the current group's MFMAs
   f32x4 va1[kOSTM], va2[kOSTM], vb1[kOSTV], vb2[kOSTV];
   auto load = [&](int g) {
-    const int p = g + 4 * slot;
+    // past the block's atoms the loads read the segment start instead (always
+    // inside the padded rows) and are masked to zero
     const bool in = g < p1;
+    const int p = (in ? g : start) + 4 * slot;
 #pragma unroll
     for (int t = 0; t < kOSTM; ++t) {
-      va1[t] = (in && am[t]) ? ld_atoms4(a1[t], p, p1) : f32x4{0.f, 0.f, 0.f, 0.f};
-      va2[t] = (in && am[t]) ? -ld_atoms4(a2[t], p, p1) : f32x4{0.f, 0.f, 0.f, 0.f};
+      va1[t] = ld_atoms4(a1[t], p, p1, in && am[t]);
+      va2[t] = -ld_atoms4(a2[t], p, p1, in && am[t]);
     }
 #pragma unroll
     for (int t = 0; t < kOSTV; ++t) {
-      vb1[t] = (in && bm[t]) ? ld_atoms4(b1[t], p, p1) : f32x4{0.f, 0.f, 0.f, 0.f};
-      vb2[t] = (in && bm[t]) ? ld_atoms4(b2[t], p, p1) : f32x4{0.f, 0.f, 0.f, 0.f};
+      vb1[t] = ld_atoms4(b1[t], p, p1, in && bm[t]);
+      vb2[t] = ld_atoms4(b2[t], p, p1, in && bm[t]);
     }
   };
   load(p0 + 16 * wv);
