@@ -45,6 +45,7 @@ __device__ __forceinline__ unsigned axis_candidates(double d0, double L, double 
 // tiles of kNbrTile atoms; every lane of the block walks the same tiles.
 constexpr int kNbrAPB = 256 / 8;   // atoms per block
 constexpr int kNbrTile = 1024;
+constexpr int kNbrBuf = 24;   // entries buffered per lane (angular mask: 32 bits)
 constexpr float kNbrDelta = 0.01f;
 constexpr float kNbrFastL = 512.0f;
 
@@ -132,6 +133,7 @@ __device__ __forceinline__ void scan_range(const ScanCtx& c, const PosTile& t, i
 
 __global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
   __shared__ float tx[kNbrTile], ty[kNbrTile], tz[kNbrTile];
+  __shared__ uint32_t nbuf[256 * kNbrBuf];
   __shared__ int jr[2];
   const int s = threadIdx.x & 7;
   const int b0 = blockIdx.x * kNbrAPB;
@@ -205,12 +207,22 @@ __global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
       __syncthreads();
     }
   };
+  // one scan: each lane keeps its entries in an LDS buffer (angular
+  // membership as a bit mask), and after the 8-lane prefix copies them to
+  // their slots; a lane with more than kNbrBuf entries makes the whole block
+  // rescan and write directly
+  uint32_t* mybuf = nbuf + threadIdx.x;   // slot u at mybuf[256 u]
   int nR = 0, nA = 0;
-  auto count = [&](int, int, bool ang) {
+  uint32_t angmask = 0;
+  auto keep = [&](int j, int code, bool ang) {
+    if (nR < kNbrBuf) {
+      mybuf[blockDim.x * nR] = ((uint32_t)j << 5) | (uint32_t)code;
+      angmask |= ang ? (1u << nR) : 0u;
+    }
     ++nR;
     nA += ang ? 1 : 0;
   };
-  sweep(jb, je, count);
+  sweep(jb, je, keep);
   // inclusive prefix over the 8 lanes of the atom
   int pR = nR, pA = nA;
 #pragma unroll
@@ -224,17 +236,30 @@ __global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
   const int totR = __shfl(pR, 7, 8), totA = __shfl(pA, 7, 8);
   int wR = pR - nR, wA = pA - nA;
   const size_t col = (size_t)c.i;
-  auto write = [&](int j, int code, bool ang) {
-    const uint32_t e = ((uint32_t)j << 5) | (uint32_t)code;
-    if (wR < a.capR) a.idxR[col * a.capR + wR] = e;
-    ++wR;
-    if (ang) {
-      if (wA < a.capA) a.idxA[col * a.capA + wA] = e;
-      ++wA;
+  const bool spill = nR > kNbrBuf;
+  if (live && !spill) {
+    for (int u = 0; u < nR; ++u) {
+      const uint32_t e = mybuf[blockDim.x * u];
+      if (wR + u < a.capR) a.idxR[col * a.capR + wR + u] = e;
+      if ((angmask >> u) & 1u) {
+        if (wA < a.capA) a.idxA[col * a.capA + wA] = e;
+        ++wA;
+      }
     }
-  };
-  const bool wr = live && nR > 0 && wR < a.capR;
-  sweep(wr ? jb : 0, wr ? je : 0, write);
+  }
+  if (__syncthreads_or(live && spill)) {
+    auto write = [&](int j, int code, bool ang) {
+      const uint32_t e = ((uint32_t)j << 5) | (uint32_t)code;
+      if (wR < a.capR) a.idxR[col * a.capR + wR] = e;
+      ++wR;
+      if (ang) {
+        if (wA < a.capA) a.idxA[col * a.capA + wA] = e;
+        ++wA;
+      }
+    };
+    const bool wr = live && spill && wR < a.capR;
+    sweep(wr ? jb : 0, wr ? je : 0, write);
+  }
   if (live && s == 0) {
     a.cntR[i] = totR;
     a.cntA[i] = totA;
