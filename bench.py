@@ -94,12 +94,24 @@ def measured_traffic(kernel: str, workload: str):
     return d.get("bytes_per_launch")
 
 
+def measured_counters(kernel: str, workload: str):
+    """SQ busy fractions of a kernel from the committed rocprofv3 counter
+    summary, only if it was taken on the current kernel sources."""
+    p = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return {k: d[k] for k in ("valu_busy", "mfma_busy", "valu_instr_per_wave") if k in d}
+
+
 # ---------------------------------------------------------------- the bench
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--profile-reps", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -186,21 +198,54 @@ def main():
     stream.synchronize()
     loss_first = loss.cpu().numpy().copy()
     nep.check_flags(flags, "graph warmup")
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # one event between consecutive replays: the total gives ms_per_step, the
+    # differences the per-replay distribution
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     w0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
+    evs[0].record(stream)
+    for k in range(args.steps):
         graph.launch(stream)
-    ev1.record(stream)
+        evs[k + 1].record(stream)
     stream.synchronize()
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
-    ms_batched = ev0.elapsed_time(ev1) / args.steps
+    ms_batched = evs[0].elapsed_time(evs[-1]) / args.steps
+    per_replay = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)])
+    dist = {"median_ms": float(np.median(per_replay)), "p10_ms": float(np.percentile(per_replay, 10)),
+            "p90_ms": float(np.percentile(per_replay, 90))}
     loss_last = loss.cpu().numpy().copy()
     nep.check_flags(flags, "graph replays")
-    log(f"batched: {ms_batched:.3f} ms/step (events), {1e3 * wall / args.steps:.3f} ms/step (wall); "
+    log(f"batched: {ms_batched:.3f} ms/step (events), {1e3 * wall / args.steps:.3f} ms/step (wall), "
+        f"median {dist['median_ms']:.3f} p10 {dist['p10_ms']:.3f} p90 {dist['p90_ms']:.3f}; "
         f"loss {loss_first[0]:.5g} -> {loss_last[0]:.5g}")
+
+    # context only: the same step with the neighbor lists built once beforehand
+    # (training positions never change); the metric above rebuilds them
+    nb_c = nep.Neighbors(model, N)
+    ws_c = nep.workspace(model, S, N)
+    fl_c = torch.zeros(1, dtype=torch.int32, device="cuda")
+    nep.build_neighbors(model, dev, nb_c, ws_c, fl_c)
+    pc = theta.clone()
+    mc_, vc_, gc_ = (torch.zeros(P, device="cuda") for _ in range(3))
+    lc_ = torch.zeros(4, device="cuda")
+    sc_ = torch.ones(1, dtype=torch.int32, device="cuda")
+    graph_c = nep.TrainStepGraph(model, dev, nb_c, labels, lam, pc, mc_, vc_, gc_, lc_, sc_, ws_c, fl_c,
+                                 lr_start=lr, lr_stop=lr, stream=stream, cached_neighbors=True)
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            graph_c.launch(stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        graph_c.launch(stream)
+    e1.record(stream)
+    stream.synchronize()
+    nep.check_flags(fl_c, "cached-neighbor replays")
+    ms_cached = e0.elapsed_time(e1) / args.steps
+    graph_c.close()
+    log(f"cached neighbors: {ms_cached:.3f} ms/step")
     if args.mode == "batched":
         return
 
@@ -283,6 +328,7 @@ def main():
     flops = fm.get(dom, 0.0) * units
     achieved = flops / (kern_ms[dom] * 1e-3)
     traffic = measured_traffic(dom, args.workload)
+    counters = measured_counters(dom, args.workload)
     log("kernels (ms): " + ", ".join(f"{k} {v:.4f}" for k, v in sorted(kern_ms.items(), key=lambda x: -x[1])))
 
     # ---------------- CPU baseline: the FP64 oracle on a bounded sample
@@ -331,7 +377,13 @@ def main():
         "plain": plain_out,
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": traffic,
-                     "flops_per_atom": fm.get(dom, 0.0), "units": units, "kernel_ms": kern_ms[dom]},
+                     "flops_per_atom": fm.get(dom, 0.0), "units": units, "kernel_ms": kern_ms[dom],
+                     "frac_of_nonpacked_peak": achieved / (PEAK_FP32_VECTOR / 2),
+                     "hbm_frac": (traffic / (kern_ms[dom] * 1e-3) / PEAK_HBM) if traffic else None,
+                     "counters": counters},
+        "replay_distribution": dist,
+        "cached_neighbors": {"ms_per_step": ms_cached, "value": N / (ms_cached * 1e-3), "unit": "atoms/s",
+                             "note": "context only: lists built once before timing"},
         "kernels_ms": kern_ms,
         "cpu_baseline": cpu,
         "loss": {"at_theta": float(loss0[0]), "after_warmup": float(loss_first[0]),

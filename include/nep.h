@@ -201,11 +201,17 @@ typedef struct {
   float beta1, beta2, eps;
 } nep_adam_config;
 
+/* graph_flags bit NEP_GRAPH_CACHED_NEIGHBORS: the graph leaves out the neighbor
+ * build (lists, reverse index and species order) and reuses what an earlier
+ * nep_build_neighbors() call with the same nbrs and ws produced.  Training
+ * positions never change, so this is the step with cached lists. */
+#define NEP_GRAPH_CACHED_NEIGHBORS 1
+
 int nep_train_step_graph_create(const nep_model* model, const nep_batch* batch, nep_neighbors* nbrs,
                                 const nep_labels* labels, const float lambda[3], float* params,
                                 float* m, float* v, float* grad, float* loss, int32_t* d_step,
                                 const nep_adam_config* adam, void* ws, int32_t* d_flags,
-                                void* stream, void** graph);
+                                int32_t graph_flags, void* stream, void** graph);
 int nep_train_step_graph_launch(void* graph, void* stream);
 int nep_train_step_graph_destroy(void* graph);
 

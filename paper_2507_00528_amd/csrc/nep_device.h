@@ -249,6 +249,17 @@ __device__ __forceinline__ void sym_proj(const Sym3& q, float (&o)[5]) {
 }
 
 // ----------------------------------------------------------- wave helpers
+// Workgroups of one launch are dealt round-robin to the 8 XCDs, each with its
+// own L2.  xcd_block() renumbers them so that XCD x runs a contiguous range
+// of logical blocks (a bijection for any grid size): blocks that read the
+// same structure's data then share one L2 instead of filling all eight.
+constexpr int kXCD = 8;
+__device__ __forceinline__ int xcd_block() {
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int q = nb / kXCD, r = nb % kXCD, x = b % kXCD;
+  return x * q + min(x, r) + b / kXCD;
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);

@@ -136,7 +136,7 @@ __global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
   __shared__ uint32_t nbuf[256 * kNbrBuf];
   __shared__ int jr[2];
   const int s = threadIdx.x & 7;
-  const int b0 = blockIdx.x * kNbrAPB;
+  const int b0 = xcd_block() * kNbrAPB;
   const int i = b0 + (threadIdx.x >> 3);
   const bool live = i < a.N;
   ScanCtx c;
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
 __global__ __launch_bounds__(256) void k_reverse(int N, const uint32_t* __restrict__ idx,
                                                  const int* __restrict__ cnt, int cap, int* __restrict__ rev) {
   const int s = threadIdx.x & 7;
-  const int i = blockIdx.x * 32 + (threadIdx.x >> 3);
+  const int i = xcd_block() * 32 + (threadIdx.x >> 3);
   if (i >= N) return;
   const int n = min(cnt[i], cap);
   for (int k = s; k < n; k += 8) {
@@ -973,7 +973,7 @@ __global__ __launch_bounds__(256) void k_force_gather(int N, PairLists nb, const
                                                       const float* __restrict__ fA, float* __restrict__ F,
                                                       float* __restrict__ Fuser) {
   const int s = threadIdx.x & 7;
-  const int i = blockIdx.x * 32 + (threadIdx.x >> 3);
+  const int i = xcd_block() * 32 + (threadIdx.x >> 3);
   float fx = 0.f, fy = 0.f, fz = 0.f;
   if (i < N) {
     gather_list(i, s, nb.idxR, nb.cntR, nb.revR, nb.capR, fR, fx, fy, fz);
@@ -999,6 +999,34 @@ __global__ __launch_bounds__(256) void k_force_gather(int N, PairLists nb, const
 // Eqs. 10-12 and the cotangents dL/dE(n), dL/dF_i, dL/dW(n).  Sums run in
 // float64 in a fixed order.
 constexpr int kRedBlk = 256;
+
+// Loss of Eqs. 9-12 from the per-structure partials, float64 in a fixed
+// order (one block).
+__device__ void loss_final_block(int S, int N, float le, float lf, float lv, const double* lpart, float* loss,
+                                 int* flags) {
+  __shared__ double red[3][kRedBlk];
+  double acc[3] = {0, 0, 0};
+  for (int s = threadIdx.x; s < S; s += kRedBlk)
+    for (int q = 0; q < 3; ++q) acc[q] += lpart[3 * s + q];
+  for (int q = 0; q < 3; ++q) red[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int st = kRedBlk / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st)
+      for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double Le = S > 0 ? red[0][0] / S : 0.0;
+    const double Lf = N > 0 ? red[1][0] / (3.0 * N) : 0.0;
+    const double Lv = S > 0 ? red[2][0] / (6.0 * S) : 0.0;
+    const double L = le * Le + lf * Lf + lv * Lv;
+    loss[0] = (float)L;
+    loss[1] = (float)Le;
+    loss[2] = (float)Lf;
+    loss[3] = (float)Lv;
+    if (flags && !isfinite(L)) atomicOr(flags, FL_NONFINITE);
+  }
+}
 
 struct StructArgs {
   int S, N;
@@ -1084,28 +1112,7 @@ __global__ __launch_bounds__(kRedBlk) void k_struct(StructArgs a) {
 __global__ __launch_bounds__(kRedBlk) void k_loss_final(int S, int N, float le, float lf, float lv,
                                                         const double* __restrict__ lpart, float* __restrict__ loss,
                                                         int* __restrict__ flags) {
-  __shared__ double red[3][kRedBlk];
-  double acc[3] = {0, 0, 0};
-  for (int s = threadIdx.x; s < S; s += kRedBlk)
-    for (int q = 0; q < 3; ++q) acc[q] += lpart[3 * s + q];
-  for (int q = 0; q < 3; ++q) red[q][threadIdx.x] = acc[q];
-  __syncthreads();
-  for (int st = kRedBlk / 2; st > 0; st >>= 1) {
-    if (threadIdx.x < st)
-      for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + st];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    const double Le = S > 0 ? red[0][0] / S : 0.0;
-    const double Lf = N > 0 ? red[1][0] / (3.0 * N) : 0.0;
-    const double Lv = S > 0 ? red[2][0] / (6.0 * S) : 0.0;
-    const double L = le * Le + lf * Lf + lv * Lv;
-    loss[0] = (float)L;
-    loss[1] = (float)Le;
-    loss[2] = (float)Lf;
-    loss[3] = (float)Lv;
-    if (flags && !isfinite(L)) atomicOr(flags, FL_NONFINITE);
-  }
+  loss_final_block(S, N, le, lf, lv, lpart, loss, flags);
 }
 
 // ================================================================= adjoint
@@ -1655,7 +1662,22 @@ dim3 outer_grid(int M, int V, int T) {
 // wavefronts of species I; one thread per slot, so reads run along rows.
 constexpr int kPRChunks = 128;
 
-__global__ __launch_bounds__(256) void k_part_reduce(int PW, const int* seg, const float* part, double* pp) {
+// Loss reduction carried by k_part_reduce (one extra row of blocks) so that a
+// loss-and-gradient pass spends no launch on it.
+struct LossArgs {
+  int on, S, N;
+  float le, lf, lv;
+  const double* lpart;
+  float* loss;
+  int* flags;
+};
+
+__global__ __launch_bounds__(256) void k_part_reduce(int PW, const int* seg, const float* part, double* pp,
+                                                     LossArgs la) {
+  if ((int)blockIdx.y == (int)gridDim.y - 1 && la.on) {
+    if (blockIdx.x == 0) loss_final_block(la.S, la.N, la.le, la.lf, la.lv, la.lpart, la.loss, la.flags);
+    return;
+  }
   const int I = blockIdx.y, b = blockIdx.x;
   const int start = seg[2 * I], count = seg[2 * I + 1];
   const int w0 = start / kAPW, w1 = count > 0 ? (start + count + kAPW - 1) / kAPW : w0;
@@ -1780,8 +1802,15 @@ __global__ __launch_bounds__(256) void k_adam_dev(int64_t P, float* __restrict__
   adam_one(th, m, v, g[q], lr, c.b1, c.b2, c.eps, c1, c2, q);
 }
 
-__global__ void k_step_inc(int* step) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *step += 1;
+// First node of a captured train step: clear the flags, latch the step this
+// replay uses (Adam reads the latched copy) and advance the caller's counter.
+__global__ void k_graph_head(int* flags, int* step, int* cur) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    flags[0] = 0;
+    const int st = step[0];
+    cur[0] = st;
+    step[0] = st + 1;
+  }
 }
 
 __global__ void k_fill_i32(int* p, int n, int v) {
@@ -1876,7 +1905,7 @@ size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
   int N, S, T, D, Y, H, NR, TKR, Npad, nwaves, nblk, PW, NA, capR, capA;
   size_t order, seg, blk, astruct, revR, revA, G, Sst, Ep, X, eatom, fR, fA, wv, F, fbar, Es, Ws, eps, wbar, lpart,
-      Gd, FRst, FPst, Gbr, beta, w1s, part, pp, w0part, crpart, total;
+      Gd, FRst, FPst, Gbr, beta, w1s, part, pp, w0part, crpart, cur_step, total;
 };
 
 Layout make_layout(const nep_model* m, const Ops* o, int S, int N) {
@@ -1937,6 +1966,7 @@ Layout make_layout(const nep_model* m, const Ops* o, int S, int N) {
   L.pp = take(8 * (size_t)L.T * kPRChunks * L.PW);
   L.w0part = take(4 * (size_t)L.T * kOSBlocks * L.H * L.D);
   L.crpart = take(4 * (size_t)L.T * kOSBlocks * L.NR * L.TKR);
+  L.cur_step = take(4);
   L.total = off;
   return L;
 }
@@ -2093,7 +2123,7 @@ FwdArgs fwd_args(const Ctx& c, const nep_neighbors* nb, const float* params) {
 // forward + force gather + per-structure sums (+ loss when labels given)
 void run_forward(const Ctx& c, const nep_neighbors* nb, const float* params, float* e_atom, float* e_struct,
                  float* force, float* virial, const nep_labels* lab, const float* lam, float* loss, int32_t* flags,
-                 Prof* pr) {
+                 Prof* pr, bool defer_loss = false) {
   const int N = c.L.N, S = c.b->n_struct;
   if (N > 0) {
     FwdArgs a = fwd_args(c, nb, params);
@@ -2126,7 +2156,8 @@ void run_forward(const Ctx& c, const nep_neighbors* nb, const float* params, flo
     s.fbar = at<float>(c.ws, c.L.fbar);
     s.lpart = at<double>(c.ws, c.L.lpart);
     NEP_LAUNCH(pr, "struct_sums", hipLaunchKernelGGL(k_struct, dim3(S), dim3(kRedBlk), 0, c.st, s));
-    if (lab)
+    // with defer_loss the adjoint's first reduction launch sums the loss
+    if (lab && !defer_loss)
       NEP_LAUNCH(pr, "loss_final",
                  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kRedBlk), 0, c.st, S, N, s.le, s.lf, s.lv, s.lpart,
                                     loss, flags));
@@ -2135,7 +2166,7 @@ void run_forward(const Ctx& c, const nep_neighbors* nb, const float* params, flo
 
 // adjoint + gradient reductions; cotangents from eps/fbar/wbar pointers
 void run_adjoint(const Ctx& c, const nep_neighbors* nb, const float* params, const float* eps, const float* fbar,
-                 const float* wbar, float* grad, Prof* pr) {
+                 const float* wbar, float* grad, Prof* pr, LossArgs la = LossArgs{}) {
   const nep_model* m = c.m;
   const int N = c.L.N;
   if (N > 0) {
@@ -2187,7 +2218,8 @@ void run_adjoint(const Ctx& c, const nep_neighbors* nb, const float* params, con
     }
     double* pp = at<double>(c.ws, c.L.pp);
     NEP_LAUNCH(pr, "part_reduce",
-               hipLaunchKernelGGL(k_part_reduce, dim3(kPRChunks, T), dim3(256), 0, c.st, c.L.PW, seg, a.part, pp));
+               hipLaunchKernelGGL(k_part_reduce, dim3(kPRChunks, T + (la.on ? 1 : 0)), dim3(256), 0, c.st, c.L.PW,
+                                  seg, a.part, pp, la));
     GradArgs g;
     g.T = T;
     g.NR = m->n_rad;
@@ -2231,9 +2263,23 @@ int loss_grad_seq(Ctx& c, nep_neighbors* nb, const float* params, const nep_labe
                   float* loss, float* grad, float* e_struct, float* force, float* virial, int32_t* flags, Prof* pr,
                   bool with_neighbors) {
   if (with_neighbors) run_neighbors(c, nb, flags, pr);
-  run_forward(c, nb, params, nullptr, e_struct, force, virial, labels, lam, loss, flags, pr);
+  // with atoms present the loss is summed by the adjoint's reduction launch
+  const int N = c.L.N, S = c.b->n_struct;
+  LossArgs la{};
+  if (N > 0 && S > 0 && labels) {
+    la.on = 1;
+    la.S = S;
+    la.N = N;
+    la.le = lam[0];
+    la.lf = lam[1];
+    la.lv = lam[2];
+    la.lpart = at<double>(c.ws, c.L.lpart);
+    la.loss = loss;
+    la.flags = flags;
+  }
+  run_forward(c, nb, params, nullptr, e_struct, force, virial, labels, lam, loss, flags, pr, la.on != 0);
   run_adjoint(c, nb, params, at<float>(c.ws, c.L.eps), at<float>(c.ws, c.L.fbar), at<float>(c.ws, c.L.wbar), grad,
-              pr);
+              pr, la);
   return hip_ok();
 }
 
@@ -2362,7 +2408,7 @@ float nep_lr_schedule(int64_t s, float lr_start, float lr_stop, int64_t n_warmup
 int nep_train_step_graph_create(const nep_model* m, const nep_batch* b, nep_neighbors* nb, const nep_labels* labels,
                                 const float lambda[3], float* params, float* mm, float* vv, float* grad, float* loss,
                                 int32_t* d_step, const nep_adam_config* adam, void* ws, int32_t* d_flags,
-                                void* stream, void** graph) {
+                                int32_t graph_flags, void* stream, void** graph) {
   Ctx c;
   int rc = setup(c, m, b, ws, stream);
   if (rc) return rc;
@@ -2377,13 +2423,14 @@ int nep_train_step_graph_create(const nep_model* m, const nep_batch* b, nep_neig
     (void)hipStreamDestroy(cap);
     return NEP_ERR_HIP;
   }
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, cap, d_flags, 1, 0);
-  loss_grad_seq(c, nb, params, labels, lambda, loss, grad, nullptr, nullptr, nullptr, d_flags, nullptr, true);
+  int* cur = at<int>(c.ws, c.L.cur_step);
+  hipLaunchKernelGGL(k_graph_head, dim3(1), dim3(64), 0, cap, d_flags, d_step, cur);
+  loss_grad_seq(c, nb, params, labels, lambda, loss, grad, nullptr, nullptr, nullptr, d_flags, nullptr,
+                (graph_flags & NEP_GRAPH_CACHED_NEIGHBORS) == 0);
   const int64_t P = param_count(m);
   AdamDev ad{adam->lr_start, adam->lr_stop, adam->n_warmup, adam->n_total, adam->beta1, adam->beta2, adam->eps};
   hipLaunchKernelGGL(k_adam_dev, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, cap, P, params, mm, vv, grad,
-                     d_step, ad);
-  hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(64), 0, cap, d_step);
+                     cur, ad);
   const hipError_t e1 = hipStreamEndCapture(cap, &g);
   (void)hipStreamDestroy(cap);
   if (e1 != hipSuccess || !g) return NEP_ERR_HIP;

@@ -163,3 +163,36 @@ def test_graph_step_matches_eager():
         np.testing.assert_allclose(params_g.cpu().numpy(), params_e.cpu().numpy(), rtol=0, atol=1e-7)
     assert int(step.item()) == 4
     g.close()
+
+
+def test_graph_with_cached_neighbors_matches_eager():
+    """A graph that reuses an earlier neighbor build gives the eager loss,
+    gradient and Adam update."""
+    import torch
+    from paper_2507_00528_amd import nep
+    c, r = case("tiny")
+    P = c.sizes.n_params
+    ws2 = nep.workspace(r.model, c.batch.n_struct, c.batch.n_atom)
+    nb2 = nep.Neighbors(r.model, c.batch.n_atom)
+    flags2 = torch.zeros(1, dtype=torch.int32, device="cuda")
+    nep.build_neighbors(r.model, r.batch, nb2, ws2, flags2)
+    params_g = r.params.clone()
+    m_g, v_g, grad_g = (torch.zeros(P, device="cuda") for _ in range(3))
+    loss_g = torch.zeros(4, device="cuda")
+    step = torch.ones(1, dtype=torch.int32, device="cuda")
+    g = nep.TrainStepGraph(r.model, r.batch, nb2, r.labels, c.lam, params_g, m_g, v_g, grad_g, loss_g, step, ws2,
+                           flags2, lr_start=1e-3, lr_stop=1e-3, cached_neighbors=True)
+    params_e = r.params.clone()
+    m_e, v_e, grad_e = (torch.zeros(P, device="cuda") for _ in range(3))
+    loss_e = torch.zeros(4, device="cuda")
+    nep.build_neighbors(r.model, r.batch, r.nbrs, r.ws, r.flags)
+    for it in range(1, 4):
+        g.launch()
+        torch.cuda.synchronize()
+        nep.loss_grad(r.model, r.batch, r.nbrs, params_e, r.labels, c.lam, loss_e, grad_e, r.ws, r.flags)
+        nep.adam_step(params_e, m_e, v_e, grad_e, 1e-3, it)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(loss_g.cpu().numpy(), loss_e.cpu().numpy(), rtol=1e-6)
+        np.testing.assert_allclose(params_g.cpu().numpy(), params_e.cpu().numpy(), rtol=0, atol=1e-7)
+    assert int(flags2.item()) == 0
+    g.close()
