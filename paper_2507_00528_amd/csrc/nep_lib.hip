@@ -504,6 +504,11 @@ __device__ __forceinline__ WaveCtx wave_ctx(const int* __restrict__ order, const
   return c;
 }
 
+// LDS written by one lane and read by another lane of the same wavefront: a
+// wavefront's LDS instructions complete in issue order, so it is enough that
+// the compiler keeps every memory access on its side of this point.
+__device__ __forceinline__ void lds_lane_exchange() { asm volatile("" ::: "memory"); }
+
 // ========================================================= atom groups
 // Per-atom kernels run 8 lanes per atom, 8 atoms per wavefront and 32 atoms
 // per block.  Lane s = l & 7 of an atom's group splits the radial pairs
@@ -1273,52 +1278,59 @@ __global__ __launch_bounds__(256, 2) void k_adjoint(AdjArgs a) {
 #pragma unroll
     for (int e = 0; e < YG; ++e) Sd[n][e] = quad_sum(Sd[n][e]);
 
-  // ---- Gdot of the angular descriptors, one channel at a time; S (stored by
-  //      the forward pass) and Sdot are parked in the atom's LDS row
+  // ---- Gdot of the angular descriptors.  Sdot is parked in the atom's LDS
+  //      row; channel n is then handled by the lanes of pair slot n mod 4
+  //      (both harmonic groups), which also park S (stored by the forward
+  //      pass) for the later phases
   {
     const int nAg = g ? HS::nA1 : HS::nA0;
     const int lA = g ? 2 : 1, lB = g ? 3 : 4;
 #pragma unroll
-    for (int n = 0; n < NA; ++n) {
-      float Sn[YG];
+    for (int n = 0; n < NA; ++n)
+      if (w.p == (n & 3)) {
+#pragma unroll
+        for (int e = 0; e < YG; ++e) {
+          const int q = g ? HS::q(1, e) : HS::q(0, e);
+          if (q >= 0) rowSb[n * Y + q] = Sd[n][e];
+        }
+      }
+    lds_lane_exchange();
+    for (int n = w.p; n < NA; n += 4) {
+      float Sn[YG], Sdn[YG];
 #pragma unroll
       for (int e = 0; e < YG; ++e) {
         const int q = g ? HS::q(1, e) : HS::q(0, e);
-        // unconditional load from a valid address, then the mask: a guarded
+        const int qc = q >= 0 ? q : 0;
+        // unconditional loads from valid addresses, then the mask: a guarded
         // load would become a branch that waits for each value in turn
-        const float v = a.Sst[(size_t)(n * Y + (q >= 0 ? q : 0)) * a.Npad + pa];
+        const float v = a.Sst[(size_t)(n * Y + qc) * a.Npad + pa];
+        const float d = rowSb[n * Y + qc];
         Sn[e] = (w.valid && q >= 0) ? v : 0.f;
+        Sdn[e] = q >= 0 ? d : 0.f;
       }
       float qa = 0.f, qb = 0.f;
 #pragma unroll
       for (int e = 0; e < YG; ++e) {
-        const float v = 2.0f * csel<HS>(g, e) * Sn[e] * Sd[n][e];
+        const float v = 2.0f * csel<HS>(g, e) * Sn[e] * Sdn[e];
         if (e < nAg) qa += v; else qb += v;
       }
-      if (w.p == 0) {
-        if (lA <= L3) row[NR + (lA - 1) * NA + n] = qa;
-        if (lB <= L3) row[NR + (lB - 1) * NA + n] = qb;
-      }
+      if (lA <= L3) row[NR + (lA - 1) * NA + n] = qa;
+      if (lB <= L3) row[NR + (lB - 1) * NA + n] = qb;
       if constexpr (L4 != 0) {
         const Sym3 M = sym_of(Sn[0], Sn[1], Sn[2], Sn[3], Sn[4]);
-        const Sym3 Md = sym_of(Sd[n][0], Sd[n][1], Sd[n][2], Sd[n][3], Sd[n][4]);
+        const Sym3 Md = sym_of(Sdn[0], Sdn[1], Sdn[2], Sdn[3], Sdn[4]);
         const float v = 3.0f * sym_dot(sym_mul(M, M), Md);
-        if (g == 1 && w.p == 0) row[NR + L3 * NA + n] = v;
+        if (g == 1) row[NR + L3 * NA + n] = v;
       }
       if constexpr (L5 != 0) {
         const float P = Sn[0] * Sn[0] + Sn[1] * Sn[1] + Sn[2] * Sn[2];
-        const float SS = Sn[0] * Sd[n][0] + Sn[1] * Sd[n][1] + Sn[2] * Sd[n][2];
-        if (g == 0 && w.p == 0) row[NR + L3 * NA + (L4 ? NA : 0) + n] = 4.0f * P * SS;
+        const float SS = Sn[0] * Sdn[0] + Sn[1] * Sdn[1] + Sn[2] * Sdn[2];
+        if (g == 0) row[NR + L3 * NA + (L4 ? NA : 0) + n] = 4.0f * P * SS;
       }
-      if (w.p == 0) {
 #pragma unroll
-        for (int e = 0; e < YG; ++e) {
-          const int q = g ? HS::q(1, e) : HS::q(0, e);
-          if (q >= 0) {
-            rowA[n * Y + q] = Sn[e];
-            rowSb[n * Y + q] = Sd[n][e];
-          }
-        }
+      for (int e = 0; e < YG; ++e) {
+        const int q = g ? HS::q(1, e) : HS::q(0, e);
+        if (q >= 0) rowA[n * Y + q] = Sn[e];
       }
     }
   }
@@ -1373,13 +1385,19 @@ __global__ __launch_bounds__(256, 2) void k_adjoint(AdjArgs a) {
   for (int n = 0; n < NR; ++n)
     if (w.valid && s == (n & 7)) a.Gbr[(size_t)n * a.Npad + pa] = Gb[n];
 
-  // ---- Sbar and A of this lane's harmonic group, in place in the atom's LDS row
+  // ---- Sbar and A of this lane's harmonic group, in place in the atom's LDS
+  //      row, channel n by the lanes of pair slot n mod 4; Gbar goes to the
+  //      row's first D floats (Gdot there has been read)
+#pragma unroll
+  for (int v = 0; v < D; ++v)
+    if (s == (v & 7)) row[v] = Gb[v];
+  lds_lane_exchange();
   {
     const int nAg = g ? HS::nA1 : HS::nA0;
     const int lA = g ? 2 : 1, lB = g ? 3 : 4;
+    const int lAc = lA <= L3 ? lA : 1, lBc = lB <= L3 ? lB : 1;
     const size_t Np = a.Npad;
-#pragma unroll
-    for (int n = 0; n < NA; ++n) {
+    for (int n = w.p; n < NA; n += 4) {
       float Sn[YG], Sdn[YG];
 #pragma unroll
       for (int e = 0; e < YG; ++e) {
@@ -1389,12 +1407,12 @@ __global__ __launch_bounds__(256, 2) void k_adjoint(AdjArgs a) {
         Sdn[e] = q >= 0 ? vb : 0.f;
       }
       // E' and Gbar of the descriptors built from these sums
-      const float vA = a.Ep[(size_t)(NR + ((lA <= L3 ? lA : 1) - 1) * NA + n) * Np + pa];
-      const float vB = a.Ep[(size_t)(NR + ((lB <= L3 ? lB : 1) - 1) * NA + n) * Np + pa];
+      const float vA = a.Ep[(size_t)(NR + (lAc - 1) * NA + n) * Np + pa];
+      const float vB = a.Ep[(size_t)(NR + (lBc - 1) * NA + n) * Np + pa];
+      const float bA = row[NR + (lAc - 1) * NA + n], bB = row[NR + (lBc - 1) * NA + n];
       const float eA = (w.valid && lA <= L3) ? vA : 0.f;
       const float eB = (w.valid && lB <= L3) ? vB : 0.f;
-      float gA, gB;
-      ep_blocks<NR, NA, L3, D>(Gb, n, g, gA, gB);
+      const float gA = lA <= L3 ? bA : 0.f, gB = lB <= L3 ? bB : 0.f;
       float o[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, od[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
       float e4 = 0.f, g4 = 0.f, e5 = 0.f, g5 = 0.f, P = 0.f, SS = 0.f;
       if constexpr (L4 != 0) {
@@ -1403,17 +1421,17 @@ __global__ __launch_bounds__(256, 2) void k_adjoint(AdjArgs a) {
         sym_proj(sym_mul(M, M), o);
         sym_proj(sym_mul(Md, M), od);
         const int v4 = NR + L3 * NA + n;
-        const float v = a.Ep[(size_t)v4 * Np + pa];
+        const float v = a.Ep[(size_t)v4 * Np + pa], b = row[v4];
         e4 = (w.valid && g == 1) ? v : 0.f;
-        g4 = g == 1 ? Gb[v4] : 0.f;
+        g4 = g == 1 ? b : 0.f;
       }
       if constexpr (L5 != 0) {
         P = Sn[0] * Sn[0] + Sn[1] * Sn[1] + Sn[2] * Sn[2];
         SS = Sn[0] * Sdn[0] + Sn[1] * Sdn[1] + Sn[2] * Sdn[2];
         const int v5 = NR + L3 * NA + (L4 ? NA : 0) + n;
-        const float v = a.Ep[(size_t)v5 * Np + pa];
+        const float v = a.Ep[(size_t)v5 * Np + pa], b = row[v5];
         e5 = (w.valid && g == 0) ? v : 0.f;
-        g5 = g == 0 ? Gb[v5] : 0.f;
+        g5 = g == 0 ? b : 0.f;
       }
 #pragma unroll
       for (int e = 0; e < YG; ++e) {
@@ -1430,7 +1448,7 @@ __global__ __launch_bounds__(256, 2) void k_adjoint(AdjArgs a) {
           Av += 4.0f * e5 * P * Sn[e];
           Sb += 4.0f * g5 * P * Sn[e] - e5 * (8.0f * SS * Sn[e] + 4.0f * P * Sdn[e]);
         }
-        if (w.p == 0 && q >= 0) {
+        if (q >= 0) {
           rowA[n * Y + q] = Av;
           rowSb[n * Y + q] = Sb;
         }
