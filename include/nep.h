@@ -186,6 +186,26 @@ int nep_adam_step(int64_t P, float* params, float* m, float* v, const float* gra
 /* Learning rate of Eq. 17 at step s (host scalar helper). */
 float nep_lr_schedule(int64_t s, float lr_start, float lr_stop, int64_t n_warmup, int64_t n_total);
 
+/* Inference path (outside the training step): n_steps of velocity Verlet
+ * with the NEP forces, in eV, A, fs and amu.  Each step kicks the velocities
+ * by half a step with `force`, moves and wraps the positions into [0, L),
+ * rebuilds the neighbor lists, evaluates E and F (Eqs. 1-3) and kicks again.
+ *   pos     must be batch->pos; advanced in place (device, SoA [3*n_atom])
+ *   mass    [n_types] atomic masses in amu (device)
+ *   vel     [3*n_atom] SoA velocities in A/fs, updated (device)
+ *   force   [3*n_atom] SoA forces at the current positions on entry (from
+ *           nep_energy_force_virial or the previous call), at the final
+ *           positions on return (device)
+ *   e_pot   [n_struct] potential energies at the final positions (device)
+ *   e_kin   [n_struct] kinetic energies at the final velocities, or NULL
+ *   ws      a workspace that already holds this batch's neighbor build
+ *   d_flags device flag word (required; see nep_build_neighbors)
+ * Returns NEP_ERR_ARG for a NULL or mismatched pointer, n_steps < 0 or a
+ * non-finite dt. */
+int nep_md_step(const nep_model* model, const nep_batch* batch, float* pos, nep_neighbors* nbrs,
+                const float* params, const float* mass, float* vel, float* force, float dt, int32_t n_steps,
+                float* e_pot, float* e_kin, void* ws, int32_t* d_flags, void* stream);
+
 /* A whole training step — neighbors, forward, loss, adjoint, gradient and
  * Adam — recorded once as a HIP graph and replayed by
  * nep_train_step_graph_launch().  All pointers are captured: their contents

@@ -55,6 +55,8 @@ SIGNATURES = [
                                 VP, VP, VP, VP, VP, VP, VP, VP]),
     ("nep_adam_step", C.c_int, [C.c_int64, VP, VP, VP, VP, F32, F32, F32, F32, I32, VP]),
     ("nep_lr_schedule", F32, [C.c_int64, F32, F32, C.c_int64, C.c_int64]),
+    ("nep_md_step", C.c_int, [P(NepModel), P(NepBatch), VP, P(NepNeighbors), VP, VP, VP, VP, F32, I32, VP, VP,
+                              VP, VP, VP]),
     ("nep_train_step_graph_create", C.c_int, [P(NepModel), P(NepBatch), P(NepNeighbors), P(NepLabels),
                                               P(F32 * 3), VP, VP, VP, VP, VP, VP, P(NepAdamConfig), VP, VP, I32,
                                               VP, P(VP)]),

@@ -1842,6 +1842,82 @@ __global__ void k_fill_f32(float* p, int64_t n, float v) {
 }
 
 // ================================================================ dispatch
+// ====================================================================== MD
+// Velocity Verlet for the inference path, in eV, A, fs and amu: the
+// acceleration of atom i is F_i / m_i times kAccel, and 1 amu A^2/fs^2 is
+// 1/kAccel eV.
+constexpr float kAccel = 9.648533212e-3f;
+
+struct MDArgs {
+  int N, T;
+  const int* type;
+  const int* astruct;
+  const float* box;
+  const float* mass;   // [T] amu
+  float* pos;          // [3][N]
+  float* vel;          // [3][N] A/fs
+  const float* F;      // [3][N] eV/A
+  float* ekin;         // [N] eV (kick only)
+  float hdt, dt;
+};
+
+__device__ __forceinline__ float inv_mass(const MDArgs& a, int i) {
+  const int t = a.type[i];
+  return (t >= 0 && t < a.T) ? kAccel / a.mass[t] : 0.f;
+}
+
+// half kick with the forces at the current positions, drift, wrap into [0, L)
+__global__ __launch_bounds__(256) void k_md_drift(MDArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.N) return;
+  const float im = inv_mass(a, i);
+  const int st = a.astruct[i];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const size_t q = (size_t)c * a.N + i;
+    const float v = fmaf(a.hdt * im, a.F[q], a.vel[q]);
+    a.vel[q] = v;
+    const float L = a.box[3 * st + c];
+    float x = fmaf(a.dt, v, a.pos[q]);
+    x -= L * floorf(x / L);
+    if (x >= L) x -= L;
+    if (!(x >= 0.f)) x = 0.f;
+    a.pos[q] = x;
+  }
+}
+
+// half kick with the forces at the new positions; kinetic energy per atom
+__global__ __launch_bounds__(256) void k_md_kick(MDArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.N) return;
+  const float im = inv_mass(a, i);
+  float v2 = 0.f;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const size_t q = (size_t)c * a.N + i;
+    const float v = fmaf(a.hdt * im, a.F[q], a.vel[q]);
+    a.vel[q] = v;
+    v2 = fmaf(v, v, v2);
+  }
+  a.ekin[i] = im > 0.f ? 0.5f * v2 / im : 0.f;
+}
+
+// out[s] = sum of x over the atoms of structure s (float64, one block each)
+__global__ __launch_bounds__(256) void k_struct_sum(const int* __restrict__ aoff, const float* __restrict__ x,
+                                                    float* __restrict__ out) {
+  __shared__ double red[256];
+  const int s = blockIdx.x;
+  double acc = 0.0;
+  for (int i = aoff[s] + threadIdx.x; i < aoff[s + 1]; i += blockDim.x) acc += x[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[s] = (float)red[0];
+}
+
 struct Ops {
   int T, NR, NA, KR, KA, L3, L4, L5, D, Y, PS;
   void (*forward)(const FwdArgs&, dim3, hipStream_t);
@@ -2369,6 +2445,41 @@ int nep_energy_force_virial(const nep_model* m, const nep_batch* b, const nep_ne
   if ((rc = check_nbrs(nb, b->n_atom))) return rc;
   if (!params) return NEP_ERR_ARG;
   run_forward(c, nb, params, e_atom, e_struct, force, virial, nullptr, nullptr, nullptr, nullptr, nullptr);
+  return hip_ok();
+}
+
+int nep_md_step(const nep_model* m, const nep_batch* b, float* pos, nep_neighbors* nb, const float* params,
+                const float* mass, float* vel, float* force, float dt, int32_t n_steps, float* e_pot, float* e_kin,
+                void* ws, int32_t* d_flags, void* stream) {
+  Ctx c;
+  int rc = setup(c, m, b, ws, stream);
+  if (rc) return rc;
+  if ((rc = check_nbrs(nb, b->n_atom))) return rc;
+  const int N = b->n_atom, S = b->n_struct;
+  if (!params || !mass || !d_flags || n_steps < 0 || !std::isfinite(dt)) return NEP_ERR_ARG;
+  if (N > 0 && (pos != b->pos || !vel || !force)) return NEP_ERR_ARG;
+  if (N == 0 || n_steps == 0) return NEP_OK;
+  MDArgs a;
+  a.N = N;
+  a.T = m->n_types;
+  a.type = b->type;
+  a.astruct = at<int>(c.ws, c.L.astruct);
+  a.box = b->box;
+  a.mass = mass;
+  a.pos = pos;
+  a.vel = vel;
+  a.F = force;
+  a.ekin = at<float>(c.ws, c.L.eatom);   // reused after the last force evaluation
+  a.hdt = 0.5f * dt;
+  a.dt = dt;
+  for (int k = 0; k < n_steps; ++k) {
+    hipLaunchKernelGGL(k_md_drift, dim3(grid1(N)), dim3(256), 0, c.st, a);
+    run_neighbors(c, nb, d_flags, nullptr);
+    run_forward(c, nb, params, nullptr, e_pot, force, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL(k_md_kick, dim3(grid1(N)), dim3(256), 0, c.st, a);
+  }
+  if (e_kin && S > 0)
+    hipLaunchKernelGGL(k_struct_sum, dim3(S), dim3(256), 0, c.st, b->atom_offset, a.ekin, e_kin);
   return hip_ok();
 }
 

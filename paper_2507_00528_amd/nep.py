@@ -227,6 +227,18 @@ def check_flags(flags, where="device"):
     _check(code, where)
 
 
+def md_step(model, batch, nbrs, params, mass, vel, force, dt, n_steps, e_pot, ws, flags, e_kin=None, stream=None):
+    """n_steps of velocity Verlet (nep_md_step); batch.pos, vel and force are
+    advanced in place, e_pot/e_kin receive per-structure energies."""
+    _want(mass, torch.float32, model.n_types, "mass")
+    for t, name in ((vel, "vel"), (force, "force")):
+        _want(t, torch.float32, 3 * batch.n_atom, name)
+    _want(e_pot, torch.float32, batch.n_struct, "e_pot")
+    _check(_lib.load().nep_md_step(C.byref(model.c()), C.byref(batch.c()), _ptr(batch.pos), C.byref(nbrs.c()),
+                                   _ptr(params), _ptr(mass), _ptr(vel), _ptr(force), float(dt), int(n_steps),
+                                   _ptr(e_pot), _ptr(e_kin), _ptr(ws), _ptr(flags), _stream(stream)), "nep_md_step")
+
+
 GRAPH_CACHED_NEIGHBORS = 1
 
 

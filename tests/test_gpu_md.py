@@ -1,0 +1,118 @@
+"""Inference path on the GPU (nep_md_step): three velocity-Verlet steps equal
+the same integrator driven by FP64 oracle forces; NVE runs conserve the total
+energy; and the energy-volume curve's slope at s = 1 equals -tr W of the
+library's virial (Eq. 4 under uniform strain)."""
+import numpy as np
+import pytest
+
+from paper_2507_00528_amd import md, synth
+
+from gpu_util import TOL_E, rel
+
+pytestmark = pytest.mark.gpu
+MASSES = [md.MASS["Sb"], md.MASS["Te"]]
+
+
+def setup(sts, sizes, seed_params):
+    import torch
+    from paper_2507_00528_amd import nep
+    model = nep.Model.of(sizes)
+    b = synth.Batch(sts)
+    db = nep.DeviceBatch(b)
+    nb = nep.Neighbors(model, b.n_atom)
+    ws = nep.workspace(model, b.n_struct, b.n_atom)
+    fl = torch.zeros(1, dtype=torch.int32, device="cuda")
+    theta = synth.draw_params(sizes.n_params, seed_params)
+    return model, b, db, nb, ws, fl, theta
+
+
+def test_three_steps_match_oracle_verlet():
+    import torch
+    from oracle import NEPOracle
+    from paper_2507_00528_amd import nep
+    sz = synth.SIZES_TINY
+    sts = synth.config_structures("c0")[:2]
+    model, b, db, nb, ws, fl, theta = setup(sts, sz, synth.SEEDS["teacher"])
+    print(f"[md parity] S={b.n_struct} N={b.n_atom}", flush=True)
+    v0 = md.maxwell_velocities(b.types, MASSES, 600.0, seed=7)
+    dt, n = 1.0, 3
+    p = torch.tensor(theta, device="cuda")
+    mass = torch.tensor(MASSES, dtype=torch.float32, device="cuda")
+    vel = torch.tensor(v0, device="cuda")
+    force = torch.zeros(3 * b.n_atom, device="cuda")
+    e_pot = torch.zeros(b.n_struct, device="cuda")
+    e_kin = torch.zeros(b.n_struct, device="cuda")
+    nep.build_neighbors(model, db, nb, ws, fl)
+    nep.energy_force_virial(model, db, nb, p, ws, None, e_pot, force, None)
+    nep.md_step(model, db, nb, p, mass, vel, force, dt, n, e_pot, ws, fl, e_kin=e_kin)
+    torch.cuda.synchronize()
+    assert int(fl.item()) == 0
+    # the same integrator on the host with oracle forces
+    o = NEPOracle(sz)
+    off = b.atom_offset
+    m = np.asarray(MASSES)[b.types]
+    x = [st.pos.astype(np.float64) for st in sts]
+    v = v0.reshape(3, -1).T.astype(np.float64)
+    vs = [v[off[k]:off[k + 1]].copy() for k in range(len(sts))]
+    for k, st in enumerate(sts):
+        mk = m[off[k]:off[k + 1], None]
+        cur = st
+        F = o.predict(theta, [cur])["F"][0]
+        for _ in range(n):
+            vs[k] += 0.5 * dt * md.ACCEL * F / mk
+            xn = x[k] + dt * vs[k]
+            xn -= st.box * np.floor(xn / st.box)
+            cur = synth.Structure(xn.astype(np.float32), st.box, st.types)
+            x[k] = cur.pos.astype(np.float64)
+            out = o.predict(theta, [cur])
+            F = out["F"][0]
+            vs[k] += 0.5 * dt * md.ACCEL * F / mk
+        ref_e = out["E"][0]
+        assert abs(float(e_pot[k]) - ref_e) / st.n < TOL_E * max(1.0, abs(ref_e) / st.n)
+        ke = 0.5 * (mk[:, 0] * (vs[k] ** 2).sum(1)).sum() / md.ACCEL
+        assert abs(float(e_kin[k]) - ke) < 1e-4 * ke
+    xg = db.pos.cpu().numpy().reshape(3, -1).T
+    vg = vel.cpu().numpy().reshape(3, -1).T
+    assert np.abs(xg - np.concatenate(x)).max() < 1e-4
+    assert rel(vg, np.concatenate(vs)) < 1e-4
+
+
+def test_nve_conserves_total_energy():
+    import torch
+    sz = synth.SIZES_SMALL
+    sts = synth.config_structures("c1", n_struct=4)
+    model, b, db, nb, ws, fl, theta = setup(sts, sz, synth.SEEDS["teacher"])
+    print(f"[md nve] S={b.n_struct} N={b.n_atom}", flush=True)
+    mass = torch.tensor(MASSES, dtype=torch.float32, device="cuda")
+    vel = torch.tensor(md.maxwell_velocities(b.types, MASSES, 300.0, seed=3), device="cuda")
+    pot, kin = md.run_nve(model, db, nb, torch.tensor(theta, device="cuda"), mass, vel, ws, fl, 0.5, 20, 20)
+    tot = pot + kin
+    for k in range(b.n_struct):
+        dpot = np.abs(pot[:, k] - pot[0, k]).max()
+        dtot = np.abs(tot[:, k] - tot[0, k]).max()
+        assert dpot > 0
+        assert dtot < 0.05 * dpot, (k, dtot, dpot)
+
+
+def test_energy_volume_slope_equals_virial_trace():
+    import torch
+    from paper_2507_00528_amd import nep
+    sz = synth.SIZES_SMALL
+    st = synth.lattice_structure(np.random.default_rng(9), 216, 200, 240, 0.031)
+    h = 2e-3
+    scales = [1.0 - h, 1.0, 1.0 + h] + [0.96, 0.98, 1.02, 1.04]
+    sts = [md.scaled(st, s) for s in scales]
+    model, b, db, nb, ws, fl, theta = setup(sts, sz, synth.SEEDS["teacher"])
+    print(f"[md eos] S={b.n_struct} N={b.n_atom}", flush=True)
+    e = torch.zeros(b.n_struct, device="cuda")
+    w = torch.zeros(6 * b.n_struct, device="cuda")
+    nep.build_neighbors(model, db, nb, ws, fl)
+    nep.energy_force_virial(model, db, nb, torch.tensor(theta, device="cuda"), ws, None, e, None, w)
+    torch.cuda.synchronize()
+    assert int(fl.item()) == 0
+    e = e.cpu().numpy().astype(np.float64)
+    w = w.cpu().numpy().reshape(-1, 6).astype(np.float64)
+    slope = (e[2] - e[0]) / (2 * h)           # dE/ds at s = 1
+    trw = w[1, :3].sum()
+    assert abs(slope + trw) < 2e-2 * max(abs(trw), 1.0), (slope, trw)
+    assert np.all(np.isfinite(e))
