@@ -192,6 +192,7 @@ def main():
     step = torch.ones(1, dtype=torch.int32, device="cuda")
     graph = nep.TrainStepGraph(model, dev, nbrs, labels, lam, params, m, v, grad, loss, step, ws, flags,
                                lr_start=lr, lr_stop=lr, stream=stream)
+    torch.cuda.synchronize()   # inputs were filled on the default stream
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
             graph.launch(stream)
@@ -232,6 +233,7 @@ def main():
     sc_ = torch.ones(1, dtype=torch.int32, device="cuda")
     graph_c = nep.TrainStepGraph(model, dev, nb_c, labels, lam, pc, mc_, vc_, gc_, lc_, sc_, ws_c, fl_c,
                                  lr_start=lr, lr_stop=lr, stream=stream, cached_neighbors=True)
+    torch.cuda.synchronize()   # lists and buffers come from the default stream; the replays run on `stream`
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
             graph_c.launch(stream)
@@ -295,6 +297,7 @@ def main():
                 lacc.add_(loss_p)
             nep.adam_step(params_p, m_p, v_p, gacc, lr, it, stream=stream)
 
+        torch.cuda.synchronize()
         with torch.cuda.stream(stream):
             plain_step(1)
             stream.synchronize()

@@ -123,6 +123,8 @@ class Trainer:
         self.fixed = None if self.reshuffle else [self._prepare(idx, graph=True)
                                                   for idx in epoch_batches(len(self.structures), self.batch_size,
                                                                            self.rng)]
+        # device arrays are filled on the default stream; the steps run on self.stream
+        torch.cuda.synchronize()
         self.history = []
 
     # one mini-batch's device arrays (and, for fixed batches, its graph)
@@ -166,6 +168,7 @@ class Trainer:
             self.step_host = int(self.step.item())
             order = [self._prepare(idx, graph=False)
                      for idx in epoch_batches(len(self.structures), self.batch_size, self.rng)]
+            torch.cuda.synchronize()   # batch arrays come from the default stream
             for st in order:
                 self._eager_step(st)
             self.step.fill_(self.step_host)
