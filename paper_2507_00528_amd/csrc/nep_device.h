@@ -291,18 +291,35 @@ __device__ __forceinline__ float quad_sum(float v) {
   v += dpp<kDppXor2>(v);
   return v;
 }
+// v of lane l ^ 4 inside each row of 16: rotate the row by 12 (lanes with
+// bit 2 clear) or by 4 (bit 2 set).  Only the partner lane is read, so this
+// is valid in divergent code as long as that partner is active.
+constexpr int kDppRowRor4 = 0x124, kDppRowRor12 = 0x12C;
+__device__ __forceinline__ float xor4_val(float v) {
+  const float hi = dpp<kDppRowRor12>(v), lo = dpp<kDppRowRor4>(v);
+  return (threadIdx.x & 4) ? lo : hi;
+}
 // sum over the 8 lanes of an atom group
 __device__ __forceinline__ float grp8_sum(float v) {
   v = quad_sum(v);
   v += dpp<kDppHalfMirror>(v);
   return v;
 }
+// v + v[lane ^ 16] and v + v[lane ^ 32] with gfx950's lane-swap instructions
+// (no LDS): swapping a copy of v with itself leaves one half in each result,
+// so every lane gets the same two operands in the same order.
+__device__ __forceinline__ float xor16_sum(float v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float xor32_sum(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
 // sum over the 8 lanes of the wavefront with the same (l & 7)
 __device__ __forceinline__ float atoms8_sum(float v) {
   v += dpp<kDppRowRor8>(v);
-  v += __shfl_xor(v, 16, kWave);
-  v += __shfl_xor(v, 32, kWave);
-  return v;
+  return xor32_sum(xor16_sum(v));
 }
 
 // Image shift of a neighbor code: code = 9(sx+1) + 3(sy+1) + (sz+1).

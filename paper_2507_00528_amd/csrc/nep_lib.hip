@@ -926,10 +926,10 @@ __global__ __launch_bounds__(256, 2) void k_forward(FwdArgs a) {
     float fy = vv * uy + (gy - rad * uy) * q.inv_r;
     float fz = vv * uz + (gz - rad * uz) * q.inv_r;
     // the partner lane (other harmonic group, same pair) runs the same
-    // iterations; a single-hop permute reads it while other lanes idle
-    fx += __shfl_xor(fx, 4, kWave);
-    fy += __shfl_xor(fy, 4, kWave);
-    fz += __shfl_xor(fz, 4, kWave);
+    // iterations, so the DPP read below only touches active lanes
+    fx += xor4_val(fx);
+    fy += xor4_val(fy);
+    fz += xor4_val(fz);
     if (g == 0) {
       float* fo = a.fA + 3 * ((size_t)i * a.nb.capA + k);
       fo[0] = fx;
