@@ -155,43 +155,80 @@ __device__ __forceinline__ void harm_val(float x, float y, float z, float (&b)[L
   }
 }
 
-// Cartesian gradient of each b_lm at u: (gx, gy, gz)[lm].  Delivered through a
-// functor so that callers contract it on the fly without storing 3*Y values.
-template <int LM, class Fn>
-__device__ __forceinline__ void harm_grad(float x, float y, float z, Fn&& fn) {
-  fn(0, 0.f, 0.f, 1.f);
-  fn(1, 1.f, 0.f, 0.f);
-  fn(2, 0.f, 1.f, 0.f);
+// Gradients of the b_lm at u, written out term by term so that components
+// that vanish identically cost nothing (a multiply by a literal zero cannot be
+// folded without fast-math).
+//   harm_dir:      d[lm] = grad b_lm(u) . w
+//   harm_grad_sum: g = sum_lm w[lm] grad b_lm(u)
+template <int LM>
+__device__ __forceinline__ void harm_dir(float x, float y, float z, float wx, float wy, float wz,
+                                         float (&d)[LM * (LM + 2)]) {
+  d[0] = wz;
+  d[1] = wx;
+  d[2] = wy;
   if constexpr (LM >= 2) {
-    fn(3, 0.f, 0.f, 6.0f * z);
-    fn(4, z, 0.f, x);
-    fn(5, 0.f, z, y);
-    fn(6, 2.0f * x, -2.0f * y, 0.f);
-    fn(7, 2.0f * y, 2.0f * x, 0.f);
+    const float P = x * wx - y * wy, Q = y * wx + x * wy;
+    d[3] = 6.0f * z * wz;
+    d[4] = z * wx + x * wz;
+    d[5] = z * wy + y * wz;
+    d[6] = 2.0f * P;
+    d[7] = 2.0f * Q;
+    if constexpr (LM >= 3) {
+      const float x2 = x * x, y2 = y * y, z2 = z * z;
+      const float f5 = 5.0f * z2 - 1.0f, dxy = x2 - y2, xy = x * y;
+      d[8] = (15.0f * z2 - 3.0f) * wz;
+      d[9] = f5 * wx + 10.0f * x * z * wz;
+      d[10] = f5 * wy + 10.0f * y * z * wz;
+      d[11] = 2.0f * z * P + dxy * wz;
+      d[12] = 2.0f * z * Q + 2.0f * xy * wz;
+      d[13] = 3.0f * dxy * wx - 6.0f * xy * wy;
+      d[14] = 6.0f * xy * wx + 3.0f * dxy * wy;
+      if constexpr (LM >= 4) {
+        const float a = 7.0f * z2 - 1.0f, c = (7.0f * z2 - 3.0f) * z, e = 21.0f * z2 - 3.0f;
+        d[15] = (140.0f * z2 - 60.0f) * z * wz;
+        d[16] = c * wx + e * x * wz;
+        d[17] = c * wy + e * y * wz;
+        d[18] = 2.0f * a * P + 14.0f * z * dxy * wz;
+        d[19] = 2.0f * a * Q + 28.0f * xy * z * wz;
+        d[20] = 3.0f * dxy * z * wx - 6.0f * xy * z * wy + (x2 - 3.0f * y2) * x * wz;
+        d[21] = 6.0f * xy * z * wx + 3.0f * dxy * z * wy + (3.0f * x2 - y2) * y * wz;
+        d[22] = 4.0f * x * (x2 - 3.0f * y2) * wx + 4.0f * y * (y2 - 3.0f * x2) * wy;
+        d[23] = 4.0f * y * (3.0f * x2 - y2) * wx + 4.0f * x * (x2 - 3.0f * y2) * wy;
+      }
+    }
   }
-  if constexpr (LM >= 3) {
-    const float z2 = z * z, x2 = x * x, y2 = y * y;
-    fn(8, 0.f, 0.f, 15.0f * z2 - 3.0f);
-    fn(9, 5.0f * z2 - 1.0f, 0.f, 10.0f * x * z);
-    fn(10, 0.f, 5.0f * z2 - 1.0f, 10.0f * y * z);
-    fn(11, 2.0f * x * z, -2.0f * y * z, x2 - y2);
-    fn(12, 2.0f * y * z, 2.0f * x * z, 2.0f * x * y);
-    fn(13, 3.0f * (x2 - y2), -6.0f * x * y, 0.f);
-    fn(14, 6.0f * x * y, 3.0f * (x2 - y2), 0.f);
-  }
-  if constexpr (LM >= 4) {
-    const float z2 = z * z, x2 = x * x, y2 = y * y;
-    const float a = 7.0f * z2 - 1.0f;
-    const float c = (7.0f * z2 - 3.0f) * z;
-    fn(15, 0.f, 0.f, (140.0f * z2 - 60.0f) * z);
-    fn(16, c, 0.f, (21.0f * z2 - 3.0f) * x);
-    fn(17, 0.f, c, (21.0f * z2 - 3.0f) * y);
-    fn(18, 2.0f * x * a, -2.0f * y * a, 14.0f * z * (x2 - y2));
-    fn(19, 2.0f * y * a, 2.0f * x * a, 28.0f * x * y * z);
-    fn(20, 3.0f * (x2 - y2) * z, -6.0f * x * y * z, (x2 - 3.0f * y2) * x);
-    fn(21, 6.0f * x * y * z, 3.0f * (x2 - y2) * z, (3.0f * x2 - y2) * y);
-    fn(22, 4.0f * x * (x2 - 3.0f * y2), 4.0f * y * (y2 - 3.0f * x2), 0.f);
-    fn(23, 4.0f * y * (3.0f * x2 - y2), 4.0f * x * (x2 - 3.0f * y2), 0.f);
+}
+
+template <int LM>
+__device__ __forceinline__ void harm_grad_sum(float x, float y, float z, const float (&w)[LM * (LM + 2)], float& gx,
+                                              float& gy, float& gz) {
+  gx = w[1];
+  gy = w[2];
+  gz = w[0];
+  if constexpr (LM >= 2) {
+    gx = fmaf(z, w[4], fmaf(2.0f * x, w[6], fmaf(2.0f * y, w[7], gx)));
+    gy = fmaf(z, w[5], fmaf(-2.0f * y, w[6], fmaf(2.0f * x, w[7], gy)));
+    gz = fmaf(6.0f * z, w[3], fmaf(x, w[4], fmaf(y, w[5], gz)));
+    if constexpr (LM >= 3) {
+      const float x2 = x * x, y2 = y * y, z2 = z * z;
+      const float f5 = 5.0f * z2 - 1.0f, dxy = x2 - y2, xy = x * y;
+      gx = fmaf(f5, w[9], fmaf(2.0f * x * z, w[11], fmaf(2.0f * y * z, w[12],
+           fmaf(3.0f * dxy, w[13], fmaf(6.0f * xy, w[14], gx)))));
+      gy = fmaf(f5, w[10], fmaf(-2.0f * y * z, w[11], fmaf(2.0f * x * z, w[12],
+           fmaf(-6.0f * xy, w[13], fmaf(3.0f * dxy, w[14], gy)))));
+      gz = fmaf(15.0f * z2 - 3.0f, w[8], fmaf(10.0f * x * z, w[9], fmaf(10.0f * y * z, w[10],
+           fmaf(dxy, w[11], fmaf(2.0f * xy, w[12], gz)))));
+      if constexpr (LM >= 4) {
+        const float a = 7.0f * z2 - 1.0f, c = (7.0f * z2 - 3.0f) * z, e = 21.0f * z2 - 3.0f;
+        const float xyz = xy * z, t1 = x2 - 3.0f * y2, t2 = 3.0f * x2 - y2;
+        gx = fmaf(c, w[16], fmaf(2.0f * x * a, w[18], fmaf(2.0f * y * a, w[19], fmaf(3.0f * dxy * z, w[20],
+             fmaf(6.0f * xyz, w[21], fmaf(4.0f * x * t1, w[22], fmaf(4.0f * y * t2, w[23], gx)))))));
+        gy = fmaf(c, w[17], fmaf(-2.0f * y * a, w[18], fmaf(2.0f * x * a, w[19], fmaf(-6.0f * xyz, w[20],
+             fmaf(3.0f * dxy * z, w[21], fmaf(-4.0f * y * t2, w[22], fmaf(4.0f * x * t1, w[23], gy)))))));
+        gz = fmaf((140.0f * z2 - 60.0f) * z, w[15], fmaf(e * x, w[16], fmaf(e * y, w[17],
+             fmaf(14.0f * z * dxy, w[18], fmaf(28.0f * xyz, w[19], fmaf(t1 * x, w[20], fmaf(t2 * y, w[21], gz)))))));
+      }
+    }
   }
 }
 

@@ -915,12 +915,8 @@ __global__ __launch_bounds__(256, 2) void k_forward(FwdArgs a) {
       if (q0 >= 0) uf[q0] = g ? uf[q0] : su;
       if (q1 >= 0) uf[q1] = g ? su : uf[q1];
     }
-    float gx = 0.f, gy = 0.f, gz = 0.f;
-    harm_grad<LM>(ux, uy, uz, [&](int qq, float ax, float ay, float az) {
-      gx = fmaf(uf[qq], ax, gx);
-      gy = fmaf(uf[qq], ay, gy);
-      gz = fmaf(uf[qq], az, gz);
-    });
+    float gx, gy, gz;
+    harm_grad_sum<LM>(ux, uy, uz, uf, gx, gy, gz);
     const float rad = ux * gx + uy * gy + uz * gz;
     float fx = vv * ux + (gx - rad * ux) * q.inv_r;
     float fy = vv * uy + (gy - rad * uy) * q.inv_r;
@@ -1263,9 +1259,8 @@ __global__ __launch_bounds__(256, 2) void k_adjoint(AdjArgs a) {
     }
     float B[Y], gbt[Y];
     harm_val<LM>(ux, uy, uz, B);
-    harm_grad<LM>(ux, uy, uz, [&](int qq, float ax, float ay, float az) {
-      gbt[qq] = ((ax * tx + ay * ty + az * tz) - (ax * ux + ay * uy + az * uz) * dt) * q.inv_r;
-    });
+    // grad B . t = grad b(u) . (t - (u.t) u) / r
+    harm_dir<LM>(ux, uy, uz, (tx - dt * ux) * q.inv_r, (ty - dt * uy) * q.inv_r, (tz - dt * uz) * q.inv_r, gbt);
 #pragma unroll
     for (int e = 0; e < YG; ++e) {
       const float b = hsel<HS, Y>(g, e, B), c = hsel<HS, Y>(g, e, gbt);
@@ -1480,9 +1475,8 @@ __global__ __launch_bounds__(256, 2) void k_adjoint(AdjArgs a) {
     const int J = a.type[q.j];
     float B[Y], gbt[Y];
     harm_val<LM>(ux, uy, uz, B);
-    harm_grad<LM>(ux, uy, uz, [&](int qq, float ax, float ay, float az) {
-      gbt[qq] = ((ax * tx + ay * ty + az * tz) - (ax * ux + ay * uy + az * uz) * dt) * q.inv_r;
-    });
+    // grad B . t = grad b(u) . (t - (u.t) u) / r
+    harm_dir<LM>(ux, uy, uz, (tx - dt * ux) * q.inv_r, (ty - dt * uy) * q.inv_r, (tz - dt * uz) * q.inv_r, gbt);
 #pragma unroll
     for (int j = 0; j < NAH; ++j) {
       const int n = g * NAH + j;
