@@ -45,7 +45,7 @@ __device__ __forceinline__ unsigned axis_candidates(double d0, double L, double 
 // tiles of kNbrTile atoms; every lane of the block walks the same tiles.
 constexpr int kNbrAPB = 256 / 8;   // atoms per block
 constexpr int kNbrTile = 1024;
-constexpr int kNbrBuf = 24;   // entries buffered per lane (angular mask: 32 bits)
+constexpr int kNbrBuf = 24;   // entries buffered per lane (angular mask: 32 bits), plus a scratch slot
 constexpr float kNbrDelta = 0.01f;
 constexpr float kNbrFastL = 512.0f;
 
@@ -131,9 +131,51 @@ __device__ __forceinline__ void scan_range(const ScanCtx& c, const PosTile& t, i
   }
 }
 
+// The buffered scan of the single pass.  Outside the shell the decision is
+// made without branches: every candidate's entry is written to the lane's
+// next buffer slot and the count only advances when the pair is inside, so a
+// later entry overwrites a rejected one (slot kNbrBuf takes the writes once
+// the buffer is full).  Pairs in the shell, and cells too small or too large
+// for the single-image test, branch to the float64 predicate.
+template <class Keep>
+__device__ __forceinline__ void scan_keep(const ScanCtx& c, const PosTile& t, int jb, int je, uint32_t* buf,
+                                          int& nR, int& nA, uint32_t& angmask, Keep& keep) {
+  for (int j = jb; j < je; ++j) {
+    if (!c.fast) {
+      exact_pair(c, t, j, keep);
+      continue;
+    }
+    const int q = j - t.base;
+    const float px = t.x[q], py = t.y[q], pz = t.z[q];
+    float ex = px - c.xf, ey = py - c.yf, ez = pz - c.zf;
+    const float kx = rintf(ex * c.ilx), ky = rintf(ey * c.ily), kz = rintf(ez * c.ilz);
+    ex -= c.Lxf * kx;
+    ey -= c.Lyf * ky;
+    ez -= c.Lzf * kz;
+    const float r2 = ex * ex + ey * ey + ez * ez;
+    const bool one = fabsf(kx) <= 1.f && fabsf(ky) <= 1.f && fabsf(kz) <= 1.f;
+    const int code = 9 * (1 - (int)kx) + 3 * (1 - (int)ky) + (1 - (int)kz);
+    const bool decided = r2 < c.inR2 && one;
+    const bool in = decided && !(j == c.i && code == 13);
+    bool ang = r2 < c.inA2;
+    buf[blockDim.x * min(nR, kNbrBuf)] = ((uint32_t)j << 5) | (uint32_t)(code & 31);
+    if (in && !ang && r2 < c.outA2) {
+      const double dx = __dadd_rn(__dadd_rn((double)px, -c.xi), -(double)kx * c.Lx);
+      const double dy = __dadd_rn(__dadd_rn((double)py, -c.yi), -(double)ky * c.Ly);
+      const double dz = __dadd_rn(__dadd_rn((double)pz, -c.zi), -(double)kz * c.Lz);
+      const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+      ang = d2 < c.rcA2;
+    }
+    angmask |= (in && ang && nR < kNbrBuf) ? (1u << nR) : 0u;
+    nR += in ? 1 : 0;
+    nA += (in && ang) ? 1 : 0;
+    if (!decided && r2 < c.outR2) exact_pair(c, t, j, keep);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
   __shared__ float tx[kNbrTile], ty[kNbrTile], tz[kNbrTile];
-  __shared__ uint32_t nbuf[256 * kNbrBuf];
+  __shared__ uint32_t nbuf[256 * (kNbrBuf + 1)];
   __shared__ int jr[2];
   const int s = threadIdx.x & 7;
   const int b0 = xcd_block() * kNbrAPB;
@@ -193,7 +235,7 @@ __global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
   __syncthreads();
   const int jlo = jr[0], jhi = jr[1];
   // walks the tiles of [jlo, jhi); this lane scans [b, e) of each
-  auto sweep = [&](int b, int e, auto& emit) {
+  auto sweep = [&](int b, int e, auto&& scan) {
     for (int t0 = jlo; t0 < jhi; t0 += kNbrTile) {
       const int tn = min(kNbrTile, jhi - t0);
       for (int q = threadIdx.x; q < tn; q += blockDim.x) {
@@ -203,7 +245,7 @@ __global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
       }
       __syncthreads();
       const PosTile t{tx, ty, tz, t0};
-      scan_range(c, t, max(b, t0), min(e, t0 + tn), emit);
+      scan(t, max(b, t0), min(e, t0 + tn));
       __syncthreads();
     }
   };
@@ -222,7 +264,7 @@ __global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
     ++nR;
     nA += ang ? 1 : 0;
   };
-  sweep(jb, je, keep);
+  sweep(jb, je, [&](const PosTile& t, int b2, int e2) { scan_keep(c, t, b2, e2, mybuf, nR, nA, angmask, keep); });
   // inclusive prefix over the 8 lanes of the atom
   int pR = nR, pA = nA;
 #pragma unroll
@@ -258,7 +300,7 @@ __global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
       }
     };
     const bool wr = live && spill && wR < a.capR;
-    sweep(wr ? jb : 0, wr ? je : 0, write);
+    sweep(wr ? jb : 0, wr ? je : 0, [&](const PosTile& t, int b2, int e2) { scan_range(c, t, b2, e2, write); });
   }
   if (live && s == 0) {
     a.cntR[i] = totR;
