@@ -11,6 +11,17 @@ TOL_E = 1e-5   # energy per atom
 TOL_F = 1e-4   # forces, virials, parameter gradients
 
 
+_STRUCTURES = {}
+
+
+def structures(name):
+    """synth.config_structures(name), generated once per test session (the
+    c4 set takes most of a minute)."""
+    if name not in _STRUCTURES:
+        _STRUCTURES[name] = synth.config_structures(name)
+    return _STRUCTURES[name]
+
+
 def rel(a, ref):
     a = np.asarray(a, np.float64)
     ref = np.asarray(ref, np.float64)

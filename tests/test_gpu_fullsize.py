@@ -1,6 +1,7 @@
 """Full-size parity: the 512-structure uneven batch (87k atoms, the benchmark
-workload) and the single 27,000-atom amorphous cell, against expected values
-that tests/golden/make_golden.py wrote with the FP64 oracle.
+workload), the single 27,000-atom amorphous cell and the 2,000-structure
+training set (228k atoms, structures up to 1,000 atoms), against expected
+values that tests/golden/make_golden.py wrote with the FP64 oracle.
 
 Neighbor lists are compared bit-exactly through per-atom counts and a SHA-256
 digest of the canonical (i, j, code) lists; loss, every gradient block,
@@ -15,7 +16,7 @@ import pytest
 
 from paper_2507_00528_amd import synth
 
-from gpu_util import TOL_E, TOL_F, param_blocks, rel
+from gpu_util import TOL_E, TOL_F, param_blocks, rel, structures
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -36,12 +37,12 @@ def digest(idx, cnt, cap, N):
     return hashlib.sha256(np.ascontiguousarray(arr).tobytes()).hexdigest()
 
 
-@pytest.mark.parametrize("name", ["c2", "c3"])
+@pytest.mark.parametrize("name", ["c2", "c3", "c4"])
 def test_full_size_against_golden(name):
     import torch
     from paper_2507_00528_amd import nep
     gd, meta = golden(name)
-    sts = synth.config_structures(name)
+    sts = structures(name)
     batch = synth.Batch(sts)
     N, S = batch.n_atom, batch.n_struct
     print(f"[full {name}] S={S} N={N}", flush=True)
