@@ -169,7 +169,7 @@ int nep_vjp(const nep_model* model, const nep_batch* batch, const nep_neighbors*
  *   Le = 1/S sum_n ((E(n) - E_tar(n))/N_n)^2,
  *   Lf = 1/(3N) sum (F - F_tar)^2,
  *   Lv = 1/(6S) sum_n sum_c ((W_c(n) - W_tar_c(n))/N_n)^2.
- * loss [4] = (L, Le, Lf, Lv); grad [P] overwritten.  e_struct, force, virial
+ * loss [4] = (L, Le, Lf, Lv), zeros for an empty batch; grad [P] overwritten.  e_struct, force, virial
  * (may be NULL) receive the predictions.  Sets NEP_FLAG_NONFINITE. */
 int nep_loss_grad(const nep_model* model, const nep_batch* batch, const nep_neighbors* nbrs,
                   const float* params, const nep_labels* labels, const float lambda[3],

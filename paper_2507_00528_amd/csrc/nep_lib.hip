@@ -2393,6 +2393,7 @@ int loss_grad_seq(Ctx& c, nep_neighbors* nb, const float* params, const nep_labe
                   float* loss, float* grad, float* e_struct, float* force, float* virial, int32_t* flags, Prof* pr,
                   bool with_neighbors) {
   if (with_neighbors) run_neighbors(c, nb, flags, pr);
+  if (c.b->n_struct == 0) hipLaunchKernelGGL(k_fill_f32, dim3(1), dim3(64), 0, c.st, loss, (int64_t)4, 0.f);
   // with atoms present the loss is summed by the adjoint's reduction launch
   const int N = c.L.N, S = c.b->n_struct;
   LossArgs la{};
