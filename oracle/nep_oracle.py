@@ -7,8 +7,9 @@ leg of the benchmark may import it; the library never does, and nothing here
 calls the library.
 
 What it computes, in the paper's order (Sec. II):
-  * neighbor sets within r_c (Eq. 2) under orthorhombic periodic boundaries,
-    brute force over every atom and every image shift in {-1,0,1}^3;
+  * neighbor sets within r_c (Eq. 2) under periodic boundaries of an
+    orthorhombic or triclinic cell, brute force over every atom and every
+    image shift in {-1,0,1}^3;
   * radial descriptors q_n (Eqs. 5-6) with the Chebyshev basis and cosine
     cutoff of Appendix A;
   * 3-body angular descriptors q_nl (Eqs. 7-8) from the Cartesian harmonics of
@@ -106,14 +107,30 @@ def unpack(sz: Sizes, theta: torch.Tensor) -> dict:
 # ----------------------------------------------------------------------------
 # neighbors (Eq. 2)
 # ----------------------------------------------------------------------------
-def neighbor_pairs(pos32: np.ndarray, box32: np.ndarray, rc: float, rows=None):
-    """All (i, j, code) with |x_j + s*L - x_i| < r_c, (j, s) != (i, 0),
+def shift_vectors(box32, tilt32=None) -> np.ndarray:
+    """[27, 3] image shifts H s in code order, H the cell matrix with edge
+    vectors a = (lx,0,0), b = (xy,ly,0), c = (xz,yz,lz); each component is
+    summed in a fixed order: x = ((sa lx) + sb xy) + sc xz, y = sb ly + sc yz,
+    z = sc lz (products exact: s is 0 or +-1)."""
+    lx, ly, lz = np.asarray(box32, np.float32).astype(np.float64)
+    xy, xz, yz = (0.0, 0.0, 0.0) if tilt32 is None else np.asarray(tilt32, np.float32).astype(np.float64)
+    sa, sb, sc = SHIFTS[:, 0], SHIFTS[:, 1], SHIFTS[:, 2]
+    return np.stack([sa * lx + sb * xy + sc * xz, sb * ly + sc * yz, sc * lz], 1)
+
+
+def neighbor_pairs(pos32: np.ndarray, box32: np.ndarray, rc: float, rows=None, tilt32=None):
+    """All (i, j, code) with |x_j + H s - x_i| < r_c, (j, s) != (i, 0),
     s in {-1,0,1}^3, in canonical order (i, then j, then code ascending).
 
     The predicate is evaluated in IEEE float64 on the float32 inputs as
-    d = (x_j - x_i) + s*L and d2 = (dx*dx + dy*dy) + dz*dz, compared with
-    r_c^2 strictly.  `rows` restricts the centers i to the given indices.
-    A per-axis test |d_a| < r_c, implied by the predicate, only prunes."""
+    d = (x_j - x_i) + H s, each component summed left to right as
+    dx = (((x_j - x_i) + sa lx) + sb xy) + sc xz, dy = ((y_j - y_i) + sb ly) + sc yz,
+    dz = (z_j - z_i) + sc lz, and d2 = (dx*dx + dy*dy) + dz*dz, compared with
+    r_c^2 strictly.  With zero tilts this is (x_j - x_i) + s L.  `rows`
+    restricts the centers i.  Pruning tests, implied by the predicate, only
+    skip work."""
+    if tilt32 is not None and np.any(np.asarray(tilt32, np.float32) != 0):
+        return _neighbor_pairs_triclinic(pos32, box32, rc, rows, tilt32)
     x = np.asarray(pos32, np.float32).astype(np.float64)
     L = np.asarray(box32, np.float32).astype(np.float64)
     rc64 = float(np.float32(rc))
@@ -147,12 +164,46 @@ def neighbor_pairs(pos32: np.ndarray, box32: np.ndarray, rc: float, rows=None):
     return p[order].astype(np.int64)
 
 
-def pair_vectors(pos32: np.ndarray, box32: np.ndarray, pairs: np.ndarray) -> torch.Tensor:
-    """d_ij = x_j + s*L - x_i in float64 for each (i, j, code)."""
+def _neighbor_pairs_triclinic(pos32, box32, rc, rows, tilt32):
     x = np.asarray(pos32, np.float32).astype(np.float64)
-    L = np.asarray(box32, np.float32).astype(np.float64)
+    lx, ly, lz = np.asarray(box32, np.float32).astype(np.float64)
+    xy, xz, yz = np.asarray(tilt32, np.float32).astype(np.float64)
+    rc64 = float(np.float32(rc))
+    rc2 = rc64 * rc64
+    n = x.shape[0]
+    rows = np.arange(n) if rows is None else np.asarray(rows)
+    sa, sb, sc = SHIFTS[:, 0], SHIFTS[:, 1], SHIFTS[:, 2]
+    out = []
+    chunk = max(1, min(256, 2_000_000 // max(n, 1)))
+    for c0 in range(0, len(rows), chunk):
+        ii = rows[c0:c0 + chunk]
+        diff = x[None, :, :] - x[ii][:, None, :]                        # [c, n, 3]
+        # |dz| < rc for some sc (dz depends on sc only)
+        dzc = diff[:, :, 2, None] + np.array([-lz, 0.0, lz])[None, None, :]
+        ci, cj = np.nonzero(np.any(np.abs(dzc) < rc64, axis=2))
+        if len(ci) == 0:
+            continue
+        dd = diff[ci, cj]                                               # [m, 3]
+        dx = ((dd[:, 0, None] + sa * lx) + sb * xy) + sc * xz
+        dy = (dd[:, 1, None] + sb * ly) + sc * yz
+        dz = dd[:, 2, None] + sc * lz
+        d2 = (dx * dx + dy * dy) + dz * dz
+        ok = d2 < rc2
+        ok &= ~((ii[ci] == cj)[:, None] & (np.arange(27) == SELF_CODE)[None, :])
+        m, code = np.nonzero(ok)
+        out.append(np.stack([ii[ci[m]], cj[m], code], 1))
+    if not out:
+        return np.zeros((0, 3), np.int64)
+    p = np.concatenate(out, 0)
+    order = np.lexsort((p[:, 2], p[:, 1], p[:, 0]))
+    return p[order].astype(np.int64)
+
+
+def pair_vectors(pos32: np.ndarray, box32: np.ndarray, pairs: np.ndarray, tilt32=None) -> torch.Tensor:
+    """d_ij = x_j + H s - x_i in float64 for each (i, j, code)."""
+    x = np.asarray(pos32, np.float32).astype(np.float64)
     i, j, c = pairs[:, 0], pairs[:, 1], pairs[:, 2]
-    return torch.tensor((x[j] - x[i]) + SHIFTS[c] * L, dtype=DT)
+    return torch.tensor((x[j] - x[i]) + shift_vectors(box32, tilt32)[c], dtype=DT)
 
 
 # ----------------------------------------------------------------------------
@@ -229,8 +280,9 @@ class NEPOracle:
 
     # -- one structure --------------------------------------------------------
     def neighbors(self, st):
-        return (neighbor_pairs(st.pos, st.box, self.sz.rc_rad),
-                neighbor_pairs(st.pos, st.box, self.sz.rc_ang))
+        tilt = getattr(st, "tilt", None)
+        return (neighbor_pairs(st.pos, st.box, self.sz.rc_rad, tilt32=tilt),
+                neighbor_pairs(st.pos, st.box, self.sz.rc_ang, tilt32=tilt))
 
     def structure(self, theta: torch.Tensor, st, nbrs=None, create_graph=False, need_forces=True):
         """Per-atom energies, total energy, forces [n,3] and the 3x3 virial
@@ -240,11 +292,11 @@ class NEPOracle:
         n = st.n
         x = torch.tensor(np.asarray(st.pos, np.float32).astype(np.float64), dtype=DT, requires_grad=need_forces)
         strain = torch.zeros(3, 3, dtype=DT, requires_grad=need_forces)
-        L = torch.tensor(np.asarray(st.box, np.float32).astype(np.float64), dtype=DT)
+        HS = torch.tensor(shift_vectors(st.box, getattr(st, "tilt", None)), dtype=DT)   # [27, 3]
 
         def vec(pairs):
             i, j, c = (torch.as_tensor(pairs[:, k]) for k in range(3))
-            d = (x[j] - x[i]) + torch.as_tensor(SHIFTS)[c] * L
+            d = (x[j] - x[i]) + HS[c]
             # homogeneous deformation r -> (1 + strain) r of positions and box
             return d + d @ strain.T
 

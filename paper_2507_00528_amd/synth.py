@@ -60,10 +60,13 @@ SIZES_MONO = NEPSizes(n_types=1, n_rad=4, n_ang=3, k_rad=6, k_ang=5, l3=2, l4=2,
 
 @dataclass
 class Structure:
-    pos: np.ndarray      # float32 [n, 3], wrapped into [0, L)
-    box: np.ndarray      # float32 [3], orthorhombic edge lengths
+    pos: np.ndarray      # float32 [n, 3], wrapped into the cell
+    box: np.ndarray      # float32 [3], cell lengths (lx, ly, lz)
     types: np.ndarray    # int32 [n]
     kind: str = ""
+    # float32 [3] tilts (xy, xz, yz) of a triclinic cell with edge vectors
+    # a = (lx, 0, 0), b = (xy, ly, 0), c = (xz, yz, lz); None: orthorhombic
+    tilt: np.ndarray = None
 
     @property
     def n(self) -> int:
@@ -78,6 +81,7 @@ class Batch:
     types: np.ndarray = field(init=False)        # int32 [N]
     atom_offset: np.ndarray = field(init=False)  # int32 [S+1]
     box: np.ndarray = field(init=False)          # float32 [S*3]
+    tilt: np.ndarray = field(init=False)         # float32 [S*3] (xy, xz, yz), zeros when orthorhombic
 
     def __post_init__(self):
         sizes = [s.n for s in self.structures]
@@ -87,6 +91,12 @@ class Batch:
         self.pos_soa = np.ascontiguousarray(pos.T.reshape(-1)).astype(np.float32)
         self.types = np.concatenate([s.types for s in self.structures]).astype(np.int32) if sizes else np.zeros(0, np.int32)
         self.box = np.concatenate([s.box for s in self.structures]).astype(np.float32) if sizes else np.zeros(0, np.float32)
+        self.tilt = (np.concatenate([np.zeros(3, np.float32) if s.tilt is None else np.asarray(s.tilt, np.float32)
+                                     for s in self.structures]).astype(np.float32) if sizes else np.zeros(0, np.float32))
+
+    @property
+    def triclinic(self) -> bool:
+        return bool(np.any(self.tilt != 0))
 
     @property
     def n_struct(self) -> int:
@@ -108,6 +118,52 @@ def wrap32(pos: np.ndarray, box: np.ndarray) -> np.ndarray:
     p = np.where(p >= box32, np.float32(0.0), p)
     p = np.where(p < 0, np.float32(0.0), p)
     return p.astype(np.float32)
+
+
+def cell_matrix(box, tilt=None) -> np.ndarray:
+    """Columns are the edge vectors a = (lx, 0, 0), b = (xy, ly, 0),
+    c = (xz, yz, lz), in float64 from the float32 lengths and tilts."""
+    lx, ly, lz = (float(np.float32(v)) for v in box)
+    xy, xz, yz = (0.0, 0.0, 0.0) if tilt is None else (float(np.float32(v)) for v in tilt)
+    return np.array([[lx, xy, xz], [0.0, ly, yz], [0.0, 0.0, lz]])
+
+
+def wrap_cell32(pos: np.ndarray, box, tilt) -> np.ndarray:
+    """Wrap float64 positions into a triclinic cell (fractional coordinates
+    in [0, 1)) and round to float32."""
+    H = cell_matrix(box, tilt)
+    f = np.linalg.solve(H, np.asarray(pos, np.float64).T).T
+    f -= np.floor(f)
+    return (f @ H.T).astype(np.float32)
+
+
+_IMAGES27 = np.array([[a, b, c] for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)], np.float64)
+
+
+def triclinic_structure(rng, n: int, density: float, dmin: float, tilt_frac: float = 0.3,
+                        kind: str = "triclinic") -> Structure:
+    """Random sequential packing (periodic minimum distance dmin) in a cell of
+    volume n/density with edge lengths within 10% of the cube's and tilts
+    xy, xz (yz) drawn uniformly in +-tilt_frac lx (ly)."""
+    L = (n / density) ** (1.0 / 3.0)
+    box = (L * rng.uniform(0.9, 1.1, 3)).astype(np.float32)
+    tilt = np.array([rng.uniform(-tilt_frac, tilt_frac) * box[0], rng.uniform(-tilt_frac, tilt_frac) * box[0],
+                     rng.uniform(-tilt_frac, tilt_frac) * box[1]], np.float32)
+    H = cell_matrix(box, tilt)
+    images = _IMAGES27 @ H.T
+    pts = np.zeros((0, 3))
+    tries = 0
+    while len(pts) < n:
+        tries += 1
+        if tries > 200 * n:
+            raise RuntimeError("packing failed: lower the density or dmin")
+        x = H @ rng.uniform(0.0, 1.0, 3)
+        if len(pts):
+            d = (pts[:, None, :] + images[None]) - x
+            if np.min(np.einsum("ijk,ijk->ij", d, d)) < dmin * dmin:
+                continue
+        pts = np.vstack([pts, x])
+    return Structure(wrap_cell32(pts, box, tilt), box, assign_types(rng, n), kind, tilt)
 
 
 def rsa_positions(rng: np.random.Generator, n: int, box: np.ndarray, dmin: float,
