@@ -42,13 +42,13 @@ extern "C" {
 enum {
   NEP_OK = 0,
   NEP_ERR_ARG = -1,          /* bad size, NULL pointer or unsupported model   */
-  NEP_ERR_BOX = -2,          /* a box edge shorter than rc_rad (device flag)  */
+  NEP_ERR_BOX = -2,          /* a cell narrower than rc_rad (device flag)     */
   NEP_ERR_NBR_OVERFLOW = -3, /* more neighbors than cap_rad / cap_ang         */
   NEP_ERR_NONFINITE = -4,    /* loss not finite                               */
   NEP_ERR_HIP = -5,          /* a HIP runtime call failed                     */
   NEP_ERR_WORKSPACE = -6,    /* workspace NULL or misaligned                  */
   NEP_ERR_TYPE = -7,         /* an atom type outside [0, n_types)             */
-  NEP_ERR_POSITION = -8      /* a coordinate outside [0, L)                   */
+  NEP_ERR_POSITION = -8      /* an atom outside its cell (device flag)        */
 };
 
 #define NEP_FLAG_NBR_OVERFLOW 1
@@ -75,17 +75,28 @@ typedef struct {
   int32_t cap_rad, cap_ang;
 } nep_model;
 
-/* A batch of orthorhombic periodic structures (device pointers).
+/* A batch of periodic structures (device pointers).  Cell of structure n:
+ * edge vectors a = (Lx, 0, 0), b = (xy, Ly, 0), c = (xz, yz, Lz), the
+ * image shift s = (sa, sb, sc) moving an atom by sa a + sb b + sc c (Eq. 2).
  *   atom_offset [n_struct+1] int32, atom_offset[0] = 0, last = n_atom
- *   box   [n_struct*3] float edge lengths (Lx, Ly, Lz); each >= rc_rad
- *   pos   [3*n_atom] float SoA, each coordinate in [0, L)
- *   type  [n_atom] int32 species in [0, n_types) */
+ *   box   [n_struct*3] float edge lengths (Lx, Ly, Lz)
+ *   pos   [3*n_atom] float SoA
+ *   type  [n_atom] int32 species in [0, n_types)
+ *   tilt  [n_struct*3] float (xy, xz, yz), or NULL when every cell is
+ *         orthorhombic (all tilts zero).
+ * Orthorhombic cell (all three tilts zero): each L >= rc_rad and each
+ * coordinate in [0, L).  Triclinic cell: each perpendicular width (cell
+ * volume over the area of the opposite face) >= rc_rad / (1 - 2e-5) and the
+ * fractional coordinates of every atom in [-1e-5, 1 + 1e-5).  Cells that
+ * break these raise NEP_FLAG_BOX / NEP_FLAG_POSITION (the image set
+ * {-1,0,1}^3 then no longer covers every neighbor). */
 typedef struct {
   int32_t n_struct, n_atom;
   const int32_t* atom_offset;
   const float* box;
   const float* pos;
   const int32_t* type;
+  const float* tilt;
 } nep_batch;
 
 /* Neighbor lists (Eq. 2), one for rc_rad and one for rc_ang (device).
@@ -188,8 +199,9 @@ float nep_lr_schedule(int64_t s, float lr_start, float lr_stop, int64_t n_warmup
 
 /* Inference path (outside the training step): n_steps of velocity Verlet
  * with the NEP forces, in eV, A, fs and amu.  Each step kicks the velocities
- * by half a step with `force`, moves and wraps the positions into [0, L),
- * rebuilds the neighbor lists, evaluates E and F (Eqs. 1-3) and kicks again.
+ * by half a step with `force`, moves and wraps the positions into the cell
+ * (into [0, L) per axis when orthorhombic; by the lattice vector of the
+ * floored fractional coordinates when triclinic), rebuilds the neighbor lists, evaluates E and F (Eqs. 1-3) and kicks again.
  *   pos     must be batch->pos; advanced in place (device, SoA [3*n_atom])
  *   mass    [n_types] atomic masses in amu (device)
  *   vel     [3*n_atom] SoA velocities in A/fs, updated (device)

@@ -22,6 +22,7 @@ struct NbrArgs {
   float rcR, rcA;
   const int* aoff;
   const float* box;
+  const float* tilt;  // [S][3] (xy, xz, yz), null: every cell orthorhombic
   const float* pos;
   const int* type;
   uint32_t* idxR;
@@ -48,6 +49,7 @@ struct FwdArgs {
   const int* order;
   const int* astruct;
   const float* box;
+  const float* tilt;  // null: every cell orthorhombic
   const float* pos;
   const int* type;
   PairLists nb;
@@ -74,6 +76,7 @@ struct AdjArgs {
   const int* order;
   const int* astruct;
   const float* box;
+  const float* tilt;  // null: every cell orthorhombic
   const float* pos;
   const int* type;
   PairLists nb;

@@ -51,8 +51,8 @@ constexpr float kNbrFastL = 512.0f;
 
 struct ScanCtx {
   int i;
-  double xi, yi, zi, Lx, Ly, Lz, rcR, rcR2, rcA2;
-  float xf, yf, zf, Lxf, Lyf, Lzf, ilx, ily, ilz;
+  double xi, yi, zi, Lx, Ly, Lz, xy, xz, yz, rcR, rcR2, rcA2;
+  float xf, yf, zf, Lxf, Lyf, Lzf, xyf, xzf, yzf, ilx, ily, ilz;
   float inR2, outR2, inA2, outA2;
   bool fast;
 };
@@ -98,17 +98,110 @@ __device__ __forceinline__ void exact_pair(const ScanCtx& c, const PosTile& t, i
   }
 }
 
+// The same predicate in a triclinic cell with edge vectors a = (Lx, 0, 0),
+// b = (xy, Ly, 0), c = (xz, yz, Lz): d = (x_j - x_i) + sa a + sb b + sc c with
+// each component summed left to right, dx = ((x0 + sa Lx) + sb xy) + sc xz,
+// dy = (y0 + sb Ly) + sc yz, dz = z0 + sc Lz (the products are exact).  dz
+// prunes sc, dy prunes (sb, sc), then dx is formed per surviving shift.
 template <class Emit>
+__device__ __forceinline__ void exact_pair_tri(const ScanCtx& c, const PosTile& t, int j, Emit& emit) {
+  const int q = j - t.base;
+  const double z0 = __dadd_rn((double)t.z[q], -c.zi);
+  const unsigned mz = axis_candidates(z0, c.Lz, c.rcR);
+  if (!mz) return;
+  const double y0 = __dadd_rn((double)t.y[q], -c.yi);
+  double dyv[9], dzv[3];
+#pragma unroll
+  for (int sc = 0; sc < 3; ++sc) dzv[sc] = sc == 1 ? z0 : __dadd_rn(z0, sc == 0 ? -c.Lz : c.Lz);
+  unsigned myz = 0;
+#pragma unroll
+  for (int sb = 0; sb < 3; ++sb) {
+    const double yb = sb == 1 ? y0 : __dadd_rn(y0, sb == 0 ? -c.Ly : c.Ly);
+#pragma unroll
+    for (int sc = 0; sc < 3; ++sc) {
+      const double dy = sc == 1 ? yb : __dadd_rn(yb, sc == 0 ? -c.yz : c.yz);
+      dyv[3 * sb + sc] = dy;
+      myz |= (((mz >> sc) & 1u) && fabs(dy) < c.rcR) ? (1u << (3 * sb + sc)) : 0u;
+    }
+  }
+  if (!myz) return;
+  const double x0 = __dadd_rn((double)t.x[q], -c.xi);
+#pragma unroll
+  for (int sa = 0; sa < 3; ++sa) {
+    const double xa = sa == 1 ? x0 : __dadd_rn(x0, sa == 0 ? -c.Lx : c.Lx);
+#pragma unroll
+    for (int sb = 0; sb < 3; ++sb) {
+      const double xb = sb == 1 ? xa : __dadd_rn(xa, sb == 0 ? -c.xy : c.xy);
+#pragma unroll
+      for (int sc = 0; sc < 3; ++sc) {
+        if (!((myz >> (3 * sb + sc)) & 1u)) continue;
+        const double dx = sc == 1 ? xb : __dadd_rn(xb, sc == 0 ? -c.xz : c.xz);
+        const double dy = dyv[3 * sb + sc], dz = dzv[sc];
+        const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+        const int code = 9 * sa + 3 * sb + sc;
+        if (d2 < c.rcR2 && !(j == c.i && code == 13)) emit(j, code, d2 < c.rcA2);
+      }
+    }
+  }
+}
+
+template <bool kTri, class Emit>
+__device__ __forceinline__ void exact_any(const ScanCtx& c, const PosTile& t, int j, Emit& emit) {
+  if constexpr (kTri)
+    exact_pair_tri(c, t, j, emit);
+  else
+    exact_pair(c, t, j, emit);
+}
+
+// Single-precision minimum image: e = x_j - x_i minus the lattice vector
+// H k, k the rounded fractional coordinates of e (H upper triangular, so
+// f_c = e_z / Lz, f_b = (e_y - yz f_c) / Ly, f_a = (e_x - xy f_b - xz f_c) / Lx).
+// In an orthorhombic cell this is the per-axis rounding.
+template <bool kTri>
+__device__ __forceinline__ void min_image(const ScanCtx& c, float& ex, float& ey, float& ez, float& kx, float& ky,
+                                          float& kz) {
+  if constexpr (kTri) {
+    const float fc = ez * c.ilz;
+    const float fb = (ey - c.yzf * fc) * c.ily;
+    const float fa = (ex - c.xyf * fb - c.xzf * fc) * c.ilx;
+    kx = rintf(fa);
+    ky = rintf(fb);
+    kz = rintf(fc);
+    ex = ex - c.Lxf * kx - c.xyf * ky - c.xzf * kz;
+    ey = ey - c.Lyf * ky - c.yzf * kz;
+    ez -= c.Lzf * kz;
+  } else {
+    kx = rintf(ex * c.ilx);
+    ky = rintf(ey * c.ily);
+    kz = rintf(ez * c.ilz);
+    ex -= c.Lxf * kx;
+    ey -= c.Lyf * ky;
+    ez -= c.Lzf * kz;
+  }
+}
+
+// float64 squared length of the image s = -k of j, in the predicate's order
+template <bool kTri>
+__device__ __forceinline__ double image_d2(const ScanCtx& c, float px, float py, float pz, float kx, float ky,
+                                           float kz) {
+  double dx = __dadd_rn(__dadd_rn((double)px, -c.xi), -(double)kx * c.Lx);
+  double dy = __dadd_rn(__dadd_rn((double)py, -c.yi), -(double)ky * c.Ly);
+  const double dz = __dadd_rn(__dadd_rn((double)pz, -c.zi), -(double)kz * c.Lz);
+  if constexpr (kTri) {
+    dx = __dadd_rn(__dadd_rn(dx, -(double)ky * c.xy), -(double)kz * c.xz);
+    dy = __dadd_rn(dy, -(double)kz * c.yz);
+  }
+  return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+}
+
+template <bool kTri, class Emit>
 __device__ __forceinline__ void scan_range(const ScanCtx& c, const PosTile& t, int jb, int je, Emit& emit) {
   for (int j = jb; j < je; ++j) {
     if (c.fast) {
       const int q = j - t.base;
       const float px = t.x[q], py = t.y[q], pz = t.z[q];
-      float ex = px - c.xf, ey = py - c.yf, ez = pz - c.zf;
-      const float kx = rintf(ex * c.ilx), ky = rintf(ey * c.ily), kz = rintf(ez * c.ilz);
-      ex -= c.Lxf * kx;
-      ey -= c.Lyf * ky;
-      ez -= c.Lzf * kz;
+      float ex = px - c.xf, ey = py - c.yf, ez = pz - c.zf, kx, ky, kz;
+      min_image<kTri>(c, ex, ey, ez, kx, ky, kz);
       const float r2 = ex * ex + ey * ey + ez * ez;
       if (r2 >= c.outR2) continue;
       if (r2 < c.inR2 && fabsf(kx) <= 1.f && fabsf(ky) <= 1.f && fabsf(kz) <= 1.f) {
@@ -116,18 +209,12 @@ __device__ __forceinline__ void scan_range(const ScanCtx& c, const PosTile& t, i
         const int code = 9 * (1 - (int)kx) + 3 * (1 - (int)ky) + (1 - (int)kz);
         if (j == c.i && code == 13) continue;
         bool ang = r2 < c.inA2;
-        if (!ang && r2 < c.outA2) {
-          const double dx = __dadd_rn(__dadd_rn((double)px, -c.xi), -(double)kx * c.Lx);
-          const double dy = __dadd_rn(__dadd_rn((double)py, -c.yi), -(double)ky * c.Ly);
-          const double dz = __dadd_rn(__dadd_rn((double)pz, -c.zi), -(double)kz * c.Lz);
-          const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-          ang = d2 < c.rcA2;
-        }
+        if (!ang && r2 < c.outA2) ang = image_d2<kTri>(c, px, py, pz, kx, ky, kz) < c.rcA2;
         emit(j, code, ang);
         continue;
       }
     }
-    exact_pair(c, t, j, emit);
+    exact_any<kTri>(c, t, j, emit);
   }
 }
 
@@ -137,21 +224,18 @@ __device__ __forceinline__ void scan_range(const ScanCtx& c, const PosTile& t, i
 // later entry overwrites a rejected one (slot kNbrBuf takes the writes once
 // the buffer is full).  Pairs in the shell, and cells too small or too large
 // for the single-image test, branch to the float64 predicate.
-template <class Keep>
+template <bool kTri, class Keep>
 __device__ __forceinline__ void scan_keep(const ScanCtx& c, const PosTile& t, int jb, int je, uint32_t* buf,
                                           int& nR, int& nA, uint32_t& angmask, Keep& keep) {
   for (int j = jb; j < je; ++j) {
     if (!c.fast) {
-      exact_pair(c, t, j, keep);
+      exact_any<kTri>(c, t, j, keep);
       continue;
     }
     const int q = j - t.base;
     const float px = t.x[q], py = t.y[q], pz = t.z[q];
-    float ex = px - c.xf, ey = py - c.yf, ez = pz - c.zf;
-    const float kx = rintf(ex * c.ilx), ky = rintf(ey * c.ily), kz = rintf(ez * c.ilz);
-    ex -= c.Lxf * kx;
-    ey -= c.Lyf * ky;
-    ez -= c.Lzf * kz;
+    float ex = px - c.xf, ey = py - c.yf, ez = pz - c.zf, kx, ky, kz;
+    min_image<kTri>(c, ex, ey, ez, kx, ky, kz);
     const float r2 = ex * ex + ey * ey + ez * ez;
     const bool one = fabsf(kx) <= 1.f && fabsf(ky) <= 1.f && fabsf(kz) <= 1.f;
     const int code = 9 * (1 - (int)kx) + 3 * (1 - (int)ky) + (1 - (int)kz);
@@ -159,20 +243,61 @@ __device__ __forceinline__ void scan_keep(const ScanCtx& c, const PosTile& t, in
     const bool in = decided && !(j == c.i && code == 13);
     bool ang = r2 < c.inA2;
     buf[blockDim.x * min(nR, kNbrBuf)] = ((uint32_t)j << 5) | (uint32_t)(code & 31);
-    if (in && !ang && r2 < c.outA2) {
-      const double dx = __dadd_rn(__dadd_rn((double)px, -c.xi), -(double)kx * c.Lx);
-      const double dy = __dadd_rn(__dadd_rn((double)py, -c.yi), -(double)ky * c.Ly);
-      const double dz = __dadd_rn(__dadd_rn((double)pz, -c.zi), -(double)kz * c.Lz);
-      const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-      ang = d2 < c.rcA2;
-    }
+    if (in && !ang && r2 < c.outA2) ang = image_d2<kTri>(c, px, py, pz, kx, ky, kz) < c.rcA2;
     angmask |= (in && ang && nR < kNbrBuf) ? (1u << nR) : 0u;
     nR += in ? 1 : 0;
     nA += (in && ang) ? 1 : 0;
-    if (!decided && r2 < c.outR2) exact_pair(c, t, j, keep);
+    if (!decided && r2 < c.outR2) exact_any<kTri>(c, t, j, keep);
   }
 }
 
+// Triclinic cells.  Every neighbor lies among the 27 images when the
+// positions' fractional coordinates are in [0, 1) and each perpendicular
+// width of the cell is at least rc: the fractional coordinates of a vector
+// shorter than rc are then below 1 in magnitude.  Positions are accepted with
+// fractional coordinates in [-kFracTol, 1 + kFracTol) and widths from
+// rc / (1 - 2 kFracTol) up, which keeps the same bound.  The single-image fast
+// decision needs each width at least 2 (rc + delta): an image within
+// rc + delta then has fractional coordinates of magnitude below 1/2 by a
+// margin of delta / (2 (rc + delta)), so the rounded fractional coordinates
+// select it.
+constexpr double kFracTol = 1e-5;
+
+struct CellCheck {
+  bool box_ok, pos_ok, fast_ok;
+};
+
+template <bool kTri>
+__device__ __forceinline__ CellCheck check_cell(const ScanCtx& c, float rcR, float rcA) {
+  CellCheck k;
+  const float wide = 2.0f * (rcR + kNbrDelta);
+  const bool small = c.Lxf <= kNbrFastL && c.Lyf <= kNbrFastL && c.Lzf <= kNbrFastL && rcA >= 1.0f;
+  const bool tilted = kTri && (c.xyf != 0.f || c.xzf != 0.f || c.yzf != 0.f);
+  if (!tilted) {
+    k.pos_ok = c.xf >= 0.f && c.xf < c.Lxf && c.yf >= 0.f && c.yf < c.Lyf && c.zf >= 0.f && c.zf < c.Lzf;
+    k.box_ok = c.Lxf >= rcR && c.Lyf >= rcR && c.Lzf >= rcR;
+    k.fast_ok = c.Lxf >= wide && c.Lyf >= wide && c.Lzf >= wide && small;
+    return k;
+  }
+  // perpendicular widths V / |b x c|, V / |c x a|, V / |a x b|
+  const double bc_x = c.Ly * c.Lz, bc_y = -c.xy * c.Lz, bc_z = c.xy * c.yz - c.Ly * c.xz;
+  const double V = c.Lx * c.Ly * c.Lz;
+  const double ha = fabs(V) / sqrt(bc_x * bc_x + bc_y * bc_y + bc_z * bc_z);
+  const double hb = fabs(c.Ly * c.Lz) / sqrt(c.Lz * c.Lz + c.yz * c.yz);
+  const double hc = fabs(c.Lz);
+  const double hmin = fmin(ha, fmin(hb, hc));
+  k.box_ok = c.Lxf > 0.f && c.Lyf > 0.f && c.Lzf > 0.f && hmin * (1.0 - 2.0 * kFracTol) >= (double)rcR;
+  const double fc = c.zi / c.Lz;
+  const double fb = (c.yi - c.yz * fc) / c.Ly;
+  const double fa = (c.xi - c.xy * fb - c.xz * fc) / c.Lx;
+  k.pos_ok = fa >= -kFracTol && fa < 1.0 + kFracTol && fb >= -kFracTol && fb < 1.0 + kFracTol &&
+             fc >= -kFracTol && fc < 1.0 + kFracTol;
+  k.fast_ok = hmin >= (double)wide && small && fabsf(c.xyf) <= kNbrFastL && fabsf(c.xzf) <= kNbrFastL &&
+              fabsf(c.yzf) <= kNbrFastL;
+  return k;
+}
+
+template <bool kTri>
 __global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
   __shared__ float tx[kNbrTile], ty[kNbrTile], tz[kNbrTile];
   __shared__ uint32_t nbuf[256 * (kNbrBuf + 1)];
@@ -196,13 +321,26 @@ __global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
   c.Lxf = a.box[3 * st];
   c.Lyf = a.box[3 * st + 1];
   c.Lzf = a.box[3 * st + 2];
+  c.xyf = kTri ? a.tilt[3 * st] : 0.f;
+  c.xzf = kTri ? a.tilt[3 * st + 1] : 0.f;
+  c.yzf = kTri ? a.tilt[3 * st + 2] : 0.f;
   c.xf = a.pos[c.i];
   c.yf = a.pos[a.N + c.i];
   c.zf = a.pos[2 * a.N + c.i];
+  c.xi = c.xf;
+  c.yi = c.yf;
+  c.zi = c.zf;
+  c.Lx = c.Lxf;
+  c.Ly = c.Lyf;
+  c.Lz = c.Lzf;
+  c.xy = c.xyf;
+  c.xz = c.xzf;
+  c.yz = c.yzf;
+  const CellCheck ck = check_cell<kTri>(c, a.rcR, a.rcA);
   int fl = 0;
-  if (!(c.xf >= 0.f && c.xf < c.Lxf && c.yf >= 0.f && c.yf < c.Lyf && c.zf >= 0.f && c.zf < c.Lzf)) fl |= FL_POS;
+  if (!ck.pos_ok) fl |= FL_POS;
   bool ok = live;
-  if (!(c.Lxf >= a.rcR && c.Lyf >= a.rcR && c.Lzf >= a.rcR)) {
+  if (!ck.box_ok) {
     fl |= FL_BOX;
     ok = false;
   }
@@ -211,21 +349,13 @@ __global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
     const int ti = a.type[i];
     if (ti < 0 || ti >= a.T) fl |= FL_TYPE;
   }
-  c.xi = c.xf;
-  c.yi = c.yf;
-  c.zi = c.zf;
-  c.Lx = c.Lxf;
-  c.Ly = c.Lyf;
-  c.Lz = c.Lzf;
   c.rcR = (double)a.rcR;
   c.rcR2 = c.rcR * c.rcR;  // exact: a float squared in double
   c.rcA2 = (double)a.rcA * (double)a.rcA;
   c.ilx = 1.0f / c.Lxf;
   c.ily = 1.0f / c.Lyf;
   c.ilz = 1.0f / c.Lzf;
-  const float wide = 2.0f * (a.rcR + kNbrDelta);
-  c.fast = c.Lxf >= wide && c.Lyf >= wide && c.Lzf >= wide &&
-           c.Lxf <= kNbrFastL && c.Lyf <= kNbrFastL && c.Lzf <= kNbrFastL && a.rcA >= 1.0f;
+  c.fast = ck.fast_ok;
   c.inR2 = (a.rcR - kNbrDelta) * (a.rcR - kNbrDelta);
   c.outR2 = (a.rcR + kNbrDelta) * (a.rcR + kNbrDelta);
   c.inA2 = (a.rcA - kNbrDelta) * (a.rcA - kNbrDelta);
@@ -264,7 +394,8 @@ __global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
     ++nR;
     nA += ang ? 1 : 0;
   };
-  sweep(jb, je, [&](const PosTile& t, int b2, int e2) { scan_keep(c, t, b2, e2, mybuf, nR, nA, angmask, keep); });
+  sweep(jb, je,
+        [&](const PosTile& t, int b2, int e2) { scan_keep<kTri>(c, t, b2, e2, mybuf, nR, nA, angmask, keep); });
   // inclusive prefix over the 8 lanes of the atom
   int pR = nR, pA = nA;
 #pragma unroll
@@ -300,7 +431,8 @@ __global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
       }
     };
     const bool wr = live && spill && wR < a.capR;
-    sweep(wr ? jb : 0, wr ? je : 0, [&](const PosTile& t, int b2, int e2) { scan_range(c, t, b2, e2, write); });
+    sweep(wr ? jb : 0, wr ? je : 0,
+          [&](const PosTile& t, int b2, int e2) { scan_range<kTri>(c, t, b2, e2, write); });
   }
   if (live && s == 0) {
     a.cntR[i] = totR;
@@ -505,15 +637,39 @@ struct PairGeom {
   float dx, dy, dz, r, inv_r;
 };
 
+// cell of a structure: edge vectors a = (Lx, 0, 0), b = (xy, Ly, 0),
+// c = (xz, yz, Lz); the tilts are read only for triclinic batches
+struct Cell {
+  float Lx, Ly, Lz, xy, xz, yz;
+};
+
+template <bool kTri>
+__device__ __forceinline__ Cell load_cell(const float* __restrict__ box, const float* __restrict__ tilt, int st) {
+  Cell c;
+  c.Lx = box[3 * st];
+  c.Ly = box[3 * st + 1];
+  c.Lz = box[3 * st + 2];
+  c.xy = kTri ? tilt[3 * st] : 0.f;
+  c.xz = kTri ? tilt[3 * st + 1] : 0.f;
+  c.yz = kTri ? tilt[3 * st + 2] : 0.f;
+  return c;
+}
+
+// d = x_j - x_i + sa a + sb b + sc c for the entry's image shift
+template <bool kTri>
 __device__ __forceinline__ PairGeom pair_geom(uint32_t e, const float* __restrict__ pos, int N, float xi, float yi,
-                                              float zi, float Lx, float Ly, float Lz) {
+                                              float zi, const Cell& cl) {
   PairGeom g;
   g.j = (int)(e >> 5);
   float sx, sy, sz;
   decode_shift(e & 31u, sx, sy, sz);
-  g.dx = (pos[g.j] - xi) + sx * Lx;
-  g.dy = (pos[N + g.j] - yi) + sy * Ly;
-  g.dz = (pos[2 * N + g.j] - zi) + sz * Lz;
+  g.dx = (pos[g.j] - xi) + sx * cl.Lx;
+  g.dy = (pos[N + g.j] - yi) + sy * cl.Ly;
+  g.dz = (pos[2 * N + g.j] - zi) + sz * cl.Lz;
+  if constexpr (kTri) {
+    g.dx += sy * cl.xy + sz * cl.xz;
+    g.dy += sz * cl.yz;
+  }
   const float r2 = g.dx * g.dx + g.dy * g.dy + g.dz * g.dz;
   g.inv_r = rsq_hw(r2);
   g.r = r2 * g.inv_r;
@@ -652,7 +808,7 @@ __device__ __forceinline__ void stage_weights(float* wl, const float* __restrict
 // gives E_i and E' = dE_i/dG (D1.1-D1.5).  With forces on, every listed
 // pair's partial force f_ij = dE_i/dr_ij is stored (C3.6) with this atom's
 // share -sum_j f_ij (x) r_ij of the virial.
-template <class C>
+template <class C, bool kTri>
 __global__ __launch_bounds__(256, 2) void k_forward(FwdArgs a) {
   constexpr int T = C::T, NR = C::NR, NA = C::NA, KR = C::KR, KA = C::KA, Y = C::Y, D = C::D, LM = C::LMAX;
   constexpr int L3 = C::L3, L4 = C::L4, L5 = C::L5;
@@ -675,7 +831,7 @@ __global__ __launch_bounds__(256, 2) void k_forward(FwdArgs a) {
   float* row = rows + w.al * RW;
   float* rowS = row + DP;
   const int st = a.astruct[i];
-  const float Lx = a.box[3 * st], Ly = a.box[3 * st + 1], Lz = a.box[3 * st + 2];
+  const Cell cell = load_cell<kTri>(a.box, a.tilt, st);
   const float xi = a.pos[i], yi = a.pos[N + i], zi = a.pos[2 * N + i];
   const int cR_i = a.nb.cntR[i], cA_i = a.nb.cntA[i];
   const int nR = w.valid ? min(cR_i, a.nb.capR) : 0;
@@ -689,7 +845,7 @@ __global__ __launch_bounds__(256, 2) void k_forward(FwdArgs a) {
 #pragma unroll
     for (int k = 0; k < KR; ++k) FR[t][k] = 0.f;
   for (int k = s; k < nR; k += kLPA) {
-    const PairGeom q = pair_geom(a.nb.idxR[(size_t)i * a.nb.capR + k], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+    const PairGeom q = pair_geom<kTri>(a.nb.idxR[(size_t)i * a.nb.capR + k], a.pos, N, xi, yi, zi, cell);
     float f[KR];
     radial_basis<KR>(q.r, a.inv_rcR, f);
     const int J = a.type[q.j];
@@ -722,7 +878,7 @@ __global__ __launch_bounds__(256, 2) void k_forward(FwdArgs a) {
 #pragma unroll
     for (int e = 0; e < YG; ++e) Sg[n][e] = 0.f;
   for (int k = w.p; k < nA; k += 4) {
-    const PairGeom q = pair_geom(a.nb.idxA[(size_t)i * a.nb.capA + k], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+    const PairGeom q = pair_geom<kTri>(a.nb.idxA[(size_t)i * a.nb.capA + k], a.pos, N, xi, yi, zi, cell);
     float f[KA];
     radial_basis<KA>(q.r, a.inv_rcA, f);
     const int J = a.type[q.j];
@@ -855,7 +1011,7 @@ __global__ __launch_bounds__(256, 2) void k_forward(FwdArgs a) {
     }
   float vxx = 0.f, vyy = 0.f, vzz = 0.f, vxy = 0.f, vyz = 0.f, vzx = 0.f;
   for (int k = s; k < nR; k += kLPA) {
-    const PairGeom q = pair_geom(a.nb.idxR[(size_t)i * a.nb.capR + k], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+    const PairGeom q = pair_geom<kTri>(a.nb.idxR[(size_t)i * a.nb.capR + k], a.pos, N, xi, yi, zi, cell);
     float f[KR], fp[KR];
     radial_basis_d<KR>(q.r, a.inv_rcR, f, fp);
     const int J = a.type[q.j];
@@ -919,7 +1075,7 @@ __global__ __launch_bounds__(256, 2) void k_forward(FwdArgs a) {
   // ---- angular partial forces: f_ij = sum_nlm A_nlm (g'_n r_hat B_lm + g_n grad B_lm);
   //      each harmonic group adds its half, the two halves are summed across lanes
   for (int k = w.p; k < nA; k += 4) {
-    const PairGeom q = pair_geom(a.nb.idxA[(size_t)i * a.nb.capA + k], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+    const PairGeom q = pair_geom<kTri>(a.nb.idxA[(size_t)i * a.nb.capA + k], a.pos, N, xi, yi, zi, cell);
     const float ux = q.dx * q.inv_r, uy = q.dy * q.inv_r, uz = q.dz * q.inv_r;
     float f[KA], fp[KA];
     radial_basis_d<KA>(q.r, a.inv_rcA, f, fp);
@@ -1178,7 +1334,7 @@ __global__ __launch_bounds__(kRedBlk) void k_loss_final(int S, int N, float le, 
 //            coupling that Algorithm 1 enumerates).
 // Outputs: per-atom vectors for the outer-product sums (W0, c^R) and, per
 // wavefront, the sums of the c^A, b0, w1, b1 partials over its 8 atoms.
-template <class C>
+template <class C, bool kTri>
 __global__ __launch_bounds__(256, 2) void k_adjoint(AdjArgs a) {
   constexpr int T = C::T, NR = C::NR, NA = C::NA, KR = C::KR, KA = C::KA, Y = C::Y, D = C::D, LM = C::LMAX;
   constexpr int L3 = C::L3, L4 = C::L4, L5 = C::L5;
@@ -1208,7 +1364,7 @@ __global__ __launch_bounds__(256, 2) void k_adjoint(AdjArgs a) {
   float* rowSb = row + DP;
   float* rowA = rowSb + NA * Y;
   const int st = a.astruct[i];
-  const float Lx = a.box[3 * st], Ly = a.box[3 * st + 1], Lz = a.box[3 * st + 2];
+  const Cell cell = load_cell<kTri>(a.box, a.tilt, st);
   const float xi = a.pos[i], yi = a.pos[N + i], zi = a.pos[2 * N + i];
   const int cR_i = a.nb.cntR[i], cA_i = a.nb.cntA[i];
   const int nR = w.valid ? min(cR_i, a.nb.capR) : 0;
@@ -1227,7 +1383,7 @@ __global__ __launch_bounds__(256, 2) void k_adjoint(AdjArgs a) {
 #pragma unroll
     for (int k = 0; k < KR; ++k) FR[t][k] = FP[t][k] = 0.f;
   for (int k = s; k < nR; k += kLPA) {
-    const PairGeom q = pair_geom(a.nb.idxR[(size_t)i * a.nb.capR + k], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+    const PairGeom q = pair_geom<kTri>(a.nb.idxR[(size_t)i * a.nb.capR + k], a.pos, N, xi, yi, zi, cell);
     const float tx = (a.fbar[q.j] - fbx) + gxx * q.dx + gxy * q.dy;
     const float ty = (a.fbar[N + q.j] - fby) + gyy * q.dy + gyz * q.dz;
     const float tz = (a.fbar[2 * N + q.j] - fbz) + gzz * q.dz + gzx * q.dx;
@@ -1276,7 +1432,7 @@ __global__ __launch_bounds__(256, 2) void k_adjoint(AdjArgs a) {
 #pragma unroll
     for (int e = 0; e < YG; ++e) Sd[n][e] = 0.f;
   for (int k = w.p; k < nA; k += 4) {
-    const PairGeom q = pair_geom(a.nb.idxA[(size_t)i * a.nb.capA + k], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+    const PairGeom q = pair_geom<kTri>(a.nb.idxA[(size_t)i * a.nb.capA + k], a.pos, N, xi, yi, zi, cell);
     const float ux = q.dx * q.inv_r, uy = q.dy * q.inv_r, uz = q.dz * q.inv_r;
     const float tx = (a.fbar[q.j] - fbx) + gxx * q.dx + gxy * q.dy;
     const float ty = (a.fbar[N + q.j] - fby) + gyy * q.dy + gyz * q.dz;
@@ -1506,7 +1662,7 @@ __global__ __launch_bounds__(256, 2) void k_adjoint(AdjArgs a) {
     // reload Sbar and A from LDS every pair: hoisted out of the loop they
     // would take 2 NAH Y registers and halve the occupancy
     asm volatile("" ::: "memory");
-    const PairGeom q = pair_geom(a.nb.idxA[(size_t)i * a.nb.capA + k], a.pos, N, xi, yi, zi, Lx, Ly, Lz);
+    const PairGeom q = pair_geom<kTri>(a.nb.idxA[(size_t)i * a.nb.capA + k], a.pos, N, xi, yi, zi, cell);
     const float ux = q.dx * q.inv_r, uy = q.dy * q.inv_r, uz = q.dz * q.inv_r;
     const float tx = (a.fbar[q.j] - fbx) + gxx * q.dx + gxy * q.dy;
     const float ty = (a.fbar[N + q.j] - fby) + gyy * q.dy + gyz * q.dz;
@@ -1889,6 +2045,7 @@ struct MDArgs {
   const int* type;
   const int* astruct;
   const float* box;
+  const float* tilt;   // null: every cell orthorhombic
   const float* mass;   // [T] amu
   float* pos;          // [3][N]
   float* vel;          // [3][N] A/fs
@@ -1902,24 +2059,44 @@ __device__ __forceinline__ float inv_mass(const MDArgs& a, int i) {
   return (t >= 0 && t < a.T) ? kAccel / a.mass[t] : 0.f;
 }
 
-// half kick with the forces at the current positions, drift, wrap into [0, L)
+// half kick with the forces at the current positions, drift, wrap into the
+// cell: [0, L) per axis for an orthorhombic cell; for a triclinic one, minus
+// the lattice vector H floor(f) of the fractional coordinates f = H^-1 x
 __global__ __launch_bounds__(256) void k_md_drift(MDArgs a) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.N) return;
   const float im = inv_mass(a, i);
   const int st = a.astruct[i];
+  float x[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const size_t q = (size_t)c * a.N + i;
     const float v = fmaf(a.hdt * im, a.F[q], a.vel[q]);
     a.vel[q] = v;
-    const float L = a.box[3 * st + c];
-    float x = fmaf(a.dt, v, a.pos[q]);
-    x -= L * floorf(x / L);
-    if (x >= L) x -= L;
-    if (!(x >= 0.f)) x = 0.f;
-    a.pos[q] = x;
+    x[c] = fmaf(a.dt, v, a.pos[q]);
   }
+  const float Lx = a.box[3 * st], Ly = a.box[3 * st + 1], Lz = a.box[3 * st + 2];
+  const float xy = a.tilt ? a.tilt[3 * st] : 0.f, xz = a.tilt ? a.tilt[3 * st + 1] : 0.f,
+              yz = a.tilt ? a.tilt[3 * st + 2] : 0.f;
+  if (xy != 0.f || xz != 0.f || yz != 0.f) {
+    const float fc = x[2] / Lz;
+    const float fb = (x[1] - yz * fc) / Ly;
+    const float fa = (x[0] - xy * fb - xz * fc) / Lx;
+    const float ka = floorf(fa), kb = floorf(fb), kc = floorf(fc);
+    x[0] = x[0] - Lx * ka - xy * kb - xz * kc;
+    x[1] = x[1] - Ly * kb - yz * kc;
+    x[2] = x[2] - Lz * kc;
+  } else {
+    const float L[3] = {Lx, Ly, Lz};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      x[c] -= L[c] * floorf(x[c] / L[c]);
+      if (x[c] >= L[c]) x[c] -= L[c];
+      if (!(x[c] >= 0.f)) x[c] = 0.f;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) a.pos[(size_t)c * a.N + i] = x[c];
 }
 
 // half kick with the forces at the new positions; kinetic energy per atom
@@ -1976,11 +2153,17 @@ static size_t lds_adjoint(int H) {
 }
 template <class C>
 static void launch_forward(const FwdArgs& a, dim3 grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_forward<C>, grid, dim3(256), lds_forward<C>(a.H), st, a);
+  if (a.tilt)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forward<C, true>), grid, dim3(256), lds_forward<C>(a.H), st, a);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forward<C, false>), grid, dim3(256), lds_forward<C>(a.H), st, a);
 }
 template <class C>
 static void launch_adjoint(const AdjArgs& a, dim3 grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_adjoint<C>, grid, dim3(256), lds_adjoint<C>(a.H), st, a);
+  if (a.tilt)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adjoint<C, true>), grid, dim3(256), lds_adjoint<C>(a.H), st, a);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adjoint<C, false>), grid, dim3(256), lds_adjoint<C>(a.H), st, a);
 }
 template <class C>
 static Ops make_ops() {
@@ -2188,6 +2371,7 @@ void run_neighbors(const Ctx& c, nep_neighbors* nb, int32_t* flags, Prof* pr) {
   a.rcA = c.m->rc_ang;
   a.aoff = c.b->atom_offset;
   a.box = c.b->box;
+  a.tilt = c.b->tilt;
   a.pos = c.b->pos;
   a.type = c.b->type;
   a.idxR = nb->idx_rad;
@@ -2196,7 +2380,12 @@ void run_neighbors(const Ctx& c, nep_neighbors* nb, int32_t* flags, Prof* pr) {
   a.cntA = nb->cnt_ang;
   a.astruct = at<int>(c.ws, c.L.astruct);
   a.flags = flags;
-  NEP_LAUNCH(pr, "neighbors", hipLaunchKernelGGL(k_neighbors, dim3(grid1(N, kNbrAPB)), dim3(256), 0, c.st, a));
+  if (a.tilt)
+    NEP_LAUNCH(pr, "neighbors",
+               hipLaunchKernelGGL(k_neighbors<true>, dim3(grid1(N, kNbrAPB)), dim3(256), 0, c.st, a));
+  else
+    NEP_LAUNCH(pr, "neighbors",
+               hipLaunchKernelGGL(k_neighbors<false>, dim3(grid1(N, kNbrAPB)), dim3(256), 0, c.st, a));
   NEP_LAUNCH(pr, "reverse_rad",
              hipLaunchKernelGGL(k_reverse, dim3(grid1(N, 32)), dim3(256), 0, c.st, N, nb->idx_rad,
                                 nb->cnt_rad, c.m->cap_rad, at<int>(c.ws, c.L.revR)));
@@ -2227,6 +2416,7 @@ FwdArgs fwd_args(const Ctx& c, const nep_neighbors* nb, const float* params) {
   a.order = at<int>(c.ws, c.L.order);
   a.astruct = at<int>(c.ws, c.L.astruct);
   a.box = c.b->box;
+  a.tilt = c.b->tilt;
   a.pos = c.b->pos;
   a.type = c.b->type;
   a.nb = pair_lists(c, nb);
@@ -2310,6 +2500,7 @@ void run_adjoint(const Ctx& c, const nep_neighbors* nb, const float* params, con
     a.order = at<int>(c.ws, c.L.order);
     a.astruct = at<int>(c.ws, c.L.astruct);
     a.box = c.b->box;
+    a.tilt = c.b->tilt;
     a.pos = c.b->pos;
     a.type = c.b->type;
     a.nb = pair_lists(c, nb);
@@ -2502,6 +2693,7 @@ int nep_md_step(const nep_model* m, const nep_batch* b, float* pos, nep_neighbor
   a.type = b->type;
   a.astruct = at<int>(c.ws, c.L.astruct);
   a.box = b->box;
+  a.tilt = b->tilt;
   a.mass = mass;
   a.pos = pos;
   a.vel = vel;

@@ -114,11 +114,16 @@ class DeviceBatch:
         self.box = torch.as_tensor(np.asarray(batch.box, np.float32), device=device)
         self.pos = torch.as_tensor(np.asarray(batch.pos_soa, np.float32), device=device)
         self.type = torch.as_tensor(np.asarray(batch.types, np.int32), device=device)
+        # tilts (xy, xz, yz) per structure; None when every cell is orthorhombic
+        tilt = getattr(batch, "tilt", None)
+        self.tilt = (torch.as_tensor(np.asarray(tilt, np.float32), device=device)
+                     if tilt is not None and np.any(np.asarray(tilt) != 0) else None)
 
     def c(self):
         return _lib.NepBatch(self.n_struct, self.n_atom, self.atom_offset.data_ptr(), self.box.data_ptr(),
                              self.pos.data_ptr() if self.n_atom else None,
-                             self.type.data_ptr() if self.n_atom else None)
+                             self.type.data_ptr() if self.n_atom else None,
+                             self.tilt.data_ptr() if self.tilt is not None else None)
 
 
 class Neighbors:

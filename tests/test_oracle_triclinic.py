@@ -14,22 +14,9 @@ from oracle import NEPOracle, neighbor_pairs, unpack
 from oracle.nep_oracle import _neighbor_pairs_triclinic
 from paper_2507_00528_amd import synth
 
-from _helpers import small_structures
+from _helpers import grid_structure, hmat, sheared, small_structures, widths
 
 DT = torch.float64
-
-
-def hmat(box, tilt):
-    lx, ly, lz = np.asarray(box, np.float32).astype(np.float64)
-    xy, xz, yz = np.asarray(tilt, np.float32).astype(np.float64)
-    return np.array([[lx, xy, xz], [0, ly, yz], [0, 0, lz]])
-
-
-def widths(H):
-    a, b, c = H.T
-    V = abs(np.linalg.det(H))
-    return np.array([V / np.linalg.norm(np.cross(b, c)), V / np.linalg.norm(np.cross(c, a)),
-                     V / np.linalg.norm(np.cross(a, b))])
 
 
 def brute_force(st, rc, reach=2):
@@ -70,33 +57,6 @@ def test_zero_tilt_search_equals_the_orthorhombic_search():
             a = neighbor_pairs(st.pos, st.box, rc)
             b = _neighbor_pairs_triclinic(st.pos, st.box, rc, None, np.zeros(3, np.float32))
             np.testing.assert_array_equal(a, b)
-
-
-def grid_structure(seed, n, L):
-    """An orthorhombic cell of edge L whose coordinates are multiples of 1/256,
-    so that adding an edge vector is exact in float32."""
-    rng = np.random.default_rng(seed)
-    while True:
-        p = np.round(rng.uniform(0, L, (n, 3)) * 256) / 256
-        p = np.where(p >= L, 0.0, p)
-        box = np.full(3, L)
-        d = np.linalg.norm((p[:, None] - p[None] + L / 2) % L - L / 2, axis=-1) + np.eye(n) * 9
-        if d.min() > 1.9:
-            break
-    return synth.Structure(p.astype(np.float32), box.astype(np.float32), (np.arange(n) % 2).astype(np.int32), "grid")
-
-
-def sheared(st, tilt):
-    """The same crystal in the cell with the given tilts, which are integer
-    combinations of the orthorhombic edges: positions moved by whole edge
-    vectors into the new cell (exact in float32)."""
-    H = hmat(st.box, tilt)
-    x = st.pos.astype(np.float64)
-    f = np.linalg.solve(H, x.T).T
-    k = np.floor(f)
-    x2 = x - k @ H.T
-    assert np.all(x2.astype(np.float32).astype(np.float64) == x2)
-    return synth.Structure(x2.astype(np.float32), st.box, st.types, "sheared", np.asarray(tilt, np.float32))
 
 
 @pytest.mark.parametrize("L,tilt_of", [
