@@ -61,7 +61,7 @@ enum {
  *   n_rad radial channels q_n, n = 0..n_rad-1              (Eq. 5)
  *   k_rad Chebyshev terms per radial function, k = 0..k_rad-1 (Eq. 6)
  *   n_ang, k_ang: the same for the angular radial functions g_n of Eq. 8
- *   l3:  3-body degrees l = 1..l3 of Eq. 7 (0..4 supported)
+ *   l3:  3-body degrees l = 1..l3 of Eq. 7 (0..8 supported)
  *   l4:  0, or 2 for the 4-body invariant tr(M_n^3) of the l = 2 sums
  *   l5:  0, or 1 for the 5-body invariant (sum_m S_n1m^2)^2
  *   hidden: hidden neurons of the per-species tanh network (D1.1)

@@ -13,6 +13,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libnep.so")
 SOURCES = [os.path.join(HERE, "csrc", "nep_lib.hip")]
 HEADERS = [os.path.join(HERE, "csrc", "nep_device.h"), os.path.join(HERE, "csrc", "nep_kernels.h"),
+           os.path.join(HERE, "csrc", "nep_highl.h"),
            os.path.join(ROOT, "include", "nep.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

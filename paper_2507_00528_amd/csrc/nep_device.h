@@ -29,8 +29,12 @@ template <int T_, int NR_, int NA_, int KR_, int KA_, int L3_, int L4_, int L5_>
 struct Cfg {
   static constexpr int T = T_, NR = NR_, NA = NA_, KR = KR_, KA = KA_;
   static constexpr int L3 = L3_, L4 = L4_, L5 = L5_;
-  static constexpr int LMAX = (L3 > L4 ? (L3 > L5 ? L3 : L5) : (L4 > L5 ? L4 : L5));
+  // the per-atom kernels hold the harmonics of l <= 4 (and of the 4-/5-body
+  // terms); degrees 5..L3 run in separate kernels (nep_highl.h)
+  static constexpr int L3LO = L3 < 4 ? L3 : 4;
+  static constexpr int LMAX = (L3LO > L4 ? (L3LO > L5 ? L3LO : L5) : (L4 > L5 ? L4 : L5));
   static constexpr int Y = LMAX * (LMAX + 2);
+  static constexpr int YH = L3 > 4 ? (L3 + 1) * (L3 + 1) - 25 : 0;   // harmonics of l = 5..L3
   static constexpr int D = NR + NA * L3 + (L4 ? NA : 0) + (L5 ? NA : 0);
   static constexpr int PS = T * NR * KR + T * NA * KA;  // c-grad slots of one center species
 };

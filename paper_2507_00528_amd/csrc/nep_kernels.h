@@ -100,4 +100,29 @@ struct AdjArgs {
   int PW;
 };
 
+// Kernels of the angular degrees l = 5..L3 (nep_highl.h)
+struct HighArgs {
+  int N, Npad, PW;
+  float inv_rcA;
+  const int* order;
+  const int* astruct;
+  const float* box;
+  const float* tilt;
+  const float* pos;
+  const int* type;
+  PairLists nb;
+  const float* cA;
+  float* Sh;          // [Npad][NA][YH] sums S~ of the orthonormal harmonics
+  float* Sdh;         // [Npad][NA][YH] their tangents
+  float* G;           // [D][Npad] descriptor rows (q_nl of l > 4 written here)
+  const float* Ep;    // [D][Npad] dE/dG
+  float* Gd;          // [D][Npad] descriptor tangents
+  const float* Gb;    // [D][Npad] Gbar (rows of l > 4)
+  float* fA;          // [N][capA][3] angular pair forces (added to)
+  float* wv;          // [6][N] per-atom virials (added to)
+  const float* fbar;  // [3][N]
+  const float* wbar;  // [S][6]
+  float* part;        // [n_waves][PW] (c^A slots added to)
+};
+
 }  // namespace nep

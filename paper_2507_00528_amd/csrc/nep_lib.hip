@@ -720,6 +720,9 @@ constexpr int kLPA = 8;                    // lanes per atom
 constexpr int kAPB = 256 / kLPA;           // atoms per block
 constexpr int kAPW = kWave / kLPA;         // atoms per wavefront
 static_assert(kAPW == kSegAlign, "species segments must align to wavefronts");
+}  // namespace nep
+#include "nep_highl.h"
+namespace nep {
 
 template <int LM>
 struct HSplit {
@@ -949,6 +952,13 @@ __global__ __launch_bounds__(256, 2) void k_forward(FwdArgs a) {
           if (w.valid && a.Sst) a.Sst[(size_t)(n * Y + q) * a.Npad + pa] = Sg[n][e];
         }
       }
+  }
+  if constexpr (C::YH > 0) {
+    // q_nl of l = 5..L3, from k_high_desc
+    for (int v = NR + 4 * NA + s; v < NR + L3 * NA; v += kLPA) {
+      const float x = a.G[(size_t)v * a.Npad + pa];
+      row[v] = w.valid ? x : 0.f;
+    }
   }
   __syncthreads();
   float G[D];
@@ -1527,6 +1537,13 @@ __global__ __launch_bounds__(256, 2) void k_adjoint(AdjArgs a) {
       }
     }
   }
+  if constexpr (C::YH > 0) {
+    // Gdot of q_nl, l = 5..L3, from k_high_tangent
+    for (int v = NR + 4 * NA + s; v < NR + L3 * NA; v += kLPA) {
+      const float x = a.Gd[(size_t)v * a.Npad + pa];
+      row[v] = w.valid ? x : 0.f;
+    }
+  }
   __syncthreads();
   float Gd[D];
 #pragma unroll
@@ -1577,6 +1594,12 @@ __global__ __launch_bounds__(256, 2) void k_adjoint(AdjArgs a) {
 #pragma unroll
   for (int n = 0; n < NR; ++n)
     if (w.valid && s == (n & 7)) a.Gbr[(size_t)n * a.Npad + pa] = Gb[n];
+  if constexpr (C::YH > 0) {
+    // Gbar of q_nl, l = 5..L3, for k_high_coef (the rows hold D entries)
+#pragma unroll
+    for (int v = NR + 4 * NA; v < NR + L3 * NA; ++v)
+      if (w.valid && s == (v & 7)) a.Gbr[(size_t)v * a.Npad + pa] = Gb[v];
+  }
 
   // ---- Sbar and A of this lane's harmonic group, in place in the atom's LDS
   //      row, channel n by the lanes of pair slot n mod 4; Gbar goes to the
@@ -2131,12 +2154,15 @@ __global__ __launch_bounds__(256) void k_struct_sum(const int* __restrict__ aoff
   if (threadIdx.x == 0) out[s] = (float)red[0];
 }
 
+enum HighKernel { kHighDesc, kHighForce, kHighTangent, kHighCoef };
+
 struct Ops {
-  int T, NR, NA, KR, KA, L3, L4, L5, D, Y, PS;
+  int T, NR, NA, KR, KA, L3, L4, L5, D, Y, PS, YH;
   void (*forward)(const FwdArgs&, dim3, hipStream_t);
   void (*adjoint)(const AdjArgs&, dim3, hipStream_t);
   size_t (*lds_fwd)(int);
   size_t (*lds_adj)(int);
+  void (*high)(HighKernel, const HighArgs&, dim3, hipStream_t);   // null without degrees l > 4
 };
 
 template <class C>
@@ -2165,10 +2191,30 @@ static void launch_adjoint(const AdjArgs& a, dim3 grid, hipStream_t st) {
   else
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adjoint<C, false>), grid, dim3(256), lds_adjoint<C>(a.H), st, a);
 }
+template <class C, bool kTri>
+static void launch_high_t(HighKernel k, const HighArgs& a, dim3 grid, hipStream_t st) {
+  switch (k) {
+    case kHighDesc: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_high_desc<C, kTri>), grid, dim3(256), 0, st, a); break;
+    case kHighForce: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_high_force<C, kTri>), grid, dim3(256), 0, st, a); break;
+    case kHighTangent:
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_high_tangent<C, kTri>), grid, dim3(256), 0, st, a);
+      break;
+    case kHighCoef: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_high_coef<C, kTri>), grid, dim3(256), 0, st, a); break;
+  }
+}
+template <class C>
+static void launch_high(HighKernel k, const HighArgs& a, dim3 grid, hipStream_t st) {
+  if (a.tilt)
+    launch_high_t<C, true>(k, a, grid, st);
+  else
+    launch_high_t<C, false>(k, a, grid, st);
+}
 template <class C>
 static Ops make_ops() {
-  return Ops{C::T, C::NR, C::NA, C::KR, C::KA, C::L3, C::L4, C::L5, C::D, C::Y, C::PS,
-             &launch_forward<C>, &launch_adjoint<C>, &lds_forward<C>, &lds_adjoint<C>};
+  void (*high)(HighKernel, const HighArgs&, dim3, hipStream_t) = nullptr;
+  if constexpr (C::YH > 0) high = &launch_high<C>;
+  return Ops{C::T, C::NR, C::NA, C::KR, C::KA, C::L3, C::L4, C::L5, C::D, C::Y, C::PS, C::YH,
+             &launch_forward<C>, &launch_adjoint<C>, &lds_forward<C>, &lds_adjoint<C>, high};
 }
 
 // Compiled-in model sizes (n_types, n_rad, n_ang, k_rad, k_ang, l3, l4, l5).
@@ -2177,6 +2223,7 @@ static const Ops kOps[] = {
     make_ops<Cfg<2, 7, 5, 11, 11, 4, 2, 1>>(),  // 3/4/5-body NEP, basis 10, n_max 6/4
     make_ops<Cfg<2, 3, 2, 4, 3, 4, 2, 1>>(),    // small two-species model
     make_ops<Cfg<1, 4, 3, 6, 5, 2, 2, 0>>(),    // small one-species model
+    make_ops<Cfg<2, 5, 4, 8, 8, 8, 2, 1>>(),    // 3-body degrees up to l = 8, n_max 4/3
 };
 
 }  // namespace nep
@@ -2197,7 +2244,7 @@ const Ops* find_ops(const nep_model* m) {
 int model_valid(const nep_model* m) {
   if (!m) return NEP_ERR_ARG;
   if (m->n_types < 1 || m->n_types > 8 || m->n_rad < 1 || m->n_ang < 0 || m->k_rad < 1 || m->k_ang < 1 ||
-      m->l3 < 0 || m->l3 > 4 || (m->l4 != 0 && m->l4 != 2) || (m->l5 != 0 && m->l5 != 1) || m->hidden < 1 ||
+      m->l3 < 0 || m->l3 > 8 || (m->l4 != 0 && m->l4 != 2) || (m->l5 != 0 && m->l5 != 1) || m->hidden < 1 ||
       m->hidden > 256 || !(m->rc_rad > 0.f) || !(m->rc_ang > 0.f) || m->rc_ang > m->rc_rad || m->cap_rad < 1 ||
       m->cap_ang < 1 || m->cap_rad > 4096 || m->cap_ang > 4096)
     return NEP_ERR_ARG;
@@ -2218,7 +2265,7 @@ size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
   int N, S, T, D, Y, H, NR, TKR, Npad, nwaves, nblk, PW, NA, capR, capA;
   size_t order, seg, blk, astruct, revR, revA, G, Sst, Ep, X, eatom, fR, fA, wv, F, fbar, Es, Ws, eps, wbar, lpart,
-      Gd, FRst, FPst, Gbr, beta, w1s, part, pp, w0part, crpart, cur_step, total;
+      Gd, FRst, FPst, Gbr, beta, w1s, part, pp, w0part, crpart, Sh, Sdh, cur_step, total;
 };
 
 Layout make_layout(const nep_model* m, const Ops* o, int S, int N) {
@@ -2272,13 +2319,15 @@ Layout make_layout(const nep_model* m, const Ops* o, int S, int N) {
   L.Gd = take(4 * (size_t)L.D * Np);
   L.FRst = take(4 * (size_t)L.TKR * Np);
   L.FPst = take(4 * (size_t)L.TKR * Np);
-  L.Gbr = take(4 * (size_t)L.NR * Np);
+  L.Gbr = take(4 * (size_t)(o->YH > 0 ? L.D : L.NR) * Np);
   L.beta = take(4 * (size_t)L.H * Np);
   L.w1s = take(4 * (size_t)L.H * Np);
   L.part = take(4 * (size_t)L.nwaves * L.PW);
   L.pp = take(8 * (size_t)L.T * kPRChunks * L.PW);
   L.w0part = take(4 * (size_t)L.T * kOSBlocks * L.H * L.D);
   L.crpart = take(4 * (size_t)L.T * kOSBlocks * L.NR * L.TKR);
+  L.Sh = take(4 * (size_t)Np * L.NA * o->YH);
+  L.Sdh = take(4 * (size_t)Np * L.NA * o->YH);
   L.cur_step = take(4);
   L.total = off;
   return L;
@@ -2441,6 +2490,50 @@ FwdArgs fwd_args(const Ctx& c, const nep_neighbors* nb, const float* params) {
 }
 
 // forward + force gather + per-structure sums (+ loss when labels given)
+// arguments of the kernels of degrees l > 4 (fbar/wbar only for the adjoint's)
+HighArgs high_args(const Ctx& c, const nep_neighbors* nb, const float* params, const float* fbar = nullptr,
+                   const float* wbar = nullptr) {
+  HighArgs h;
+  const nep_model* m = c.m;
+  h.N = c.L.N;
+  h.Npad = c.L.Npad;
+  h.PW = c.L.PW;
+  h.inv_rcA = 1.0f / m->rc_ang;
+  h.order = at<int>(c.ws, c.L.order);
+  h.astruct = at<int>(c.ws, c.L.astruct);
+  h.box = c.b->box;
+  h.tilt = c.b->tilt;
+  h.pos = c.b->pos;
+  h.type = c.b->type;
+  h.nb = pair_lists(c, nb);
+  h.cA = params + (size_t)m->n_types * m->n_types * m->n_rad * m->k_rad;
+  h.Sh = at<float>(c.ws, c.L.Sh);
+  h.Sdh = at<float>(c.ws, c.L.Sdh);
+  h.G = at<float>(c.ws, c.L.G);
+  h.Ep = at<float>(c.ws, c.L.Ep);
+  h.Gd = at<float>(c.ws, c.L.Gd);
+  h.Gb = at<float>(c.ws, c.L.Gbr);
+  h.fA = at<float>(c.ws, c.L.fA);
+  h.wv = at<float>(c.ws, c.L.wv);
+  h.fbar = fbar;
+  h.wbar = wbar;
+  h.part = at<float>(c.ws, c.L.part);
+  return h;
+}
+
+void run_high(const Ctx& c, HighKernel k, const HighArgs& h, Prof* pr) {
+  static const char* const names[] = {"high_desc", "high_force", "high_tangent", "high_coef"};
+  if (c.o->high) NEP_LAUNCH(pr, names[k], c.o->high(k, h, dim3(c.L.Npad / kAPB), c.st));
+}
+
+// forward pass with the degrees l > 4 around it
+void launch_forward_pass(const Ctx& c, const nep_neighbors* nb, const float* params, const FwdArgs& a, Prof* pr) {
+  const HighArgs h = high_args(c, nb, params);
+  run_high(c, kHighDesc, h, pr);
+  NEP_LAUNCH(pr, "forward", c.o->forward(a, dim3(c.L.Npad / kAPB), c.st));
+  if (a.do_mlp && a.do_force) run_high(c, kHighForce, h, pr);
+}
+
 void run_forward(const Ctx& c, const nep_neighbors* nb, const float* params, float* e_atom, float* e_struct,
                  float* force, float* virial, const nep_labels* lab, const float* lam, float* loss, int32_t* flags,
                  Prof* pr, bool defer_loss = false) {
@@ -2448,7 +2541,7 @@ void run_forward(const Ctx& c, const nep_neighbors* nb, const float* params, flo
   if (N > 0) {
     FwdArgs a = fwd_args(c, nb, params);
     a.eatom2 = e_atom;
-    NEP_LAUNCH(pr, "forward", c.o->forward(a, dim3(c.L.Npad / kAPB), c.st));
+    launch_forward_pass(c, nb, params, a, pr);
     NEP_LAUNCH(pr, "force_gather",
                hipLaunchKernelGGL(k_force_gather, dim3(grid1(N, 32)), dim3(256), 0, c.st, N, a.nb, a.fR, a.fA,
                                   at<float>(c.ws, c.L.F), force));
@@ -2523,7 +2616,10 @@ void run_adjoint(const Ctx& c, const nep_neighbors* nb, const float* params, con
     a.w1s = at<float>(c.ws, c.L.w1s);
     a.part = at<float>(c.ws, c.L.part);
     a.PW = c.L.PW;
+    const HighArgs h = high_args(c, nb, params, fbar, wbar);
+    run_high(c, kHighTangent, h, pr);
     NEP_LAUNCH(pr, "adjoint", c.o->adjoint(a, dim3(c.L.Npad / kAPB), c.st));
+    run_high(c, kHighCoef, h, pr);
     const int* seg = at<int>(c.ws, c.L.seg);
     {
       OuterArgs o{c.L.Npad, m->hidden, c.o->D, kOSBlocks, seg, a.beta, at<float>(c.ws, c.L.G), a.w1s, a.Gd,
@@ -2661,7 +2757,7 @@ int nep_descriptors(const nep_model* m, const nep_batch* b, const nep_neighbors*
   a.Guser = G;
   a.do_mlp = 0;
   a.do_force = 0;
-  c.o->forward(a, dim3(c.L.Npad / kAPB), c.st);
+  launch_forward_pass(c, nb, params, a, nullptr);
   return hip_ok();
 }
 
@@ -2723,7 +2819,7 @@ int nep_vjp(const nep_model* m, const nep_batch* b, const nep_neighbors* nb, con
   if (b->n_atom > 0) {
     FwdArgs a = fwd_args(c, nb, params);
     a.do_force = 0;
-    c.o->forward(a, dim3(c.L.Npad / kAPB), c.st);
+    launch_forward_pass(c, nb, params, a, nullptr);
   }
   run_adjoint(c, nb, params, e_bar, f_bar, v_bar, grad, nullptr);
   return hip_ok();

@@ -56,6 +56,7 @@ SIZES_SMALL = NEPSizes()  # 3-body only, hidden 30
 SIZES_LARGE = NEPSizes(n_rad=7, n_ang=5, k_rad=11, k_ang=11, l3=4, l4=2, l5=1, hidden=50)
 SIZES_TINY = NEPSizes(n_rad=3, n_ang=2, k_rad=4, k_ang=3, l3=4, l4=2, l5=1, hidden=6)
 SIZES_MONO = NEPSizes(n_types=1, n_rad=4, n_ang=3, k_rad=6, k_ang=5, l3=2, l4=2, l5=0, hidden=8)
+SIZES_L8 = NEPSizes(n_rad=5, n_ang=4, k_rad=8, k_ang=8, l3=8, l4=2, l5=1, hidden=16)   # 3-body l up to 8
 
 
 @dataclass

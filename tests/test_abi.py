@@ -30,7 +30,7 @@ def test_every_declared_symbol_is_exported_and_bound():
 
 
 def test_counts_match_the_oracle_layout():
-    for sz in (synth.SIZES_SMALL, synth.SIZES_LARGE, synth.SIZES_TINY, synth.SIZES_MONO):
+    for sz in (synth.SIZES_SMALL, synth.SIZES_LARGE, synth.SIZES_TINY, synth.SIZES_MONO, synth.SIZES_L8):
         m = nep.Model.of(sz)
         assert nep.param_count(m) == sz.n_params
         assert nep.descriptor_count(m) == sz.n_desc
@@ -48,6 +48,9 @@ def test_unsupported_and_invalid_models():
     bad = nep.Model.of(synth.SIZES_SMALL)
     bad.rc_ang = 7.0   # rc_ang > rc_rad
     assert _lib.load().nep_param_count(C.byref(bad.c())) == -1
+    deg = nep.Model.of(synth.SIZES_L8)
+    deg.l3 = 9         # 3-body degrees end at l = 8 (Appendix B)
+    assert _lib.load().nep_param_count(C.byref(deg.c())) == -1
 
 
 def test_workspace_grows_with_batch():
