@@ -42,8 +42,9 @@ def flop_model(sz, mR: float, mA: float) -> dict:
     arithmetic the mathematics needs once; recomputation inside a kernel is
     not counted."""
     T, NR, NA, KR, KA, H, D = sz.n_types, sz.n_rad, sz.n_ang, sz.k_rad, sz.k_ang, sz.hidden, sz.n_desc
-    lmax = max(sz.l3, sz.l4, sz.l5)
+    lmax = max(min(sz.l3, 4), sz.l4, sz.l5)   # harmonics of the per-atom kernels
     Y = lmax * (lmax + 2)
+    YH = (sz.l3 + 1) ** 2 - 25 if sz.l3 > 4 else 0   # l = 5..l3, in kernels of their own
     geo = 13                       # d = x_j + sL - x_i, r^2, sqrt, 1/r
     tan = 20                       # t = Fbar_j - Fbar_i + Gamma d, r_hat . t
     basis = lambda K: 10 + 6 * K        # xi, cutoff, T_k recursion, f_k
@@ -71,7 +72,17 @@ def flop_model(sz, mR: float, mA: float) -> dict:
            + NA * (8 * Y + 4 * q4 + 2 * q5)                              # Sbar, A
            + mA * (6 * NA * Y + 4 * NA * KA))                            # X_n, Y_n, angular coefficient gradient
     w0 = 4 * H * D
-    return {"forward": fwd, "adjoint": adj, "w0_grad": w0}
+    out = {"forward": fwd, "adjoint": adj, "w0_grad": w0}
+    if YH:
+        hv, hg = 2 * YH, 3 * YH    # harmonic values and gradients of l = 5..l3
+        out["high_desc"] = mA * (geo + basis(KA) + 2 * NA * KA + hv + 2 * NA * YH) + 2 * NA * YH
+        out["high_force"] = (2 * NA * YH + mA * (geo + basis_d(KA) + 4 * NA * KA + hv + hg
+                                                 + 4 * NA * YH + 6 * YH + 27))
+        out["high_tangent"] = mA * (geo + tan + basis_d(KA) + 4 * NA * KA + hv + hg + 6 * YH
+                                    + 4 * NA * YH) + 3 * NA * YH
+        out["high_coef"] = 5 * NA * YH + mA * (geo + tan + basis_d(KA) + hv + hg + 6 * YH + 6 * NA * YH
+                                               + 4 * NA * KA)
+    return out
 
 
 def kernel_source_hash() -> str:
@@ -118,6 +129,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--workload", default="c2")
+    ap.add_argument("--sizes", default=None, choices=[None, "large", "small", "l8"],
+                    help="model sizes in place of the workload's own (l8: 3-body degrees up to 8)")
     ap.add_argument("--mode", default="full", choices=["full", "batched", "copy-probe"],
                     help="full: the JSON line; batched: graph replays only (for profilers); "
                          "copy-probe: a plain 512 MiB device copy, the HBM-counter calibration")
@@ -144,7 +157,8 @@ def main():
         return
 
     t0 = time.time()
-    sizes = synth.CONFIG_SIZES[args.workload]
+    sizes = (synth.CONFIG_SIZES[args.workload] if args.sizes is None else
+             {"large": synth.SIZES_LARGE, "small": synth.SIZES_SMALL, "l8": synth.SIZES_L8}[args.sizes])
     structures = synth.config_structures(args.workload)
     batch = synth.Batch(structures)
     S, N = batch.n_struct, batch.n_atom
@@ -330,8 +344,8 @@ def main():
     units = N
     flops = fm.get(dom, 0.0) * units
     achieved = flops / (kern_ms[dom] * 1e-3)
-    traffic = measured_traffic(dom, args.workload)
-    counters = measured_counters(dom, args.workload)
+    traffic = measured_traffic(dom, args.workload) if args.sizes is None else None
+    counters = measured_counters(dom, args.workload) if args.sizes is None else None
     log("kernels (ms): " + ", ".join(f"{k} {v:.4f}" for k, v in sorted(kern_ms.items(), key=lambda x: -x[1])))
 
     # ---------------- CPU baseline: the FP64 oracle on a bounded sample

@@ -8,11 +8,12 @@
 //   k_high_tangent (before the adjoint)  Sdot_nlm and Gdot of these q_nl
 //   k_high_coef    (after the adjoint)   their share of dL/dc^A
 //
-// One wavefront takes the 8 atoms of an atom group (the same species-ordered
-// positions as the main kernels), one atom after the other; lane c holds
-// harmonic (l, m) number c of l = 5..L3 (at most 56), for every channel n.
-// Pair data (direction, g_n, g'_n, tangent) is staged once per pair in LDS by
-// the lane of that pair and read back by every lane.
+// One wavefront takes the 8 atoms of an atom group (the species-ordered
+// positions of one wavefront of the main kernels).  Their angular pairs form
+// one stream; chunks of 64 pairs are staged in LDS, one lane per pair
+// (direction, g_n, g'_n, tangent, the powers (x + iy)^k), and then every lane
+// walks the chunk.  Lane c holds harmonic (l, m) number c of l = 5..L3 (at
+// most 56) for every channel n.
 //
 // Harmonic basis.  q_nl = sum_m C_lm S_nlm^2 with C_lm = 1 / integral of b_lm^2
 // equals sum_m S~_nlm^2 for the sums S~ of any orthonormal real harmonics of
@@ -20,110 +21,203 @@
 // theorem).  So these kernels use the orthonormal real harmonics
 //   Y_lm = N_lM Q_l^M(z) Re (x + i y)^M   (m = 2M - 1, or m = 0 with M = 0)
 //   Y_lm = N_lM Q_l^M(z) Im (x + i y)^M   (m = 2M)
-// with Q_l^M the associated Legendre function over (1 - z^2)^(M/2), from the
-// three-term recurrence in l, and N_lM^2 = (2l+1)/(4 pi) (l-M)!/(l+M)! (times
-// 2 for M > 0).  With C = 1 in this basis, dq/dS~ = 2 S~.
+// with Q_l^M the associated Legendre function over (1 - z^2)^(M/2) (a
+// polynomial in z from the three-term recurrence in l) and N_lM^2 =
+// (2l+1)/(4 pi) (l-M)!/(l+M)! (times 2 for M > 0).  With C = 1 in this basis,
+// dq/dS~ = 2 S~.  Each lane keeps N Q_l^M as z^par H(z^2), H of degree <= 4, and
+// evaluates it by Horner's rule.
 #pragma once
 #include "nep_device.h"
 #include "nep_kernels.h"
 
 namespace nep {
 
+constexpr int kPwStride = 19;   // words per pair in the power table (odd: no bank conflicts)
+
 struct HighLane {
-  int l, M;
-  bool sine;
-  float N;   // 0 for lanes past the last harmonic
+  int l;
+  bool on;
+  bool par;                  // Q has odd degree
+  float a[5], b[4];          // H(w) = sum a_k w^k, H'(w) = sum b_k w^k
+  int iP, iD1, iD2;          // power-table words of P, and of the two derivative factors
+  float sD1, sD2;            // dP/dx = sD1 pw[iD1], dP/dy = sD2 pw[iD2]
 };
 
 __device__ __forceinline__ HighLane high_lane(int c, int L3) {
-  HighLane h{5, 0, false, 0.f};
-  int off = 0;
-  bool on = false;
+  HighLane h;
+  h.l = 5;
+  h.on = false;
+  int M = 0, off = 0;
+  bool sine = false;
   for (int l = 5; l <= L3; ++l) {
     const int w = 2 * l + 1;
     if (c >= off && c < off + w) {
       const int mi = c - off;
       h.l = l;
-      h.M = (mi + 1) >> 1;
-      h.sine = mi > 0 && (mi & 1) == 0;
-      on = true;
+      M = (mi + 1) >> 1;
+      sine = mi > 0 && (mi & 1) == 0;
+      h.on = true;
     }
     off += w;
   }
-  double r = (2.0 * h.l + 1.0) / (4.0 * 3.141592653589793);
-  for (int k = h.l - h.M + 1; k <= h.l + h.M; ++k) r /= (double)k;
-  if (h.M > 0) r *= 2.0;
-  h.N = on ? (float)sqrt(r) : 0.f;
+  // coefficients of Q_l^M in powers of z, by the recurrence
+  //   Q_M^M = (2M-1)!!,  (l-M) Q_l = (2l-1) z Q_{l-1} - (l+M-1) Q_{l-2}
+  double q0[9], q1[9];
+#pragma unroll
+  for (int p = 0; p < 9; ++p) q0[p] = q1[p] = 0.0;
+  double df = 1.0;
+  for (int k = 1; k <= M; ++k) df *= (double)(2 * k - 1);
+  q1[0] = df;
+  for (int lp = M + 1; lp <= h.l; ++lp) {
+    double qn[9];
+#pragma unroll
+    for (int p = 0; p < 9; ++p)
+      qn[p] = ((2.0 * lp - 1.0) * (p > 0 ? q1[p - 1] : 0.0) - (lp + M - 1.0) * q0[p]) / (double)(lp - M);
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+      q0[p] = q1[p];
+      q1[p] = qn[p];
+    }
+  }
+  double nrm = (2.0 * h.l + 1.0) / (4.0 * 3.141592653589793);
+  for (int k = h.l - M + 1; k <= h.l + M; ++k) nrm /= (double)k;
+  if (M > 0) nrm *= 2.0;
+  nrm = h.on ? sqrt(nrm) : 0.0;
+  h.par = ((h.l - M) & 1) != 0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    double v = 0.0;
+#pragma unroll
+    for (int p = 0; p < 9; ++p) v = (p == 2 * k + (h.par ? 1 : 0)) ? q1[p] : v;
+    h.a[k] = (float)(nrm * v);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) h.b[k] = (float)(k + 1) * h.a[k + 1];
+  // d/dx (x+iy)^M = M (x+iy)^(M-1), d/dy (x+iy)^M = i M (x+iy)^(M-1)
+  const int m1 = M > 0 ? M - 1 : 0;
+  h.iP = (sine ? 9 : 0) + M;
+  h.iD1 = (sine ? 9 : 0) + m1;
+  h.iD2 = (sine ? 0 : 9) + m1;
+  h.sD1 = (float)M;
+  h.sD2 = sine ? (float)M : -(float)M;
   return h;
 }
 
-// Y_lm(u) and the gradient of its polynomial extension at u (on the unit
-// sphere its tangential part is the surface gradient).
-__device__ __forceinline__ void high_harm(const HighLane& h, float x, float y, float z, float& v, float& gx, float& gy,
+// Y(u) and the gradient of its polynomial extension at u (its tangential part
+// is the surface gradient); pw: the pair's powers (x + iy)^k, k = 0..8, real
+// parts then imaginary parts
+__device__ __forceinline__ void high_eval(const HighLane& h, float z, const float* pw, float& v, float& gx, float& gy,
                                           float& gz) {
-  float c = 1.f, s = 0.f, c1 = 0.f, s1 = 0.f;   // (x + iy)^M and (x + iy)^(M-1)
-  for (int k = 0; k < h.M; ++k) {
-    c1 = c;
-    s1 = s;
-    const float cn = c * x - s * y;
-    s = s * x + c * y;
-    c = cn;
-  }
-  float q1 = 1.f;   // Q_M^M = (2M - 1)!!
-  for (int k = 1; k <= h.M; ++k) q1 *= (float)(2 * k - 1);
-  float q0 = 0.f, d0 = 0.f, d1 = 0.f;
-  for (int lp = h.M + 1; lp <= h.l; ++lp) {
-    const float a = (float)(2 * lp - 1), b = (float)(lp + h.M - 1), inv = 1.0f / (float)(lp - h.M);
-    const float qn = (a * z * q1 - b * q0) * inv;
-    const float dn = (a * fmaf(z, d1, q1) - b * d0) * inv;
-    q0 = q1;
-    d0 = d1;
-    q1 = qn;
-    d1 = dn;
-  }
-  const float Mf = (float)h.M;
-  const float P = h.sine ? s : c;
-  const float Px = Mf * (h.sine ? s1 : c1);
-  const float Py = Mf * (h.sine ? c1 : -s1);
-  const float nq = h.N * q1;
-  v = nq * P;
-  gx = nq * Px;
-  gy = nq * Py;
-  gz = h.N * d1 * P;
+  const float w = z * z;
+  float H = fmaf(h.a[4], w, h.a[3]);
+  H = fmaf(H, w, h.a[2]);
+  H = fmaf(H, w, h.a[1]);
+  H = fmaf(H, w, h.a[0]);
+  float Hp = fmaf(h.b[3], w, h.b[2]);
+  Hp = fmaf(Hp, w, h.b[1]);
+  Hp = fmaf(Hp, w, h.b[0]);
+  const float zp = h.par ? z : 1.0f;
+  const float Q = zp * H;
+  const float dQ = fmaf(2.0f * z * zp, Hp, h.par ? H : 0.0f);
+  const float P = pw[h.iP];
+  v = Q * P;
+  gx = Q * h.sD1 * pw[h.iD1];
+  gy = Q * h.sD2 * pw[h.iD2];
+  gz = dQ * P;
 }
 
 // sum over the 64 lanes (every lane must be active)
 __device__ __forceinline__ float wave_total(float v) { return atoms8_sum(grp8_sum(v)); }
 
-// Per-wave LDS record of up to 64 pairs, field-major: rec[f * 64 + slot].
-template <int NA, int KA>
-struct HighRec {
-  static constexpr int DX = 0, DY = 1, DZ = 2, IR = 3, DT = 4, WX = 5, WY = 6, WZ = 7, J = 8, K = 9;
-  static constexpr int G = 10, GP = G + NA, F = GP + NA, FP = F + KA, W = FP + KA;
-};
-
-template <class C, bool kTri>
-struct HighAtom {
-  int pa, i, I, st, nA;
-  float xi, yi, zi;
-  Cell cell;
-};
-
-// Stages pairs [k0, k0 + 64) of atom A: lane k0 + lane writes its pair.
-template <class C, bool kTri, bool kTangent>
-__device__ __forceinline__ void high_stage(const HighArgs& a, const HighAtom<C, kTri>& at, int k0, float* rec,
-                                           float fbx, float fby, float fbz, const float (&gw)[6]) {
-  constexpr int T = C::T, NA = C::NA, KA = C::KA;
-  using R = HighRec<NA, KA>;
+// Sums of V = 4 or 8 values over the 64 lanes, scattered: on return the lanes
+// with (lane & (V - 1)) == v hold the total of value v.  A butterfly over
+// lane bits 0, 1 (and 2) halves the values a lane carries at each step, so the
+// V sums take V - 1 lane exchanges before the sum over the 8 groups instead
+// of 3 V.
+template <int V>
+__device__ __forceinline__ float wave_scatter_sum(const float (&x)[V]) {
+  static_assert(V == 4 || V == 8, "4 or 8 values");
   const int lane = threadIdx.x & (kWave - 1);
-  const int k = k0 + lane;
-  if (k < at.nA) {
-    const PairGeom q = pair_geom<kTri>(a.nb.idxA[(size_t)at.i * a.nb.capA + k], a.pos, a.N, at.xi, at.yi, at.zi,
-                                       at.cell);
+  const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
+  float y[V / 2];
+#pragma unroll
+  for (int w = 0; w < V / 2; ++w) {   // y[w]: value 2w + b0
+    const float send = b0 ? x[2 * w] : x[2 * w + 1];
+    y[w] = (b0 ? x[2 * w + 1] : x[2 * w]) + dpp<kDppXor1>(send);
+  }
+  float z[V / 4];
+#pragma unroll
+  for (int u = 0; u < V / 4; ++u) {   // z[u]: value 4u + 2 b1 + b0
+    const float send = b1 ? y[2 * u] : y[2 * u + 1];
+    z[u] = (b1 ? y[2 * u + 1] : y[2 * u]) + dpp<kDppXor2>(send);
+  }
+  float r;
+  if constexpr (V == 8) {             // value lane & 7 over the 8-lane group
+    const float send = b2 ? z[0] : z[1];
+    r = (b2 ? z[1] : z[0]) + xor4_val(send);
+  } else {                            // value lane & 3 over the quad, then the group
+    r = z[0] + xor4_val(z[0]);
+  }
+  return atoms8_sum(r);
+}
+
+// Per-wave LDS record of up to 64 pairs, field-major: rec[f * 64 + slot].
+// kTan: tangent fields; kF: the radial basis f_k, f'_k.
+template <int NA, int KA, bool kTan, bool kF>
+struct HighRec {
+  static constexpr int DX = 0, DY = 1, DZ = 2, IR = 3, U = 4, AI = 5, KI = 6, J = 7, G = 8, GP = G + NA;
+  static constexpr int DT = GP + NA, WX = DT + 1, WY = DT + 2, WZ = DT + 3;
+  static constexpr int F = kTan ? WZ + 1 : DT;
+  static constexpr int FP = F + (kF ? KA : 0);
+  static constexpr int W = FP + (kF ? KA : 0);
+};
+
+// The 8 atom slots of a wavefront and their pair counts.
+struct HighGroup {
+  int pa0, total;
+  int cum[kAPW + 1];   // pairs before slot u
+};
+
+__device__ __forceinline__ HighGroup high_group(const HighArgs& a, int pa0) {
+  HighGroup g;
+  g.pa0 = pa0;
+  g.cum[0] = 0;
+#pragma unroll
+  for (int u = 0; u < kAPW; ++u) {
+    const int i = a.order[pa0 + u];
+    const int n = i >= 0 ? min(a.nb.cntA[i], a.nb.capA) : 0;
+    g.cum[u + 1] = g.cum[u] + n;
+  }
+  g.total = g.cum[kAPW];
+  return g;
+}
+
+// Stages pairs [c0, c0 + 64) of the group's stream, one per lane.
+template <class C, bool kTri, bool kTan, bool kF>
+__device__ __forceinline__ void high_stage(const HighArgs& a, const HighGroup& gr, int c0, float* rec, float* pw) {
+  constexpr int T = C::T, NA = C::NA, KA = C::KA;
+  using R = HighRec<NA, KA, kTan, kF>;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int gidx = c0 + lane;
+  if (gidx < gr.total) {
+    int u = 0, base = 0;
+#pragma unroll
+    for (int v = 1; v < kAPW; ++v) {
+      const bool past = gidx >= gr.cum[v];
+      u = past ? v : u;
+      base = past ? gr.cum[v] : base;
+    }
+    const int k = gidx - base;
+    const int i = a.order[gr.pa0 + u];
+    const int I = a.type[i], st = a.astruct[i];
+    const Cell cell = load_cell<kTri>(a.box, a.tilt, st);
+    const size_t off = (size_t)i * a.nb.capA + k;
+    const PairGeom q = pair_geom<kTri>(a.nb.idxA[off], a.pos, a.N, a.pos[i], a.pos[a.N + i], a.pos[2 * a.N + i],
+                                       cell);
     float f[KA], fp[KA];
     radial_basis_d<KA>(q.r, a.inv_rcA, f, fp);
     const int J = a.type[q.j];
-    const float* cJ = a.cA + (size_t)(at.I * T + J) * NA * KA;
+    const float* cJ = a.cA + (size_t)(I * T + J) * NA * KA;
 #pragma unroll
     for (int n = 0; n < NA; ++n) {
       float s0 = 0.f, s1 = 0.f;
@@ -135,23 +229,38 @@ __device__ __forceinline__ void high_stage(const HighArgs& a, const HighAtom<C, 
       rec[(R::G + n) * kWave + lane] = s0;
       rec[(R::GP + n) * kWave + lane] = s1;
     }
+    if constexpr (kF) {
 #pragma unroll
-    for (int kk = 0; kk < KA; ++kk) {
-      rec[(R::F + kk) * kWave + lane] = f[kk];
-      rec[(R::FP + kk) * kWave + lane] = fp[kk];
+      for (int kk = 0; kk < KA; ++kk) {
+        rec[(R::F + kk) * kWave + lane] = f[kk];
+        rec[(R::FP + kk) * kWave + lane] = fp[kk];
+      }
     }
+    const float ux = q.dx * q.inv_r, uy = q.dy * q.inv_r, uz = q.dz * q.inv_r;
     rec[R::DX * kWave + lane] = q.dx;
     rec[R::DY * kWave + lane] = q.dy;
     rec[R::DZ * kWave + lane] = q.dz;
     rec[R::IR * kWave + lane] = q.inv_r;
-    rec[R::J * kWave + lane] = (float)J;
-    rec[R::K * kWave + lane] = (float)k;
-    if constexpr (kTangent) {
+    rec[R::U * kWave + lane] = __int_as_float(u);
+    rec[R::AI * kWave + lane] = __int_as_float(i);
+    rec[R::KI * kWave + lane] = __int_as_float(k);
+    rec[R::J * kWave + lane] = __int_as_float(J);
+    float c = 1.f, s = 0.f;
+    float* p = pw + lane * kPwStride;
+#pragma unroll
+    for (int m = 0; m < 9; ++m) {
+      p[m] = c;
+      p[9 + m] = s;
+      const float cn = c * ux - s * uy;
+      s = fmaf(s, ux, c * uy);
+      c = cn;
+    }
+    if constexpr (kTan) {
       // t = (fbar_j - fbar_i) + Wbar d, as in the main adjoint
-      const float tx = (a.fbar[q.j] - fbx) + gw[0] * q.dx + gw[3] * q.dy;
-      const float ty = (a.fbar[a.N + q.j] - fby) + gw[1] * q.dy + gw[4] * q.dz;
-      const float tz = (a.fbar[2 * a.N + q.j] - fbz) + gw[2] * q.dz + gw[5] * q.dx;
-      const float ux = q.dx * q.inv_r, uy = q.dy * q.inv_r, uz = q.dz * q.inv_r;
+      const float* wb = a.wbar + 6 * st;
+      const float tx = (a.fbar[q.j] - a.fbar[i]) + wb[0] * q.dx + wb[3] * q.dy;
+      const float ty = (a.fbar[a.N + q.j] - a.fbar[a.N + i]) + wb[1] * q.dy + wb[4] * q.dz;
+      const float tz = (a.fbar[2 * a.N + q.j] - a.fbar[2 * a.N + i]) + wb[2] * q.dz + wb[5] * q.dx;
       const float dt = ux * tx + uy * ty + uz * tz;
       rec[R::DT * kWave + lane] = dt;
       rec[R::WX * kWave + lane] = (tx - dt * ux) * q.inv_r;
@@ -162,20 +271,39 @@ __device__ __forceinline__ void high_stage(const HighArgs& a, const HighAtom<C, 
   lds_lane_exchange();
 }
 
-template <class C, bool kTri>
-__device__ __forceinline__ bool high_atom(const HighArgs& a, int pa, HighAtom<C, kTri>& at) {
-  const int iraw = a.order[pa];
-  if (iraw < 0) return false;
-  at.pa = pa;
-  at.i = iraw;
-  at.I = a.type[iraw];
-  at.st = a.astruct[iraw];
-  at.cell = load_cell<kTri>(a.box, a.tilt, at.st);
-  at.xi = a.pos[iraw];
-  at.yi = a.pos[a.N + iraw];
-  at.zi = a.pos[2 * a.N + iraw];
-  at.nA = min(a.nb.cntA[iraw], a.nb.capA);
-  return true;
+// Walks the group's pair stream: start(u) before the first pair of slot u,
+// pair(u, jj) for each staged pair jj of slot u, finish(u) after its last pair
+// (also for slots without pairs), flush(c0) after each chunk of 64 pairs.
+struct NoFlush {
+  __device__ void operator()(int) const {}
+};
+
+template <class C, bool kTri, bool kTan, bool kF, class Start, class Pair, class Finish, class Flush = NoFlush>
+__device__ __forceinline__ void high_walk(const HighArgs& a, const HighGroup& gr, float* rec, float* pw,
+                                          Start&& start, Pair&& pair, Finish&& finish, Flush&& flush = Flush{}) {
+  using R = HighRec<C::NA, C::KA, kTan, kF>;
+  int cur = 0;
+  start(0);
+  for (int c0 = 0; c0 < gr.total; c0 += kWave) {
+    high_stage<C, kTri, kTan, kF>(a, gr, c0, rec, pw);
+    const int np = min(kWave, gr.total - c0);
+    for (int jj = 0; jj < np; ++jj) {
+      const int u = __float_as_int(rec[R::U * kWave + jj]);
+      while (cur < u) {
+        finish(cur);
+        ++cur;
+        start(cur);
+      }
+      pair(cur, jj);
+    }
+    flush(c0);
+    lds_lane_exchange();
+  }
+  for (;;) {
+    finish(cur);
+    if (++cur == kAPW) break;
+    start(cur);
+  }
 }
 
 // descriptor row of q_nl
@@ -184,223 +312,236 @@ __device__ __forceinline__ int high_row(int l, int n) {
   return C::NR + (l - 1) * C::NA + n;
 }
 
-template <class C, bool kTri>
-__global__ __launch_bounds__(256) void k_high_desc(HighArgs a) {
-  constexpr int NA = C::NA, KA = C::KA, L3 = C::L3, YH = C::YH;
-  using R = HighRec<NA, KA>;
-  __shared__ float recs[4][R::W * kWave];
-  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-  float* rec = recs[wv];
-  const HighLane h = high_lane(lane, L3);
-  const float gw[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  for (int u = 0; u < kAPW; ++u) {
-    HighAtom<C, kTri> at;
-    if (!high_atom<C, kTri>(a, (blockIdx.x * 4 + wv) * kAPW + u, at)) continue;
-    float S[NA];
+// a descriptor-row value of this lane's degree, channel n
+template <class C>
+__device__ __forceinline__ float high_rowval(const float* __restrict__ rows, int Npad, int pa, const HighLane& h,
+                                            int n) {
+  const float v = rows[(size_t)high_row<C>(h.l, n) * Npad + pa];
+  return h.on ? v : 0.f;
+}
+
+// Stores the wave totals of the per-lane values vals[(l - 5) NA + n] to the
+// descriptor rows of (l, n), l = 5..L3 (row NR + (l - 1) NA + n), eight
+// values per scattered sum.
+template <class C>
+__device__ __forceinline__ void high_rows_store(const float (&vals)[(C::L3 - 4) * C::NA], float* rows, int Npad,
+                                                int pa) {
+  constexpr int NV = (C::L3 - 4) * C::NA;
+  const int lane = threadIdx.x & (kWave - 1);
 #pragma unroll
-    for (int n = 0; n < NA; ++n) S[n] = 0.f;
-    for (int k0 = 0; k0 < at.nA; k0 += kWave) {
-      high_stage<C, kTri, false>(a, at, k0, rec, 0.f, 0.f, 0.f, gw);
-      const int np = min(kWave, at.nA - k0);
-      for (int jj = 0; jj < np; ++jj) {
-        const float ir = rec[R::IR * kWave + jj];
-        float v, gx, gy, gz;
-        high_harm(h, rec[R::DX * kWave + jj] * ir, rec[R::DY * kWave + jj] * ir, rec[R::DZ * kWave + jj] * ir, v, gx,
-                  gy, gz);
+  for (int g0 = 0; g0 < NV; g0 += 8) {
+    float xs[8];
 #pragma unroll
-        for (int n = 0; n < NA; ++n) S[n] = fmaf(rec[(R::G + n) * kWave + jj], v, S[n]);
-      }
-      lds_lane_exchange();
-    }
-    if (lane < YH)
-#pragma unroll
-      for (int n = 0; n < NA; ++n) a.Sh[((size_t)at.pa * NA + n) * YH + lane] = S[n];
-#pragma unroll
-    for (int l = 5; l <= L3; ++l)
-#pragma unroll
-      for (int n = 0; n < NA; ++n) {
-        const float q = wave_total(h.l == l ? S[n] * S[n] : 0.f);
-        if (lane == 0) a.G[(size_t)high_row<C>(l, n) * a.Npad + at.pa] = q;
-      }
+    for (int v = 0; v < 8; ++v) xs[v] = g0 + v < NV ? vals[g0 + v < NV ? g0 + v : 0] : 0.f;
+    const float t = wave_scatter_sum<8>(xs);
+    if (lane < 8 && g0 + lane < NV) rows[(size_t)(C::NR + 4 * C::NA + g0 + lane) * Npad + pa] = t;
   }
 }
 
-// E' of this lane's q_nl, channel n
 template <class C>
-__device__ __forceinline__ float high_ep(const float* __restrict__ rows, int Npad, int pa, const HighLane& h, int n) {
-  const float v = rows[(size_t)high_row<C>(h.l, n) * Npad + pa];
-  return h.N != 0.f ? v : 0.f;
+__device__ __forceinline__ size_t high_slot(int pa, int n, int lane) {
+  return ((size_t)pa * C::NA + n) * C::YH + (lane < C::YH ? lane : 0);
+}
+
+#define NEP_HIGH_PROLOGUE(TAN, F)                                        \
+  constexpr int NA = C::NA, KA = C::KA, L3 = C::L3, YH = C::YH;         \
+  using R = HighRec<NA, KA, TAN, F>;                                     \
+  __shared__ float recs[4][R::W * kWave];                                \
+  __shared__ float pws[4][kWave * kPwStride];                            \
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;  \
+  const int wave = blockIdx.x * 4 + wv;                                  \
+  float* rec = recs[wv];                                                 \
+  float* pw = pws[wv];                                                   \
+  const HighLane h = high_lane(lane, L3);                                \
+  const HighGroup gr = high_group(a, wave * kAPW);                       \
+  (void)KA;                                                              \
+  (void)YH;
+
+template <class C, bool kTri>
+__global__ __launch_bounds__(256) void k_high_desc(HighArgs a) {
+  NEP_HIGH_PROLOGUE(false, false)
+  float S[NA];
+  auto start = [&](int) {
+#pragma unroll
+    for (int n = 0; n < NA; ++n) S[n] = 0.f;
+  };
+  auto pair = [&](int, int jj) {
+    float v, gx, gy, gz;
+    high_eval(h, rec[R::DZ * kWave + jj] * rec[R::IR * kWave + jj], pw + jj * kPwStride, v, gx, gy, gz);
+#pragma unroll
+    for (int n = 0; n < NA; ++n) S[n] = fmaf(rec[(R::G + n) * kWave + jj], v, S[n]);
+  };
+  auto finish = [&](int u) {
+    const int pa = gr.pa0 + u;
+    if (a.order[pa] < 0) return;
+    if (lane < YH)
+#pragma unroll
+      for (int n = 0; n < NA; ++n) a.Sh[high_slot<C>(pa, n, lane)] = S[n];
+    float q[(L3 - 4) * NA];
+#pragma unroll
+    for (int l = 5; l <= L3; ++l)
+#pragma unroll
+      for (int n = 0; n < NA; ++n) q[(l - 5) * NA + n] = h.l == l ? S[n] * S[n] : 0.f;
+    high_rows_store<C>(q, a.G, a.Npad, pa);
+  };
+  high_walk<C, kTri, false, false>(a, gr, rec, pw, start, pair, finish);
 }
 
 template <class C, bool kTri>
 __global__ __launch_bounds__(256) void k_high_force(HighArgs a) {
-  constexpr int NA = C::NA, KA = C::KA, L3 = C::L3, YH = C::YH;
-  using R = HighRec<NA, KA>;
-  __shared__ float recs[4][R::W * kWave];
-  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-  float* rec = recs[wv];
-  const HighLane h = high_lane(lane, L3);
-  const float gw[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  for (int u = 0; u < kAPW; ++u) {
-    HighAtom<C, kTri> at;
-    if (!high_atom<C, kTri>(a, (blockIdx.x * 4 + wv) * kAPW + u, at)) continue;
+  NEP_HIGH_PROLOGUE(false, false)
+  float A[NA];
+  float vir[6];
+  float pfx = 0.f, pfy = 0.f, pfz = 0.f;   // this lane's staged pair
+  auto start = [&](int u) {
     // A = dE/dS~ = 2 E'_nl S~
-    float A[NA];
+    const int pa = gr.pa0 + u;
 #pragma unroll
     for (int n = 0; n < NA; ++n) {
-      const float s = a.Sh[((size_t)at.pa * NA + n) * YH + (lane < YH ? lane : 0)];
-      A[n] = 2.0f * high_ep<C>(a.Ep, a.Npad, at.pa, h, n) * (lane < YH ? s : 0.f);
+      const float s = a.Sh[high_slot<C>(pa, n, lane)];
+      A[n] = 2.0f * high_rowval<C>(a.Ep, a.Npad, pa, h, n) * (lane < YH ? s : 0.f);
     }
-    float vir[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < at.nA; k0 += kWave) {
-      high_stage<C, kTri, false>(a, at, k0, rec, 0.f, 0.f, 0.f, gw);
-      const int np = min(kWave, at.nA - k0);
-      for (int jj = 0; jj < np; ++jj) {
-        const float ir = rec[R::IR * kWave + jj];
-        const float dx = rec[R::DX * kWave + jj], dy = rec[R::DY * kWave + jj], dz = rec[R::DZ * kWave + jj];
-        const float ux = dx * ir, uy = dy * ir, uz = dz * ir;
-        float v, gx, gy, gz;
-        high_harm(h, ux, uy, uz, v, gx, gy, gz);
-        float su = 0.f, sv = 0.f;
 #pragma unroll
-        for (int n = 0; n < NA; ++n) {
-          su = fmaf(A[n], rec[(R::G + n) * kWave + jj], su);
-          sv = fmaf(A[n], rec[(R::GP + n) * kWave + jj], sv);
-        }
-        // f_ij = sum A (g'_n u Y + g_n grad Y), grad Y = (I - u u^T) grad p / r
-        const float vv = wave_total(sv * v);
-        const float Gx = wave_total(su * gx), Gy = wave_total(su * gy), Gz = wave_total(su * gz);
-        const float rad = ux * Gx + uy * Gy + uz * Gz;
-        const float fx = vv * ux + (Gx - rad * ux) * ir;
-        const float fy = vv * uy + (Gy - rad * uy) * ir;
-        const float fz = vv * uz + (Gz - rad * uz) * ir;
-        if (lane == 0) {
-          float* fo = a.fA + 3 * ((size_t)at.i * a.nb.capA + (int)rec[R::K * kWave + jj]);
-          fo[0] += fx;
-          fo[1] += fy;
-          fo[2] += fz;
-        }
-        vir[0] -= fx * dx; vir[1] -= fy * dy; vir[2] -= fz * dz;
-        vir[3] -= fx * dy; vir[4] -= fy * dz; vir[5] -= fz * dx;
-      }
-      lds_lane_exchange();
+    for (int c = 0; c < 6; ++c) vir[c] = 0.f;
+  };
+  auto pair = [&](int, int jj) {
+    const float ir = rec[R::IR * kWave + jj];
+    const float dx = rec[R::DX * kWave + jj], dy = rec[R::DY * kWave + jj], dz = rec[R::DZ * kWave + jj];
+    const float ux = dx * ir, uy = dy * ir, uz = dz * ir;
+    float v, gx, gy, gz;
+    high_eval(h, uz, pw + jj * kPwStride, v, gx, gy, gz);
+    float su = 0.f, sv = 0.f;
+#pragma unroll
+    for (int n = 0; n < NA; ++n) {
+      su = fmaf(A[n], rec[(R::G + n) * kWave + jj], su);
+      sv = fmaf(A[n], rec[(R::GP + n) * kWave + jj], sv);
     }
-    if (lane == 0)
+    // f_ij = sum A (g'_n u Y + g_n grad Y), grad Y = (I - u u^T) grad p / r
+    const float parts[4] = {sv * v, su * gx, su * gy, su * gz};
+    const float tot = wave_scatter_sum<4>(parts);
+    const float vv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tot), 0));
+    const float Gx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tot), 1));
+    const float Gy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tot), 2));
+    const float Gz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tot), 3));
+    const float rad = ux * Gx + uy * Gy + uz * Gz;
+    const float fx = vv * ux + (Gx - rad * ux) * ir;
+    const float fy = vv * uy + (Gy - rad * uy) * ir;
+    const float fz = vv * uz + (Gz - rad * uz) * ir;
+    // the lane that staged pair jj adds it to fA after the chunk
+    const bool mine = lane == jj;
+    pfx = mine ? fx : pfx;
+    pfy = mine ? fy : pfy;
+    pfz = mine ? fz : pfz;
+    vir[0] -= fx * dx; vir[1] -= fy * dy; vir[2] -= fz * dz;
+    vir[3] -= fx * dy; vir[4] -= fy * dz; vir[5] -= fz * dx;
+  };
+  auto finish = [&](int u) {
+    const int i = a.order[gr.pa0 + u];
+    if (i >= 0 && lane == 0)
 #pragma unroll
-      for (int c = 0; c < 6; ++c) a.wv[(size_t)c * a.N + at.i] += vir[c];
-  }
+      for (int c = 0; c < 6; ++c) a.wv[(size_t)c * a.N + i] += vir[c];
+  };
+  auto flush = [&](int c0) {
+    if (c0 + lane < gr.total) {
+      const size_t o = (size_t)__float_as_int(rec[R::AI * kWave + lane]) * a.nb.capA +
+                       __float_as_int(rec[R::KI * kWave + lane]);
+      float* fo = a.fA + 3 * o;
+      fo[0] += pfx;
+      fo[1] += pfy;
+      fo[2] += pfz;
+    }
+  };
+  high_walk<C, kTri, false, false>(a, gr, rec, pw, start, pair, finish, flush);
 }
 
 template <class C, bool kTri>
 __global__ __launch_bounds__(256) void k_high_tangent(HighArgs a) {
-  constexpr int NA = C::NA, KA = C::KA, L3 = C::L3, YH = C::YH;
-  using R = HighRec<NA, KA>;
-  __shared__ float recs[4][R::W * kWave];
-  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-  float* rec = recs[wv];
-  const HighLane h = high_lane(lane, L3);
-  for (int u = 0; u < kAPW; ++u) {
-    HighAtom<C, kTri> at;
-    if (!high_atom<C, kTri>(a, (blockIdx.x * 4 + wv) * kAPW + u, at)) continue;
-    const float* wb = a.wbar + 6 * at.st;
-    const float gw[6] = {wb[0], wb[1], wb[2], wb[3], wb[4], wb[5]};
-    const float fbx = a.fbar[at.i], fby = a.fbar[a.N + at.i], fbz = a.fbar[2 * a.N + at.i];
-    float Sd[NA];
+  NEP_HIGH_PROLOGUE(true, false)
+  float Sd[NA];
+  auto start = [&](int) {
 #pragma unroll
     for (int n = 0; n < NA; ++n) Sd[n] = 0.f;
-    for (int k0 = 0; k0 < at.nA; k0 += kWave) {
-      high_stage<C, kTri, true>(a, at, k0, rec, fbx, fby, fbz, gw);
-      const int np = min(kWave, at.nA - k0);
-      for (int jj = 0; jj < np; ++jj) {
-        const float ir = rec[R::IR * kWave + jj];
-        float v, gx, gy, gz;
-        high_harm(h, rec[R::DX * kWave + jj] * ir, rec[R::DY * kWave + jj] * ir, rec[R::DZ * kWave + jj] * ir, v, gx,
-                  gy, gz);
-        // Sdot = sum_j g'_n (u.t) Y + g_n grad p . (t - (u.t) u) / r
-        const float gwt = gx * rec[R::WX * kWave + jj] + gy * rec[R::WY * kWave + jj] + gz * rec[R::WZ * kWave + jj];
-        const float vdt = v * rec[R::DT * kWave + jj];
+  };
+  auto pair = [&](int, int jj) {
+    float v, gx, gy, gz;
+    high_eval(h, rec[R::DZ * kWave + jj] * rec[R::IR * kWave + jj], pw + jj * kPwStride, v, gx, gy, gz);
+    // Sdot = sum_j g'_n (u.t) Y + g_n grad p . (t - (u.t) u) / r
+    const float gwt = gx * rec[R::WX * kWave + jj] + gy * rec[R::WY * kWave + jj] + gz * rec[R::WZ * kWave + jj];
+    const float vdt = v * rec[R::DT * kWave + jj];
 #pragma unroll
-        for (int n = 0; n < NA; ++n)
-          Sd[n] = fmaf(rec[(R::GP + n) * kWave + jj], vdt, fmaf(rec[(R::G + n) * kWave + jj], gwt, Sd[n]));
-      }
-      lds_lane_exchange();
-    }
+    for (int n = 0; n < NA; ++n)
+      Sd[n] = fmaf(rec[(R::GP + n) * kWave + jj], vdt, fmaf(rec[(R::G + n) * kWave + jj], gwt, Sd[n]));
+  };
+  auto finish = [&](int u) {
+    const int pa = gr.pa0 + u;
+    if (a.order[pa] < 0) return;
     if (lane < YH)
 #pragma unroll
-      for (int n = 0; n < NA; ++n) a.Sdh[((size_t)at.pa * NA + n) * YH + lane] = Sd[n];
-#pragma unroll
-    for (int l = 5; l <= L3; ++l)
-#pragma unroll
-      for (int n = 0; n < NA; ++n) {
-        const float s = a.Sh[((size_t)at.pa * NA + n) * YH + (lane < YH ? lane : 0)];
-        const float q = wave_total(h.l == l ? 2.0f * s * Sd[n] : 0.f);
-        if (lane == 0) a.Gd[(size_t)high_row<C>(l, n) * a.Npad + at.pa] = q;
-      }
-  }
-}
-
-template <class C, bool kTri>
-__global__ __launch_bounds__(256) void k_high_coef(HighArgs a) {
-  constexpr int T = C::T, NA = C::NA, KA = C::KA, L3 = C::L3, YH = C::YH;
-  static_assert(NA * KA <= kWave, "one coefficient slot per lane");
-  using R = HighRec<NA, KA>;
-  __shared__ float recs[4][R::W * kWave];
-  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-  const int wave = blockIdx.x * 4 + wv;
-  float* rec = recs[wv];
-  const HighLane h = high_lane(lane, L3);
-  const int ne = lane / KA, ke = lane % KA;   // this lane's coefficient slot (n, k)
-  float cb[T];
-#pragma unroll
-  for (int t = 0; t < T; ++t) cb[t] = 0.f;
-  for (int u = 0; u < kAPW; ++u) {
-    HighAtom<C, kTri> at;
-    if (!high_atom<C, kTri>(a, wave * kAPW + u, at)) continue;
-    const float* wb = a.wbar + 6 * at.st;
-    const float gw[6] = {wb[0], wb[1], wb[2], wb[3], wb[4], wb[5]};
-    const float fbx = a.fbar[at.i], fby = a.fbar[a.N + at.i], fbz = a.fbar[2 * a.N + at.i];
-    // Sbar = 2 (Gbar S~ - E' Sdot~), A = 2 E' S~ (signs as in the main adjoint)
-    float Sb[NA], Av[NA];
+      for (int n = 0; n < NA; ++n) a.Sdh[high_slot<C>(pa, n, lane)] = Sd[n];
+    float q[(L3 - 4) * NA];
 #pragma unroll
     for (int n = 0; n < NA; ++n) {
-      const size_t o = ((size_t)at.pa * NA + n) * YH + (lane < YH ? lane : 0);
+      const float s = lane < YH ? a.Sh[high_slot<C>(pa, n, lane)] : 0.f;
+#pragma unroll
+      for (int l = 5; l <= L3; ++l) q[(l - 5) * NA + n] = h.l == l ? 2.0f * s * Sd[n] : 0.f;
+    }
+    high_rows_store<C>(q, a.Gd, a.Npad, pa);
+  };
+  high_walk<C, kTri, true, false>(a, gr, rec, pw, start, pair, finish);
+}
+
+// The c^A gradient: for each pair, X_n = sum_lm (Sbar_nlm Y - A_nlm grad Y . w)
+// and Y_n = sum_lm A_nlm Y (sums over the lanes), then
+// dL/dc_nk^{IJ} += X_n f_k - Y_n (u.t) f'_k.  The 2 NA sums of a pair come
+// out of one scattered sum: lanes with (lane & 7) = n hold X_n, with
+// (lane & 7) = 4 + n hold Y_n; lane l then takes channel n = l & 3 and
+// coefficient slot (J, k) = (l >> 2) / KA, (l >> 2) % KA.
+template <class C, bool kTri>
+__global__ __launch_bounds__(256) void k_high_coef(HighArgs a) {
+  constexpr int T = C::T;
+  NEP_HIGH_PROLOGUE(true, true)
+  static_assert(NA <= 4 && T * KA <= 16, "one coefficient slot per lane");
+  const int ne = lane & 3, se = lane >> 2;
+  const int te = se / KA, ke = se % KA;
+  const bool slot = ne < NA && se < T * KA;
+  float cb = 0.f;
+  float Sb[NA], Av[NA];
+  auto start = [&](int u) {
+    // Sbar = 2 (Gbar S~ - E' Sdot~), A = 2 E' S~ (signs as in the main adjoint)
+    const int pa = gr.pa0 + u;
+#pragma unroll
+    for (int n = 0; n < NA; ++n) {
+      const size_t o = high_slot<C>(pa, n, lane);
       const float s = lane < YH ? a.Sh[o] : 0.f, sd = lane < YH ? a.Sdh[o] : 0.f;
-      const float ep = high_ep<C>(a.Ep, a.Npad, at.pa, h, n), gb = high_ep<C>(a.Gb, a.Npad, at.pa, h, n);
+      const float ep = high_rowval<C>(a.Ep, a.Npad, pa, h, n), gb = high_rowval<C>(a.Gb, a.Npad, pa, h, n);
       Sb[n] = 2.0f * (gb * s - ep * sd);
       Av[n] = 2.0f * ep * s;
     }
-    for (int k0 = 0; k0 < at.nA; k0 += kWave) {
-      high_stage<C, kTri, true>(a, at, k0, rec, fbx, fby, fbz, gw);
-      const int np = min(kWave, at.nA - k0);
-      for (int jj = 0; jj < np; ++jj) {
-        const float ir = rec[R::IR * kWave + jj];
-        float v, gx, gy, gz;
-        high_harm(h, rec[R::DX * kWave + jj] * ir, rec[R::DY * kWave + jj] * ir, rec[R::DZ * kWave + jj] * ir, v, gx,
-                  gy, gz);
-        const float gwt = gx * rec[R::WX * kWave + jj] + gy * rec[R::WY * kWave + jj] + gz * rec[R::WZ * kWave + jj];
-        float Xe = 0.f, Ye = 0.f;
+  };
+  auto pair = [&](int, int jj) {
+    float v, gx, gy, gz;
+    high_eval(h, rec[R::DZ * kWave + jj] * rec[R::IR * kWave + jj], pw + jj * kPwStride, v, gx, gy, gz);
+    const float gwt = gx * rec[R::WX * kWave + jj] + gy * rec[R::WY * kWave + jj] + gz * rec[R::WZ * kWave + jj];
+    float xs[8];
 #pragma unroll
-        for (int n = 0; n < NA; ++n) {
-          const float X = wave_total(fmaf(Sb[n], v, -Av[n] * gwt));
-          const float Yv = wave_total(Av[n] * v);
-          Xe = ne == n ? X : Xe;
-          Ye = ne == n ? Yv : Ye;
-        }
-        const int J = (int)rec[R::J * kWave + jj];
-        const float dt = rec[R::DT * kWave + jj];
-        const float fk = rec[(R::F + ke) * kWave + jj], fpk = rec[(R::FP + ke) * kWave + jj];
-        const float add = fmaf(Xe, fk, -Ye * dt * fpk);
-#pragma unroll
-        for (int t = 0; t < T; ++t) cb[t] += (T == 1 || J == t) ? add : 0.f;
-      }
-      lds_lane_exchange();
+    for (int n = 0; n < 4; ++n) {
+      xs[n] = n < NA ? fmaf(Sb[n < NA ? n : 0], v, -Av[n < NA ? n : 0] * gwt) : 0.f;
+      xs[4 + n] = n < NA ? Av[n < NA ? n : 0] * v : 0.f;
     }
-  }
-  if (lane < NA * KA) {
-    float* part = a.part + (size_t)wave * a.PW;
-#pragma unroll
-    for (int t = 0; t < T; ++t) part[(t * NA + ne) * KA + ke] += cb[t];
-  }
+    const float own = wave_scatter_sum<8>(xs);
+    const float other = xor4_val(own);
+    const bool lo = (lane & 4) == 0;
+    const float Xe = lo ? own : other, Ye = lo ? other : own;
+    const int J = __float_as_int(rec[R::J * kWave + jj]);
+    const float dt = rec[R::DT * kWave + jj];
+    const float fk = rec[(R::F + ke) * kWave + jj], fpk = rec[(R::FP + ke) * kWave + jj];
+    cb += (T == 1 || J == te) ? fmaf(Xe, fk, -Ye * dt * fpk) : 0.f;
+  };
+  auto finish = [&](int) {};
+  high_walk<C, kTri, true, true>(a, gr, rec, pw, start, pair, finish);
+  if (slot) a.part[(size_t)wave * a.PW + (te * NA + ne) * KA + ke] += cb;
 }
+
+#undef NEP_HIGH_PROLOGUE
 
 }  // namespace nep
