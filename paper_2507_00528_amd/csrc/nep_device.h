@@ -35,6 +35,10 @@ struct Cfg {
   static constexpr int LMAX = (L3LO > L4 ? (L3LO > L5 ? L3LO : L5) : (L4 > L5 ? L4 : L5));
   static constexpr int Y = LMAX * (LMAX + 2);
   static constexpr int YH = L3 > 4 ? (L3 + 1) * (L3 + 1) - 25 : 0;   // harmonics of l = 5..L3
+  // waves per SIMD the adjoint is compiled for: 3 (a few registers spill, and
+  // the extra wave hides more latency than the spills cost), except with
+  // degrees l > 4, whose larger descriptor would spill too much
+  static constexpr int ADJ_WAVES = YH > 0 ? 2 : 3;
   static constexpr int D = NR + NA * L3 + (L4 ? NA : 0) + (L5 ? NA : 0);
   static constexpr int PS = T * NR * KR + T * NA * KA;  // c-grad slots of one center species
 };

@@ -502,7 +502,7 @@ __global__ __launch_bounds__(256) void k_reverse(int N, const uint32_t* __restri
 // and a counting sort over keys keeps the layout deterministic.
 constexpr int kOrdBlk = 1024;
 constexpr int kOrdBuckets = 64;
-constexpr int kSegAlign = 8;   // species segments start on multiples of the atoms per wavefront
+constexpr int kSegAlign = 32;  // species segments start on multiples of the atoms per block
 
 __device__ __forceinline__ int order_key(int t, int T, int nA) {
   if (t < 0 || t >= T) return -1;
@@ -719,7 +719,7 @@ __device__ __forceinline__ void lds_lane_exchange() { asm volatile("" ::: "memor
 constexpr int kLPA = 8;                    // lanes per atom
 constexpr int kAPB = 256 / kLPA;           // atoms per block
 constexpr int kAPW = kWave / kLPA;         // atoms per wavefront
-static_assert(kAPW == kSegAlign, "species segments must align to wavefronts");
+static_assert(kSegAlign % kAPB == 0, "species segments must align to blocks (one species per block)");
 }  // namespace nep
 #include "nep_highl.h"
 namespace nep {
@@ -787,18 +787,26 @@ __device__ __forceinline__ GroupCtx group_ctx(const int* __restrict__ order, con
   return c;
 }
 
-// stage every species' W0 (rows padded to DP floats), b0 and w1 into LDS
-__device__ __forceinline__ void stage_weights(float* wl, const float* __restrict__ nn, int nn_stride, int T, int H,
+// Species of the block's atoms.  Segments start on block boundaries, so a
+// block holds one species, and its first position is an atom unless the
+// whole block is padding.
+__device__ __forceinline__ int block_species(const int* __restrict__ order, const int* __restrict__ type) {
+  const int ip = order[blockIdx.x * kAPB];
+  return ip >= 0 ? type[ip] : 0;
+}
+
+// stage species I's W0 (rows padded to DP floats), b0 and w1 into LDS
+__device__ __forceinline__ void stage_weights(float* wl, const float* __restrict__ nn, int nn_stride, int I, int H,
                                               int D, int DP) {
   const int WS = H * DP + 2 * H;
-  for (int q = threadIdx.x; q < T * WS; q += blockDim.x) {
-    const int I = q / WS, o = q % WS;
+  const float* w = nn + (size_t)I * nn_stride;
+  for (int q = threadIdx.x; q < WS; q += blockDim.x) {
     float v = 0.f;
-    if (o < H * DP) {
-      const int mu = o / DP, d = o % DP;
-      if (d < D) v = nn[(size_t)I * nn_stride + mu * D + d];
+    if (q < H * DP) {
+      const int mu = q / DP, d = q % DP;
+      if (d < D) v = w[mu * D + d];
     } else {
-      v = nn[(size_t)I * nn_stride + H * D + (o - H * DP)];
+      v = w[H * D + (q - H * DP)];
     }
     wl[q] = v;
   }
@@ -812,7 +820,7 @@ __device__ __forceinline__ void stage_weights(float* wl, const float* __restrict
 // pair's partial force f_ij = dE_i/dr_ij is stored (C3.6) with this atom's
 // share -sum_j f_ij (x) r_ij of the virial.
 template <class C, bool kTri>
-__global__ __launch_bounds__(256, 2) void k_forward(FwdArgs a) {
+__global__ __launch_bounds__(256, 3) void k_forward(FwdArgs a) {
   constexpr int T = C::T, NR = C::NR, NA = C::NA, KR = C::KR, KA = C::KA, Y = C::Y, D = C::D, LM = C::LMAX;
   constexpr int L3 = C::L3, L4 = C::L4, L5 = C::L5;
   using HS = HSplit<LM>;
@@ -824,10 +832,10 @@ __global__ __launch_bounds__(256, 2) void k_forward(FwdArgs a) {
   constexpr int RW = DP + NA * Y;         // LDS row per atom: G, S
   using CT = CTab<T, NA, KA>;
   float* ctab = lds;                     // [T][T][NA][KAP]
-  float* wl = lds + CT::size;            // [T][WS]
-  float* rows = wl + T * WS;             // [kAPB][RW]
+  float* wl = lds + CT::size;            // [WS] of the block's species
+  float* rows = wl + WS;                 // [kAPB][RW]
   stage_ctab<T, NA, KA>(ctab, a.cA);
-  if (a.do_mlp) stage_weights(wl, a.nn, a.nn_stride, T, H, D, DP);
+  if (a.do_mlp) stage_weights(wl, a.nn, a.nn_stride, block_species(a.order, a.type), H, D, DP);
   __syncthreads();
   const GroupCtx w = group_ctx(a.order, a.type, a.Npad);
   const int N = a.N, i = w.i, I = w.I, pa = w.pa, s = w.s, g = w.g;
@@ -975,7 +983,7 @@ __global__ __launch_bounds__(256, 2) void k_forward(FwdArgs a) {
   if (!a.do_mlp) return;
 
   // ---- network: hidden units mu = s, s+8, ... (weights from LDS)
-  const float* Wl = wl + I * WS;
+  const float* Wl = wl;
   float Ep[D];
 #pragma unroll
   for (int v = 0; v < D; ++v) Ep[v] = 0.f;
@@ -1345,7 +1353,7 @@ __global__ __launch_bounds__(kRedBlk) void k_loss_final(int S, int N, float le, 
 // Outputs: per-atom vectors for the outer-product sums (W0, c^R) and, per
 // wavefront, the sums of the c^A, b0, w1, b1 partials over its 8 atoms.
 template <class C, bool kTri>
-__global__ __launch_bounds__(256, 2) void k_adjoint(AdjArgs a) {
+__global__ __launch_bounds__(256, C::ADJ_WAVES) void k_adjoint(AdjArgs a) {
   constexpr int T = C::T, NR = C::NR, NA = C::NA, KR = C::KR, KA = C::KA, Y = C::Y, D = C::D, LM = C::LMAX;
   constexpr int L3 = C::L3, L4 = C::L4, L5 = C::L5;
   using HS = HSplit<LM>;
@@ -1359,10 +1367,10 @@ __global__ __launch_bounds__(256, 2) void k_adjoint(AdjArgs a) {
   const int WS = H * DP + 2 * H;
   using CT = CTab<T, NA, KA>;
   float* ctab = lds;                     // [T][T][NA][KAP]
-  float* wl = lds + CT::size;            // [T][WS]
-  float* rows = wl + T * WS;             // [kAPB][RW]
+  float* wl = lds + CT::size;            // [WS] of the block's species
+  float* rows = wl + WS;                 // [kAPB][RW]
   stage_ctab<T, NA, KA>(ctab, a.cA);
-  stage_weights(wl, a.nn, a.nn_stride, T, H, D, DP);
+  stage_weights(wl, a.nn, a.nn_stride, block_species(a.order, a.type), H, D, DP);
   __syncthreads();
   const GroupCtx w = group_ctx(a.order, a.type, a.Npad);
   const int N = a.N, i = w.i, I = w.I, pa = w.pa, s = w.s, g = w.g;
@@ -1553,7 +1561,7 @@ __global__ __launch_bounds__(256, 2) void k_adjoint(AdjArgs a) {
   }
 
   // ---- network adjoint, hidden units mu = s, s+8, ...
-  const float* Wl = wl + I * WS;
+  const float* Wl = wl;
   float Gb[D];
 #pragma unroll
   for (int v = 0; v < D; ++v) Gb[v] = 0.f;
@@ -2168,13 +2176,13 @@ struct Ops {
 template <class C>
 static size_t lds_forward(int H) {
   const int DP = (C::D + 3) & ~3;
-  return sizeof(float) * ((size_t)CTab<C::T, C::NA, C::KA>::size + (size_t)C::T * (H * DP + 2 * H) +
+  return sizeof(float) * ((size_t)CTab<C::T, C::NA, C::KA>::size + (size_t)(H * DP + 2 * H) +
                           (size_t)kAPB * (DP + C::NA * C::Y));
 }
 template <class C>
 static size_t lds_adjoint(int H) {
   const int DP = (C::D + 3) & ~3;
-  return sizeof(float) * ((size_t)CTab<C::T, C::NA, C::KA>::size + (size_t)C::T * (H * DP + 2 * H) +
+  return sizeof(float) * ((size_t)CTab<C::T, C::NA, C::KA>::size + (size_t)(H * DP + 2 * H) +
                           (size_t)kAPB * (DP + 2 * C::NA * C::Y));
 }
 template <class C>
@@ -2281,7 +2289,7 @@ Layout make_layout(const nep_model* m, const Ops* o, int S, int N) {
   L.TKR = m->n_types * m->k_rad;
   L.capR = m->cap_rad;
   L.capA = m->cap_ang;
-  // species segments (each rounded up to 8 atoms) plus 16 atoms of slack for
+  // species segments (each rounded up to 32 atoms, one block) plus 16 atoms of slack for
   // the 16-atom groups of the outer-product sums
   const int n8 = ((N + kSegAlign - 1) / kSegAlign) * kSegAlign + L.T * kSegAlign + 16;
   L.Npad = ((n8 + kAPB - 1) / kAPB) * kAPB;
