@@ -367,6 +367,80 @@ __device__ __forceinline__ float atoms8_sum(float v) {
   return xor32_sum(xor16_sum(v));
 }
 
+// ------------------------------------------- reduce-scatter over lane bits
+// One butterfly step over a lane bit: values (2w, 2w+1) become one value per
+// lane, the even one summed over the pair of lanes where the bit is clear and
+// the odd one where it is set, so each step halves the values a lane carries.
+template <int CTRL>
+struct DppStep {   // lane bit reached by a DPP pattern (xor 1, xor 2, row_ror 8 = xor 8)
+  int bit;
+  __device__ __forceinline__ float operator()(float e, float o) const {
+    const bool hi = (threadIdx.x >> bit) & 1;
+    const float send = hi ? e : o;
+    return (hi ? o : e) + dpp<CTRL>(send);
+  }
+};
+// lane bit 4 / 5: v_permlane16_swap / v_permlane32_swap exchange the odd
+// 16-lane rows (upper 32-lane half) of the first operand with the even rows
+// (lower half) of the second, so swap(e, o) leaves every lane with its kept
+// value and the partner's copy of it
+struct Perm16Step {
+  __device__ __forceinline__ float operator()(float e, float o) const {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(e), __float_as_uint(o), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+};
+struct Perm32Step {
+  __device__ __forceinline__ float operator()(float e, float o) const {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(e), __float_as_uint(o), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+};
+template <int V, class Step>
+__device__ __forceinline__ void rs_step(const float (&x)[V], float (&y)[(V + 1) / 2], Step st) {
+#pragma unroll
+  for (int w = 0; w < (V + 1) / 2; ++w) y[w] = st(x[2 * w], 2 * w + 1 < V ? x[2 * w + 1] : 0.f);
+}
+
+// Sums of V per-lane values over the 4 pair slots and the 8 atoms of a
+// wavefront (lane bits 0, 1, 3, 4, 5; bit 2, the harmonic group, is kept
+// apart), scattered: out[r] holds the sum of value 32 r + c, where
+// c = b0 + 2 b1 + 4 b3 + 8 b4 + 16 b5 from the lane's bits.  Takes about V / 2
+// lane exchanges in all instead of 5 V.
+template <int V>
+__device__ __forceinline__ void rs_slots_atoms(const float (&x)[V], float (&out)[(V + 31) / 32]) {
+  constexpr int V1 = (V + 1) / 2, V2 = (V1 + 1) / 2, V3 = (V2 + 1) / 2, V4 = (V3 + 1) / 2;
+  float y1[V1], y2[V2], y3[V3], y4[V4];
+  rs_step(x, y1, DppStep<kDppXor1>{0});
+  rs_step(y1, y2, DppStep<kDppXor2>{1});
+  rs_step(y2, y3, DppStep<kDppRowRor8>{3});
+  rs_step(y3, y4, Perm16Step{});
+  rs_step(y4, out, Perm32Step{});
+}
+// Sums of V per-lane values over the 8 lanes of an atom group (lane bits 0,
+// 1, 2), scattered: out[r] of lane s holds the sum of value 8 r + s.
+struct Xor4Step {
+  __device__ __forceinline__ float operator()(float e, float o) const {
+    const bool hi = threadIdx.x & 4;
+    const float send = hi ? e : o;
+    return (hi ? o : e) + xor4_val(send);
+  }
+};
+template <int V>
+__device__ __forceinline__ void rs_group8(const float (&x)[V], float (&out)[(V + 7) / 8]) {
+  constexpr int V1 = (V + 1) / 2, V2 = (V1 + 1) / 2;
+  float y1[V1], y2[V2];
+  rs_step(x, y1, DppStep<kDppXor1>{0});
+  rs_step(y1, y2, DppStep<kDppXor2>{1});
+  rs_step(y2, out, Xor4Step{});
+}
+
+// value index c of the lane's first output of rs_slots_atoms
+__device__ __forceinline__ int rs_slots_atoms_code() {
+  const int l = threadIdx.x;
+  return (l & 1) | ((l >> 1) & 1) << 1 | ((l >> 3) & 1) << 2 | ((l >> 4) & 1) << 3 | ((l >> 5) & 1) << 4;
+}
+
 // Image shift of a neighbor code: code = 9(sx+1) + 3(sy+1) + (sz+1).
 __device__ __forceinline__ void decode_shift(uint32_t code, float& sx, float& sy, float& sz) {
   const int c = (int)code;

@@ -1729,16 +1729,28 @@ __global__ __launch_bounds__(256, C::ADJ_WAVES) void k_adjoint(AdjArgs a) {
       }
     }
   }
+  // sums over the pair slots and atoms, scattered over the lanes of each
+  // harmonic group: value v = (t NAH + j) KA + k
+  {
+    constexpr int V = T * NAH * KA;
+    float cv[V];
 #pragma unroll
-  for (int t = 0; t < T; ++t)
+    for (int t = 0; t < T; ++t)
 #pragma unroll
-    for (int j = 0; j < NAH; ++j)
+      for (int j = 0; j < NAH; ++j)
 #pragma unroll
-      for (int k = 0; k < KA; ++k) {
-        const float r = atoms8_sum(quad_sum(cb[t][j][k]));
-        const int n = g * NAH + j;
-        if (first_atom && w.p == 0 && n < NA) part[(t * NA + n) * KA + k] = r;
-      }
+        for (int k = 0; k < KA; ++k) cv[(t * NAH + j) * KA + k] = cb[t][j][k];
+    float out[(V + 31) / 32];
+    rs_slots_atoms(cv, out);
+    const int c = rs_slots_atoms_code();
+#pragma unroll
+    for (int r = 0; r < (V + 31) / 32; ++r) {
+      const int v = 32 * r + c;
+      const int t = v / (NAH * KA), j = (v / KA) % NAH, k = v % KA;
+      const int n = g * NAH + j;
+      if (v < V && n < NA) part[(t * NA + n) * KA + k] = out[r];
+    }
+  }
 }
 
 // Sums over the atoms of each species of an outer product,
