@@ -867,20 +867,25 @@ __global__ __launch_bounds__(256, 3) void k_forward(FwdArgs a) {
       for (int kk = 0; kk < KR; ++kk) FR[t][kk] = fmaf(m, f[kk], FR[t][kk]);
     }
   }
+  // q_n from this lane's partial sums, then summed over the 8 lanes
+  // (scattered: q_n in lane n & 7)
+  {
+    float qn[NR];
 #pragma unroll
-  for (int t = 0; t < T; ++t)
-#pragma unroll
-    for (int k = 0; k < KR; ++k) FR[t][k] = grp8_sum(FR[t][k]);
-#pragma unroll
-  for (int n = 0; n < NR; ++n)
-    if (s == (n & 7)) {
+    for (int n = 0; n < NR; ++n) {
       float acc = 0.f;
 #pragma unroll
       for (int t = 0; t < T; ++t)
 #pragma unroll
         for (int k = 0; k < KR; ++k) acc = fmaf(cRI[(t * NR + n) * KR + k], FR[t][k], acc);
-      row[n] = acc;
+      qn[n] = acc;
     }
+    float qo[(NR + 7) / 8];
+    rs_group8(qn, qo);
+#pragma unroll
+    for (int r = 0; r < (NR + 7) / 8; ++r)
+      if (8 * r + s < NR) row[8 * r + s] = qo[r];
+  }
 
   // ---- angular sums S_nlm: harmonic group g, pairs p, p+4, ...
   float Sg[NA][YG];
@@ -1001,14 +1006,25 @@ __global__ __launch_bounds__(256, 3) void k_forward(FwdArgs a) {
     for (int v = 0; v < D; ++v) Ep[v] = fmaf(sg, wr[v], Ep[v]);
     if (w.valid && a.X) a.X[(size_t)mu * a.Npad + pa] = x;
   }
+  // E' summed over the 8 lanes, scattered (entry v in lane v & 7), shared
+  // through the atom's LDS row (G there has been read)
+  {
+    float eo[(D + 7) / 8];
+    rs_group8(Ep, eo);
 #pragma unroll
-  for (int v = 0; v < D; ++v) Ep[v] = grp8_sum(Ep[v]);
+    for (int r = 0; r < (D + 7) / 8; ++r) {
+      const int v = 8 * r + s;
+      if (v < D) {
+        row[v] = eo[r];
+        if (w.valid && a.Ep) a.Ep[(size_t)v * a.Npad + pa] = eo[r];
+      }
+    }
+    lds_lane_exchange();
+#pragma unroll
+    for (int v = 0; v < D; ++v) Ep[v] = row[v];
+  }
   E = grp8_sum(E) + a.nn[(size_t)I * a.nn_stride + H * D + 2 * H];
   if (w.valid) {
-    if (a.Ep)
-#pragma unroll
-      for (int v = 0; v < D; ++v)
-        if (s == (v & 7)) a.Ep[(size_t)v * a.Npad + pa] = Ep[v];
     if (s == 0) {
       if (a.eatom) a.eatom[i] = E;
       if (a.eatom2) a.eatom2[i] = E;
