@@ -20,6 +20,25 @@ namespace nep {
 // every candidate (j, s) is tested exactly with the float64 predicate of
 // Eq. 2, evaluated without fused multiply-add.  j runs ascending and the
 // shifts in code order, so the lists come out in canonical order.
+// IEEE double product and sum with one rounding each.  The library is built
+// with floating-point contraction, and d^2 = (dx dx + dy dy) + dz dz of the
+// predicate must not become fused multiply-adds (a pair within an ulp of rc
+// can change sides), so the squares and their sums are single instructions
+// the compiler cannot merge.
+__device__ __forceinline__ double mul_d(double a, double b) {
+  double r;
+  asm("v_mul_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ double add_d(double a, double b) {
+  double r;
+  asm("v_add_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ double dist2_d(double dx, double dy, double dz) {
+  return add_d(add_d(mul_d(dx, dx), mul_d(dy, dy)), mul_d(dz, dz));
+}
+
 __device__ __forceinline__ unsigned axis_candidates(double d0, double L, double rc) {
   unsigned m = 0;
   if (fabs(__dadd_rn(d0, -L)) < rc) m |= 1u;
@@ -82,16 +101,16 @@ __device__ __forceinline__ void exact_pair(const ScanCtx& c, const PosTile& t, i
   for (unsigned bx = mx; bx; bx &= bx - 1u) {
     const int sx = __builtin_ctz(bx);
     const double dx = sx == 1 ? x0 : __dadd_rn(x0, sx == 0 ? -c.Lx : c.Lx);
-    const double dx2 = __dmul_rn(dx, dx);
+    const double dx2 = mul_d(dx, dx);
     for (unsigned by = my; by; by &= by - 1u) {
       const int sy = __builtin_ctz(by);
       const double dy = sy == 1 ? y0 : __dadd_rn(y0, sy == 0 ? -c.Ly : c.Ly);
-      const double dxy = __dadd_rn(dx2, __dmul_rn(dy, dy));
+      const double dxy = add_d(dx2, mul_d(dy, dy));
       for (unsigned bz = mz; bz; bz &= bz - 1u) {
         const int sz = __builtin_ctz(bz);
         const int code = 9 * sx + 3 * sy + sz;
         const double dz = sz == 1 ? z0 : __dadd_rn(z0, sz == 0 ? -c.Lz : c.Lz);
-        const double d2 = __dadd_rn(dxy, __dmul_rn(dz, dz));
+        const double d2 = add_d(dxy, mul_d(dz, dz));
         if (d2 < c.rcR2 && !(j == c.i && code == 13)) emit(j, code, d2 < c.rcA2);
       }
     }
@@ -137,7 +156,7 @@ __device__ __forceinline__ void exact_pair_tri(const ScanCtx& c, const PosTile& 
         if (!((myz >> (3 * sb + sc)) & 1u)) continue;
         const double dx = sc == 1 ? xb : __dadd_rn(xb, sc == 0 ? -c.xz : c.xz);
         const double dy = dyv[3 * sb + sc], dz = dzv[sc];
-        const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+        const double d2 = dist2_d(dx, dy, dz);
         const int code = 9 * sa + 3 * sb + sc;
         if (d2 < c.rcR2 && !(j == c.i && code == 13)) emit(j, code, d2 < c.rcA2);
       }
@@ -181,6 +200,7 @@ __device__ __forceinline__ void min_image(const ScanCtx& c, float& ex, float& ey
 }
 
 // float64 squared length of the image s = -k of j, in the predicate's order
+// (the products k L are exact, k being 0 or +-1, so contracting them is harmless)
 template <bool kTri>
 __device__ __forceinline__ double image_d2(const ScanCtx& c, float px, float py, float pz, float kx, float ky,
                                            float kz) {
@@ -191,7 +211,7 @@ __device__ __forceinline__ double image_d2(const ScanCtx& c, float px, float py,
     dx = __dadd_rn(__dadd_rn(dx, -(double)ky * c.xy), -(double)kz * c.xz);
     dy = __dadd_rn(dy, -(double)kz * c.yz);
   }
-  return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+  return dist2_d(dx, dy, dz);
 }
 
 template <bool kTri, class Emit>

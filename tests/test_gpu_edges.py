@@ -145,3 +145,48 @@ def test_empty_batch():
     assert int(fl.item()) == 0
     assert (grad.cpu().numpy() == 0).all()
     assert (loss.cpu().numpy() == 0).all()
+
+
+def test_predicate_rounding_order():
+    """Pairs whose squared distance lies within an ulp of rc^2, so that the
+    predicate's rounding order decides them: with (dx^2 + dy^2) + dz^2
+    rounded after each operation they are inside, while either fused
+    multiply-add order puts them outside.  One pair at the radial cutoff
+    (6 A, the float64 test of all images), one at an angular cutoff of 3 A
+    (the shell check of the single-image decision).  Atom i sits at a few
+    2^-56 A from the origin so that the differences carry 53 bits."""
+    import dataclasses
+    from fractions import Fraction
+    import torch
+    e = 2.0 ** -56
+    cases = [((27 * e, 30 * e, 12 * e), (4.0, 2.0, 4.0), 6.0), ((16 * e, 21 * e, 6 * e), (1.0, 2.0, 2.0), 3.0)]
+
+    def fma(a, b, c):
+        return float(Fraction(a) * Fraction(b) + Fraction(c))
+
+    sts = []
+    for xi, xj, rc in cases:
+        d = [b - a for a, b in zip(xi, xj)]
+        sep = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]
+        assert sep < rc * rc
+        assert fma(d[2], d[2], fma(d[1], d[1], d[0] * d[0])) >= rc * rc
+        assert fma(d[2], d[2], fma(d[0], d[0], d[1] * d[1])) >= rc * rc
+        pos = np.array([xi, xj], np.float32)
+        assert (pos.astype(np.float64) == np.array([xi, xj])).all()
+        sts.append(synth.Structure(pos, np.full(3, 20.0, np.float32), np.array([0, 1], np.int32), "edge"))
+    sz = dataclasses.replace(synth.SIZES_SMALL, rc_ang=3.0)
+    c = Case(sz, sts, with_oracle=False)
+    r = GPURun(c)
+    print(f"[rounding order] N={c.batch.n_atom}", flush=True)
+    r.neighbors()
+    torch.cuda.synchronize()
+    assert int(r.flags.item()) == 0
+    for which in ("rad", "ang"):
+        got, cnt = r.lists(which)
+        ref = oracle_lists(c, which)
+        assert cnt.tolist() == [len(x) for x in ref]
+        assert all([int(v) for v in g] == x for g, x in zip(got, ref))
+    rad, _ = r.lists("rad")
+    ang, _ = r.lists("ang")
+    assert len(rad[0]) == 1 and len(rad[1]) == 1      # the 6 A pair
+    assert len(ang[2]) == 1 and len(ang[3]) == 1      # the 3 A pair
