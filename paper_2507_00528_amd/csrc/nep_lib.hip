@@ -62,7 +62,8 @@ __device__ __forceinline__ unsigned axis_candidates(double d0, double L, double 
 //
 // Positions of the atoms j that a block's 32 atoms scan are staged in LDS in
 // tiles of kNbrTile atoms; every lane of the block walks the same tiles.
-constexpr int kNbrAPB = 256 / 8;   // atoms per block
+constexpr int kNbrThreads = 256;   // threads per block
+constexpr int kNbrAPB = kNbrThreads / 8;   // atoms per block
 constexpr int kNbrTile = 1024;
 constexpr int kNbrBuf = 24;   // entries buffered per lane (angular mask: 32 bits), plus a scratch slot
 constexpr float kNbrDelta = 0.01f;
@@ -257,12 +258,13 @@ __device__ __forceinline__ void scan_keep(const ScanCtx& c, const PosTile& t, in
     float ex = px - c.xf, ey = py - c.yf, ez = pz - c.zf, kx, ky, kz;
     min_image<kTri>(c, ex, ey, ez, kx, ky, kz);
     const float r2 = ex * ex + ey * ey + ez * ez;
-    const bool one = fabsf(kx) <= 1.f && fabsf(ky) <= 1.f && fabsf(kz) <= 1.f;
-    const int code = 9 * (1 - (int)kx) + 3 * (1 - (int)ky) + (1 - (int)kz);
-    const bool decided = r2 < c.inR2 && one;
+    // k is 0 or +-1 for positions inside the cell (the position flag's
+    // condition), so the shift s = -k always has a code
+    const int code = 13 - (int)fmaf(9.f, kx, fmaf(3.f, ky, kz));
+    const bool decided = r2 < c.inR2;
     const bool in = decided && !(j == c.i && code == 13);
     bool ang = r2 < c.inA2;
-    buf[blockDim.x * min(nR, kNbrBuf)] = ((uint32_t)j << 5) | (uint32_t)(code & 31);
+    buf[kNbrThreads * min(nR, kNbrBuf)] = ((uint32_t)j << 5) | (uint32_t)(code & 31);
     if (in && !ang && r2 < c.outA2) ang = image_d2<kTri>(c, px, py, pz, kx, ky, kz) < c.rcA2;
     angmask |= (in && ang && nR < kNbrBuf) ? (1u << nR) : 0u;
     nR += in ? 1 : 0;
@@ -318,9 +320,9 @@ __device__ __forceinline__ CellCheck check_cell(const ScanCtx& c, float rcR, flo
 }
 
 template <bool kTri>
-__global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
+__global__ __launch_bounds__(kNbrThreads) void k_neighbors(NbrArgs a) {
   __shared__ float tx[kNbrTile], ty[kNbrTile], tz[kNbrTile];
-  __shared__ uint32_t nbuf[256 * (kNbrBuf + 1)];
+  __shared__ uint32_t nbuf[kNbrThreads * (kNbrBuf + 1)];
   __shared__ int jr[2];
   const int s = threadIdx.x & 7;
   const int b0 = xcd_block() * kNbrAPB;
@@ -388,7 +390,7 @@ __global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
   auto sweep = [&](int b, int e, auto&& scan) {
     for (int t0 = jlo; t0 < jhi; t0 += kNbrTile) {
       const int tn = min(kNbrTile, jhi - t0);
-      for (int q = threadIdx.x; q < tn; q += blockDim.x) {
+      for (int q = threadIdx.x; q < tn; q += kNbrThreads) {
         tx[q] = a.pos[t0 + q];
         ty[q] = a.pos[a.N + t0 + q];
         tz[q] = a.pos[2 * a.N + t0 + q];
@@ -403,12 +405,12 @@ __global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
   // membership as a bit mask), and after the 8-lane prefix copies them to
   // their slots; a lane with more than kNbrBuf entries makes the whole block
   // rescan and write directly
-  uint32_t* mybuf = nbuf + threadIdx.x;   // slot u at mybuf[256 u]
+  uint32_t* mybuf = nbuf + threadIdx.x;   // slot u at mybuf[kNbrThreads u]
   int nR = 0, nA = 0;
   uint32_t angmask = 0;
   auto keep = [&](int j, int code, bool ang) {
     if (nR < kNbrBuf) {
-      mybuf[blockDim.x * nR] = ((uint32_t)j << 5) | (uint32_t)code;
+      mybuf[kNbrThreads * nR] = ((uint32_t)j << 5) | (uint32_t)code;
       angmask |= ang ? (1u << nR) : 0u;
     }
     ++nR;
@@ -432,7 +434,7 @@ __global__ __launch_bounds__(256) void k_neighbors(NbrArgs a) {
   const bool spill = nR > kNbrBuf;
   if (live && !spill) {
     for (int u = 0; u < nR; ++u) {
-      const uint32_t e = mybuf[blockDim.x * u];
+      const uint32_t e = mybuf[kNbrThreads * u];
       if (wR + u < a.capR) a.idxR[col * a.capR + wR + u] = e;
       if ((angmask >> u) & 1u) {
         if (wA < a.capA) a.idxA[col * a.capA + wA] = e;
@@ -2487,10 +2489,10 @@ void run_neighbors(const Ctx& c, nep_neighbors* nb, int32_t* flags, Prof* pr) {
   a.flags = flags;
   if (a.tilt)
     NEP_LAUNCH(pr, "neighbors",
-               hipLaunchKernelGGL(k_neighbors<true>, dim3(grid1(N, kNbrAPB)), dim3(256), 0, c.st, a));
+               hipLaunchKernelGGL(k_neighbors<true>, dim3(grid1(N, kNbrAPB)), dim3(kNbrThreads), 0, c.st, a));
   else
     NEP_LAUNCH(pr, "neighbors",
-               hipLaunchKernelGGL(k_neighbors<false>, dim3(grid1(N, kNbrAPB)), dim3(256), 0, c.st, a));
+               hipLaunchKernelGGL(k_neighbors<false>, dim3(grid1(N, kNbrAPB)), dim3(kNbrThreads), 0, c.st, a));
   NEP_LAUNCH(pr, "reverse_rad",
              hipLaunchKernelGGL(k_reverse, dim3(grid1(N, 32)), dim3(256), 0, c.st, N, nb->idx_rad,
                                 nb->cnt_rad, c.m->cap_rad, at<int>(c.ws, c.L.revR)));
