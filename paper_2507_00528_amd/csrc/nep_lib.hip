@@ -464,18 +464,20 @@ __global__ __launch_bounds__(kNbrThreads) void k_neighbors(NbrArgs a) {
   if (live && s == 0 && fl) atomicOr(a.flags, fl);
 }
 
-// Position of the reverse entry (i, -s) in j's list; 8 lanes per atom take
-// slots s, s + 8, ....  The search over j's sorted list takes two dependent
-// rounds instead of log2(cap): the last entry of every run of 8 (independent
-// loads) picks the run, then the run's 8 entries (two 16-byte loads) give the
-// position.  Entries past j's count are treated as larger than any key.
+// Position of the reverse entry (i, -s) in j's list; LPA lanes per atom take
+// slots s, s + LPA, ... (32 for the radial lists, 8 for the shorter angular
+// ones).  The search over j's sorted list takes two dependent rounds instead
+// of log2(cap): the last entry of every run of 8 (independent loads) picks
+// the run, then the run's 8 entries (two 16-byte loads) give the position.
+// Entries past j's count are treated as larger than any key.
+template <int LPA>
 __global__ __launch_bounds__(256) void k_reverse(int N, const uint32_t* __restrict__ idx,
                                                  const int* __restrict__ cnt, int cap, int* __restrict__ rev) {
-  const int s = threadIdx.x & 7;
-  const int i = xcd_block() * 32 + (threadIdx.x >> 3);
+  const int s = threadIdx.x % LPA;
+  const int i = xcd_block() * (256 / LPA) + threadIdx.x / LPA;
   if (i >= N) return;
   const int n = min(cnt[i], cap);
-  for (int k = s; k < n; k += 8) {
+  for (int k = s; k < n; k += LPA) {
     const size_t o = (size_t)i * cap + k;
     const uint32_t e = idx[o];
     const int j = (int)(e >> 5);
@@ -489,8 +491,10 @@ __global__ __launch_bounds__(256) void k_reverse(int N, const uint32_t* __restri
       uint32_t last[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
+        // unconditional loads from inside j's row, then the mask
         const int q = 8 * (r0 + u) + 7;
-        last[u] = (r0 + u < nrun && q < m) ? lj[q] : 0xFFFFFFFFu;
+        const uint32_t x = lj[min(q, cap - 1)];
+        last[u] = (r0 + u < nrun && q < m) ? x : 0xFFFFFFFFu;
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) below += (r0 + u < nrun && last[u] < key) ? 1 : 0;
@@ -2494,10 +2498,10 @@ void run_neighbors(const Ctx& c, nep_neighbors* nb, int32_t* flags, Prof* pr) {
     NEP_LAUNCH(pr, "neighbors",
                hipLaunchKernelGGL(k_neighbors<false>, dim3(grid1(N, kNbrAPB)), dim3(kNbrThreads), 0, c.st, a));
   NEP_LAUNCH(pr, "reverse_rad",
-             hipLaunchKernelGGL(k_reverse, dim3(grid1(N, 32)), dim3(256), 0, c.st, N, nb->idx_rad,
+             hipLaunchKernelGGL(k_reverse<32>, dim3(grid1(N, 8)), dim3(256), 0, c.st, N, nb->idx_rad,
                                 nb->cnt_rad, c.m->cap_rad, at<int>(c.ws, c.L.revR)));
   NEP_LAUNCH(pr, "reverse_ang",
-             hipLaunchKernelGGL(k_reverse, dim3(grid1(N, 32)), dim3(256), 0, c.st, N, nb->idx_ang,
+             hipLaunchKernelGGL(k_reverse<8>, dim3(grid1(N, 32)), dim3(256), 0, c.st, N, nb->idx_ang,
                                 nb->cnt_ang, c.m->cap_ang, at<int>(c.ws, c.L.revA)));
   int* order = at<int>(c.ws, c.L.order);
   int* blk = at<int>(c.ws, c.L.blk);
