@@ -557,29 +557,44 @@ __global__ __launch_bounds__(kOrdBlk) void k_order_count(int N, int Npad, int T,
 // the per-block offsets.  seg[2t], seg[2t+1] = start and count of species t.
 __global__ __launch_bounds__(8 * kOrdBuckets) void k_order_scan(int nblk, int T, int* __restrict__ blk,
                                                                int* __restrict__ seg) {
+  constexpr int NT = 8 * kOrdBuckets;
   const int K = T * kOrdBuckets;
-  const int k = threadIdx.x;
-  __shared__ int sc[8 * kOrdBuckets];
+  // each bucket's rows are split into P parts, one thread per (bucket, part)
+  const int P = max(1, NT / K);
+  const int k = threadIdx.x % K, p = threadIdx.x / K;
+  const bool act = threadIdx.x < K * P;
+  const int b0 = (int)((long long)nblk * p / P), b1 = (int)((long long)nblk * (p + 1) / P);
+  __shared__ int part[NT];
+  __shared__ int sc[NT];
   __shared__ int sstart[9];
-  int tot = 0;
-  if (k < K)
-    for (int b0 = 0; b0 < nblk; b0 += 8) {
+  int mine = 0;
+  if (act)
+    for (int b = b0; b < b1; b += 8) {
       int v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = b0 + u < nblk ? blk[(size_t)(b0 + u) * K + k] : 0;
+      for (int u = 0; u < 8; ++u) v[u] = b + u < b1 ? blk[(size_t)(b + u) * K + k] : 0;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) tot += v[u];
+      for (int u = 0; u < 8; ++u) mine += v[u];
     }
-  sc[k] = k < K ? tot : 0;
+  if (act) part[p * K + k] = mine;
   __syncthreads();
-  // inclusive scan (Hillis-Steele)
-  for (int d = 1; d < 8 * kOrdBuckets; d <<= 1) {
-    const int v = k >= d ? sc[k - d] : 0;
+  int tot = 0, before = 0;   // bucket total, and the rows of earlier parts
+  if (act)
+    for (int q = 0; q < P; ++q) {
+      const int v = part[q * K + k];
+      tot += v;
+      before += q < p ? v : 0;
+    }
+  sc[threadIdx.x] = threadIdx.x < K ? tot : 0;
+  __syncthreads();
+  // inclusive scan over the buckets (Hillis-Steele)
+  for (int d = 1; d < NT; d <<= 1) {
+    const int v = (int)threadIdx.x >= d ? sc[threadIdx.x - d] : 0;
     __syncthreads();
-    sc[k] += v;
+    sc[threadIdx.x] += v;
     __syncthreads();
   }
-  if (k == 0) {
+  if (threadIdx.x == 0) {
     int start = 0;
     for (int t = 0; t < T; ++t) {
       const int lo = t == 0 ? 0 : sc[t * kOrdBuckets - 1];
@@ -591,15 +606,15 @@ __global__ __launch_bounds__(8 * kOrdBuckets) void k_order_scan(int nblk, int T,
     }
   }
   __syncthreads();
-  if (k < K) {
-    int off = sstart[k / kOrdBuckets] + sc[k] - tot;
-    for (int b0 = 0; b0 < nblk; b0 += 8) {
+  if (act) {
+    int off = sstart[k / kOrdBuckets] + sc[k] - tot + before;
+    for (int b = b0; b < b1; b += 8) {
       int v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = b0 + u < nblk ? blk[(size_t)(b0 + u) * K + k] : 0;
+      for (int u = 0; u < 8; ++u) v[u] = b + u < b1 ? blk[(size_t)(b + u) * K + k] : 0;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        if (b0 + u < nblk) blk[(size_t)(b0 + u) * K + k] = off;
+        if (b + u < b1) blk[(size_t)(b + u) * K + k] = off;
         off += v[u];
       }
     }
