@@ -1221,12 +1221,14 @@ __global__ __launch_bounds__(256, 3) void k_forward(FwdArgs a) {
 }
 
 // F_i = sum_j f_ij - f_ji (Eq. 3), gathering f_ji through the reverse index;
-// 8 lanes per atom take list slots s, s + 8, ... and are summed by DPP.
+// 16 lanes per atom take list slots s, s + 16, ... (more loads in flight for
+// the dependent reverse reads) and are summed by DPP.
+constexpr int kGatherLPA = 16;
 __device__ __forceinline__ void gather_list(int i, int s, const uint32_t* __restrict__ idx, const int* __restrict__ cnt,
                                             const int* __restrict__ rev, int cap, const float* __restrict__ f,
                                             float& fx, float& fy, float& fz) {
   const int n = min(cnt[i], cap);
-  for (int k = s; k < n; k += 8) {
+  for (int k = s; k < n; k += kGatherLPA) {
     const size_t o = (size_t)i * cap + k;
     const int j = (int)(idx[o] >> 5);
     const int rk = rev[o];
@@ -1246,16 +1248,20 @@ __device__ __forceinline__ void gather_list(int i, int s, const uint32_t* __rest
 __global__ __launch_bounds__(256) void k_force_gather(int N, PairLists nb, const float* __restrict__ fR,
                                                       const float* __restrict__ fA, float* __restrict__ F,
                                                       float* __restrict__ Fuser) {
-  const int s = threadIdx.x & 7;
-  const int i = xcd_block() * 32 + (threadIdx.x >> 3);
+  const int s = threadIdx.x % kGatherLPA;
+  const int i = xcd_block() * (256 / kGatherLPA) + threadIdx.x / kGatherLPA;
   float fx = 0.f, fy = 0.f, fz = 0.f;
   if (i < N) {
     gather_list(i, s, nb.idxR, nb.cntR, nb.revR, nb.capR, fR, fx, fy, fz);
     gather_list(i, s, nb.idxA, nb.cntA, nb.revA, nb.capA, fA, fx, fy, fz);
   }
+  // the 16 lanes of an atom: 8-lane groups, then the other half of the row
   fx = grp8_sum(fx);
   fy = grp8_sum(fy);
   fz = grp8_sum(fz);
+  fx += dpp<kDppRowRor8>(fx);
+  fy += dpp<kDppRowRor8>(fy);
+  fz += dpp<kDppRowRor8>(fz);
   if (i < N && s == 0) {
     F[i] = fx;
     F[N + i] = fy;
@@ -2620,7 +2626,7 @@ void run_forward(const Ctx& c, const nep_neighbors* nb, const float* params, flo
     a.eatom2 = e_atom;
     launch_forward_pass(c, nb, params, a, pr);
     NEP_LAUNCH(pr, "force_gather",
-               hipLaunchKernelGGL(k_force_gather, dim3(grid1(N, 32)), dim3(256), 0, c.st, N, a.nb, a.fR, a.fA,
+               hipLaunchKernelGGL(k_force_gather, dim3(grid1(N, 256 / kGatherLPA)), dim3(256), 0, c.st, N, a.nb, a.fR, a.fA,
                                   at<float>(c.ws, c.L.F), force));
   }
   if (S > 0) {
