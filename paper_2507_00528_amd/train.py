@@ -272,6 +272,8 @@ def main(argv=None):
     from . import synth
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--config", default="c1", help="synthetic workload (c0..c4)")
+    ap.add_argument("--sizes", default=None, choices=["small", "large", "tiny", "l8"],
+                    help="model sizes in place of the workload's own (l8: 3-body degrees up to 8)")
     ap.add_argument("--structures", type=int, default=None, help="use only the first n structures")
     ap.add_argument("--epochs", type=int, default=10)
     ap.add_argument("--batch-size", type=int, default=1)
@@ -283,7 +285,9 @@ def main(argv=None):
     ap.add_argument("--sweep-batch", default=None, help="comma-separated batch sizes")
     ap.add_argument("--sweep-epochs", default=None, help="comma-separated epoch counts")
     args = ap.parse_args(argv)
-    sizes = synth.CONFIG_SIZES[args.config]
+    sizes = (synth.CONFIG_SIZES[args.config] if args.sizes is None else
+             {"small": synth.SIZES_SMALL, "large": synth.SIZES_LARGE, "tiny": synth.SIZES_TINY,
+              "l8": synth.SIZES_L8}[args.sizes])
     structures = synth.config_structures(args.config, n_struct=args.structures)
     labels = teacher_labels(sizes, structures, synth.SEEDS["teacher"], synth.SEEDS["noise"])
     print(f"[train] {args.config}: {len(structures)} structures, {sum(s.n for s in structures)} atoms",

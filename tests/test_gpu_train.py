@@ -64,3 +64,24 @@ def test_training_lowers_loss_and_rmse(reshuffle):
     assert ev1["rmse_f"] < ev0["rmse_f"] and ev1["rmse_e"] < ev0["rmse_e"], (ev0, ev1)
     assert hist[-1]["steps"] == 6 * 16
     tr.close()
+
+
+def test_training_with_high_degrees_and_tilted_cells():
+    """The training driver with 3-body degrees up to l = 8 on a mix of
+    orthorhombic and triclinic cells lowers the loss and the force RMSE."""
+    from paper_2507_00528_amd.train import Trainer, teacher_labels
+    rng = np.random.default_rng(12)
+    sts = synth.config_structures("c1", n_struct=6) + [synth.triclinic_structure(rng, n, 0.031, 2.3, 0.3)
+                                                        for n in (60, 90, 120)]
+    sz = synth.SIZES_L8
+    lab = teacher_labels(sz, sts, synth.SEEDS["teacher"], synth.SEEDS["noise"])
+    print(f"[train l8] S={len(sts)}", flush=True)
+    tr = Trainer(sz, sts, lab, synth.draw_params(sz.n_params, synth.SEEDS["student"]), batch_size=3, epochs=8,
+                 warmup_epochs=0.5, lr_start=3e-3, lr_stop=1e-4, seed=3)
+    ev0 = tr.evaluate()
+    hist = [tr.train_epoch() for _ in range(8)]
+    ev1 = tr.evaluate()
+    assert all(np.isfinite(h["loss"]) for h in hist)
+    assert hist[-1]["loss"] < 0.5 * hist[0]["loss"], [h["loss"] for h in hist]
+    assert ev1["rmse_f"] < ev0["rmse_f"], (ev0, ev1)
+    tr.close()
