@@ -71,8 +71,8 @@ def flop_model(sz, mR: float, mA: float) -> dict:
            + 4 * T * NR * KR                                             # radial coefficient gradient
            + NA * (8 * Y + 4 * q4 + 2 * q5)                              # Sbar, A
            + mA * (6 * NA * Y + 4 * NA * KA))                            # X_n, Y_n, angular coefficient gradient
-    w0 = 4 * H * D
-    out = {"forward": fwd, "adjoint": adj, "w0_grad": w0}
+    outer = 4 * H * D + 4 * NR * T * KR   # dW0 and dc^R, contracted over atoms (one launch)
+    out = {"forward": fwd, "adjoint": adj, "outer_sums": outer}
     if YH:
         hv, hg = 2 * YH, 3 * YH    # harmonic values and gradients of l = 5..l3
         out["high_desc"] = mA * (geo + basis(KA) + 2 * NA * KA + hv + 2 * NA * YH) + 2 * NA * YH

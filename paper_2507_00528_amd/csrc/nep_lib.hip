@@ -471,10 +471,10 @@ __global__ __launch_bounds__(kNbrThreads) void k_neighbors(NbrArgs a) {
 // the run, then the run's 8 entries (two 16-byte loads) give the position.
 // Entries past j's count are treated as larger than any key.
 template <int LPA>
-__global__ __launch_bounds__(256) void k_reverse(int N, const uint32_t* __restrict__ idx,
-                                                 const int* __restrict__ cnt, int cap, int* __restrict__ rev) {
+__device__ __forceinline__ void reverse_block(int blk, int N, const uint32_t* __restrict__ idx,
+                                              const int* __restrict__ cnt, int cap, int* __restrict__ rev) {
   const int s = threadIdx.x % LPA;
-  const int i = xcd_block() * (256 / LPA) + threadIdx.x / LPA;
+  const int i = blk * (256 / LPA) + threadIdx.x / LPA;
   if (i >= N) return;
   const int n = min(cnt[i], cap);
   for (int k = s; k < n; k += LPA) {
@@ -518,6 +518,28 @@ __global__ __launch_bounds__(256) void k_reverse(int N, const uint32_t* __restri
     }
     rev[o] = pos;
   }
+}
+
+// Both lists in one launch (they are independent, and neither fills the GPU
+// alone): the first nbR blocks, in XCD-aware order, take the radial list.
+struct RevArgs {
+  int N, nbR;
+  const uint32_t* idxR;
+  const int* cntR;
+  int capR;
+  int* revR;
+  const uint32_t* idxA;
+  const int* cntA;
+  int capA;
+  int* revA;
+};
+
+__global__ __launch_bounds__(256) void k_reverse(RevArgs a) {
+  const int b = xcd_block();
+  if (b < a.nbR)
+    reverse_block<32>(b, a.N, a.idxR, a.cntR, a.capR, a.revR);
+  else
+    reverse_block<8>(b - a.nbR, a.N, a.idxA, a.cntA, a.capA, a.revA);
 }
 
 // ============================================================ species order
@@ -1858,11 +1880,10 @@ __device__ __forceinline__ f32x4 ld_atoms4(const float* row, int p, int p1, bool
   return r;
 }
 
-__global__ __launch_bounds__(256) void k_outer_sum(OuterArgs o) {
-  __shared__ f32x4 red[3][kOSTM * kOSTV][kWave];
+__device__ __forceinline__ void outer_sum_block(const OuterArgs& o, int z, f32x4 (&red)[3][kOSTM * kOSTV][kWave]) {
   const int I = blockIdx.y, b = blockIdx.x;
   const int nzv = (o.V + 16 * kOSTV - 1) / (16 * kOSTV);
-  const int mz = blockIdx.z / nzv, vz = blockIdx.z % nzv;
+  const int mz = z / nzv, vz = z % nzv;
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const int start = o.seg[2 * I], count = o.seg[2 * I + 1];
   const int per = ((count + o.NB - 1) / o.NB + 15) & ~15;   // multiple of 16 atoms
@@ -1968,9 +1989,20 @@ __global__ __launch_bounds__(256) void k_outer_sum(OuterArgs o) {
     }
 }
 
-dim3 outer_grid(int M, int V, int T) {
+// dW0 and dc^R in one launch: grid z slices [0, nz0) take the first product,
+// the rest the second (each alone leaves most of the GPU idle)
+__global__ __launch_bounds__(256) void k_outer_sum(OuterArgs o0, OuterArgs o1, int nz0) {
+  __shared__ f32x4 red[3][kOSTM * kOSTV][kWave];
+  const int z = blockIdx.z;
+  if (z < nz0)
+    outer_sum_block(o0, z, red);
+  else
+    outer_sum_block(o1, z - nz0, red);
+}
+
+int outer_slices(int M, int V) {
   const int nzm = (M + 16 * kOSTM - 1) / (16 * kOSTM), nzv = (V + 16 * kOSTV - 1) / (16 * kOSTV);
-  return dim3(kOSBlocks, T, nzm * nzv);
+  return nzm * nzv;
 }
 
 // First stage of the final reduction for the wavefront partials (c^A, b0,
@@ -2518,12 +2550,12 @@ void run_neighbors(const Ctx& c, nep_neighbors* nb, int32_t* flags, Prof* pr) {
   else
     NEP_LAUNCH(pr, "neighbors",
                hipLaunchKernelGGL(k_neighbors<false>, dim3(grid1(N, kNbrAPB)), dim3(kNbrThreads), 0, c.st, a));
-  NEP_LAUNCH(pr, "reverse_rad",
-             hipLaunchKernelGGL(k_reverse<32>, dim3(grid1(N, 8)), dim3(256), 0, c.st, N, nb->idx_rad,
-                                nb->cnt_rad, c.m->cap_rad, at<int>(c.ws, c.L.revR)));
-  NEP_LAUNCH(pr, "reverse_ang",
-             hipLaunchKernelGGL(k_reverse<8>, dim3(grid1(N, 32)), dim3(256), 0, c.st, N, nb->idx_ang,
-                                nb->cnt_ang, c.m->cap_ang, at<int>(c.ws, c.L.revA)));
+  {
+    RevArgs r{N, grid1(N, 8), nb->idx_rad, nb->cnt_rad, c.m->cap_rad, at<int>(c.ws, c.L.revR),
+              nb->idx_ang, nb->cnt_ang, c.m->cap_ang, at<int>(c.ws, c.L.revA)};
+    NEP_LAUNCH(pr, "reverse",
+               hipLaunchKernelGGL(k_reverse, dim3(r.nbR + grid1(N, 32)), dim3(256), 0, c.st, r));
+  }
   int* order = at<int>(c.ws, c.L.order);
   int* blk = at<int>(c.ws, c.L.blk);
   int* seg = at<int>(c.ws, c.L.seg);
@@ -2705,16 +2737,13 @@ void run_adjoint(const Ctx& c, const nep_neighbors* nb, const float* params, con
     run_high(c, kHighCoef, h, pr);
     const int* seg = at<int>(c.ws, c.L.seg);
     {
-      OuterArgs o{c.L.Npad, m->hidden, c.o->D, kOSBlocks, seg, a.beta, at<float>(c.ws, c.L.G), a.w1s, a.Gd,
-                  at<float>(c.ws, c.L.w0part)};
-      NEP_LAUNCH(pr, "w0_grad",
-                 hipLaunchKernelGGL(k_outer_sum, outer_grid(o.M, o.V, T), dim3(256), 0, c.st, o));
-    }
-    {
-      OuterArgs o{c.L.Npad, m->n_rad, c.L.TKR, kOSBlocks, seg, a.Gbr, a.FRst, at<float>(c.ws, c.L.Ep), a.FPst,
-                  at<float>(c.ws, c.L.crpart)};
-      NEP_LAUNCH(pr, "crad_grad",
-                 hipLaunchKernelGGL(k_outer_sum, outer_grid(o.M, o.V, T), dim3(256), 0, c.st, o));
+      const OuterArgs ow{c.L.Npad, m->hidden, c.o->D, kOSBlocks, seg, a.beta, at<float>(c.ws, c.L.G), a.w1s,
+                         a.Gd, at<float>(c.ws, c.L.w0part)};
+      const OuterArgs oc{c.L.Npad, m->n_rad, c.L.TKR, kOSBlocks, seg, a.Gbr, a.FRst, at<float>(c.ws, c.L.Ep),
+                         a.FPst, at<float>(c.ws, c.L.crpart)};
+      const int nzw = outer_slices(ow.M, ow.V), nzc = outer_slices(oc.M, oc.V);
+      NEP_LAUNCH(pr, "outer_sums",
+                 hipLaunchKernelGGL(k_outer_sum, dim3(kOSBlocks, T, nzw + nzc), dim3(256), 0, c.st, ow, oc, nzw));
     }
     double* pp = at<double>(c.ws, c.L.pp);
     NEP_LAUNCH(pr, "part_reduce",
