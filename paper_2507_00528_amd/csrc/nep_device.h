@@ -305,18 +305,6 @@ __device__ __forceinline__ int xcd_block() {
   return x * q + min(x, r) + b / kXCD;
 }
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
-}
-
-__device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
-}
-
 // ----------------------------------------- groups of 8 lanes (one atom)
 // Lane l of a wavefront works on atom l/8; DPP moves data inside the group
 // without touching LDS.  DPP reads return 0 from inactive lanes, so these

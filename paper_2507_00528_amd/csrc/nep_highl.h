@@ -126,9 +126,6 @@ __device__ __forceinline__ void high_eval(const HighLane& h, float z, const floa
   gz = dQ * P;
 }
 
-// sum over the 64 lanes (every lane must be active)
-__device__ __forceinline__ float wave_total(float v) { return atoms8_sum(grp8_sum(v)); }
-
 // Sums of V = 4 or 8 values over the 64 lanes, scattered: on return the lanes
 // with (lane & (V - 1)) == v hold the total of value v.  A butterfly over
 // lane bits 0, 1 (and 2) halves the values a lane carries at each step, so the

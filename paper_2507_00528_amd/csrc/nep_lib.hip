@@ -739,32 +739,6 @@ __device__ __forceinline__ PairGeom pair_geom(uint32_t e, const float* __restric
   return g;
 }
 
-struct WaveCtx {
-  int p, i, I, lane, wave;
-  bool valid, any;
-};
-
-__device__ __forceinline__ WaveCtx wave_ctx(const int* __restrict__ order, const int* __restrict__ type, int Npad) {
-  WaveCtx c;
-  c.p = blockIdx.x * blockDim.x + threadIdx.x;
-  c.lane = threadIdx.x & (kWave - 1);
-  c.wave = c.p / kWave;
-  const int iraw = c.p < Npad ? order[c.p] : -1;
-  c.valid = iraw >= 0;
-  const unsigned long long vm = __ballot(c.valid);
-  c.any = vm != 0ull;
-  if (!c.any) {
-    c.i = 0;
-    c.I = 0;
-    return c;
-  }
-  const int lead = __ffsll(vm) - 1;
-  const int ilead = __shfl(iraw, lead, kWave);
-  c.i = c.valid ? iraw : ilead;
-  c.I = __builtin_amdgcn_readfirstlane(type[ilead]);
-  return c;
-}
-
 // LDS written by one lane and read by another lane of the same wavefront: a
 // wavefront's LDS instructions complete in issue order, so it is enough that
 // the compiler keeps every memory access on its side of this point.
