@@ -84,6 +84,11 @@ typedef struct {
  *   type  [n_atom] int32 species in [0, n_types)
  *   tilt  [n_struct*3] float (xy, xz, yz), or NULL when every cell is
  *         orthorhombic (all tilts zero).
+ *   max_atoms  host value: 0, or an upper bound on the atoms of any one
+ *         structure.  It only selects the search: structures of at least 1024
+ *         atoms in cells wide enough are searched through cell lists, and a
+ *         bound below 1024 skips those kernels.  The lists do not depend on
+ *         it; a negative value is NEP_ERR_ARG.
  * Orthorhombic cell (all three tilts zero): each L >= rc_rad and each
  * coordinate in [0, L).  Triclinic cell: each perpendicular width (cell
  * volume over the area of the opposite face) >= rc_rad / (1 - 2e-5) and the
@@ -97,6 +102,7 @@ typedef struct {
   const float* pos;
   const int32_t* type;
   const float* tilt;
+  int32_t max_atoms;
 } nep_batch;
 
 /* Neighbor lists (Eq. 2), one for rc_rad and one for rc_ang (device).

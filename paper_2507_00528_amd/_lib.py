@@ -20,7 +20,8 @@ class NepModel(C.Structure):
 
 class NepBatch(C.Structure):
     _fields_ = [("n_struct", C.c_int32), ("n_atom", C.c_int32), ("atom_offset", C.c_void_p),
-                ("box", C.c_void_p), ("pos", C.c_void_p), ("type", C.c_void_p), ("tilt", C.c_void_p)]
+                ("box", C.c_void_p), ("pos", C.c_void_p), ("type", C.c_void_p), ("tilt", C.c_void_p),
+                ("max_atoms", C.c_int32)]
 
 
 class NepNeighbors(C.Structure):

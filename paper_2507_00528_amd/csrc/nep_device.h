@@ -299,11 +299,11 @@ __device__ __forceinline__ void sym_proj(const Sym3& q, float (&o)[5]) {
 // of logical blocks (a bijection for any grid size): blocks that read the
 // same structure's data then share one L2 instead of filling all eight.
 constexpr int kXCD = 8;
-__device__ __forceinline__ int xcd_block() {
-  const int nb = gridDim.x, b = blockIdx.x;
+__device__ __forceinline__ int xcd_block_of(int b, int nb) {
   const int q = nb / kXCD, r = nb % kXCD, x = b % kXCD;
   return x * q + min(x, r) + b / kXCD;
 }
+__device__ __forceinline__ int xcd_block() { return xcd_block_of(blockIdx.x, gridDim.x); }
 
 // ----------------------------------------- groups of 8 lanes (one atom)
 // Lane l of a wavefront works on atom l/8; DPP moves data inside the group

@@ -31,6 +31,14 @@ struct NbrArgs {
   int* cntA;
   int* astruct;
   int* flags;
+  // cell-list search of large structures (cells = 0: all-pairs only)
+  int cells;
+  int4* grid;    // [S] bins per axis (na, nb, nc, na nb nc), zero: all-pairs
+  int* cell;     // [N+1] bin counts, then bin start offsets; [N] = binned atoms
+  int* cpart;    // [N / kScanChunk + 1] per-chunk counts
+  int* acell;    // [N] bin id of the atom, -1: all-pairs
+  int* aslot;    // [N] slot in the bin
+  float4* cpos;  // [N] binned atoms bin by bin (x, y, z, j)
 };
 
 struct PairLists {

@@ -239,12 +239,33 @@ __device__ __forceinline__ void scan_range(const ScanCtx& c, const PosTile& t, i
   }
 }
 
-// The buffered scan of the single pass.  Outside the shell the decision is
-// made without branches: every candidate's entry is written to the lane's
-// next buffer slot and the count only advances when the pair is inside, so a
+// The buffered decision of one candidate j at (px, py, pz).  Outside the
+// shell it is made without branches: the entry is written to the lane's next
+// buffer slot and the count only advances when the pair is inside, so a
 // later entry overwrites a rejected one (slot kNbrBuf takes the writes once
-// the buffer is full).  Pairs in the shell, and cells too small or too large
-// for the single-image test, branch to the float64 predicate.
+// the buffer is full).  Pairs in the shell branch to the float64 predicate.
+template <bool kTri, class Keep>
+__device__ __forceinline__ void keep_one(const ScanCtx& c, const PosTile& t, int j, float px, float py, float pz,
+                                         uint32_t* buf, int& nR, int& nA, uint32_t& angmask, Keep& keep) {
+  float ex = px - c.xf, ey = py - c.yf, ez = pz - c.zf, kx, ky, kz;
+  min_image<kTri>(c, ex, ey, ez, kx, ky, kz);
+  const float r2 = ex * ex + ey * ey + ez * ez;
+  // k is 0 or +-1 for positions inside the cell (the position flag's
+  // condition), so the shift s = -k always has a code
+  const int code = 13 - (int)fmaf(9.f, kx, fmaf(3.f, ky, kz));
+  const bool decided = r2 < c.inR2;
+  const bool in = decided && !(j == c.i && code == 13);
+  bool ang = r2 < c.inA2;
+  buf[kNbrThreads * min(nR, kNbrBuf)] = ((uint32_t)j << 5) | (uint32_t)(code & 31);
+  if (in && !ang && r2 < c.outA2) ang = image_d2<kTri>(c, px, py, pz, kx, ky, kz) < c.rcA2;
+  angmask |= (in && ang && nR < kNbrBuf) ? (1u << nR) : 0u;
+  nR += in ? 1 : 0;
+  nA += (in && ang) ? 1 : 0;
+  if (!decided && r2 < c.outR2) exact_any<kTri>(c, t, j, keep);
+}
+
+// The buffered scan of the single pass over [jb, je); cells too small or too
+// large for the single-image test take the float64 predicate for every pair.
 template <bool kTri, class Keep>
 __device__ __forceinline__ void scan_keep(const ScanCtx& c, const PosTile& t, int jb, int je, uint32_t* buf,
                                           int& nR, int& nA, uint32_t& angmask, Keep& keep) {
@@ -254,22 +275,7 @@ __device__ __forceinline__ void scan_keep(const ScanCtx& c, const PosTile& t, in
       continue;
     }
     const int q = j - t.base;
-    const float px = t.x[q], py = t.y[q], pz = t.z[q];
-    float ex = px - c.xf, ey = py - c.yf, ez = pz - c.zf, kx, ky, kz;
-    min_image<kTri>(c, ex, ey, ez, kx, ky, kz);
-    const float r2 = ex * ex + ey * ey + ez * ez;
-    // k is 0 or +-1 for positions inside the cell (the position flag's
-    // condition), so the shift s = -k always has a code
-    const int code = 13 - (int)fmaf(9.f, kx, fmaf(3.f, ky, kz));
-    const bool decided = r2 < c.inR2;
-    const bool in = decided && !(j == c.i && code == 13);
-    bool ang = r2 < c.inA2;
-    buf[kNbrThreads * min(nR, kNbrBuf)] = ((uint32_t)j << 5) | (uint32_t)(code & 31);
-    if (in && !ang && r2 < c.outA2) ang = image_d2<kTri>(c, px, py, pz, kx, ky, kz) < c.rcA2;
-    angmask |= (in && ang && nR < kNbrBuf) ? (1u << nR) : 0u;
-    nR += in ? 1 : 0;
-    nA += (in && ang) ? 1 : 0;
-    if (!decided && r2 < c.outR2) exact_any<kTri>(c, t, j, keep);
+    keep_one<kTri>(c, t, j, t.x[q], t.y[q], t.z[q], buf, nR, nA, angmask, keep);
   }
 }
 
@@ -289,6 +295,15 @@ struct CellCheck {
   bool box_ok, pos_ok, fast_ok;
 };
 
+// perpendicular widths V / |b x c|, V / |c x a|, V / |a x b| of the cell
+__device__ __forceinline__ void cell_widths(const ScanCtx& c, double& ha, double& hb, double& hc) {
+  const double bc_x = c.Ly * c.Lz, bc_y = -c.xy * c.Lz, bc_z = c.xy * c.yz - c.Ly * c.xz;
+  const double V = c.Lx * c.Ly * c.Lz;
+  ha = fabs(V) / sqrt(bc_x * bc_x + bc_y * bc_y + bc_z * bc_z);
+  hb = fabs(c.Ly * c.Lz) / sqrt(c.Lz * c.Lz + c.yz * c.yz);
+  hc = fabs(c.Lz);
+}
+
 template <bool kTri>
 __device__ __forceinline__ CellCheck check_cell(const ScanCtx& c, float rcR, float rcA) {
   CellCheck k;
@@ -301,12 +316,8 @@ __device__ __forceinline__ CellCheck check_cell(const ScanCtx& c, float rcR, flo
     k.fast_ok = c.Lxf >= wide && c.Lyf >= wide && c.Lzf >= wide && small;
     return k;
   }
-  // perpendicular widths V / |b x c|, V / |c x a|, V / |a x b|
-  const double bc_x = c.Ly * c.Lz, bc_y = -c.xy * c.Lz, bc_z = c.xy * c.yz - c.Ly * c.xz;
-  const double V = c.Lx * c.Ly * c.Lz;
-  const double ha = fabs(V) / sqrt(bc_x * bc_x + bc_y * bc_y + bc_z * bc_z);
-  const double hb = fabs(c.Ly * c.Lz) / sqrt(c.Lz * c.Lz + c.yz * c.yz);
-  const double hc = fabs(c.Lz);
+  double ha, hb, hc;
+  cell_widths(c, ha, hb, hc);
   const double hmin = fmin(ha, fmin(hb, hc));
   k.box_ok = c.Lxf > 0.f && c.Lyf > 0.f && c.Lzf > 0.f && hmin * (1.0 - 2.0 * kFracTol) >= (double)rcR;
   const double fc = c.zi / c.Lz;
@@ -319,36 +330,21 @@ __device__ __forceinline__ CellCheck check_cell(const ScanCtx& c, float rcR, flo
   return k;
 }
 
+// The scan context of atom i of structure st at (x, y, z): cell, cutoffs and
+// the shell bounds of the single-precision decision.
 template <bool kTri>
-__global__ __launch_bounds__(kNbrThreads) void k_neighbors(NbrArgs a) {
-  __shared__ float tx[kNbrTile], ty[kNbrTile], tz[kNbrTile];
-  __shared__ uint32_t nbuf[kNbrThreads * (kNbrBuf + 1)];
-  __shared__ int jr[2];
-  const int s = threadIdx.x & 7;
-  const int b0 = xcd_block() * kNbrAPB;
-  const int i = b0 + (threadIdx.x >> 3);
-  const bool live = i < a.N;
-  ScanCtx c;
-  c.i = live ? i : a.N - 1;
-  int lo = 0, hi = a.S;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (a.aoff[mid] <= c.i) lo = mid; else hi = mid;
-  }
-  const int st = lo;
-  const int a0 = max(a.aoff[st], 0), a1 = min(a.aoff[st + 1], a.N);
-  // the block's atoms are consecutive, so their structures cover [jr[0], jr[1])
-  if (threadIdx.x == 0) jr[0] = a0;
-  if (i == min(b0 + kNbrAPB - 1, a.N - 1) && s == 0) jr[1] = a1;
+__device__ __forceinline__ CellCheck init_ctx(const NbrArgs& a, int st, int i, float x, float y, float z,
+                                              ScanCtx& c) {
+  c.i = i;
   c.Lxf = a.box[3 * st];
   c.Lyf = a.box[3 * st + 1];
   c.Lzf = a.box[3 * st + 2];
   c.xyf = kTri ? a.tilt[3 * st] : 0.f;
   c.xzf = kTri ? a.tilt[3 * st + 1] : 0.f;
   c.yzf = kTri ? a.tilt[3 * st + 2] : 0.f;
-  c.xf = a.pos[c.i];
-  c.yf = a.pos[a.N + c.i];
-  c.zf = a.pos[2 * a.N + c.i];
+  c.xf = x;
+  c.yf = y;
+  c.zf = z;
   c.xi = c.xf;
   c.yi = c.yf;
   c.zi = c.zf;
@@ -359,6 +355,42 @@ __global__ __launch_bounds__(kNbrThreads) void k_neighbors(NbrArgs a) {
   c.xz = c.xzf;
   c.yz = c.yzf;
   const CellCheck ck = check_cell<kTri>(c, a.rcR, a.rcA);
+  c.rcR = (double)a.rcR;
+  c.rcR2 = c.rcR * c.rcR;  // exact: a float squared in double
+  c.rcA2 = (double)a.rcA * (double)a.rcA;
+  c.ilx = 1.0f / c.Lxf;
+  c.ily = 1.0f / c.Lyf;
+  c.ilz = 1.0f / c.Lzf;
+  c.fast = ck.fast_ok;
+  c.inR2 = (a.rcR - kNbrDelta) * (a.rcR - kNbrDelta);
+  c.outR2 = (a.rcR + kNbrDelta) * (a.rcR + kNbrDelta);
+  c.inA2 = (a.rcA - kNbrDelta) * (a.rcA - kNbrDelta);
+  c.outA2 = (a.rcA + kNbrDelta) * (a.rcA + kNbrDelta);
+  return ck;
+}
+
+template <bool kTri>
+__global__ __launch_bounds__(kNbrThreads) void k_neighbors(NbrArgs a) {
+  __shared__ float tx[kNbrTile], ty[kNbrTile], tz[kNbrTile];
+  __shared__ uint32_t nbuf[kNbrThreads * (kNbrBuf + 1)];
+  __shared__ int jr[2];
+  const int s = threadIdx.x & 7;
+  const int b0 = xcd_block() * kNbrAPB;
+  const int i = b0 + (threadIdx.x >> 3);
+  const bool live = i < a.N;
+  const int ic = live ? i : a.N - 1;
+  int lo = 0, hi = a.S;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (a.aoff[mid] <= ic) lo = mid; else hi = mid;
+  }
+  const int st = lo;
+  const int a0 = max(a.aoff[st], 0), a1 = min(a.aoff[st + 1], a.N);
+  // the block's atoms are consecutive, so their structures cover [jr[0], jr[1])
+  if (threadIdx.x == 0) jr[0] = a0;
+  if (i == min(b0 + kNbrAPB - 1, a.N - 1) && s == 0) jr[1] = a1;
+  ScanCtx c;
+  const CellCheck ck = init_ctx<kTri>(a, st, ic, a.pos[ic], a.pos[a.N + ic], a.pos[2 * a.N + ic], c);
   int fl = 0;
   if (!ck.pos_ok) fl |= FL_POS;
   bool ok = live;
@@ -371,21 +403,13 @@ __global__ __launch_bounds__(kNbrThreads) void k_neighbors(NbrArgs a) {
     const int ti = a.type[i];
     if (ti < 0 || ti >= a.T) fl |= FL_TYPE;
   }
-  c.rcR = (double)a.rcR;
-  c.rcR2 = c.rcR * c.rcR;  // exact: a float squared in double
-  c.rcA2 = (double)a.rcA * (double)a.rcA;
-  c.ilx = 1.0f / c.Lxf;
-  c.ily = 1.0f / c.Lyf;
-  c.ilz = 1.0f / c.Lzf;
-  c.fast = ck.fast_ok;
-  c.inR2 = (a.rcR - kNbrDelta) * (a.rcR - kNbrDelta);
-  c.outR2 = (a.rcR + kNbrDelta) * (a.rcR + kNbrDelta);
-  c.inA2 = (a.rcA - kNbrDelta) * (a.rcA - kNbrDelta);
-  c.outA2 = (a.rcA + kNbrDelta) * (a.rcA + kNbrDelta);
-  const int len = ok ? a1 - a0 : 0;
+  // atoms whose lists the cell search wrote (it leaves acell[i] >= 0)
+  const bool mine = live && !(a.cells && a.acell[ic] >= 0);
+  const int len = ok && mine ? a1 - a0 : 0;
   const int jb = a0 + (len * s) / 8, je = a0 + (len * (s + 1)) / 8;
-  __syncthreads();
-  const int jlo = jr[0], jhi = jr[1];
+  // a block with no atom to scan walks no tiles
+  const bool any = __syncthreads_or(len > 0);
+  const int jlo = jr[0], jhi = any ? jr[1] : jr[0];
   // walks the tiles of [jlo, jhi); this lane scans [b, e) of each
   auto sweep = [&](int b, int e, auto&& scan) {
     for (int t0 = jlo; t0 < jhi; t0 += kNbrTile) {
@@ -432,7 +456,7 @@ __global__ __launch_bounds__(kNbrThreads) void k_neighbors(NbrArgs a) {
   int wR = pR - nR, wA = pA - nA;
   const size_t col = (size_t)c.i;
   const bool spill = nR > kNbrBuf;
-  if (live && !spill) {
+  if (mine && !spill) {
     for (int u = 0; u < nR; ++u) {
       const uint32_t e = mybuf[kNbrThreads * u];
       if (wR + u < a.capR) a.idxR[col * a.capR + wR + u] = e;
@@ -442,7 +466,7 @@ __global__ __launch_bounds__(kNbrThreads) void k_neighbors(NbrArgs a) {
       }
     }
   }
-  if (__syncthreads_or(live && spill)) {
+  if (__syncthreads_or(mine && spill)) {
     auto write = [&](int j, int code, bool ang) {
       const uint32_t e = ((uint32_t)j << 5) | (uint32_t)code;
       if (wR < a.capR) a.idxR[col * a.capR + wR] = e;
@@ -452,16 +476,283 @@ __global__ __launch_bounds__(kNbrThreads) void k_neighbors(NbrArgs a) {
         ++wA;
       }
     };
-    const bool wr = live && spill && wR < a.capR;
+    // angular entries are a subset, so a lane past the radial capacity may
+    // still have angular slots to fill
+    const bool wr = mine && spill && (wR < a.capR || wA < a.capA);
     sweep(wr ? jb : 0, wr ? je : 0,
           [&](const PosTile& t, int b2, int e2) { scan_range<kTri>(c, t, b2, e2, write); });
   }
-  if (live && s == 0) {
+  if (mine && s == 0) {
     a.cntR[i] = totR;
     a.cntA[i] = totA;
     if (totR > a.capR || totA > a.capA) fl |= FL_OVERFLOW;
   }
   if (live && s == 0 && fl) atomicOr(a.flags, fl);
+}
+
+// Cell-list search of large structures.  A structure of at least
+// kCellMinAtoms atoms whose cell takes the single-image decision is cut into
+// na x nb x nc bins along its edge vectors, each bin at least rc + kCellPad
+// thick across (perpendicular width over the bin count), at least 3 bins per
+// axis and at most one bin per atom.  An atom's bin comes from its
+// single-precision fractional coordinates; their error, and the accepted
+// positions up to 1e-5 outside the cell, move an atom by under 0.006 A for
+// cells up to kNbrFastL, so two atoms in bins that are not adjacent along some
+// axis lie more than rc apart in every image.  Each atom then meets as
+// candidates exactly the atoms of its 27 surrounding bins and takes the same
+// per-candidate decision as the all-pairs scan, so its entries are the same.
+// Within rc + delta every j has one image at most (each width is at least
+// 2 (rc + delta)), so an entry's rank among the atom's entries by (j, code)
+// is its canonical slot.
+//
+// Bins of structure n have the ids atom_offset[n] + bin (< atom_offset[n+1]);
+// the bins are counted, scanned into start offsets, and the binned atoms
+// placed bin by bin as (x, y, z, j).  An atom whose lane buffer overflows is
+// left to the all-pairs kernel (acell[i] = -1), which runs afterwards.
+constexpr int kCellMinAtoms = 1024;
+constexpr double kCellPad = 0.05;
+constexpr int kScanChunk = 2048;   // bin ids per block of the offset scan
+
+// bins per axis of structure st, (0, 0, 0, 0) for the all-pairs search
+template <bool kTri>
+__device__ int4 cell_grid(const NbrArgs& a, int st) {
+  const int4 none = make_int4(0, 0, 0, 0);
+  const int n = a.aoff[st + 1] - a.aoff[st];
+  if (n < kCellMinAtoms) return none;
+  ScanCtx c;
+  if (!init_ctx<kTri>(a, st, a.aoff[st], 0.f, 0.f, 0.f, c).fast_ok) return none;
+  double ha, hb, hc;
+  cell_widths(c, ha, hb, hc);
+  // the single-image cells are at most kNbrFastL wide and rc >= 1 A: at most
+  // 512 bins per axis
+  const double w = (double)a.rcR + kCellPad;
+  int na = (int)(ha / w), nb = (int)(hb / w), nc = (int)(hc / w);
+  while ((long long)na * nb * nc > n) {
+    if (na >= nb && na >= nc)
+      --na;
+    else if (nb >= nc)
+      --nb;
+    else
+      --nc;
+  }
+  if (na < 3 || nb < 3 || nc < 3) return none;
+  return make_int4(na, nb, nc, na * nb * nc);
+}
+
+// zeroes the bin counts and sets every structure's bins
+template <bool kTri>
+__global__ __launch_bounds__(256) void k_cell_setup(NbrArgs a) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t <= a.N) a.cell[t] = 0;
+  if (t < a.S) a.grid[t] = cell_grid<kTri>(a, t);
+}
+
+// bin of each atom of a binned structure and its slot in the bin
+template <bool kTri>
+__global__ __launch_bounds__(256) void k_cell_bin(NbrArgs a) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.N) return;
+  int lo = 0, hi = a.S;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (a.aoff[mid] <= i) lo = mid; else hi = mid;
+  }
+  const int st = lo;
+  a.astruct[i] = st;
+  const int4 g = a.grid[st];
+  int bin = -1, slot = 0;
+  if (g.w > 0) {
+    const float x = a.pos[i], y = a.pos[a.N + i], z = a.pos[2 * a.N + i];
+    float fa, fb, fc;
+    if constexpr (kTri) {
+      const float xy = a.tilt[3 * st], xz = a.tilt[3 * st + 1], yz = a.tilt[3 * st + 2];
+      fc = z / a.box[3 * st + 2];
+      fb = (y - yz * fc) / a.box[3 * st + 1];
+      fa = (x - xy * fb - xz * fc) / a.box[3 * st];
+    } else {
+      fa = x / a.box[3 * st];
+      fb = y / a.box[3 * st + 1];
+      fc = z / a.box[3 * st + 2];
+    }
+    // clamped in float (a NaN goes to bin 0; the position flag reports it)
+    const int ia = (int)fminf(fmaxf(floorf(fa * (float)g.x), 0.f), (float)(g.x - 1));
+    const int ib = (int)fminf(fmaxf(floorf(fb * (float)g.y), 0.f), (float)(g.y - 1));
+    const int ic = (int)fminf(fmaxf(floorf(fc * (float)g.z), 0.f), (float)(g.z - 1));
+    bin = a.aoff[st] + (ia * g.y + ib) * g.z + ic;
+    slot = atomicAdd(&a.cell[bin], 1);
+  }
+  a.acell[i] = bin;
+  a.aslot[i] = slot;
+}
+
+// exclusive prefix over 256 threads; returns the block total
+__device__ __forceinline__ int block_exclusive_scan(int v, int& excl, int* red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int u = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += u;
+  }
+  if (lane == 63) red[w] = inc;
+  __syncthreads();
+  int before = 0, total = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    before += q < w ? red[q] : 0;
+    total += red[q];
+  }
+  __syncthreads();
+  excl = before + inc - v;
+  return total;
+}
+
+// per chunk of kScanChunk bin ids: the sum of the counts
+__global__ __launch_bounds__(256) void k_cell_part(int n, const int* __restrict__ cnt, int* __restrict__ part) {
+  __shared__ int red[4];
+  const int b = blockIdx.x * kScanChunk + threadIdx.x * 8;
+  int v = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) v += b + q < n ? cnt[b + q] : 0;
+  int excl;
+  const int tot = block_exclusive_scan(v, excl, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// counts -> start offsets in place over [0, n), and the total at [n]
+__global__ __launch_bounds__(256) void k_cell_start(int n, int* __restrict__ cell, const int* __restrict__ part) {
+  __shared__ int red[4];
+  int off = 0;
+  for (int q = threadIdx.x; q < (int)blockIdx.x; q += 256) off += part[q];
+  int excl;
+  off = block_exclusive_scan(off, excl, red);
+  const int b = blockIdx.x * kScanChunk + threadIdx.x * 8;
+  int v[8], sum = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    v[q] = b + q < n ? cell[b + q] : 0;
+    sum += v[q];
+  }
+  const int tot = block_exclusive_scan(sum, excl, red);
+  int run = off + excl;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    if (b + q < n) cell[b + q] = run;
+    run += v[q];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) cell[n] = off + tot;
+}
+
+// binned atoms bin by bin as (x, y, z, j)
+__global__ __launch_bounds__(256) void k_cell_place(NbrArgs a) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.N) return;
+  const int bin = a.acell[i];
+  if (bin < 0) return;
+  a.cpos[a.cell[bin] + a.aslot[i]] =
+      make_float4(a.pos[i], a.pos[a.N + i], a.pos[2 * a.N + i], __int_as_float(i));
+}
+
+// Lists of the binned atoms, 8 lanes per atom taking the candidates of the 27
+// bins in turn.  Blocks take the atoms in bin order, so a block's atoms share
+// most of their candidates.
+template <bool kTri>
+__global__ __launch_bounds__(kNbrThreads) void k_cell_neighbors(NbrArgs a) {
+  __shared__ uint32_t nbuf[kNbrThreads * (kNbrBuf + 1)];
+  // the first ceil(M / 32) blocks work, renumbered over the XCDs among themselves
+  const int M = a.cell[a.N], nbw = (M + kNbrAPB - 1) / kNbrAPB;
+  if ((int)blockIdx.x >= nbw) return;
+  const int b0 = xcd_block_of(blockIdx.x, nbw) * kNbrAPB;
+  const int s = threadIdx.x & 7;
+  const int k = b0 + (int)(threadIdx.x >> 3);
+  const bool live = k < M;
+  const float4 me = a.cpos[min(k, M - 1)];
+  const int i = __float_as_int(me.w);
+  const int st = a.astruct[i];
+  const int4 g = a.grid[st];
+  ScanCtx c;
+  init_ctx<kTri>(a, st, i, me.x, me.y, me.z, c);   // single-image decision: c.fast holds
+  const int base = a.aoff[st];
+  const int loc = a.acell[i] - base;
+  const int kc = loc % g.z, kb = (loc / g.z) % g.y, ka = loc / (g.y * g.z);
+  const PosTile t{a.pos, a.pos + a.N, a.pos + 2 * a.N, 0};
+  uint32_t* mybuf = nbuf + threadIdx.x;   // slot u at mybuf[kNbrThreads u]
+  int nR = 0, nA = 0;
+  uint32_t angmask = 0;
+  auto keep = [&](int j, int code, bool ang) {
+    if (nR < kNbrBuf) {
+      mybuf[kNbrThreads * nR] = ((uint32_t)j << 5) | (uint32_t)code;
+      angmask |= ang ? (1u << nR) : 0u;
+    }
+    ++nR;
+    nA += ang ? 1 : 0;
+  };
+  // bins kc-1, kc, kc+1 of a row are consecutive ids, split in two runs when
+  // the row wraps
+  // (kc = 0: [0, 1] and [nc-1]; kc = nc-1: [0] and [nc-2, nc-1]; else [kc-1, kc+1])
+  const bool edge = kc == 0 || kc == g.z - 1;
+  const int r0lo = edge ? 0 : kc - 1, r0hi = kc == 0 ? 1 : (edge ? 0 : kc + 1);
+  const int r1lo = kc == 0 ? g.z - 1 : (edge ? g.z - 2 : 1), r1hi = edge ? g.z - 1 : 0;
+  int run = 0;   // candidates before the current run; lane s takes every 8th
+  if (live) {
+    for (int da = -1; da <= 1; ++da) {
+      const int xa = ka + da < 0 ? g.x - 1 : (ka + da == g.x ? 0 : ka + da);
+      for (int db = -1; db <= 1; ++db) {
+        const int yb = kb + db < 0 ? g.y - 1 : (kb + db == g.y ? 0 : kb + db);
+        const int row = base + (xa * g.y + yb) * g.z;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int lo = h ? r1lo : r0lo, hi = h ? r1hi : r0hi;
+          if (lo > hi) continue;
+          const int cb = a.cell[row + lo], ce = a.cell[row + hi + 1];
+          for (int q = cb + ((s - run) & 7); q < ce; q += 8) {
+            const float4 p = a.cpos[q];
+            keep_one<kTri>(c, t, __float_as_int(p.w), p.x, p.y, p.z, mybuf, nR, nA, angmask, keep);
+          }
+          run += ce - cb;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  int most = nR, ntv[8], atv[8];
+  uint32_t mtv[8];
+#pragma unroll
+  for (int d = 1; d < 8; d <<= 1) most = max(most, __shfl_xor(most, d, 8));
+  int totR = 0, totA = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    ntv[q] = __shfl(nR, q, 8);
+    atv[q] = __shfl(nA, q, 8);
+    mtv[q] = __shfl(angmask, q, 8);
+    totR += ntv[q];
+    totA += atv[q];
+  }
+  const bool spill = most > kNbrBuf;
+  if (live && !spill) {
+    const uint32_t* gbuf = nbuf + (threadIdx.x & ~7);
+    const size_t col = (size_t)i;
+    for (int u = 0; u < nR; ++u) {
+      const uint32_t e = mybuf[kNbrThreads * u];
+      int rR = 0, rA = 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        for (int u2 = 0; u2 < ntv[q]; ++u2) {
+          const int lt = gbuf[q + kNbrThreads * u2] < e ? 1 : 0;
+          rR += lt;
+          rA += lt & (int)((mtv[q] >> u2) & 1u);
+        }
+      }
+      if (rR < a.capR) a.idxR[col * a.capR + rR] = e;
+      if (((angmask >> u) & 1u) && rA < a.capA) a.idxA[col * a.capA + rA] = e;
+    }
+    if (s == 0) {
+      a.cntR[i] = totR;
+      a.cntA[i] = totA;
+      if (totR > a.capR || totA > a.capA) atomicOr(a.flags, FL_OVERFLOW);
+    }
+  }
+  if (live && spill && s == 0) a.acell[i] = -1;
 }
 
 // Position of the reverse entry (i, -s) in j's list; LPA lanes per atom take
@@ -2354,7 +2645,8 @@ size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
   int N, S, T, D, Y, H, NR, TKR, Npad, nwaves, nblk, PW, NA, capR, capA;
   size_t order, seg, blk, astruct, revR, revA, G, Sst, Ep, X, eatom, fR, fA, wv, F, fbar, Es, Ws, eps, wbar, lpart,
-      Gd, FRst, FPst, Gbr, beta, w1s, part, pp, w0part, crpart, Sh, Sdh, cur_step, total;
+      Gd, FRst, FPst, Gbr, beta, w1s, part, pp, w0part, crpart, Sh, Sdh, cgrid, cell, cpart, acell, aslot, cpos,
+      cur_step, total;
 };
 
 Layout make_layout(const nep_model* m, const Ops* o, int S, int N) {
@@ -2417,6 +2709,12 @@ Layout make_layout(const nep_model* m, const Ops* o, int S, int N) {
   L.crpart = take(4 * (size_t)L.T * kOSBlocks * L.NR * L.TKR);
   L.Sh = take(4 * (size_t)Np * L.NA * o->YH);
   L.Sdh = take(4 * (size_t)Np * L.NA * o->YH);
+  L.cgrid = take(16 * Ss);
+  L.cell = take(4 * (Nn + 1));
+  L.cpart = take(4 * (Nn / kScanChunk + 1));
+  L.acell = take(4 * Nn);
+  L.aslot = take(4 * Nn);
+  L.cpos = take(16 * Nn);
   L.cur_step = take(4);
   L.total = off;
   return L;
@@ -2432,6 +2730,7 @@ int check_batch(const nep_batch* b) {
   if (b->n_struct == 0 && b->n_atom != 0) return NEP_ERR_ARG;
   if (b->n_struct > 0 && (!b->atom_offset || !b->box)) return NEP_ERR_ARG;
   if (b->n_atom > 0 && (!b->pos || !b->type)) return NEP_ERR_ARG;
+  if (b->max_atoms < 0) return NEP_ERR_ARG;
   return NEP_OK;
 }
 
@@ -2518,6 +2817,38 @@ void run_neighbors(const Ctx& c, nep_neighbors* nb, int32_t* flags, Prof* pr) {
   a.cntA = nb->cnt_ang;
   a.astruct = at<int>(c.ws, c.L.astruct);
   a.flags = flags;
+  // the cell-list kernels run unless the caller's bound rules out every structure
+  const int S = c.b->n_struct;
+  a.cells = N >= kCellMinAtoms && (c.b->max_atoms == 0 || c.b->max_atoms >= kCellMinAtoms);
+  a.grid = at<int4>(c.ws, c.L.cgrid);
+  a.cell = at<int>(c.ws, c.L.cell);
+  a.cpart = at<int>(c.ws, c.L.cpart);
+  a.acell = at<int>(c.ws, c.L.acell);
+  a.aslot = at<int>(c.ws, c.L.aslot);
+  a.cpos = at<float4>(c.ws, c.L.cpos);
+  if (a.cells) {
+    const int nch = grid1(N, kScanChunk);
+    if (a.tilt) {
+      NEP_LAUNCH(pr, "cell_setup",
+                 hipLaunchKernelGGL(k_cell_setup<true>, dim3(grid1(max(N + 1, S), 256)), dim3(256), 0, c.st, a));
+      NEP_LAUNCH(pr, "cell_bin", hipLaunchKernelGGL(k_cell_bin<true>, dim3(grid1(N, 256)), dim3(256), 0, c.st, a));
+    } else {
+      NEP_LAUNCH(pr, "cell_setup",
+                 hipLaunchKernelGGL(k_cell_setup<false>, dim3(grid1(max(N + 1, S), 256)), dim3(256), 0, c.st, a));
+      NEP_LAUNCH(pr, "cell_bin", hipLaunchKernelGGL(k_cell_bin<false>, dim3(grid1(N, 256)), dim3(256), 0, c.st, a));
+    }
+    NEP_LAUNCH(pr, "cell_part",
+               hipLaunchKernelGGL(k_cell_part, dim3(nch), dim3(256), 0, c.st, N, a.cell, a.cpart));
+    NEP_LAUNCH(pr, "cell_start",
+               hipLaunchKernelGGL(k_cell_start, dim3(nch), dim3(256), 0, c.st, N, a.cell, a.cpart));
+    NEP_LAUNCH(pr, "cell_place", hipLaunchKernelGGL(k_cell_place, dim3(grid1(N, 256)), dim3(256), 0, c.st, a));
+    if (a.tilt)
+      NEP_LAUNCH(pr, "cell_neighbors", hipLaunchKernelGGL(k_cell_neighbors<true>, dim3(grid1(N, kNbrAPB)),
+                                                          dim3(kNbrThreads), 0, c.st, a));
+    else
+      NEP_LAUNCH(pr, "cell_neighbors", hipLaunchKernelGGL(k_cell_neighbors<false>, dim3(grid1(N, kNbrAPB)),
+                                                          dim3(kNbrThreads), 0, c.st, a));
+  }
   if (a.tilt)
     NEP_LAUNCH(pr, "neighbors",
                hipLaunchKernelGGL(k_neighbors<true>, dim3(grid1(N, kNbrAPB)), dim3(kNbrThreads), 0, c.st, a));

@@ -118,12 +118,14 @@ class DeviceBatch:
         tilt = getattr(batch, "tilt", None)
         self.tilt = (torch.as_tensor(np.asarray(tilt, np.float32), device=device)
                      if tilt is not None and np.any(np.asarray(tilt) != 0) else None)
+        # largest structure: batches of small structures skip the cell-list kernels
+        self.max_atoms = int(np.diff(np.asarray(batch.atom_offset)).max()) if self.n_struct else 0
 
     def c(self):
         return _lib.NepBatch(self.n_struct, self.n_atom, self.atom_offset.data_ptr(), self.box.data_ptr(),
                              self.pos.data_ptr() if self.n_atom else None,
                              self.type.data_ptr() if self.n_atom else None,
-                             self.tilt.data_ptr() if self.tilt is not None else None)
+                             self.tilt.data_ptr() if self.tilt is not None else None, self.max_atoms)
 
 
 class Neighbors:

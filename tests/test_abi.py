@@ -70,6 +70,8 @@ def test_validation_rejects_before_launch():
     b2 = _lib.NepBatch(0, 0, None, None, None, None)
     assert lib.nep_build_neighbors(C.byref(m), C.byref(b2), C.byref(nb), None, None, None) == -6  # no workspace
     assert lib.nep_build_neighbors(C.byref(m), C.byref(b2), C.byref(nb), C.c_void_p(0x1001), None, None) == -6
+    b3 = _lib.NepBatch(0, 0, None, None, None, None, None, -1)   # negative structure-size bound
+    assert lib.nep_build_neighbors(C.byref(m), C.byref(b3), C.byref(nb), None, None, None) == -1
     assert lib.nep_adam_step(10, None, None, None, None, 1e-3, 0.9, 0.999, 1e-8, 0, None) == -1  # step < 1
     assert lib.nep_train_step_graph_launch(None, None) == -1
 

@@ -1,0 +1,161 @@
+"""The cell-list search of large structures against the all-pairs search and
+the FP64 oracle.  Structures of at least 1024 atoms in cells at least
+3 (rc + 0.05) wide and 2 (rc + delta) across are binned; the batch's largest
+structure size, passed with the batch, below 1024 forces the all-pairs search
+for the same batch.  Lists must agree bit for bit: counts, canonical order,
+truncation at the capacity and the flags.
+
+Cases: three bins along one axis (every bin row wraps), a tilted cell, large
+cells too narrow to bin (one below the single-image width, one below three
+bins) and small structures in the same batch, a dense cluster whose atoms
+have more entries than the lane buffers hold (left to the all-pairs kernel),
+and the same cluster past the list capacity."""
+import numpy as np
+import pytest
+
+from oracle import neighbor_pairs
+from paper_2507_00528_amd import synth
+
+pytestmark = pytest.mark.gpu
+RC = synth.SIZES_LARGE.rc_rad
+RCA = synth.SIZES_LARGE.rc_ang
+
+
+def uniform(rng, n, box, tilt=None, name="uniform"):
+    """n atoms uniform in the cell (no minimum distance: the search does not need one)."""
+    box = np.asarray(box, np.float32)
+    H = synth.cell_matrix(box, tilt)
+    x = rng.uniform(0.0, 1.0, (n, 3)) @ H.T
+    t = None if tilt is None else np.asarray(tilt, np.float32)
+    return synth.Structure(synth.wrap_cell32(x, box, t), box, synth.assign_types(rng, n), name, t)
+
+
+def clustered(rng, n, L, m, radius):
+    """n atoms in a cube of edge L, m of them packed in a ball of the given radius."""
+    x = rng.uniform(0.0, L, (n, 3))
+    d = rng.normal(size=(m, 3))
+    d *= (radius * rng.uniform(0, 1, (m, 1)) ** (1 / 3)) / np.linalg.norm(d, axis=1, keepdims=True)
+    x[:m] = L / 2 + d
+    box = np.full(3, L, np.float32)
+    return synth.Structure(synth.wrap32(x, box), box, synth.assign_types(rng, n), "cluster")
+
+
+def mixed_batch():
+    rng = np.random.default_rng(77)
+    sts = [
+        uniform(rng, 1200, (18.3, 30.0, 70.0)),                 # 3 bins along a
+        synth.config_structures("c0")[0],                         # small: all-pairs
+        uniform(rng, 1200, (40.0, 40.0, 18.2)),                 # 3 bins along c
+        uniform(rng, 2500, (44.0, 42.0, 45.0), (11.0, -9.0, 12.5), "tilted"),
+        uniform(rng, 1300, (12.0, 60.0, 60.0)),                 # below 2 (rc + delta): float64 path
+        uniform(rng, 1100, (15.0, 48.0, 48.0)),                 # two bins across a: all-pairs
+        synth.config_structures("c0")[1],
+    ]
+    return sts
+
+
+def build(sts, hint, cap_rad=64, cap_ang=32):
+    import torch
+    from paper_2507_00528_amd import nep
+    b = synth.Batch(sts)
+    model = nep.Model.of(synth.SIZES_LARGE, cap_rad, cap_ang)
+    db = nep.DeviceBatch(b)
+    if hint is not None:
+        db.max_atoms = hint
+    nb = nep.Neighbors(model, b.n_atom)
+    ws = nep.workspace(model, b.n_struct, b.n_atom)
+    fl = torch.zeros(1, dtype=torch.int32, device="cuda")
+    nep.build_neighbors(model, db, nb, ws, fl)
+    torch.cuda.synchronize()
+    out = dict(flags=int(fl.item()))
+    for which, cap in (("rad", cap_rad), ("ang", cap_ang)):
+        cnt = getattr(nb, f"cnt_{which}").cpu().numpy()
+        idx = getattr(nb, f"idx_{which}").cpu().numpy().view(np.uint32).reshape(b.n_atom, cap)
+        out[which] = (cnt, [idx[i, :min(c, cap)].tolist() for i, c in enumerate(cnt)])
+    return out, (model, db, nb, ws, fl, b)
+
+
+def oracle_rows(sts, which):
+    rc = RC if which == "rad" else RCA
+    rows, base = [], 0
+    for st in sts:
+        p = neighbor_pairs(st.pos, st.box, rc, tilt32=st.tilt)
+        lists = [[] for _ in range(st.n)]
+        for i, j, c in p.tolist():
+            lists[i].append(((base + j) << 5) | c)
+        rows.extend(lists)
+        base += st.n
+    return rows
+
+
+def ran_cell_kernels(model, db, nb, ws, fl, b):
+    """Kernel names of one profiled evaluation (it rebuilds the lists)."""
+    import torch
+    from paper_2507_00528_amd import nep
+    S, N = b.n_struct, b.n_atom
+    labels = nep.Labels(torch.zeros(S, device="cuda"), torch.zeros(3 * N, device="cuda"),
+                        torch.zeros(6 * S, device="cuda"))
+    params = torch.tensor(synth.draw_params(synth.SIZES_LARGE.n_params, 3), device="cuda")
+    loss = torch.zeros(4, device="cuda")
+    grad = torch.zeros(synth.SIZES_LARGE.n_params, device="cuda")
+    names = [k for k, _ in nep.profile_loss_grad(model, db, nb, params, labels, (1.0, 1.0, 0.1), loss, grad, ws, fl)]
+    return "cell_neighbors" in names
+
+
+def test_cell_search_equals_all_pairs_and_oracle():
+    sts = mixed_batch()
+    print(f"[cells] sizes={[st.n for st in sts]}", flush=True)
+    cell, dev = build(sts, None)
+    pairs, _ = build(sts, 1)
+    assert cell["flags"] == 0 and pairs["flags"] == 0
+    for which in ("rad", "ang"):
+        assert np.array_equal(cell[which][0], pairs[which][0])
+        assert cell[which][1] == pairs[which][1]
+        ref = oracle_rows(sts, which)
+        assert cell[which][0].tolist() == [len(r) for r in ref]
+        assert cell[which][1] == ref
+    assert ran_cell_kernels(*dev)
+
+
+def test_cell_search_rebuild_on_a_used_workspace():
+    """Bin counts start from zero on every call: a second build of the same
+    batch, and of a smaller batch on the same workspace, match fresh builds."""
+    import torch
+    from paper_2507_00528_amd import nep
+    sts = mixed_batch()
+    first, (model, db, nb, ws, fl, b) = build(sts, None)
+    nep.build_neighbors(model, db, nb, ws, fl)
+    torch.cuda.synchronize()
+    assert np.array_equal(nb.cnt_rad.cpu().numpy(), first["rad"][0])
+    small = sts[2:4]
+    b2 = synth.Batch(small)
+    db2 = nep.DeviceBatch(b2)
+    nb2 = nep.Neighbors(model, b2.n_atom)
+    nep.build_neighbors(model, db2, nb2, ws, fl)
+    torch.cuda.synchronize()
+    ref, _ = build(small, 1)
+    cnt = nb2.cnt_rad.cpu().numpy()
+    idx = nb2.idx_rad.cpu().numpy().view(np.uint32).reshape(b2.n_atom, model.cap_rad)
+    assert np.array_equal(cnt, ref["rad"][0])
+    assert [idx[i, :c].tolist() for i, c in enumerate(cnt)] == ref["rad"][1]
+
+
+@pytest.mark.parametrize("cap", [(320, 320), (64, 32)])
+def test_dense_cluster_spills_to_the_all_pairs_kernel(cap):
+    """260 atoms in a ball of radius 2.9 A: each has 259 neighbors within rc,
+    more than the 8 lane buffers hold, so the all-pairs kernel writes them;
+    with the default capacity the lists also overflow."""
+    rng = np.random.default_rng(5)
+    st = clustered(rng, 1500, 40.0, 260, 2.9)
+    cell, _ = build([st], None, *cap)
+    pairs, _ = build([st], 1, *cap)
+    assert cell["flags"] == pairs["flags"]
+    from paper_2507_00528_amd import nep
+    assert bool(cell["flags"] & nep.NEP_FLAG_NBR_OVERFLOW) == (cap[0] < 320)
+    for which, c in zip(("rad", "ang"), cap):
+        assert np.array_equal(cell[which][0], pairs[which][0])
+        assert cell[which][1] == pairs[which][1]
+        ref = oracle_rows([st], which)
+        assert cell[which][0].tolist() == [len(r) for r in ref]
+        assert cell[which][1] == [r[:c] for r in ref]
+    assert cell["rad"][0][:260].min() >= 259
