@@ -369,7 +369,9 @@ __device__ __forceinline__ CellCheck init_ctx(const NbrArgs& a, int st, int i, f
   return ck;
 }
 
-template <bool kTri>
+// kCells: the cell search ran before and wrote the lists of the atoms with
+// acell[i] >= 0
+template <bool kTri, bool kCells>
 __global__ __launch_bounds__(kNbrThreads) void k_neighbors(NbrArgs a) {
   __shared__ float tx[kNbrTile], ty[kNbrTile], tz[kNbrTile];
   __shared__ uint32_t nbuf[kNbrThreads * (kNbrBuf + 1)];
@@ -404,11 +406,15 @@ __global__ __launch_bounds__(kNbrThreads) void k_neighbors(NbrArgs a) {
     if (ti < 0 || ti >= a.T) fl |= FL_TYPE;
   }
   // atoms whose lists the cell search wrote (it leaves acell[i] >= 0)
-  const bool mine = live && !(a.cells && a.acell[ic] >= 0);
+  const bool mine = live && !(kCells && a.acell[ic] >= 0);
   const int len = ok && mine ? a1 - a0 : 0;
   const int jb = a0 + (len * s) / 8, je = a0 + (len * (s + 1)) / 8;
-  // a block with no atom to scan walks no tiles
-  const bool any = __syncthreads_or(len > 0);
+  // after the cell search, a block with no atom left to scan walks no tiles
+  bool any = true;
+  if constexpr (kCells)
+    any = __syncthreads_or(len > 0);
+  else
+    __syncthreads();
   const int jlo = jr[0], jhi = any ? jr[1] : jr[0];
   // walks the tiles of [jlo, jhi); this lane scans [b, e) of each
   auto sweep = [&](int b, int e, auto&& scan) {
@@ -755,12 +761,52 @@ __global__ __launch_bounds__(kNbrThreads) void k_cell_neighbors(NbrArgs a) {
   if (live && spill && s == 0) a.acell[i] = -1;
 }
 
-// Position of the reverse entry (i, -s) in j's list; LPA lanes per atom take
-// slots s, s + LPA, ... (32 for the radial lists, 8 for the shorter angular
-// ones).  The search over j's sorted list takes two dependent rounds instead
-// of log2(cap): the last entry of every run of 8 (independent loads) picks
-// the run, then the run's 8 entries (two 16-byte loads) give the position.
-// Entries past j's count are treated as larger than any key.
+// Position of the key in a sorted row holding m valid entries (of cap), -1
+// if absent.  The last entry of every run of 8 (four independent loads at a
+// time) picks the run, then the run's 8 entries (two 16-byte loads) give the
+// position.  Entries past m are treated as larger than any key.
+__device__ __forceinline__ int row_find(const uint32_t* __restrict__ row, int m, int cap, uint32_t key) {
+  const int nrun = (m + 7) >> 3;
+  int below = 0;
+  for (int r0 = 0; r0 < nrun; r0 += 4) {
+    uint32_t last[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      // unconditional loads from inside the row, then the mask
+      const int q = 8 * (r0 + u) + 7;
+      const uint32_t x = row[min(q, cap - 1)];
+      last[u] = (r0 + u < nrun && q < m) ? x : 0xFFFFFFFFu;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) below += (r0 + u < nrun && last[u] < key) ? 1 : 0;
+  }
+  int pos = -1;
+  if (below < nrun) {
+    const int b = 8 * below;   // the key, if present, lies in entries b .. b + 7
+    uint32_t v[8];
+    if (b + 8 <= cap && (((uintptr_t)(row + b)) & 15) == 0) {
+      const uint4 x = *reinterpret_cast<const uint4*>(row + b);
+      const uint4 y = *reinterpret_cast<const uint4*>(row + b + 4);
+      v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+      v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
+    } else {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = b + u < cap ? row[b + u] : 0xFFFFFFFFu;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (b + u < m && v[u] == key) pos = b + u;
+  }
+  return pos;
+}
+
+// Reverse index: for entry k = (j, s) of atom i, the position of (i, -s) in
+// j's list (-1 if the capacity cut it off).  The two entries of a pair are
+// found by one search: the one with the larger key, (j, s) > (i, self) (j > i,
+// or j = i and s past the zero shift), searches j's list and writes both
+// slots.  Those entries are the tail of i's sorted list, so LPA lanes per
+// atom take only them; an entry below (i, self) searches for itself only
+// when its partner may be missing, i.e. j's list overflowed.
 template <int LPA>
 __device__ __forceinline__ void reverse_block(int blk, int N, const uint32_t* __restrict__ idx,
                                               const int* __restrict__ cnt, int cap, int* __restrict__ rev) {
@@ -768,48 +814,30 @@ __device__ __forceinline__ void reverse_block(int blk, int N, const uint32_t* __
   const int i = blk * (256 / LPA) + threadIdx.x / LPA;
   if (i >= N) return;
   const int n = min(cnt[i], cap);
+  const uint32_t self = ((uint32_t)i << 5) | 13u;
+  const uint32_t* li = idx + (size_t)i * cap;
+  int low = 0;
   for (int k = s; k < n; k += LPA) {
-    const size_t o = (size_t)i * cap + k;
-    const uint32_t e = idx[o];
+    const uint32_t e = li[k];
+    if (e < self) {
+      ++low;
+      const int j = (int)(e >> 5);
+      if (cnt[j] > cap)
+        rev[(size_t)i * cap + k] = row_find(idx + (size_t)j * cap, cap, cap, ((uint32_t)i << 5) | (26u - (e & 31u)));
+    }
+  }
+#pragma unroll
+  for (int d = 1; d < LPA; d <<= 1) low += __shfl_xor(low, d, LPA);
+  for (int k = low + s; k < n; k += LPA) {
+    const uint32_t e = li[k];
     const int j = (int)(e >> 5);
-    const uint32_t key = ((uint32_t)i << 5) | (26u - (e & 31u));
-    const uint32_t* lj = idx + (size_t)j * cap;
-    const int m = min(cnt[j], cap);
-    // runs of 8 entries wholly below the key
-    const int nrun = (m + 7) >> 3;
-    int below = 0;
-    for (int r0 = 0; r0 < nrun; r0 += 8) {
-      uint32_t last[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        // unconditional loads from inside j's row, then the mask
-        const int q = 8 * (r0 + u) + 7;
-        const uint32_t x = lj[min(q, cap - 1)];
-        last[u] = (r0 + u < nrun && q < m) ? x : 0xFFFFFFFFu;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) below += (r0 + u < nrun && last[u] < key) ? 1 : 0;
-    }
-    int pos = -1;
-    if (below < nrun) {
-      const int b = 8 * below;   // the key, if present, lies in entries b .. b + 7
-      uint32_t v[8];
-      if (b + 8 <= cap && (((uintptr_t)(lj + b)) & 15) == 0) {
-        const uint4 x = *reinterpret_cast<const uint4*>(lj + b);
-        const uint4 y = *reinterpret_cast<const uint4*>(lj + b + 4);
-        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
-        v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
-      } else {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = b + u < cap ? lj[b + u] : 0xFFFFFFFFu;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (b + u < m && v[u] == key) pos = b + u;
-    }
-    rev[o] = pos;
+    const int pos = row_find(idx + (size_t)j * cap, min(cnt[j], cap), cap, ((uint32_t)i << 5) | (26u - (e & 31u)));
+    rev[(size_t)i * cap + k] = pos;
+    if (pos >= 0) rev[(size_t)j * cap + pos] = k;
   }
 }
+
+constexpr int kRevLPAR = 16, kRevLPAA = 4;   // lanes per atom: radial, angular lists
 
 // Both lists in one launch (they are independent, and neither fills the GPU
 // alone): the first nbR blocks, in XCD-aware order, take the radial list.
@@ -828,9 +856,9 @@ struct RevArgs {
 __global__ __launch_bounds__(256) void k_reverse(RevArgs a) {
   const int b = xcd_block();
   if (b < a.nbR)
-    reverse_block<32>(b, a.N, a.idxR, a.cntR, a.capR, a.revR);
+    reverse_block<kRevLPAR>(b, a.N, a.idxR, a.cntR, a.capR, a.revR);
   else
-    reverse_block<8>(b - a.nbR, a.N, a.idxA, a.cntA, a.capA, a.revA);
+    reverse_block<kRevLPAA>(b - a.nbR, a.N, a.idxA, a.cntA, a.capA, a.revA);
 }
 
 // ============================================================ species order
@@ -1613,17 +1641,29 @@ struct StructArgs {
   float* wbar;
   float* fbar;
   double* lpart;  // [S][3]
+  // structures of at least 2 kStructChunk atoms are summed from chunk partials
+  int split;
+  double* spart;  // [N / kStructChunk + 1][2][8]
 };
 
-__global__ __launch_bounds__(kRedBlk) void k_struct(StructArgs a) {
-  __shared__ double red[8][kRedBlk];
-  const int s = blockIdx.x;
-  const int a0 = a.aoff[s], a1 = a.aoff[s + 1];
+constexpr int kStructChunk = 1024;
+
+__device__ __forceinline__ int find_struct(const int* __restrict__ aoff, int S, int i) {
+  int lo = 0, hi = S;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (aoff[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Sums over atoms [lo, hi) of one structure: energy, the six virial
+// components and the squared force error (acc[0..7]); writes F-bar.
+__device__ __forceinline__ void struct_accumulate(const StructArgs& a, int lo, int hi, double* acc) {
   const int N = a.N;
-  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const bool lab = a.Et != nullptr;
   const float cf = 2.0f * a.lf / (3.0f * (float)max(N, 1));
-  for (int i = a0 + threadIdx.x; i < a1; i += kRedBlk) {
+  for (int i = lo + threadIdx.x; i < hi; i += kRedBlk) {
     acc[0] += a.eatom[i];
 #pragma unroll
     for (int c = 0; c < 6; ++c) acc[1 + c] += a.wv[(size_t)c * N + i];
@@ -1636,6 +1676,10 @@ __global__ __launch_bounds__(kRedBlk) void k_struct(StructArgs a) {
       }
     }
   }
+}
+
+// block tree sum of acc[0..7]; the result is in red[q][0]
+__device__ __forceinline__ void struct_reduce(double (*red)[kRedBlk], const double* acc) {
 #pragma unroll
   for (int q = 0; q < 8; ++q) red[q][threadIdx.x] = acc[q];
   __syncthreads();
@@ -1645,6 +1689,45 @@ __global__ __launch_bounds__(kRedBlk) void k_struct(StructArgs a) {
       for (int q = 0; q < 8; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + st];
     __syncthreads();
   }
+}
+
+// Chunk partials of the large structures: a chunk of kStructChunk atoms
+// meets at most two structures of 2 kStructChunk atoms or more, those of its
+// first and last atoms (slots 0 and 1).
+__global__ __launch_bounds__(kRedBlk) void k_struct_part(StructArgs a) {
+  __shared__ double red[8][kRedBlk];
+  const int c0 = blockIdx.x * kStructChunk, c1 = min(c0 + kStructChunk, a.N);
+  const int sa = find_struct(a.aoff, a.S, c0), sb = find_struct(a.aoff, a.S, c1 - 1);
+  for (int h = 0; h < 2; ++h) {
+    const int st = h ? sb : sa;
+    if (h && sb == sa) break;
+    const int a0 = a.aoff[st], a1 = a.aoff[st + 1];
+    if (a1 - a0 < 2 * kStructChunk) continue;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    struct_accumulate(a, max(a0, c0), min(a1, c1), acc);
+    struct_reduce(red, acc);
+    if (threadIdx.x < 8) a.spart[(2 * (size_t)blockIdx.x + h) * 8 + threadIdx.x] = red[threadIdx.x][0];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kRedBlk) void k_struct(StructArgs a) {
+  __shared__ double red[8][kRedBlk];
+  const int s = blockIdx.x;
+  const int a0 = a.aoff[s], a1 = a.aoff[s + 1];
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const bool lab = a.Et != nullptr;
+  if (a.split && a1 - a0 >= 2 * kStructChunk) {
+    // chunk b holds this structure in slot 0 if it starts at or before the chunk
+    for (int b = a0 / kStructChunk + threadIdx.x; b <= (a1 - 1) / kStructChunk; b += kRedBlk) {
+      const int h = a0 > b * kStructChunk ? 1 : 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] += a.spart[(2 * (size_t)b + h) * 8 + q];
+    }
+  } else {
+    struct_accumulate(a, a0, a1, acc);
+  }
+  struct_reduce(red, acc);
   if (threadIdx.x == 0) {
     const double E = red[0][0];
     a.Es[s] = (float)E;
@@ -2645,7 +2728,7 @@ size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
   int N, S, T, D, Y, H, NR, TKR, Npad, nwaves, nblk, PW, NA, capR, capA;
   size_t order, seg, blk, astruct, revR, revA, G, Sst, Ep, X, eatom, fR, fA, wv, F, fbar, Es, Ws, eps, wbar, lpart,
-      Gd, FRst, FPst, Gbr, beta, w1s, part, pp, w0part, crpart, Sh, Sdh, cgrid, cell, cpart, acell, aslot, cpos,
+      Gd, FRst, FPst, Gbr, beta, w1s, part, pp, w0part, crpart, Sh, Sdh, cgrid, cell, cpart, acell, aslot, cpos, spart,
       cur_step, total;
 };
 
@@ -2715,6 +2798,7 @@ Layout make_layout(const nep_model* m, const Ops* o, int S, int N) {
   L.acell = take(4 * Nn);
   L.aslot = take(4 * Nn);
   L.cpos = take(16 * Nn);
+  L.spart = take(8 * 16 * (Nn / kStructChunk + 1));
   L.cur_step = take(4);
   L.total = off;
   return L;
@@ -2849,17 +2933,16 @@ void run_neighbors(const Ctx& c, nep_neighbors* nb, int32_t* flags, Prof* pr) {
       NEP_LAUNCH(pr, "cell_neighbors", hipLaunchKernelGGL(k_cell_neighbors<false>, dim3(grid1(N, kNbrAPB)),
                                                           dim3(kNbrThreads), 0, c.st, a));
   }
-  if (a.tilt)
-    NEP_LAUNCH(pr, "neighbors",
-               hipLaunchKernelGGL(k_neighbors<true>, dim3(grid1(N, kNbrAPB)), dim3(kNbrThreads), 0, c.st, a));
-  else
-    NEP_LAUNCH(pr, "neighbors",
-               hipLaunchKernelGGL(k_neighbors<false>, dim3(grid1(N, kNbrAPB)), dim3(kNbrThreads), 0, c.st, a));
   {
-    RevArgs r{N, grid1(N, 8), nb->idx_rad, nb->cnt_rad, c.m->cap_rad, at<int>(c.ws, c.L.revR),
+    auto* k = a.tilt ? (a.cells ? k_neighbors<true, true> : k_neighbors<true, false>)
+                     : (a.cells ? k_neighbors<false, true> : k_neighbors<false, false>);
+    NEP_LAUNCH(pr, "neighbors", hipLaunchKernelGGL(k, dim3(grid1(N, kNbrAPB)), dim3(kNbrThreads), 0, c.st, a));
+  }
+  {
+    RevArgs r{N, grid1(N, 256 / kRevLPAR), nb->idx_rad, nb->cnt_rad, c.m->cap_rad, at<int>(c.ws, c.L.revR),
               nb->idx_ang, nb->cnt_ang, c.m->cap_ang, at<int>(c.ws, c.L.revA)};
     NEP_LAUNCH(pr, "reverse",
-               hipLaunchKernelGGL(k_reverse, dim3(r.nbR + grid1(N, 32)), dim3(256), 0, c.st, r));
+               hipLaunchKernelGGL(k_reverse, dim3(r.nbR + grid1(N, 256 / kRevLPAA)), dim3(256), 0, c.st, r));
   }
   int* order = at<int>(c.ws, c.L.order);
   int* blk = at<int>(c.ws, c.L.blk);
@@ -2988,6 +3071,12 @@ void run_forward(const Ctx& c, const nep_neighbors* nb, const float* params, flo
     s.wbar = at<float>(c.ws, c.L.wbar);
     s.fbar = at<float>(c.ws, c.L.fbar);
     s.lpart = at<double>(c.ws, c.L.lpart);
+    // large structures take chunk partials first, unless the caller's bound rules them out
+    s.split = N >= 2 * kStructChunk && (c.b->max_atoms == 0 || c.b->max_atoms >= 2 * kStructChunk);
+    s.spart = at<double>(c.ws, c.L.spart);
+    if (s.split)
+      NEP_LAUNCH(pr, "struct_part",
+                 hipLaunchKernelGGL(k_struct_part, dim3(grid1(N, kStructChunk)), dim3(kRedBlk), 0, c.st, s));
     NEP_LAUNCH(pr, "struct_sums", hipLaunchKernelGGL(k_struct, dim3(S), dim3(kRedBlk), 0, c.st, s));
     // with defer_loss the adjoint's first reduction launch sums the loss
     if (lab && !defer_loss)

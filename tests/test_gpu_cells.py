@@ -9,7 +9,8 @@ Cases: three bins along one axis (every bin row wraps), a tilted cell, large
 cells too narrow to bin (one below the single-image width, one below three
 bins) and small structures in the same batch, a dense cluster whose atoms
 have more entries than the lane buffers hold (left to the all-pairs kernel),
-and the same cluster past the list capacity."""
+and the same cluster past the list capacity.  Also the per-structure sums of
+large structures from chunk partials against single-block sums."""
 import numpy as np
 import pytest
 
@@ -159,3 +160,48 @@ def test_dense_cluster_spills_to_the_all_pairs_kernel(cap):
         assert cell[which][0].tolist() == [len(r) for r in ref]
         assert cell[which][1] == [r[:c] for r in ref]
     assert cell["rad"][0][:260].min() >= 259
+
+
+def test_split_structure_sums_match_single_block_sums():
+    """Structures of 2048+ atoms are summed from 1024-atom chunk partials.
+    Here one chunk holds the end of one large structure and the start of the
+    next, and a small structure sits between two large ones.  Energies,
+    virials, loss and gradient match the single-block sums of the same batch
+    (bound below 1024) to FP64-reordering precision; forces bit for bit."""
+    import torch
+    from paper_2507_00528_amd import nep
+    rng = np.random.default_rng(9)
+    sts = [uniform(rng, 3000, (46.0, 46.0, 45.7)), uniform(rng, 3000, (46.0, 45.0, 46.7)),
+           synth.config_structures("c0")[0], uniform(rng, 2100, (41.0, 40.0, 41.3), (6.0, -4.0, 5.0), "tilted")]
+    b = synth.Batch(sts)
+    N, S = b.n_atom, b.n_struct
+    sz = synth.SIZES_LARGE
+    model = nep.Model.of(sz)
+    theta = torch.tensor(synth.draw_params(sz.n_params, synth.SEEDS["student"]), device="cuda")
+    e_t, f_t, w_t = synth.random_labels(b, synth.SEEDS["labels"])
+    labels = nep.Labels(*(torch.tensor(x, device="cuda") for x in (e_t, f_t, w_t)))
+    print(f"[split sums] sizes={[st.n for st in sts]}", flush=True)
+    out = []
+    for hint in (None, 1):
+        db = nep.DeviceBatch(b)
+        if hint is not None:
+            db.max_atoms = hint
+        nb = nep.Neighbors(model, N)
+        ws = nep.workspace(model, S, N)
+        fl = torch.zeros(1, dtype=torch.int32, device="cuda")
+        nep.build_neighbors(model, db, nb, ws, fl)
+        loss = torch.zeros(4, device="cuda")
+        grad = torch.zeros(sz.n_params, device="cuda")
+        e_s = torch.zeros(S, device="cuda")
+        F = torch.zeros(3 * N, device="cuda")
+        W = torch.zeros(6 * S, device="cuda")
+        nep.loss_grad(model, db, nb, theta, labels, (1.0, 1.0, 0.1), loss, grad, ws, fl, e_s, F, W)
+        torch.cuda.synchronize()
+        assert int(fl.item()) == 0
+        out.append([x.cpu().numpy() for x in (loss, grad, e_s, F, W)])
+    (l1, g1, e1, F1, W1), (l2, g2, e2, F2, W2) = out
+    np.testing.assert_array_equal(F1, F2)
+    np.testing.assert_allclose(l1, l2, rtol=1e-6)
+    np.testing.assert_allclose(e1, e2, rtol=1e-6)
+    np.testing.assert_allclose(W1, W2, rtol=1e-6, atol=1e-6 * np.abs(W2).max())
+    np.testing.assert_allclose(g1, g2, rtol=1e-5, atol=1e-6 * np.abs(g2).max())

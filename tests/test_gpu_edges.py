@@ -44,6 +44,34 @@ def test_overflow_keeps_the_canonical_prefix():
     assert e.value.code == -3
 
 
+def test_reverse_index_complete_under_overflow():
+    """With lists cut at the capacity the reverse index is still written for
+    every stored entry (an entry whose partner may be cut off searches for
+    itself): forces from a zeroed workspace and from one holding another
+    batch's reverse index agree bit for bit.  Both fills keep every index in
+    bounds (0, or a slot below the capacity)."""
+    import torch
+    from paper_2507_00528_amd import nep
+    c0 = synth.config_structures("c0")
+    a = Case(synth.SIZES_SMALL, c0[:3], with_oracle=False)
+    b = Case(synth.SIZES_SMALL, c0[3:6], with_oracle=False)
+    assert a.batch.n_atom == b.batch.n_atom and a.batch.n_struct == b.batch.n_struct
+    r = GPURun(a, cap_rad=8, cap_ang=4)
+    r.ws.zero_()
+    print(f"[reverse overflow] N={a.batch.n_atom}", flush=True)
+    r.neighbors()
+    assert int(r.flags.item()) & nep.NEP_FLAG_NBR_OVERFLOW
+    _, _, F_fresh, _ = r.efw()
+    other = GPURun(b, cap_rad=8, cap_ang=4)
+    other.ws = r.ws
+    other.neighbors()
+    other.efw()
+    r.neighbors()
+    _, _, F_used, _ = r.efw()
+    assert np.isfinite(F_fresh).all()
+    np.testing.assert_array_equal(F_used, F_fresh)
+
+
 def test_dense_cell_spills_lane_buffers_and_stays_exact():
     import torch
     sts = [dense_cell(1, 80, 6.5), dense_cell(2, 56, 6.2)]
