@@ -2200,7 +2200,9 @@ __global__ __launch_bounds__(256, C::ADJ_WAVES) void k_adjoint(AdjArgs a) {
 // group.  A block covers a 4 x 3 grid of 16 x 16 output tiles (blockIdx.z
 // picks the grid cell for larger products); its 4 wavefronts take
 // consecutive 16-atom groups and are summed through LDS at the end.
-constexpr int kOSBlocks = 128;   // blocks per species
+// blocks per species: the W0 sums stream about three times the data of the
+// c^R sums, so they get more blocks (all blocks are resident at once)
+constexpr int kOSBlocksW = 192, kOSBlocksC = 64;
 constexpr int kOSTM = 4, kOSTV = 3;
 
 struct OuterArgs {
@@ -2230,6 +2232,7 @@ __device__ __forceinline__ f32x4 ld_atoms4(const float* row, int p, int p1, bool
 
 __device__ __forceinline__ void outer_sum_block(const OuterArgs& o, int z, f32x4 (&red)[3][kOSTM * kOSTV][kWave]) {
   const int I = blockIdx.y, b = blockIdx.x;
+  if (b >= o.NB) return;
   const int nzv = (o.V + 16 * kOSTV - 1) / (16 * kOSTV);
   const int mz = z / nzv, vz = z % nzv;
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
@@ -2399,11 +2402,11 @@ __global__ __launch_bounds__(256) void k_part_reduce(int PW, const int* seg, con
 // lane sums.  Parameter layout: c^R [T][T][NR][KR], c^A [T][T][NA][KA], then
 // per species W0 [H][D], b0 [H], w1 [H], b1.
 struct GradArgs {
-  int T, NR, NA, KR, KA, H, D, PW, NB;
+  int T, NR, NA, KR, KA, H, D, PW, NBw, NBc;
   int64_t P;
   const double* pp;      // [T][kPRChunks][PW]
-  const float* w0part;   // [T][NB][H*D]
-  const float* crpart;   // [T][NB][NR*T*KR]
+  const float* w0part;   // [T][NBw][H*D]
+  const float* crpart;   // [T][NBc][NR*T*KR]
   float* grad;
 };
 
@@ -2423,9 +2426,9 @@ __global__ __launch_bounds__(256) void k_grad_final(GradArgs a) {
     if (qi < P_R) {
       const int I = qi / (a.T * a.NR * a.KR), rem = qi % (a.T * a.NR * a.KR);
       const int t = rem / (a.NR * a.KR), n = (rem / a.KR) % a.NR, k = rem % a.KR;
-      fsrc = a.crpart + (size_t)I * a.NB * CR + n * (a.T * a.KR) + t * a.KR + k;
+      fsrc = a.crpart + (size_t)I * a.NBc * CR + n * (a.T * a.KR) + t * a.KR + k;
       stride = CR;
-      rows = a.NB;
+      rows = a.NBc;
     } else if (qi < P_R + P_A) {
       const int I = (qi - P_R) / PSA, slot = (qi - P_R) % PSA;
       dsrc = a.pp + (size_t)I * kPRChunks * a.PW + slot;
@@ -2434,9 +2437,9 @@ __global__ __launch_bounds__(256) void k_grad_final(GradArgs a) {
     } else {
       const int I = (qi - P_R - P_A) / blk, o = (qi - P_R - P_A) % blk;
       if (o < HD) {
-        fsrc = a.w0part + (size_t)I * a.NB * HD + o;
+        fsrc = a.w0part + (size_t)I * a.NBw * HD + o;
         stride = HD;
-        rows = a.NB;
+        rows = a.NBw;
       } else {
         dsrc = a.pp + (size_t)I * kPRChunks * a.PW + PSA + (o - HD);
         stride = a.PW;
@@ -2788,8 +2791,8 @@ Layout make_layout(const nep_model* m, const Ops* o, int S, int N) {
   L.w1s = take(4 * (size_t)L.H * Np);
   L.part = take(4 * (size_t)L.nwaves * L.PW);
   L.pp = take(8 * (size_t)L.T * kPRChunks * L.PW);
-  L.w0part = take(4 * (size_t)L.T * kOSBlocks * L.H * L.D);
-  L.crpart = take(4 * (size_t)L.T * kOSBlocks * L.NR * L.TKR);
+  L.w0part = take(4 * (size_t)L.T * kOSBlocksW * L.H * L.D);
+  L.crpart = take(4 * (size_t)L.T * kOSBlocksC * L.NR * L.TKR);
   L.Sh = take(4 * (size_t)Np * L.NA * o->YH);
   L.Sdh = take(4 * (size_t)Np * L.NA * o->YH);
   L.cgrid = take(16 * Ss);
@@ -3131,13 +3134,14 @@ void run_adjoint(const Ctx& c, const nep_neighbors* nb, const float* params, con
     run_high(c, kHighCoef, h, pr);
     const int* seg = at<int>(c.ws, c.L.seg);
     {
-      const OuterArgs ow{c.L.Npad, m->hidden, c.o->D, kOSBlocks, seg, a.beta, at<float>(c.ws, c.L.G), a.w1s,
+      const OuterArgs ow{c.L.Npad, m->hidden, c.o->D, kOSBlocksW, seg, a.beta, at<float>(c.ws, c.L.G), a.w1s,
                          a.Gd, at<float>(c.ws, c.L.w0part)};
-      const OuterArgs oc{c.L.Npad, m->n_rad, c.L.TKR, kOSBlocks, seg, a.Gbr, a.FRst, at<float>(c.ws, c.L.Ep),
+      const OuterArgs oc{c.L.Npad, m->n_rad, c.L.TKR, kOSBlocksC, seg, a.Gbr, a.FRst, at<float>(c.ws, c.L.Ep),
                          a.FPst, at<float>(c.ws, c.L.crpart)};
       const int nzw = outer_slices(ow.M, ow.V), nzc = outer_slices(oc.M, oc.V);
       NEP_LAUNCH(pr, "outer_sums",
-                 hipLaunchKernelGGL(k_outer_sum, dim3(kOSBlocks, T, nzw + nzc), dim3(256), 0, c.st, ow, oc, nzw));
+                 hipLaunchKernelGGL(k_outer_sum, dim3(std::max(kOSBlocksW, kOSBlocksC), T, nzw + nzc), dim3(256), 0,
+                                    c.st, ow, oc, nzw));
     }
     double* pp = at<double>(c.ws, c.L.pp);
     NEP_LAUNCH(pr, "part_reduce",
@@ -3152,7 +3156,8 @@ void run_adjoint(const Ctx& c, const nep_neighbors* nb, const float* params, con
     g.H = m->hidden;
     g.D = c.o->D;
     g.PW = c.L.PW;
-    g.NB = kOSBlocks;
+    g.NBw = kOSBlocksW;
+    g.NBc = kOSBlocksC;
     g.P = param_count(m);
     g.pp = pp;
     g.w0part = at<float>(c.ws, c.L.w0part);
