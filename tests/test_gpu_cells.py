@@ -205,3 +205,51 @@ def test_split_structure_sums_match_single_block_sums():
     np.testing.assert_allclose(e1, e2, rtol=1e-6)
     np.testing.assert_allclose(W1, W2, rtol=1e-6, atol=1e-6 * np.abs(W2).max())
     np.testing.assert_allclose(g1, g2, rtol=1e-5, atol=1e-6 * np.abs(g2).max())
+
+
+def device_lists(sts, hint, cap_rad=64, cap_ang=32):
+    """Counts and the stored entries (zero past each count) as arrays."""
+    import torch
+    from paper_2507_00528_amd import nep
+    b = synth.Batch(sts)
+    model = nep.Model.of(synth.SIZES_LARGE, cap_rad, cap_ang)
+    db = nep.DeviceBatch(b)
+    if hint is not None:
+        db.max_atoms = hint
+    nb = nep.Neighbors(model, b.n_atom)
+    ws = nep.workspace(model, b.n_struct, b.n_atom)
+    fl = torch.zeros(1, dtype=torch.int32, device="cuda")
+    nep.build_neighbors(model, db, nb, ws, fl)
+    torch.cuda.synchronize()
+    out = dict(flags=int(fl.item()))
+    for which, cap in (("rad", cap_rad), ("ang", cap_ang)):
+        cnt = getattr(nb, f"cnt_{which}")
+        idx = getattr(nb, f"idx_{which}").view(b.n_atom, cap)
+        keep = torch.arange(cap, device="cuda")[None, :] < cnt[:, None]
+        out[which] = (cnt.cpu().numpy(), torch.where(keep, idx, torch.zeros_like(idx)).cpu().numpy().view(np.uint32))
+    del ws, nb
+    torch.cuda.empty_cache()
+    return out
+
+
+def test_480k_atom_cell_against_all_pairs_and_sampled_oracle_rows():
+    """One 250 A cell of 480,000 atoms (41 bins per axis, 235 chunks in the
+    offset scan): every list equals the all-pairs search bit for bit, and
+    120 sampled atoms' lists equal the oracle's."""
+    rng = np.random.default_rng(31)
+    st = uniform(rng, 480_000, (250.0, 250.0, 250.0))
+    print(f"[cells 480k] N={st.n}", flush=True)
+    cell = device_lists([st], None)
+    print("[cells 480k] cell search done", flush=True)
+    pairs = device_lists([st], 1)
+    print("[cells 480k] all-pairs search done", flush=True)
+    assert cell["flags"] == 0 and pairs["flags"] == 0
+    rows = np.sort(rng.choice(st.n, 120, replace=False))
+    for which, rc in (("rad", RC), ("ang", RCA)):
+        assert np.array_equal(cell[which][0], pairs[which][0])
+        assert np.array_equal(cell[which][1], pairs[which][1])
+        p = neighbor_pairs(st.pos, st.box, rc, rows=rows)
+        for r in rows:
+            ref = [(int(j) << 5) | int(c) for i, j, c in p[p[:, 0] == r]]
+            assert int(cell[which][0][r]) == len(ref)
+            assert cell[which][1][r, :len(ref)].tolist() == ref
