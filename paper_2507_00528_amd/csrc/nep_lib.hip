@@ -2401,6 +2401,38 @@ __global__ __launch_bounds__(256) void k_part_reduce(int PW, const int* seg, con
 // that parameter's partials in float64, then a fixed xor tree adds the 16
 // lane sums.  Parameter layout: c^R [T][T][NR][KR], c^A [T][T][NA][KA], then
 // per species W0 [H][D], b0 [H], w1 [H], b1.
+// ==================================================================== Adam
+__device__ __forceinline__ void adam_one(float* __restrict__ th, float* __restrict__ m, float* __restrict__ v,
+                                         float g, float lr, float b1, float b2, float eps, float c1, float c2,
+                                         int64_t q) {
+  const float mm = b1 * m[q] + (1.0f - b1) * g;
+  const float vv = b2 * v[q] + (1.0f - b2) * g * g;
+  m[q] = mm;
+  v[q] = vv;
+  th[q] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+}
+
+__global__ __launch_bounds__(256) void k_adam(int64_t P, float* __restrict__ th, float* __restrict__ m,
+                                              float* __restrict__ v, const float* __restrict__ g, float lr, float b1,
+                                              float b2, float eps, float c1, float c2) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < P) adam_one(th, m, v, g[q], lr, b1, b2, eps, c1, c2, q);
+}
+
+struct AdamDev {
+  float lr_start, lr_stop;
+  int64_t n_warmup, n_total;
+  float b1, b2, eps;
+};
+
+__device__ float lr_at(const AdamDev& c, int64_t s) {
+  if (c.n_total <= 0) return c.lr_start;
+  if (s < c.n_warmup) return c.lr_stop + (float)((double)s / (double)c.n_warmup) * (c.lr_start - c.lr_stop);
+  double fr = (double)(s - c.n_warmup) / (double)max((int64_t)1, c.n_total - c.n_warmup);
+  fr = fr > 1.0 ? 1.0 : fr;
+  return c.lr_stop + (c.lr_start - c.lr_stop) * 0.5f * (1.0f + (float)cos(3.14159265358979323846 * fr));
+}
+
 struct GradArgs {
   int T, NR, NA, KR, KA, H, D, PW, NBw, NBc;
   int64_t P;
@@ -2408,6 +2440,14 @@ struct GradArgs {
   const float* w0part;   // [T][NBw][H*D]
   const float* crpart;   // [T][NBc][NR*T*KR]
   float* grad;
+  // Adam on each parameter as soon as its gradient is summed (the captured
+  // training step); step is the 1-based device step counter
+  int adam;
+  AdamDev ad;
+  float* th;
+  float* mm;
+  float* vv;
+  const int* step;
 };
 
 __global__ __launch_bounds__(256) void k_grad_final(GradArgs a) {
@@ -2454,39 +2494,16 @@ __global__ __launch_bounds__(256) void k_grad_final(GradArgs a) {
   }
 #pragma unroll
   for (int d = 8; d >= 1; d >>= 1) sum += __shfl_xor(sum, d, 16);
-  if (q < a.P && l == 0) a.grad[q] = (float)sum;
-}
-
-// ==================================================================== Adam
-__device__ __forceinline__ void adam_one(float* __restrict__ th, float* __restrict__ m, float* __restrict__ v,
-                                         float g, float lr, float b1, float b2, float eps, float c1, float c2,
-                                         int64_t q) {
-  const float mm = b1 * m[q] + (1.0f - b1) * g;
-  const float vv = b2 * v[q] + (1.0f - b2) * g * g;
-  m[q] = mm;
-  v[q] = vv;
-  th[q] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
-}
-
-__global__ __launch_bounds__(256) void k_adam(int64_t P, float* __restrict__ th, float* __restrict__ m,
-                                              float* __restrict__ v, const float* __restrict__ g, float lr, float b1,
-                                              float b2, float eps, float c1, float c2) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < P) adam_one(th, m, v, g[q], lr, b1, b2, eps, c1, c2, q);
-}
-
-struct AdamDev {
-  float lr_start, lr_stop;
-  int64_t n_warmup, n_total;
-  float b1, b2, eps;
-};
-
-__device__ float lr_at(const AdamDev& c, int64_t s) {
-  if (c.n_total <= 0) return c.lr_start;
-  if (s < c.n_warmup) return c.lr_stop + (float)((double)s / (double)c.n_warmup) * (c.lr_start - c.lr_stop);
-  double fr = (double)(s - c.n_warmup) / (double)max((int64_t)1, c.n_total - c.n_warmup);
-  fr = fr > 1.0 ? 1.0 : fr;
-  return c.lr_stop + (c.lr_start - c.lr_stop) * 0.5f * (1.0f + (float)cos(3.14159265358979323846 * fr));
+  if (q < a.P && l == 0) {
+    const float gq = (float)sum;
+    a.grad[q] = gq;
+    if (a.adam) {
+      const int st = *a.step;
+      const float lr = lr_at(a.ad, (int64_t)(st - 1));
+      const float c1 = 1.0f - powf(a.ad.b1, (float)st), c2 = 1.0f - powf(a.ad.b2, (float)st);
+      adam_one(a.th, a.mm, a.vv, gq, lr, a.ad.b1, a.ad.b2, a.ad.eps, c1, c2, q);
+    }
+  }
 }
 
 // Adam with the step counter read from device memory (graph replays).
@@ -2865,6 +2882,18 @@ struct Ctx {
   Layout L;
   void* ws;
   hipStream_t st;
+  // the captured training step: Adam after the gradient, fused into its
+  // final reduction
+  const struct AdamFuse* adam = nullptr;
+};
+
+struct AdamFuse {
+  int64_t P;
+  float* th;
+  float* mm;
+  float* vv;
+  const int* step;
+  AdamDev ad;
 };
 
 int grid1(int n, int blk = 256) { return (n + blk - 1) / blk; }
@@ -3163,11 +3192,22 @@ void run_adjoint(const Ctx& c, const nep_neighbors* nb, const float* params, con
     g.w0part = at<float>(c.ws, c.L.w0part);
     g.crpart = at<float>(c.ws, c.L.crpart);
     g.grad = grad;
+    g.adam = c.adam != nullptr;
+    if (c.adam) {
+      g.ad = c.adam->ad;
+      g.th = c.adam->th;
+      g.mm = c.adam->mm;
+      g.vv = c.adam->vv;
+      g.step = c.adam->step;
+    }
     const unsigned nblk_gf = (unsigned)((g.P * 16 + 255) / 256);
     NEP_LAUNCH(pr, "grad_final", hipLaunchKernelGGL(k_grad_final, dim3(nblk_gf), dim3(256), 0, c.st, g));
   } else {
     const int64_t P = param_count(m);
     hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, c.st, grad, P, 0.f);
+    if (c.adam)
+      hipLaunchKernelGGL(k_adam_dev, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, c.st, P, c.adam->th,
+                         c.adam->mm, c.adam->vv, grad, c.adam->step, c.adam->ad);
   }
 }
 
@@ -3390,12 +3430,13 @@ int nep_train_step_graph_create(const nep_model* m, const nep_batch* b, nep_neig
   }
   int* cur = at<int>(c.ws, c.L.cur_step);
   hipLaunchKernelGGL(k_graph_head, dim3(1), dim3(64), 0, cap, d_flags, d_step, cur);
+  // Adam runs inside the gradient's final reduction
+  const AdamFuse af{param_count(m), params, mm, vv, cur,
+                    AdamDev{adam->lr_start, adam->lr_stop, adam->n_warmup, adam->n_total, adam->beta1, adam->beta2,
+                            adam->eps}};
+  c.adam = &af;
   loss_grad_seq(c, nb, params, labels, lambda, loss, grad, nullptr, nullptr, nullptr, d_flags, nullptr,
                 (graph_flags & NEP_GRAPH_CACHED_NEIGHBORS) == 0);
-  const int64_t P = param_count(m);
-  AdamDev ad{adam->lr_start, adam->lr_stop, adam->n_warmup, adam->n_total, adam->beta1, adam->beta2, adam->eps};
-  hipLaunchKernelGGL(k_adam_dev, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, cap, P, params, mm, vv, grad,
-                     cur, ad);
   const hipError_t e1 = hipStreamEndCapture(cap, &g);
   (void)hipStreamDestroy(cap);
   if (e1 != hipSuccess || !g) return NEP_ERR_HIP;
