@@ -738,8 +738,20 @@ __global__ __launch_bounds__(kNbrThreads) void k_cell_neighbors(NbrArgs a) {
   if (live && !spill) {
     const uint32_t* gbuf = nbuf + (threadIdx.x & ~7);
     const size_t col = (size_t)i;
-    for (int u = 0; u < nR; ++u) {
-      const uint32_t e = mybuf[kNbrThreads * u];
+    // the atom's entries, taken in lane order, are ranked k = s, s + 8, ...,
+    // so the 8 lanes share the work evenly whatever each lane found
+    for (int k = s; k < totR; k += 8) {
+      int q0 = 0, u0 = k;
+#pragma unroll
+      for (int q = 0; q < 7; ++q)
+        if (q == q0 && u0 >= ntv[q]) {
+          u0 -= ntv[q];
+          q0 = q + 1;
+        }
+      const uint32_t e = gbuf[q0 + kNbrThreads * u0];
+      uint32_t m0 = 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) m0 = q == q0 ? mtv[q] : m0;
       int rR = 0, rA = 0;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
@@ -750,7 +762,7 @@ __global__ __launch_bounds__(kNbrThreads) void k_cell_neighbors(NbrArgs a) {
         }
       }
       if (rR < a.capR) a.idxR[col * a.capR + rR] = e;
-      if (((angmask >> u) & 1u) && rA < a.capA) a.idxA[col * a.capA + rA] = e;
+      if (((m0 >> u0) & 1u) && rA < a.capA) a.idxA[col * a.capA + rA] = e;
     }
     if (s == 0) {
       a.cntR[i] = totR;
