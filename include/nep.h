@@ -85,10 +85,12 @@ typedef struct {
  *   tilt  [n_struct*3] float (xy, xz, yz), or NULL when every cell is
  *         orthorhombic (all tilts zero).
  *   max_atoms  host value: 0, or an upper bound on the atoms of any one
- *         structure.  It only selects the search: structures of at least 1024
- *         atoms in cells wide enough are searched through cell lists, and a
- *         bound below 1024 skips those kernels.  The lists do not depend on
- *         it; a negative value is NEP_ERR_ARG.
+ *         structure.  It only selects kernels: structures of at least 1024
+ *         atoms in cells wide enough are searched through cell lists, and
+ *         structures of at least 2048 atoms are summed per 1024-atom chunk; a
+ *         bound below those sizes skips the corresponding kernels.  No result
+ *         depends on it beyond the order of floating-point sums; a negative
+ *         value is NEP_ERR_ARG.
  * Orthorhombic cell (all three tilts zero): each L >= rc_rad and each
  * coordinate in [0, L).  Triclinic cell: each perpendicular width (cell
  * volume over the area of the opposite face) >= rc_rad / (1 - 2e-5) and the
