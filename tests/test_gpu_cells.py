@@ -253,3 +253,61 @@ def test_480k_atom_cell_against_all_pairs_and_sampled_oracle_rows():
             ref = [(int(j) << 5) | int(c) for i, j, c in p[p[:, 0] == r]]
             assert int(cell[which][0][r]) == len(ref)
             assert cell[which][1][r, :len(ref)].tolist() == ref
+
+
+def test_empty_structures_between_large_ones():
+    """Structures without atoms before, between and after large ones: the
+    structure lookups of the binning and of the chunk partials skip them, the
+    lists match the all-pairs search and the oracle, and every per-structure
+    result and the gradient match the single-block sums; the empty
+    structures get zero energy and virial."""
+    import torch
+    from paper_2507_00528_amd import nep
+    rng = np.random.default_rng(12)
+    box = np.full(3, 20.0, np.float32)
+    empty = synth.Structure(np.zeros((0, 3), np.float32), box, np.zeros(0, np.int32), "empty")
+    big = [uniform(rng, 2600, (44.0, 44.0, 44.0)), uniform(rng, 2200, (42.0, 41.0, 42.5), (5.0, 3.0, -6.0), "tilted")]
+    sts = [empty, big[0], empty, empty, synth.config_structures("c0")[2], empty, big[1], empty]
+    b = synth.Batch(sts)
+    N, S = b.n_atom, b.n_struct
+    print(f"[empty structures] sizes={[st.n for st in sts]}", flush=True)
+    cell = device_lists(sts, None)
+    pairs = device_lists(sts, 1)
+    assert cell["flags"] == 0 and pairs["flags"] == 0
+    for which in ("rad", "ang"):
+        assert np.array_equal(cell[which][0], pairs[which][0])
+        assert np.array_equal(cell[which][1], pairs[which][1])
+        ref = oracle_rows([st for st in sts if st.n], which)
+        assert cell[which][0].tolist() == [len(r) for r in ref]
+        assert all(cell[which][1][i, :len(r)].tolist() == r for i, r in enumerate(ref))
+    sz = synth.SIZES_LARGE
+    model = nep.Model.of(sz)
+    theta = torch.tensor(synth.draw_params(sz.n_params, synth.SEEDS["student"]), device="cuda")
+    e_t, f_t, w_t = synth.random_labels(b, synth.SEEDS["labels"])
+    labels = nep.Labels(*(torch.tensor(x, device="cuda") for x in (e_t, f_t, w_t)))
+    out = []
+    for hint in (None, 1):
+        db = nep.DeviceBatch(b)
+        if hint is not None:
+            db.max_atoms = hint
+        nb = nep.Neighbors(model, N)
+        ws = nep.workspace(model, S, N)
+        fl = torch.zeros(1, dtype=torch.int32, device="cuda")
+        nep.build_neighbors(model, db, nb, ws, fl)
+        loss = torch.zeros(4, device="cuda")
+        grad = torch.zeros(sz.n_params, device="cuda")
+        e_s = torch.full((S,), 7.0, device="cuda")
+        F = torch.zeros(3 * N, device="cuda")
+        W = torch.full((6 * S,), 7.0, device="cuda")
+        nep.loss_grad(model, db, nb, theta, labels, (1.0, 1.0, 0.1), loss, grad, ws, fl, e_s, F, W)
+        torch.cuda.synchronize()
+        assert int(fl.item()) == 0
+        out.append([x.cpu().numpy() for x in (loss, grad, e_s, F, W)])
+    (l1, g1, e1, F1, W1), (l2, g2, e2, F2, W2) = out
+    empty_ids = [k for k, st in enumerate(sts) if st.n == 0]
+    assert np.all(e1[empty_ids] == 0) and np.all(W1.reshape(S, 6)[empty_ids] == 0)
+    np.testing.assert_array_equal(F1, F2)
+    np.testing.assert_allclose(l1, l2, rtol=1e-6)
+    np.testing.assert_allclose(e1, e2, rtol=1e-6)
+    np.testing.assert_allclose(W1, W2, rtol=1e-6, atol=1e-6 * np.abs(W2).max())
+    np.testing.assert_allclose(g1, g2, rtol=1e-5, atol=1e-6 * np.abs(g2).max())
