@@ -155,7 +155,10 @@ int nep_workspace_bytes(const nep_model* model, int32_t n_struct, int32_t n_atom
  * d2 = (dx*dx + dy*dy) + dz*dz < rc*rc without fused multiply-add, so the
  * lists are bit-reproducible.  Sets NEP_FLAG_NBR_OVERFLOW, _BOX, _TYPE,
  * _POSITION in d_flags (required).  Also prepares workspace state that the
- * other calls on this batch read (species order, reverse entries). */
+ * other calls on this batch read (species order, reverse entries).
+ * Structures of at least 1024 atoms in cells at least 3 (rc_rad + 0.05)
+ * wide are searched through cell lists (see nep_batch.max_atoms); the lists
+ * are the same bit for bit. */
 int nep_build_neighbors(const nep_model* model, const nep_batch* batch, nep_neighbors* out,
                         void* ws, int32_t* d_flags, void* stream);
 

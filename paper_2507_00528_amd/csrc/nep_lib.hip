@@ -500,11 +500,12 @@ __global__ __launch_bounds__(kNbrThreads) void k_neighbors(NbrArgs a) {
 // kCellMinAtoms atoms whose cell takes the single-image decision is cut into
 // na x nb x nc bins along its edge vectors, each bin at least rc + kCellPad
 // thick across (perpendicular width over the bin count), at least 3 bins per
-// axis and at most one bin per atom.  An atom's bin comes from its
+// axis and no more bins than atoms.  An atom's bin comes from its
 // single-precision fractional coordinates; their error, and the accepted
 // positions up to 1e-5 outside the cell, move an atom by under 0.006 A for
-// cells up to kNbrFastL, so two atoms in bins that are not adjacent along some
-// axis lie more than rc apart in every image.  Each atom then meets as
+// cells up to kNbrFastL (twice that is below kCellPad), so two atoms in bins
+// that are not adjacent along some axis lie more than rc apart in every
+// image.  Each atom then meets as
 // candidates exactly the atoms of its 27 surrounding bins and takes the same
 // per-candidate decision as the all-pairs scan, so its entries are the same.
 // Within rc + delta every j has one image at most (each width is at least
