@@ -9,8 +9,10 @@ Cases: three bins along one axis (every bin row wraps), a tilted cell, large
 cells too narrow to bin (one below the single-image width, one below three
 bins) and small structures in the same batch, a dense cluster whose atoms
 have more entries than the lane buffers hold (left to the all-pairs kernel),
-and the same cluster past the list capacity.  Also the per-structure sums of
-large structures from chunk partials against single-block sums."""
+and the same cluster past the list capacity, one 480,000-atom cell, empty
+structures between large ones, and strongly sheared cells.  Also the
+per-structure sums of large structures from chunk partials against
+single-block sums."""
 import numpy as np
 import pytest
 
@@ -311,3 +313,26 @@ def test_empty_structures_between_large_ones():
     np.testing.assert_allclose(e1, e2, rtol=1e-6)
     np.testing.assert_allclose(W1, W2, rtol=1e-6, atol=1e-6 * np.abs(W2).max())
     np.testing.assert_allclose(g1, g2, rtol=1e-5, atol=1e-6 * np.abs(g2).max())
+
+
+def test_strongly_sheared_large_cells():
+    """Tilts near half an edge, of both signs: the bins follow the edge
+    vectors (fractional coordinates), so the binned search still meets every
+    neighbor.  Lists against the all-pairs search and the oracle."""
+    rng = np.random.default_rng(44)
+    sts = [uniform(rng, 2400, (45.0, 44.0, 46.0), (21.0, -20.0, 19.5), "sheared+"),
+           uniform(rng, 1800, (40.0, 41.0, 40.5), (-18.5, 17.0, -20.0), "sheared-")]
+    from _helpers import hmat, widths
+    for st in sts:
+        w = widths(hmat(st.box, st.tilt))
+        assert w.min() >= 3 * (RC + 0.05), w   # binned, 3+ bins per axis
+    print(f"[sheared cells] sizes={[st.n for st in sts]}", flush=True)
+    cell = device_lists(sts, None)
+    pairs = device_lists(sts, 1)
+    assert cell["flags"] == 0 and pairs["flags"] == 0
+    for which in ("rad", "ang"):
+        assert np.array_equal(cell[which][0], pairs[which][0])
+        assert np.array_equal(cell[which][1], pairs[which][1])
+        ref = oracle_rows(sts, which)
+        assert cell[which][0].tolist() == [len(r) for r in ref]
+        assert all(cell[which][1][i, :len(r)].tolist() == r for i, r in enumerate(ref))
