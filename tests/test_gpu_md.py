@@ -1,7 +1,9 @@
 """Inference path on the GPU (nep_md_step): three velocity-Verlet steps equal
 the same integrator driven by FP64 oracle forces; NVE runs conserve the total
 energy; and the energy-volume curve's slope at s = 1 equals -tr W of the
-library's virial (Eq. 4 under uniform strain)."""
+library's virial (Eq. 4 under uniform strain); and a large cell whose lists
+are rebuilt through the cell search every step follows the same trajectory
+as with the all-pairs search."""
 import numpy as np
 import pytest
 
@@ -116,3 +118,37 @@ def test_energy_volume_slope_equals_virial_trace():
     trw = w[1, :3].sum()
     assert abs(slope + trw) < 2e-2 * max(abs(trw), 1.0), (slope, trw)
     assert np.all(np.isfinite(e))
+
+
+def test_large_cell_md_through_cell_lists_matches_all_pairs():
+    """Velocity Verlet on a 1,500-atom cell rebuilds its lists every step
+    through the cell search (bins recomputed as atoms move and cross faces);
+    the trajectory equals, bit for bit, the same run forced onto the
+    all-pairs search (structure-size bound below 1024)."""
+    import torch
+    from paper_2507_00528_amd import nep
+    rng = np.random.default_rng(3)
+    box = np.full(3, 36.0, np.float32)
+    st = synth.Structure(synth.wrap32(synth.rsa_positions(rng, 1500, box, 2.2), box), box,
+                         synth.assign_types(rng, 1500), "md-cells")
+    sz = synth.SIZES_LARGE
+    out = []
+    for hint in (None, 1):
+        model, b, db, nb, ws, fl, theta = setup([st], sz, synth.SEEDS["teacher"])
+        if hint is not None:
+            db.max_atoms = hint
+        p = torch.tensor(theta, device="cuda")
+        mass = torch.tensor(MASSES, dtype=torch.float32, device="cuda")
+        vel = torch.tensor(md.maxwell_velocities(st.types, MASSES, 1500.0, seed=5), device="cuda")
+        force = torch.zeros(3 * b.n_atom, device="cuda")
+        e_pot = torch.zeros(1, device="cuda")
+        print(f"[md cells] N={b.n_atom} bound={hint}", flush=True)
+        nep.build_neighbors(model, db, nb, ws, fl)
+        nep.energy_force_virial(model, db, nb, p, ws, None, e_pot, force, None)
+        nep.md_step(model, db, nb, p, mass, vel, force, 2.0, 5, e_pot, ws, fl)
+        torch.cuda.synchronize()
+        assert int(fl.item()) == 0
+        out.append([x.cpu().numpy() for x in (db.pos, vel, force, e_pot)])
+    for a, c in zip(*out):
+        np.testing.assert_array_equal(a, c)
+    assert not np.array_equal(out[0][0], st.pos.T.reshape(-1))   # the atoms moved
