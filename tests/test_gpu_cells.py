@@ -12,7 +12,8 @@ have more entries than the lane buffers hold (left to the all-pairs kernel),
 and the same cluster past the list capacity, one 480,000-atom cell, empty
 structures between large ones, and strongly sheared cells.  Also the
 per-structure sums of large structures from chunk partials against
-single-block sums."""
+single-block sums, and a captured training step through both against eager
+steps."""
 import numpy as np
 import pytest
 
@@ -336,3 +337,49 @@ def test_strongly_sheared_large_cells():
         ref = oracle_rows(sts, which)
         assert cell[which][0].tolist() == [len(r) for r in ref]
         assert all(cell[which][1][i, :len(r)].tolist() == r for i, r in enumerate(ref))
+
+
+def test_captured_step_with_cell_search_matches_eager():
+    """A captured training step whose lists come from the cell search and
+    whose per-structure sums come from chunk partials: three replays equal
+    eager neighbor builds, loss_grad and Adam steps (eager work and
+    synchronisation between the replays)."""
+    import torch
+    from paper_2507_00528_amd import nep
+    rng = np.random.default_rng(21)
+    sts = [uniform(rng, 2300, (42.0, 42.0, 42.0)), synth.config_structures("c0")[1],
+           uniform(rng, 2100, (41.0, 40.0, 41.5), (7.0, -5.0, 6.0), "tilted")]
+    b = synth.Batch(sts)
+    N, S = b.n_atom, b.n_struct
+    sz = synth.SIZES_LARGE
+    model = nep.Model.of(sz)
+    P = sz.n_params
+    db = nep.DeviceBatch(b)
+    e_t, f_t, w_t = synth.random_labels(b, synth.SEEDS["labels"])
+    labels = nep.Labels(*(torch.tensor(x, device="cuda") for x in (e_t, f_t, w_t)))
+    lam = (1.0, 1.0, 0.1)
+    theta = torch.tensor(synth.draw_params(P, synth.SEEDS["student"]), device="cuda")
+    params_g, params_e = theta.clone(), theta.clone()
+    m_g, v_g, grad_g, m_e, v_e, grad_e = (torch.zeros(P, device="cuda") for _ in range(6))
+    loss_g, loss_e = torch.zeros(4, device="cuda"), torch.zeros(4, device="cuda")
+    step = torch.ones(1, dtype=torch.int32, device="cuda")
+    nb_g, nb_e = nep.Neighbors(model, N), nep.Neighbors(model, N)
+    ws_g, ws_e = nep.workspace(model, S, N), nep.workspace(model, S, N)
+    fl_g = torch.zeros(1, dtype=torch.int32, device="cuda")
+    fl_e = torch.zeros(1, dtype=torch.int32, device="cuda")
+    print(f"[graph cells] sizes={[st.n for st in sts]}", flush=True)
+    g = nep.TrainStepGraph(model, db, nb_g, labels, lam, params_g, m_g, v_g, grad_g, loss_g, step, ws_g, fl_g,
+                           lr_start=1e-3, lr_stop=1e-3)
+    for it in range(1, 4):
+        g.launch()
+        torch.cuda.synchronize()
+        nep.build_neighbors(model, db, nb_e, ws_e, fl_e)
+        nep.loss_grad(model, db, nb_e, params_e, labels, lam, loss_e, grad_e, ws_e, fl_e)
+        nep.adam_step(params_e, m_e, v_e, grad_e, 1e-3, it)
+        torch.cuda.synchronize()
+        assert int(fl_g.item()) == 0 and int(fl_e.item()) == 0
+        assert np.array_equal(nb_g.cnt_rad.cpu().numpy(), nb_e.cnt_rad.cpu().numpy())
+        np.testing.assert_allclose(loss_g.cpu().numpy(), loss_e.cpu().numpy(), rtol=1e-6)
+        np.testing.assert_allclose(params_g.cpu().numpy(), params_e.cpu().numpy(), rtol=0, atol=1e-7)
+    assert int(step.item()) == 4
+    g.close()
