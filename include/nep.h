@@ -56,6 +56,7 @@ enum {
 #define NEP_FLAG_BOX 4
 #define NEP_FLAG_TYPE 8
 #define NEP_FLAG_POSITION 16
+#define NEP_FLAG_STEP 32   /* a captured step replayed with a step counter below 1 */
 
 /* NEP hyper-parameters, as counts (Sec. II.B, Appendix A):
  *   n_rad radial channels q_n, n = 0..n_rad-1              (Eq. 5)
@@ -201,7 +202,8 @@ int nep_loss_grad(const nep_model* model, const nep_batch* batch, const nep_neig
 /* One bias-corrected Adam step on P parameters (the optimizer of Sec. I):
  *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
  *   params -= lr * (m/(1-b1^step)) / (sqrt(v/(1-b2^step)) + eps);
- * step is 1-based. */
+ * step is 1-based.  NEP_ERR_ARG for step < 1, beta1 or beta2 outside [0, 1),
+ * a negative or non-finite eps or a non-finite lr. */
 int nep_adam_step(int64_t P, float* params, float* m, float* v, const float* grad, float lr,
                   float beta1, float beta2, float eps, int32_t step, void* stream);
 
@@ -237,6 +239,12 @@ int nep_md_step(const nep_model* model, const nep_batch* batch, float* pos, nep_
  * device and is advanced by each replay; the learning rate of each replay
  * follows Eq. 17 with (lr_start, lr_stop, n_warmup, n_total), or stays at
  * lr_start when n_total <= 0.  loss [4] and d_flags describe the latest replay.
+ * A replay whose neighbor build or loss raised any flag (overflow, box, type,
+ * position, non-finite loss) or whose step counter is below 1 (NEP_FLAG_STEP)
+ * writes grad but leaves params, m and v unchanged; a non-finite gradient
+ * entry raises NEP_FLAG_NONFINITE and leaves its own parameter unchanged.
+ * Returns NEP_ERR_ARG for beta1 or beta2 outside [0, 1), a negative or
+ * non-finite eps, a non-finite learning rate or n_warmup < 0.
  * Returns an opaque handle in *graph. */
 typedef struct {
   float lr_start, lr_stop;

@@ -2461,7 +2461,20 @@ struct GradArgs {
   float* mm;
   float* vv;
   const int* step;
+  int* flags;   // the replay's flag word: any raised flag skips the update
 };
+
+// Whether a captured step may update parameter q: no flag was raised by this
+// replay's neighbor build or loss (their launches precede this one), the
+// latched step is valid, and the gradient entry is finite (else the flag is
+// raised and this entry alone keeps its value).
+__device__ __forceinline__ bool adam_allowed(int* flags, int fl0, int st, float g) {
+  if (!isfinite(g)) {
+    atomicOr(flags, FL_NONFINITE);
+    return false;
+  }
+  return fl0 == 0 && st >= 1;
+}
 
 __global__ __launch_bounds__(256) void k_grad_final(GradArgs a) {
   const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
@@ -2512,9 +2525,11 @@ __global__ __launch_bounds__(256) void k_grad_final(GradArgs a) {
     a.grad[q] = gq;
     if (a.adam) {
       const int st = *a.step;
-      const float lr = lr_at(a.ad, (int64_t)(st - 1));
-      const float c1 = 1.0f - powf(a.ad.b1, (float)st), c2 = 1.0f - powf(a.ad.b2, (float)st);
-      adam_one(a.th, a.mm, a.vv, gq, lr, a.ad.b1, a.ad.b2, a.ad.eps, c1, c2, q);
+      if (adam_allowed(a.flags, __hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), st, gq)) {
+        const float lr = lr_at(a.ad, (int64_t)(st - 1));
+        const float c1 = 1.0f - powf(a.ad.b1, (float)st), c2 = 1.0f - powf(a.ad.b2, (float)st);
+        adam_one(a.th, a.mm, a.vv, gq, lr, a.ad.b1, a.ad.b2, a.ad.eps, c1, c2, q);
+      }
     }
   }
 }
@@ -2522,10 +2537,11 @@ __global__ __launch_bounds__(256) void k_grad_final(GradArgs a) {
 // Adam with the step counter read from device memory (graph replays).
 __global__ __launch_bounds__(256) void k_adam_dev(int64_t P, float* __restrict__ th, float* __restrict__ m,
                                                   float* __restrict__ v, const float* __restrict__ g,
-                                                  const int* __restrict__ step, AdamDev c) {
+                                                  const int* __restrict__ step, int* flags, AdamDev c) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= P) return;
   const int st = *step;
+  if (!adam_allowed(flags, __hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), st, g[q])) return;
   const float lr = lr_at(c, (int64_t)(st - 1));
   const float c1 = 1.0f - powf(c.b1, (float)st), c2 = 1.0f - powf(c.b2, (float)st);
   adam_one(th, m, v, g[q], lr, c.b1, c.b2, c.eps, c1, c2, q);
@@ -2533,10 +2549,12 @@ __global__ __launch_bounds__(256) void k_adam_dev(int64_t P, float* __restrict__
 
 // First node of a captured train step: clear the flags, latch the step this
 // replay uses (Adam reads the latched copy) and advance the caller's counter.
+// A step counter below 1 (Adam's bias correction needs step >= 1) raises
+// FL_STEP, which makes this replay skip its update.
 __global__ void k_graph_head(int* flags, int* step, int* cur) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    flags[0] = 0;
     const int st = step[0];
+    flags[0] = st < 1 ? FL_STEP : 0;
     cur[0] = st;
     step[0] = st + 1;
   }
@@ -2907,6 +2925,7 @@ struct AdamFuse {
   float* vv;
   const int* step;
   AdamDev ad;
+  int* flags;
 };
 
 int grid1(int n, int blk = 256) { return (n + blk - 1) / blk; }
@@ -3212,6 +3231,7 @@ void run_adjoint(const Ctx& c, const nep_neighbors* nb, const float* params, con
       g.mm = c.adam->mm;
       g.vv = c.adam->vv;
       g.step = c.adam->step;
+      g.flags = c.adam->flags;
     }
     const unsigned nblk_gf = (unsigned)((g.P * 16 + 255) / 256);
     NEP_LAUNCH(pr, "grad_final", hipLaunchKernelGGL(k_grad_final, dim3(nblk_gf), dim3(256), 0, c.st, g));
@@ -3220,7 +3240,7 @@ void run_adjoint(const Ctx& c, const nep_neighbors* nb, const float* params, con
     hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, c.st, grad, P, 0.f);
     if (c.adam)
       hipLaunchKernelGGL(k_adam_dev, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, c.st, P, c.adam->th,
-                         c.adam->mm, c.adam->vv, grad, c.adam->step, c.adam->ad);
+                         c.adam->mm, c.adam->vv, grad, c.adam->step, c.adam->flags, c.adam->ad);
   }
 }
 
@@ -3269,6 +3289,18 @@ struct GraphHandle {
   hipGraph_t g;
   hipGraphExec_t e;
 };
+
+// Adam's hyper-parameters: beta in [0, 1) (the bias correction divides by
+// 1 - beta^step), eps >= 0 finite.
+bool adam_hparams_ok(float beta1, float beta2, float eps) {
+  return beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f && std::isfinite(eps);
+}
+
+int check_adam_config(const nep_adam_config* a) {
+  if (!adam_hparams_ok(a->beta1, a->beta2, a->eps)) return NEP_ERR_ARG;
+  if (!std::isfinite(a->lr_start) || !std::isfinite(a->lr_stop) || a->n_warmup < 0) return NEP_ERR_ARG;
+  return NEP_OK;
+}
 
 }  // namespace
 
@@ -3405,7 +3437,7 @@ int nep_loss_grad(const nep_model* m, const nep_batch* b, const nep_neighbors* n
 
 int nep_adam_step(int64_t P, float* params, float* mm, float* vv, const float* grad, float lr, float beta1,
                   float beta2, float eps, int32_t step, void* stream) {
-  if (P < 0 || step < 1 || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f)) return NEP_ERR_ARG;
+  if (P < 0 || step < 1 || !adam_hparams_ok(beta1, beta2, eps) || !std::isfinite(lr)) return NEP_ERR_ARG;
   if (P == 0) return NEP_OK;
   if (!params || !mm || !vv || !grad) return NEP_ERR_ARG;
   const float c1 = 1.0f - (float)std::pow((double)beta1, (double)step);
@@ -3433,6 +3465,7 @@ int nep_train_step_graph_create(const nep_model* m, const nep_batch* b, nep_neig
   if ((rc = check_nbrs(nb, b->n_atom))) return rc;
   if (!labels || !lambda || !params || !mm || !vv || !grad || !loss || !d_step || !adam || !d_flags || !graph)
     return NEP_ERR_ARG;
+  if ((rc = check_adam_config(adam))) return rc;
   hipStream_t cap;
   if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return NEP_ERR_HIP;
   c.st = cap;
@@ -3446,7 +3479,8 @@ int nep_train_step_graph_create(const nep_model* m, const nep_batch* b, nep_neig
   // Adam runs inside the gradient's final reduction
   const AdamFuse af{param_count(m), params, mm, vv, cur,
                     AdamDev{adam->lr_start, adam->lr_stop, adam->n_warmup, adam->n_total, adam->beta1, adam->beta2,
-                            adam->eps}};
+                            adam->eps},
+                    d_flags};
   c.adam = &af;
   loss_grad_seq(c, nb, params, labels, lambda, loss, grad, nullptr, nullptr, nullptr, d_flags, nullptr,
                 (graph_flags & NEP_GRAPH_CACHED_NEIGHBORS) == 0);
@@ -3514,6 +3548,7 @@ int nep_flags_status(int32_t f) {
   if (f & FL_POS) return NEP_ERR_POSITION;
   if (f & FL_OVERFLOW) return NEP_ERR_NBR_OVERFLOW;
   if (f & FL_NONFINITE) return NEP_ERR_NONFINITE;
+  if (f & FL_STEP) return NEP_ERR_ARG;
   return NEP_OK;
 }
 

@@ -20,6 +20,7 @@ NEP_FLAG_NONFINITE = 2
 NEP_FLAG_BOX = 4
 NEP_FLAG_TYPE = 8
 NEP_FLAG_POSITION = 16
+NEP_FLAG_STEP = 32
 
 
 class NEPError(RuntimeError):

@@ -156,6 +156,8 @@ class Trainer:
             nep.build_neighbors(self.model, st.batch, st.nbrs, st.ws, st.flags, stream=self.stream)
             nep.loss_grad(self.model, st.batch, st.nbrs, self.params, st.labels, self.lam, st.loss, st.grad, st.ws,
                           st.flags, stream=self.stream)
+            # an overflowing list or a non-finite loss must not reach the optimizer state
+            nep.check_flags(st.flags, "training step")
             nep.adam_step(self.params, self.m, self.v, st.grad, lr, s, stream=self.stream)
         self.step_host += 1
 

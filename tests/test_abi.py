@@ -90,3 +90,28 @@ def test_lr_schedule_matches_eq17():
     for s in (0, 3, 10, 40, 100, 150):
         assert nep.lr_schedule(s, 1e-3, 1e-5, 10, 100) == pytest.approx(oracle_lr(s, 1e-3, 1e-5, 10, 100), rel=1e-5)
     assert nep.lr_schedule(7, 2e-3, 1e-5, 0, 0) == pytest.approx(2e-3)
+
+
+def test_graph_create_rejects_bad_adam_config_before_launch():
+    """beta = 1 would divide by 1 - beta^step = 0 in Adam's bias correction,
+    and a negative eps or a non-finite rate poisons every parameter: both are
+    rejected on the host (no stream is created, nothing launched)."""
+    lib = _lib.load()
+    m = nep.Model.of(synth.SIZES_SMALL).c()
+    b = _lib.NepBatch(0, 0, None, None, None, None)
+    nb = _lib.NepNeighbors(None, None, None, None)
+    lab = _lib.NepLabels(None, None, None)
+    lam = (C.c_float * 3)(1.0, 1.0, 0.1)
+    fake = C.c_void_p(0x100000)   # aligned, never dereferenced: validation fails first
+    h = C.c_void_p()
+    for cfg in ((1e-3, 1e-3, 0, 0, 1.0, 0.999, 1e-8), (1e-3, 1e-3, 0, 0, 0.9, 1.0, 1e-8),
+                (1e-3, 1e-3, 0, 0, 0.9, 0.999, -1e-8), (float("nan"), 1e-3, 0, 0, 0.9, 0.999, 1e-8),
+                (1e-3, 1e-3, -1, 10, 0.9, 0.999, 1e-8)):
+        c = _lib.NepAdamConfig(*cfg)
+        rc = lib.nep_train_step_graph_create(C.byref(m), C.byref(b), C.byref(nb), C.byref(lab), C.byref(lam),
+                                             fake, fake, fake, fake, fake, fake, C.byref(c), fake, fake, 0, None,
+                                             C.byref(h))
+        assert rc == -1, cfg
+    assert lib.nep_adam_step(10, fake, fake, fake, fake, 1e-3, 1.0, 0.999, 1e-8, 1, None) == -1
+    assert lib.nep_adam_step(10, fake, fake, fake, fake, float("inf"), 0.9, 0.999, 1e-8, 1, None) == -1
+    assert lib.nep_flags_status(nep.NEP_FLAG_STEP) == -1
