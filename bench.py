@@ -13,7 +13,10 @@ neighbor lists, energies/forces/virials, loss, parameter gradient and Adam.
            loss-and-gradient call per structure through the same C ABI,
            gradients summed with the batch's global normalisation, then Adam.
 
-Prints one JSON line.  Inputs are resident in HBM before timing starts.
+Prints one JSON line.  Inputs are resident in HBM before timing starts.  The
+same run also times the batched step on the 27,000-atom cell and on the
+2,000-structure set (`workloads`), and the FP64 oracle on the host's cores
+(`cpu_baseline`).
 """
 from __future__ import annotations
 
@@ -31,7 +34,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "train-step atoms/s (E+F+virial+param grad), batched vs plain, 1 MI355X"
-PEAK_FP32_VECTOR = 157.3e12   # MI355X fp32 vector, FLOP/s
+PEAK_FP32_VECTOR = 157.3e12   # MI355X fp32 vector (packed FP32), FLOP/s
+PEAK_FP32_NONPACKED = 78.6e12  # one FP32 FMA per lane per clock: 256 CUs x 4 SIMDs x 16 lanes x 2 x 2.4 GHz
 PEAK_HBM = 8.0e12             # bytes/s
 
 
@@ -85,6 +89,18 @@ def flop_model(sz, mR: float, mA: float) -> dict:
     return out
 
 
+def step_flops_formula(sz, mR: float, mA: float) -> float:
+    """Whole-step FLOPs per atom by the closed formula of the hot-path scope
+    (basis recomputed in the forward, force and adjoint passes):
+    radial m_R (18 K_R + 60 + 10 n_R K_R), angular m_A (18 K_A + 60 + 101 Y
+    + 9 n_A K_A + 16 n_A Y), network 12 D H."""
+    lmax = max(sz.l3, sz.l4, sz.l5)
+    Y = lmax * (lmax + 2)
+    rad = mR * (18 * sz.k_rad + 60 + 10 * sz.n_rad * sz.k_rad)
+    ang = mA * (18 * sz.k_ang + 60 + 101 * Y + 9 * sz.n_ang * sz.k_ang + 16 * sz.n_ang * Y)
+    return rad + ang + 12 * sz.n_desc * sz.hidden
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in ("paper_2507_00528_amd/csrc/nep_lib.hip", "paper_2507_00528_amd/csrc/nep_device.h",
@@ -117,7 +133,199 @@ def measured_counters(kernel: str, workload: str):
     return {k: d[k] for k in ("valu_busy", "mfma_busy", "valu_instr_per_wave") if k in d}
 
 
+# ------------------------------------------------------- CPU baseline (oracle)
+_W = {}
+
+
+def _cpu_worker_init(sizes, theta, lam):
+    import torch
+    torch.set_num_threads(1)
+    from oracle import NEPOracle
+    _W.update(o=NEPOracle(sizes), theta=theta, lam=lam)
+
+
+def _cpu_worker(task):
+    """One structure's neighbor lists, loss and gradient on the FP64 oracle."""
+    st, lab = task
+    o = _W["o"]
+    nb = o.neighbors(st)
+    L, g = o.loss_and_grad(_W["theta"], [st], lab, _W["lam"], nbr_cache=[nb])
+    return st.n, g
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(sizes, structures, theta_np, e_lab, f_lab, w_lab, lam, budget_s, log):
+    """The FP64 oracle (neighbors, loss and gradient of every structure of the
+    batch) over a process pool of one worker per host core, each worker one
+    torch thread; the median of up to three full passes."""
+    import multiprocessing as mp
+    cores = len(os.sched_getaffinity(0))
+    offs = np.cumsum([0] + [st.n for st in structures])
+    tasks = []
+    for k, st in enumerate(structures):
+        lab = dict(energy=e_lab[k:k + 1].astype(np.float64),
+                   force=[f_lab[:, offs[k]:offs[k + 1]].T.astype(np.float64)],
+                   virial=w_lab[k:k + 1].astype(np.float64))
+        tasks.append((st, lab))
+    order = sorted(range(len(tasks)), key=lambda k: -structures[k].n)   # largest first: balanced tail
+    tasks = [tasks[k] for k in order]
+    walls = []
+    with mp.get_context("spawn").Pool(cores, initializer=_cpu_worker_init, initargs=(sizes, theta_np, lam)) as pool:
+        pool.map(_cpu_worker, tasks[-cores:], chunksize=1)   # every worker has imported and built its oracle
+        t_all = time.perf_counter()
+        while len(walls) < 3:
+            t0 = time.perf_counter()
+            atoms = 0
+            grad = np.zeros(len(theta_np))
+            for n, g in pool.imap_unordered(_cpu_worker, tasks, chunksize=1):
+                atoms += n
+                grad += g
+            walls.append(time.perf_counter() - t0)
+            if time.perf_counter() - t_all > budget_s:
+                break
+    wall = float(np.median(walls))
+    log(f"cpu oracle: {atoms / wall:.1f} atoms/s on {cores} worker processes ({len(walls)} passes)")
+    return {"value": atoms / wall, "unit": "atoms/s", "cores": cores, "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": f"the whole batch: {len(structures)} structures, {atoms} atoms; neighbors, loss and "
+                      f"gradient in FP64 (torch CPU), one structure per task over {cores} processes of one "
+                      f"thread each; median wall time of {len(walls)} passes ({wall:.2f}s)"}
+
+
 # ---------------------------------------------------------------- the bench
+WORKLOAD_TEXT = {
+    "c2": "512 structures, atom counts log-uniform in 32-512 (rocksalt-like, liquid, amorphous)",
+    "c3": "one amorphous Sb2Te3-stoichiometry cell of 27,000 atoms (RSA, min distance 2.7 A)",
+    "c4": "2,000 structures of 32-1,024 atoms, p(N) ~ 1/N^2 (adds 10% hot liquid)",
+}
+
+
+def _generate(name):
+    from paper_2507_00528_amd import synth
+    return synth.config_structures(name)
+
+
+class Workload:
+    """Device state of one workload: batch, lists, teacher labels plus noise."""
+
+    def __init__(self, name, sizes, structures, log):
+        import torch
+        from paper_2507_00528_amd import nep, synth
+        self.name, self.sizes, self.structures = name, sizes, structures
+        self.batch = synth.Batch(structures)
+        self.S, self.N = self.batch.n_struct, self.batch.n_atom
+        self.model = nep.Model.of(sizes)
+        self.P = nep.param_count(self.model)
+        self.dev = nep.DeviceBatch(self.batch)
+        self.nbrs = nep.Neighbors(self.model, self.N)
+        self.ws = nep.workspace(self.model, self.S, self.N)
+        self.flags = torch.zeros(1, dtype=torch.int32, device="cuda")
+        self.theta = torch.tensor(synth.draw_params(self.P, synth.SEEDS["student"]), device="cuda")
+        self.teacher = torch.tensor(synth.draw_params(self.P, synth.SEEDS["teacher"]), device="cuda")
+        nep.build_neighbors(self.model, self.dev, self.nbrs, self.ws, self.flags)
+        e_t = torch.zeros(self.S, device="cuda")
+        f_t = torch.zeros(3 * self.N, device="cuda")
+        w_t = torch.zeros(6 * self.S, device="cuda")
+        nep.energy_force_virial(self.model, self.dev, self.nbrs, self.teacher, self.ws, None, e_t, f_t, w_t)
+        de, df = synth.label_noise(self.batch, synth.SEEDS["noise"])
+        self.labels = nep.Labels(e_t + torch.tensor(de, dtype=torch.float32, device="cuda"),
+                                 f_t + torch.tensor(df, dtype=torch.float32, device="cuda"), w_t)
+        torch.cuda.synchronize()
+        nep.check_flags(self.flags, f"{name} neighbors")
+        self.cnt_r = self.nbrs.cnt_rad.float().mean().item()
+        self.cnt_a = self.nbrs.cnt_ang.float().mean().item()
+        log(f"workload {name}: {self.S} structures, {self.N} atoms, mean neighbors {self.cnt_r:.2f} / "
+            f"{self.cnt_a:.2f}")
+
+    def batched(self, steps, warmup, lam, lr, stream, log, cached=False):
+        """The captured train step replayed `steps` times after `warmup`
+        replays; one event between consecutive replays."""
+        import torch
+        from paper_2507_00528_amd import nep
+        nb, ws, fl = self.nbrs, self.ws, self.flags
+        if cached:
+            nb = nep.Neighbors(self.model, self.N)
+            ws = nep.workspace(self.model, self.S, self.N)
+            fl = torch.zeros(1, dtype=torch.int32, device="cuda")
+            nep.build_neighbors(self.model, self.dev, nb, ws, fl)
+        params = self.theta.clone()
+        m, v, grad = (torch.zeros(self.P, device="cuda") for _ in range(3))
+        loss = torch.zeros(4, device="cuda")
+        step = torch.ones(1, dtype=torch.int32, device="cuda")
+        graph = nep.TrainStepGraph(self.model, self.dev, nb, self.labels, lam, params, m, v, grad, loss, step, ws,
+                                   fl, lr_start=lr, lr_stop=lr, stream=stream, cached_neighbors=cached)
+        torch.cuda.synchronize()   # inputs were filled on the default stream
+        with torch.cuda.stream(stream):
+            for _ in range(warmup):
+                graph.launch(stream)
+        stream.synchronize()
+        loss_first = loss.cpu().numpy().copy()
+        nep.check_flags(fl, f"{self.name} graph warmup")
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        evs[0].record(stream)
+        for k in range(steps):
+            graph.launch(stream)
+            evs[k + 1].record(stream)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        ms = evs[0].elapsed_time(evs[-1]) / steps
+        per = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(steps)])
+        loss_last = loss.cpu().numpy().copy()
+        nep.check_flags(fl, f"{self.name} graph replays")
+        graph.close()
+        dist = {"median_ms": float(np.median(per)), "p10_ms": float(np.percentile(per, 10)),
+                "p90_ms": float(np.percentile(per, 90))}
+        log(f"{self.name} {'cached' if cached else 'batched'}: {ms:.3f} ms/step (events), "
+            f"{1e3 * wall / steps:.3f} ms/step (wall), median {dist['median_ms']:.3f}; "
+            f"loss {loss_first[0]:.5g} -> {loss_last[0]:.5g}")
+        return ms, dist, (loss_first, loss_last)
+
+    def kernels(self, reps, lam, stream):
+        """Mean per-kernel times (HIP events on the launch stream) of the
+        unfused loss-and-gradient launches."""
+        import torch
+        from paper_2507_00528_amd import nep
+        prof = {}
+        g2 = torch.zeros(self.P, device="cuda")
+        l2 = torch.zeros(4, device="cuda")
+        for _ in range(reps):
+            for name, ms in nep.profile_loss_grad(self.model, self.dev, self.nbrs, self.theta, self.labels, lam, l2,
+                                                  g2, self.ws, self.flags, stream=stream):
+                prof.setdefault(name, []).append(ms)
+        return {k: float(np.mean(v)) for k, v in prof.items()}
+
+    def roofline(self, kern_ms, ms_step, profile_name):
+        fm = flop_model(self.sizes, self.cnt_r, self.cnt_a)
+        dom = max(kern_ms, key=kern_ms.get)
+        flops = fm.get(dom, 0.0) * self.N
+        achieved = flops / (kern_ms[dom] * 1e-3)
+        traffic = measured_traffic(dom, profile_name) if profile_name else None
+        counters = measured_counters(dom, profile_name) if profile_name else None
+        step_fpa = step_flops_formula(self.sizes, self.cnt_r, self.cnt_a)
+        step_rate = step_fpa * self.N / (ms_step * 1e-3)
+        return {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": traffic,
+                "flops_per_atom": fm.get(dom, 0.0), "units": self.N, "kernel_ms": kern_ms[dom],
+                "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED,
+                "hbm_frac": (traffic / (kern_ms[dom] * 1e-3) / PEAK_HBM) if traffic else None,
+                "counters": counters,
+                "step": {"flops_per_atom_formula": step_fpa,
+                         "flops_per_atom_kernels": float(sum(fm.values())),
+                         "achieved": step_rate / 1e12, "frac": step_rate / PEAK_FP32_VECTOR,
+                         "frac_of_nonpacked_peak": step_rate / PEAK_FP32_NONPACKED}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,10 +333,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--profile-reps", type=int, default=5)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=25.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--workload", default="c2")
+    ap.add_argument("--extra", default="c3,c4",
+                    help="further workloads measured in the same run (batched step and roofline), '' for none")
+    ap.add_argument("--extra-steps", type=int, default=20)
     ap.add_argument("--sizes", default=None, choices=[None, "large", "small", "l8"],
                     help="model sizes in place of the workload's own (l8: 3-body degrees up to 8)")
     ap.add_argument("--mode", default="full", choices=["full", "batched", "copy-probe"],
@@ -140,11 +351,21 @@ def main():
               "structures across GPUs is not part of this build.", file=sys.stderr)
         sys.exit(2)
 
-    import torch
-    from paper_2507_00528_amd import nep, synth
-
     def log(*a):
         print("[bench]", *a, file=sys.stderr, flush=True)
+
+    # the extra workloads' structures are drawn in the background while the
+    # main workload runs (geometry only: seeded RSA and lattices)
+    extra = [w for w in args.extra.split(",") if w and w != args.workload] if args.mode == "full" else []
+    gen = None
+    if extra:
+        import concurrent.futures as cf
+        import multiprocessing as mp
+        gen = cf.ProcessPoolExecutor(max_workers=len(extra), mp_context=mp.get_context("spawn"))
+        futs = {w: gen.submit(_generate, w) for w in extra}
+
+    import torch
+    from paper_2507_00528_amd import nep, synth
 
     if args.mode == "copy-probe":
         n = 512 * 1024 * 1024 // 4
@@ -160,31 +381,9 @@ def main():
     sizes = (synth.CONFIG_SIZES[args.workload] if args.sizes is None else
              {"large": synth.SIZES_LARGE, "small": synth.SIZES_SMALL, "l8": synth.SIZES_L8}[args.sizes])
     structures = synth.config_structures(args.workload)
-    batch = synth.Batch(structures)
-    S, N = batch.n_struct, batch.n_atom
-    log(f"workload {args.workload}: {S} structures, {N} atoms, generated in {time.time() - t0:.1f}s")
-    model = nep.Model.of(sizes)
-    P = nep.param_count(model)
-    dev = nep.DeviceBatch(batch)
-    nbrs = nep.Neighbors(model, N)
-    ws = nep.workspace(model, S, N)
-    flags = torch.zeros(1, dtype=torch.int32, device="cuda")
-    theta = torch.tensor(synth.draw_params(P, synth.SEEDS["student"]), device="cuda")
-    teacher = torch.tensor(synth.draw_params(P, synth.SEEDS["teacher"]), device="cuda")
-
-    # teacher labels (GPU forward) plus seeded noise
-    nep.build_neighbors(model, dev, nbrs, ws, flags)
-    e_t = torch.zeros(S, device="cuda")
-    f_t = torch.zeros(3 * N, device="cuda")
-    w_t = torch.zeros(6 * S, device="cuda")
-    nep.energy_force_virial(model, dev, nbrs, teacher, ws, None, e_t, f_t, w_t)
-    de, df = synth.label_noise(batch, synth.SEEDS["noise"])
-    labels = nep.Labels(e_t + torch.tensor(de, dtype=torch.float32, device="cuda"),
-                        f_t + torch.tensor(df, dtype=torch.float32, device="cuda"), w_t)
-    torch.cuda.synchronize()
-    nep.check_flags(flags, "neighbors")
-    cnt_r = nbrs.cnt_rad.float().mean().item()
-    cnt_a = nbrs.cnt_ang.float().mean().item()
+    log(f"workload {args.workload} generated in {time.time() - t0:.1f}s")
+    W = Workload(args.workload, sizes, structures, log)
+    S, N, P, model = W.S, W.N, W.P, W.model
     lam = (1.0, 1.0, 0.1)
     lr = 1e-3
     stream = torch.cuda.Stream()
@@ -192,76 +391,14 @@ def main():
     # reference loss and gradient at the initial parameters (eager calls)
     loss0 = torch.zeros(4, device="cuda")
     grad0 = torch.zeros(P, device="cuda")
-    nep.loss_grad(model, dev, nbrs, theta, labels, lam, loss0, grad0, ws, flags)
+    nep.loss_grad(model, W.dev, W.nbrs, W.theta, W.labels, lam, loss0, grad0, W.ws, W.flags)
     torch.cuda.synchronize()
     loss0 = loss0.cpu().numpy()
     grad0 = grad0.cpu().numpy()
 
-    # ---------------- batched: captured train step
-    params = theta.clone()
-    m = torch.zeros(P, device="cuda")
-    v = torch.zeros(P, device="cuda")
-    grad = torch.zeros(P, device="cuda")
-    loss = torch.zeros(4, device="cuda")
-    step = torch.ones(1, dtype=torch.int32, device="cuda")
-    graph = nep.TrainStepGraph(model, dev, nbrs, labels, lam, params, m, v, grad, loss, step, ws, flags,
-                               lr_start=lr, lr_stop=lr, stream=stream)
-    torch.cuda.synchronize()   # inputs were filled on the default stream
-    with torch.cuda.stream(stream):
-        for _ in range(args.warmup):
-            graph.launch(stream)
-    stream.synchronize()
-    loss_first = loss.cpu().numpy().copy()
-    nep.check_flags(flags, "graph warmup")
-    # one event between consecutive replays: the total gives ms_per_step, the
-    # differences the per-replay distribution
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    evs[0].record(stream)
-    for k in range(args.steps):
-        graph.launch(stream)
-        evs[k + 1].record(stream)
-    stream.synchronize()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ms_batched = evs[0].elapsed_time(evs[-1]) / args.steps
-    per_replay = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)])
-    dist = {"median_ms": float(np.median(per_replay)), "p10_ms": float(np.percentile(per_replay, 10)),
-            "p90_ms": float(np.percentile(per_replay, 90))}
-    loss_last = loss.cpu().numpy().copy()
-    nep.check_flags(flags, "graph replays")
-    log(f"batched: {ms_batched:.3f} ms/step (events), {1e3 * wall / args.steps:.3f} ms/step (wall), "
-        f"median {dist['median_ms']:.3f} p10 {dist['p10_ms']:.3f} p90 {dist['p90_ms']:.3f}; "
-        f"loss {loss_first[0]:.5g} -> {loss_last[0]:.5g}")
-
-    # context only: the same step with the neighbor lists built once beforehand
-    # (training positions never change); the metric above rebuilds them
-    nb_c = nep.Neighbors(model, N)
-    ws_c = nep.workspace(model, S, N)
-    fl_c = torch.zeros(1, dtype=torch.int32, device="cuda")
-    nep.build_neighbors(model, dev, nb_c, ws_c, fl_c)
-    pc = theta.clone()
-    mc_, vc_, gc_ = (torch.zeros(P, device="cuda") for _ in range(3))
-    lc_ = torch.zeros(4, device="cuda")
-    sc_ = torch.ones(1, dtype=torch.int32, device="cuda")
-    graph_c = nep.TrainStepGraph(model, dev, nb_c, labels, lam, pc, mc_, vc_, gc_, lc_, sc_, ws_c, fl_c,
-                                 lr_start=lr, lr_stop=lr, stream=stream, cached_neighbors=True)
-    torch.cuda.synchronize()   # lists and buffers come from the default stream; the replays run on `stream`
-    with torch.cuda.stream(stream):
-        for _ in range(args.warmup):
-            graph_c.launch(stream)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        graph_c.launch(stream)
-    e1.record(stream)
-    stream.synchronize()
-    nep.check_flags(fl_c, "cached-neighbor replays")
-    ms_cached = e0.elapsed_time(e1) / args.steps
-    graph_c.close()
-    log(f"cached neighbors: {ms_cached:.3f} ms/step")
+    ms_batched, dist, (loss_first, loss_last) = W.batched(args.steps, args.warmup, lam, lr, stream, log)
+    # context only: the same step with the lists built once beforehand
+    ms_cached, _, _ = W.batched(args.steps, args.warmup, lam, lr, stream, log, cached=True)
     if args.mode == "batched":
         return
 
@@ -269,15 +406,15 @@ def main():
     plain_out = None
     if not args.skip_plain:
         lib = nep._lib.load()
-        offs = batch.atom_offset
+        offs = W.batch.atom_offset
         nmax = int(np.diff(offs).max())
         ws_p = nep.workspace(model, 1, nmax)
         nb_p = nep.Neighbors(model, nmax)
         nb_c = nb_p.c()
         mc = model.c()
-        e_lab = labels.energy.cpu().numpy()
-        f_lab = labels.force.cpu().numpy().reshape(3, N)
-        w_lab = labels.virial.cpu().numpy().reshape(S, 6)
+        e_lab = W.labels.energy.cpu().numpy()
+        f_lab = W.labels.force.cpu().numpy().reshape(3, N)
+        w_lab = W.labels.virial.cpu().numpy().reshape(S, 6)
         per = []
         for k, st in enumerate(structures):
             db = nep.DeviceBatch(synth.Batch([st]))
@@ -287,7 +424,7 @@ def main():
                             torch.tensor(w_lab[k], device="cuda"))
             lam_k = (C.c_float * 3)(lam[0] / S, lam[1] * st.n / N, lam[2] / S)
             per.append((db, db.c(), lb, lb.c(), lam_k))
-        params_p = theta.clone()
+        params_p = W.theta.clone()
         m_p = torch.zeros(P, device="cuda")
         v_p = torch.zeros(P, device="cuda")
         grad_p = torch.zeros(P, device="cuda")
@@ -301,10 +438,10 @@ def main():
             gacc.zero_()
             lacc.zero_()
             for db, dbc, lb, lbc, lam_k in per:
-                rc = lib.nep_build_neighbors(C.byref(mc), C.byref(dbc), C.byref(nb_c), ptr(ws_p), ptr(flags), sp)
+                rc = lib.nep_build_neighbors(C.byref(mc), C.byref(dbc), C.byref(nb_c), ptr(ws_p), ptr(W.flags), sp)
                 rc |= lib.nep_loss_grad(C.byref(mc), C.byref(dbc), C.byref(nb_c), ptr(params_p), C.byref(lbc),
                                         C.byref(lam_k), ptr(loss_p), ptr(grad_p), None, None, None, ptr(ws_p),
-                                        ptr(flags), sp)
+                                        ptr(W.flags), sp)
                 if rc:
                     raise RuntimeError(f"plain step failed: {rc}")
                 gacc.add_(grad_p)
@@ -325,52 +462,42 @@ def main():
             ms_plain = 1e3 * (time.perf_counter() - tp) / args.plain_steps
         log(f"plain: {ms_plain:.2f} ms/step; loss at theta {loss_plain_first:.6g} vs batched {loss0[0]:.6g}; "
             f"gradient max rel diff {gdiff:.2e}")
-
         plain_out = {"value": N / (ms_plain * 1e-3), "unit": "atoms/s", "ms_per_step": ms_plain,
                      "speedup_batched_over_plain": ms_plain / ms_batched,
                      "loss_at_theta": loss_plain_first, "grad_max_rel_diff_vs_batched": gdiff}
 
     # ---------------- per-kernel timing (HIP events on the launch stream)
-    prof = {}
-    g2 = torch.zeros(P, device="cuda")
-    l2 = torch.zeros(4, device="cuda")
-    for _ in range(args.profile_reps):
-        for name, ms in nep.profile_loss_grad(model, dev, nbrs, theta, labels, lam, l2, g2, ws, flags,
-                                              stream=stream):
-            prof.setdefault(name, []).append(ms)
-    kern_ms = {k: float(np.mean(v)) for k, v in prof.items()}
-    dom = max(kern_ms, key=kern_ms.get)
-    fm = flop_model(sizes, cnt_r, cnt_a)
-    units = N
-    flops = fm.get(dom, 0.0) * units
-    achieved = flops / (kern_ms[dom] * 1e-3)
-    traffic = measured_traffic(dom, args.workload) if args.sizes is None else None
-    counters = measured_counters(dom, args.workload) if args.sizes is None else None
+    kern_ms = W.kernels(args.profile_reps, lam, stream)
+    roof = W.roofline(kern_ms, ms_batched, args.workload if args.sizes is None else None)
     log("kernels (ms): " + ", ".join(f"{k} {v:.4f}" for k, v in sorted(kern_ms.items(), key=lambda x: -x[1])))
 
-    # ---------------- CPU baseline: the FP64 oracle on a bounded sample
+    # ---------------- the other workloads: batched step and roofline
+    others = {}
+    for w in extra:
+        t1 = time.time()
+        sts = futs[w].result()
+        log(f"workload {w} ready after {time.time() - t1:.1f}s of waiting")
+        Wx = Workload(w, synth.CONFIG_SIZES[w], sts, log)
+        msx, distx, _ = Wx.batched(args.extra_steps, 3, lam, lr, stream, log)
+        msx_c, _, _ = Wx.batched(args.extra_steps, 3, lam, lr, stream, log, cached=True)
+        kx = Wx.kernels(2, lam, stream)
+        others[w] = {"workload": WORKLOAD_TEXT.get(w, w), "structures": Wx.S, "atoms": Wx.N,
+                     "ms_per_step": msx, "value": Wx.N / (msx * 1e-3), "unit": "atoms/s",
+                     "replay_distribution": distx,
+                     "cached_neighbors": {"ms_per_step": msx_c, "value": Wx.N / (msx_c * 1e-3)},
+                     "mean_neighbors_rad": Wx.cnt_r, "mean_neighbors_ang": Wx.cnt_a,
+                     "roofline": Wx.roofline(kx, msx, w), "kernels_ms": kx}
+        del Wx
+        torch.cuda.empty_cache()
+    if gen is not None:
+        gen.shutdown()
+
+    # ---------------- CPU baseline: the FP64 oracle over the host's cores
     cpu = None
     if not args.no_cpu:
-        from oracle import NEPOracle
-        o = NEPOracle(sizes)
-        th_np = theta.cpu().numpy()
-        tt_np = teacher.cpu().numpy()
-        done_atoms, spent, k = 0, 0.0, 0
-        while spent < args.cpu_seconds and k < S:
-            st = structures[k]
-            nb = o.neighbors(st)
-            pt = o.predict(tt_np, [st], [nb])
-            lab = dict(energy=pt["E"], force=pt["F"], virial=pt["W"])
-            tc = time.perf_counter()
-            o.loss_and_grad(th_np, [st], lab, lam, nbr_cache=[nb])
-            spent += time.perf_counter() - tc
-            done_atoms += st.n
-            k += 1
-        cpu = {"value": done_atoms / spent, "unit": "atoms/s", "cores": int(torch.get_num_threads()),
-               "kind": "oracle",
-               "sample": f"first {k} of {S} structures ({done_atoms} atoms), FP64 torch loss and gradient, "
-                         f"{spent:.1f}s"}
-        log(f"cpu oracle: {cpu['value']:.1f} atoms/s on {cpu['cores']} threads")
+        cpu = cpu_baseline(sizes, structures, W.theta.cpu().numpy(), W.labels.energy.cpu().numpy(),
+                           W.labels.force.cpu().numpy().reshape(3, N), W.labels.virial.cpu().numpy().reshape(S, 6),
+                           lam, args.cpu_seconds, log)
 
     value = N / (ms_batched * 1e-3)
     out = {
@@ -386,22 +513,19 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic: seeded RSA/rocksalt Sb-Te-shaped cells, teacher-NEP labels plus noise",
-        "config": {"workload": f"{args.workload}: {S} structures, {N} atoms, sizes log-uniform 32-512, "
+        "config": {"workload": f"{args.workload}: {S} structures, {N} atoms, "
+                               f"{WORKLOAD_TEXT.get(args.workload, '')}; "
                                f"NEP n_rad {sizes.n_rad} n_ang {sizes.n_ang} basis {sizes.k_rad} "
                                f"l {sizes.l3}/{sizes.l4}/{sizes.l5} hidden {sizes.hidden}",
-                   "structures": S, "atoms": N, "mean_neighbors_rad": cnt_r, "mean_neighbors_ang": cnt_a,
+                   "structures": S, "atoms": N, "mean_neighbors_rad": W.cnt_r, "mean_neighbors_ang": W.cnt_a,
                    "path": "batched HIP-graph train step (neighbors+E/F/W+loss+grad+Adam)"},
         "plain": plain_out,
-        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": traffic,
-                     "flops_per_atom": fm.get(dom, 0.0), "units": units, "kernel_ms": kern_ms[dom],
-                     "frac_of_nonpacked_peak": achieved / (PEAK_FP32_VECTOR / 2),
-                     "hbm_frac": (traffic / (kern_ms[dom] * 1e-3) / PEAK_HBM) if traffic else None,
-                     "counters": counters},
+        "roofline": roof,
         "replay_distribution": dist,
         "cached_neighbors": {"ms_per_step": ms_cached, "value": N / (ms_cached * 1e-3), "unit": "atoms/s",
                              "note": "context only: lists built once before timing"},
         "kernels_ms": kern_ms,
+        "workloads": others,
         "cpu_baseline": cpu,
         "loss": {"at_theta": float(loss0[0]), "after_warmup": float(loss_first[0]),
                  "after_steps": float(loss_last[0])},
