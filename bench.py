@@ -37,6 +37,7 @@ METRIC = "train-step atoms/s (E+F+virial+param grad), batched vs plain, 1 MI355X
 PEAK_FP32_VECTOR = 157.3e12   # MI355X fp32 vector (packed FP32), FLOP/s
 PEAK_FP32_NONPACKED = 78.6e12  # one FP32 FMA per lane per clock: 256 CUs x 4 SIMDs x 16 lanes x 2 x 2.4 GHz
 PEAK_HBM = 8.0e12             # bytes/s
+MAX_CPU_WORKERS = 15          # oracle worker processes (each opens the GPU device through torch)
 
 
 # --------------------------------------------------------------- FLOP model
@@ -166,9 +167,14 @@ def cpu_model() -> str:
 def cpu_baseline(sizes, structures, theta_np, e_lab, f_lab, w_lab, lam, budget_s, log):
     """The FP64 oracle (neighbors, loss and gradient of every structure of the
     batch) over a process pool of one worker per host core, each worker one
-    torch thread; the median of up to three full passes."""
+    torch thread; the median of up to three full passes.
+
+    Every worker imports torch, and on a ROCm host that opens the GPU device
+    even though the oracle runs on the CPU.  A GPU host allows at most 16
+    processes with the device open, this one included, so the pool takes at
+    most MAX_CPU_WORKERS of the cores."""
     import multiprocessing as mp
-    cores = len(os.sched_getaffinity(0))
+    cores = min(len(os.sched_getaffinity(0)), MAX_CPU_WORKERS)
     offs = np.cumsum([0] + [st.n for st in structures])
     tasks = []
     for k, st in enumerate(structures):
@@ -194,7 +200,8 @@ def cpu_baseline(sizes, structures, theta_np, e_lab, f_lab, w_lab, lam, budget_s
                 break
     wall = float(np.median(walls))
     log(f"cpu oracle: {atoms / wall:.1f} atoms/s on {cores} worker processes ({len(walls)} passes)")
-    return {"value": atoms / wall, "unit": "atoms/s", "cores": cores, "kind": "oracle", "cpu_model": cpu_model(),
+    return {"value": atoms / wall, "unit": "atoms/s", "cores": cores, "host_cores": len(os.sched_getaffinity(0)),
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"the whole batch: {len(structures)} structures, {atoms} atoms; neighbors, loss and "
                       f"gradient in FP64 (torch CPU), one structure per task over {cores} processes of one "
                       f"thread each; median wall time of {len(walls)} passes ({wall:.2f}s)"}
