@@ -48,7 +48,8 @@ enum {
   NEP_ERR_HIP = -5,          /* a HIP runtime call failed                     */
   NEP_ERR_WORKSPACE = -6,    /* workspace NULL or misaligned                  */
   NEP_ERR_TYPE = -7,         /* an atom type outside [0, n_types)             */
-  NEP_ERR_POSITION = -8      /* an atom outside its cell (device flag)        */
+  NEP_ERR_POSITION = -8,     /* an atom outside its cell (device flag)        */
+  NEP_ERR_SCRATCH = -9       /* batch too large for nep_loss_grad_noalloc     */
 };
 
 #define NEP_FLAG_NBR_OVERFLOW 1
@@ -198,6 +199,26 @@ int nep_loss_grad(const nep_model* model, const nep_batch* batch, const nep_neig
                   const float* params, const nep_labels* labels, const float lambda[3],
                   float* loss, float* grad, float* e_struct, float* force, float* virial,
                   void* ws, int32_t* d_flags, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the neighbor build
+ * and loss-and-gradient evaluation of nep_build_neighbors() followed by
+ * nep_loss_grad() on one workspace, with the workspace replaced by a static
+ * device array of NEP_STATIC_SCRATCH_BYTES that the library holds on each GPU
+ * it runs on until the process ends.  Arguments and outputs as in those two
+ * calls (nbrs receives the lists; d_flags is required).  No call allocates
+ * memory.  NEP_ERR_SCRATCH when nep_workspace_bytes() of the batch exceeds
+ * NEP_STATIC_SCRATCH_BYTES (64 MiB: about 18,000 atoms of the 3/4/5-body
+ * model with hidden 50, or 21,000 of the 3-body model with hidden 30).  The
+ * array is shared by every call on the same GPU and keeps the last call's
+ * contents; calls that overlap on one GPU (other streams or threads) race and
+ * must be serialised by the caller.  The stream must belong to the current
+ * device. */
+#define NEP_STATIC_SCRATCH_BYTES (64u << 20)
+int nep_loss_grad_noalloc(const nep_model* model, const nep_batch* batch, nep_neighbors* nbrs,
+                          const float* params, const nep_labels* labels, const float lambda[3],
+                          float* loss, float* grad, float* e_struct, float* force, float* virial,
+                          int32_t* d_flags, void* stream);
 
 /* One bias-corrected Adam step on P parameters (the optimizer of Sec. I):
  *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;

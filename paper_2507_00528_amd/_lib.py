@@ -54,6 +54,8 @@ SIGNATURES = [
     ("nep_vjp", C.c_int, [P(NepModel), P(NepBatch), P(NepNeighbors), VP, VP, VP, VP, VP, VP, VP]),
     ("nep_loss_grad", C.c_int, [P(NepModel), P(NepBatch), P(NepNeighbors), VP, P(NepLabels), P(F32 * 3),
                                 VP, VP, VP, VP, VP, VP, VP, VP]),
+    ("nep_loss_grad_noalloc", C.c_int, [P(NepModel), P(NepBatch), P(NepNeighbors), VP, P(NepLabels),
+                                        P(F32 * 3), VP, VP, VP, VP, VP, VP, VP]),
     ("nep_adam_step", C.c_int, [C.c_int64, VP, VP, VP, VP, F32, F32, F32, F32, I32, VP]),
     ("nep_lr_schedule", F32, [C.c_int64, F32, F32, C.c_int64, C.c_int64]),
     ("nep_md_step", C.c_int, [P(NepModel), P(NepBatch), VP, P(NepNeighbors), VP, VP, VP, VP, F32, I32, VP, VP,

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -3302,6 +3303,30 @@ int check_adam_config(const nep_adam_config* a) {
   return NEP_OK;
 }
 
+// Scratch of nep_loss_grad_noalloc: a file-scope device array, one copy per
+// GPU, held until the process ends.  Host code never passes the array's name
+// to a kernel (on the host it is only a stand-in for the symbol); it uses the
+// device address hipGetSymbolAddress returns, taken once per device with that
+// device current.
+static __device__ __align__(256) unsigned char scratch[NEP_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int static_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return NEP_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return NEP_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return NEP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -3435,6 +3460,25 @@ int nep_loss_grad(const nep_model* m, const nep_batch* b, const nep_neighbors* n
                        d_flags, nullptr, false);
 }
 
+int nep_loss_grad_noalloc(const nep_model* m, const nep_batch* b, nep_neighbors* nb, const float* params,
+                          const nep_labels* labels, const float lambda[3], float* loss, float* grad, float* e_struct,
+                          float* force, float* virial, int32_t* d_flags, void* stream) {
+  int rc = nep_model_supported(m);
+  if (rc) return rc;
+  if ((rc = check_batch(b))) return rc;
+  if (make_layout(m, find_ops(m), b->n_struct, b->n_atom).total > (size_t)NEP_STATIC_SCRATCH_BYTES)
+    return NEP_ERR_SCRATCH;
+  void* ws = nullptr;
+  if ((rc = static_scratch(&ws))) return rc;
+  Ctx c;
+  if ((rc = setup(c, m, b, ws, stream))) return rc;
+  if ((rc = check_nbrs(nb, b->n_atom))) return rc;
+  if (!params || !labels || !lambda || !loss || !grad || !d_flags) return NEP_ERR_ARG;
+  if (b->n_struct > 0 && (!labels->energy || !labels->virial)) return NEP_ERR_ARG;
+  if (b->n_atom > 0 && !labels->force) return NEP_ERR_ARG;
+  return loss_grad_seq(c, nb, params, labels, lambda, loss, grad, e_struct, force, virial, d_flags, nullptr, true);
+}
+
 int nep_adam_step(int64_t P, float* params, float* mm, float* vv, const float* grad, float lr, float beta1,
                   float beta2, float eps, int32_t step, void* stream) {
   if (P < 0 || step < 1 || !adam_hparams_ok(beta1, beta2, eps) || !std::isfinite(lr)) return NEP_ERR_ARG;
@@ -3563,6 +3607,7 @@ const char* nep_status_string(int code) {
     case NEP_ERR_WORKSPACE: return "workspace missing or not 256-byte aligned";
     case NEP_ERR_TYPE: return "atom type out of range";
     case NEP_ERR_POSITION: return "coordinate outside [0, L)";
+    case NEP_ERR_SCRATCH: return "batch needs more than the static scratch of nep_loss_grad_noalloc";
     default: return "unknown status";
   }
 }

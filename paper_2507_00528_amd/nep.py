@@ -213,6 +213,28 @@ def loss_grad(model, batch, nbrs, params, labels: Labels, lam, loss, grad, ws, f
                                      _stream(stream)), "nep_loss_grad")
 
 
+STATIC_SCRATCH_BYTES = 64 << 20   # NEP_STATIC_SCRATCH_BYTES
+
+
+def loss_grad_noalloc(model, batch, nbrs, params, labels: Labels, lam, loss, grad, flags, e_struct=None, force=None,
+                      virial=None, stream=None):
+    """Neighbor build plus loss and gradient with the library's static device
+    scratch in place of a workspace (nep_loss_grad_noalloc); nothing is
+    allocated.  Calls on one GPU share the scratch and must not overlap."""
+    P = param_count(model)
+    _want(params, torch.float32, P, "params")
+    _want(grad, torch.float32, P, "grad")
+    _want(loss, torch.float32, 4, "loss")
+    _want(flags, torch.int32, 1, "flags")
+    _want(labels.energy, torch.float32, batch.n_struct, "labels.energy")
+    _want(labels.force, torch.float32, 3 * batch.n_atom, "labels.force")
+    _want(labels.virial, torch.float32, 6 * batch.n_struct, "labels.virial")
+    _check(_lib.load().nep_loss_grad_noalloc(C.byref(model.c()), C.byref(batch.c()), C.byref(nbrs.c()),
+                                             _ptr(params), C.byref(labels.c()), C.byref(_lam(lam)), _ptr(loss),
+                                             _ptr(grad), _ptr(e_struct), _ptr(force), _ptr(virial), _ptr(flags),
+                                             _stream(stream)), "nep_loss_grad_noalloc")
+
+
 def adam_step(params, m, v, grad, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     P = params.numel()
     for t, name in ((m, "m"), (v, "v"), (grad, "grad")):

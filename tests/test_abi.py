@@ -78,7 +78,7 @@ def test_validation_rejects_before_launch():
 
 def test_status_strings_and_flags():
     lib = _lib.load()
-    for code in range(0, -9, -1):
+    for code in range(0, -10, -1):
         assert lib.nep_status_string(code).decode() not in ("", "unknown status")
     assert lib.nep_flags_status(0) == 0
     assert lib.nep_flags_status(nep.NEP_FLAG_NBR_OVERFLOW) == -3
@@ -115,3 +115,27 @@ def test_graph_create_rejects_bad_adam_config_before_launch():
     assert lib.nep_adam_step(10, fake, fake, fake, fake, 1e-3, 1.0, 0.999, 1e-8, 1, None) == -1
     assert lib.nep_adam_step(10, fake, fake, fake, fake, float("inf"), 0.9, 0.999, 1e-8, 1, None) == -1
     assert lib.nep_flags_status(nep.NEP_FLAG_STEP) == -1
+
+
+def test_noalloc_rejects_batches_beyond_its_static_scratch_on_the_host():
+    """nep_loss_grad_noalloc checks the batch against its 64 MiB static scratch
+    before any HIP call (no device is touched here)."""
+    lib = _lib.load()
+    m = nep.Model.of(synth.SIZES_LARGE)
+    fake = C.c_void_p(0x100000)
+    n_atom = 40000
+    assert nep.workspace_bytes(m, 100, n_atom) > nep.STATIC_SCRATCH_BYTES
+    b = _lib.NepBatch(100, n_atom, fake, fake, fake, fake, None, 0)
+    nb = _lib.NepNeighbors(fake, fake, fake, fake)
+    lab = _lib.NepLabels(fake, fake, fake)
+    lam = (C.c_float * 3)(1.0, 1.0, 0.1)
+    rc = lib.nep_loss_grad_noalloc(C.byref(m.c()), C.byref(b), C.byref(nb), fake, C.byref(lab), C.byref(lam),
+                                   fake, fake, None, None, None, fake, None)
+    assert rc == -9
+    assert lib.nep_status_string(-9).decode() != "unknown status"
+    # an unsupported model is rejected first
+    bad = nep.Model.of(synth.SIZES_SMALL)
+    bad.k_rad = 7
+    rc = lib.nep_loss_grad_noalloc(C.byref(bad.c()), C.byref(b), C.byref(nb), fake, C.byref(lab), C.byref(lam),
+                                   fake, fake, None, None, None, fake, None)
+    assert rc == -1
