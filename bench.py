@@ -252,9 +252,10 @@ class Workload:
         log(f"workload {name}: {self.S} structures, {self.N} atoms, mean neighbors {self.cnt_r:.2f} / "
             f"{self.cnt_a:.2f}")
 
-    def batched(self, steps, warmup, lam, lr, stream, log, cached=False):
+    def batched(self, steps, warmup, lam, lr, stream, log, cached=False, persistent=False):
         """The captured train step replayed `steps` times after `warmup`
-        replays; one event between consecutive replays."""
+        replays; one event between consecutive replays.  persistent: the step
+        after the neighbor build as one persistent launch."""
         import torch
         from paper_2507_00528_amd import nep
         nb, ws, fl = self.nbrs, self.ws, self.flags
@@ -268,7 +269,8 @@ class Workload:
         loss = torch.zeros(4, device="cuda")
         step = torch.ones(1, dtype=torch.int32, device="cuda")
         graph = nep.TrainStepGraph(self.model, self.dev, nb, self.labels, lam, params, m, v, grad, loss, step, ws,
-                                   fl, lr_start=lr, lr_stop=lr, stream=stream, cached_neighbors=cached)
+                                   fl, lr_start=lr, lr_stop=lr, stream=stream, cached_neighbors=cached,
+                                   persistent=persistent)
         torch.cuda.synchronize()   # inputs were filled on the default stream
         with torch.cuda.stream(stream):
             for _ in range(warmup):
@@ -293,10 +295,20 @@ class Workload:
         graph.close()
         dist = {"median_ms": float(np.median(per)), "p10_ms": float(np.percentile(per, 10)),
                 "p90_ms": float(np.percentile(per, 90))}
-        log(f"{self.name} {'cached' if cached else 'batched'}: {ms:.3f} ms/step (events), "
+        log(f"{self.name} {'cached' if cached else 'batched'}{' persistent' if persistent else ''}: "
+            f"{ms:.3f} ms/step (events), "
             f"{1e3 * wall / steps:.3f} ms/step (wall), median {dist['median_ms']:.3f}; "
             f"loss {loss_first[0]:.5g} -> {loss_last[0]:.5g}")
         return ms, dist, (loss_first, loss_last)
+
+    def both_paths(self, steps, warmup, lam, lr, stream, log):
+        from paper_2507_00528_amd import nep
+        out = {"graph": self.batched(steps, warmup, lam, lr, stream, log)}
+        try:
+            out["persistent"] = self.batched(steps, warmup, lam, lr, stream, log, persistent=True)
+        except nep.NEPError as e:   # a batch or model the persistent step does not cover
+            log(f"{self.name}: no persistent step ({e})")
+        return out
 
     def kernels(self, reps, lam, stream):
         """Mean per-kernel times (HIP events on the launch stream) of the
@@ -403,7 +415,11 @@ def main():
     loss0 = loss0.cpu().numpy()
     grad0 = grad0.cpu().numpy()
 
-    ms_batched, dist, (loss_first, loss_last) = W.batched(args.steps, args.warmup, lam, lr, stream, log)
+    # the two forms of the captured step: separate launches, and the step after
+    # the neighbor build as one persistent launch; the faster one is the value
+    paths = W.both_paths(args.steps, args.warmup, lam, lr, stream, log)
+    best = min(paths, key=lambda k: paths[k][0])
+    ms_batched, dist, (loss_first, loss_last) = paths[best]
     # context only: the same step with the lists built once beforehand
     ms_cached, _, _ = W.batched(args.steps, args.warmup, lam, lr, stream, log, cached=True)
     if args.mode == "batched":
@@ -485,11 +501,14 @@ def main():
         sts = futs[w].result()
         log(f"workload {w} ready after {time.time() - t1:.1f}s of waiting")
         Wx = Workload(w, synth.CONFIG_SIZES[w], sts, log)
-        msx, distx, _ = Wx.batched(args.extra_steps, 3, lam, lr, stream, log)
+        px = Wx.both_paths(args.extra_steps, 3, lam, lr, stream, log)
+        bx = min(px, key=lambda k: px[k][0])
+        msx, distx, _ = px[bx]
         msx_c, _, _ = Wx.batched(args.extra_steps, 3, lam, lr, stream, log, cached=True)
         kx = Wx.kernels(2, lam, stream)
         others[w] = {"workload": WORKLOAD_TEXT.get(w, w), "structures": Wx.S, "atoms": Wx.N,
-                     "ms_per_step": msx, "value": Wx.N / (msx * 1e-3), "unit": "atoms/s",
+                     "ms_per_step": msx, "value": Wx.N / (msx * 1e-3), "unit": "atoms/s", "path": bx,
+                     "step_paths_ms": {k: v[0] for k, v in px.items()},
                      "replay_distribution": distx,
                      "cached_neighbors": {"ms_per_step": msx_c, "value": Wx.N / (msx_c * 1e-3)},
                      "mean_neighbors_rad": Wx.cnt_r, "mean_neighbors_ang": Wx.cnt_a,
@@ -525,7 +544,9 @@ def main():
                                f"NEP n_rad {sizes.n_rad} n_ang {sizes.n_ang} basis {sizes.k_rad} "
                                f"l {sizes.l3}/{sizes.l4}/{sizes.l5} hidden {sizes.hidden}",
                    "structures": S, "atoms": N, "mean_neighbors_rad": W.cnt_r, "mean_neighbors_ang": W.cnt_a,
-                   "path": "batched HIP-graph train step (neighbors+E/F/W+loss+grad+Adam)"},
+                   "path": f"batched HIP-graph train step (neighbors+E/F/W+loss+grad+Adam), {best} form"},
+        "step_paths": {k: {"ms_per_step": v[0], "value": N / (v[0] * 1e-3), "replay_distribution": v[1]}
+                       for k, v in paths.items()},
         "plain": plain_out,
         "roofline": roof,
         "replay_distribution": dist,

@@ -58,6 +58,8 @@ enum {
 #define NEP_FLAG_TYPE 8
 #define NEP_FLAG_POSITION 16
 #define NEP_FLAG_STEP 32   /* a captured step replayed with a step counter below 1 */
+#define NEP_FLAG_BARRIER 64   /* the persistent step's grid barrier timed out (its blocks were not all
+                                 resident at once); the replay stopped early and wrote no update */
 
 /* NEP hyper-parameters, as counts (Sec. II.B, Appendix A):
  *   n_rad radial channels q_n, n = 0..n_rad-1              (Eq. 5)
@@ -278,6 +280,17 @@ typedef struct {
  * nep_build_neighbors() call with the same nbrs and ws produced.  Training
  * positions never change, so this is the step with cached lists. */
 #define NEP_GRAPH_CACHED_NEIGHBORS 1
+
+/* graph_flags bit NEP_GRAPH_PERSISTENT: everything after the neighbor build
+ * (species order, forward, force gather, per-structure sums and loss of
+ * Eqs. 9-12, adjoint, gradient reductions and Adam) runs as one persistent
+ * launch whose phases are separated by a software grid barrier, in place of
+ * about ten separate launches.  The grid takes as many blocks as are resident
+ * at once.  Same results as the separate launches up to the order of
+ * floating-point sums.  NEP_ERR_ARG for triclinic batches (tilt != NULL),
+ * empty batches and models with 3-body degrees l > 4; the caller then uses
+ * the separate launches.  A barrier wait beyond 2 s raises NEP_FLAG_BARRIER. */
+#define NEP_GRAPH_PERSISTENT 2
 
 int nep_train_step_graph_create(const nep_model* model, const nep_batch* batch, nep_neighbors* nbrs,
                                 const nep_labels* labels, const float lambda[3], float* params,

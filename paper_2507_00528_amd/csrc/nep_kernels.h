@@ -14,7 +14,7 @@
 
 namespace nep {
 
-enum : int { FL_OVERFLOW = 1, FL_NONFINITE = 2, FL_BOX = 4, FL_TYPE = 8, FL_POS = 16, FL_STEP = 32 };
+enum : int { FL_OVERFLOW = 1, FL_NONFINITE = 2, FL_BOX = 4, FL_TYPE = 8, FL_POS = 16, FL_STEP = 32, FL_BARRIER = 64 };
 
 // ---------------------------------------------------------------- arguments
 struct NbrArgs {

@@ -881,8 +881,9 @@ __global__ __launch_bounds__(256) void k_reverse(RevArgs a) {
 // similar pair counts, so the pair loops of its 8 atoms end together.  The
 // key of atom i is t * kOrdBuckets + (kOrdBuckets - 1 - min(nA_i, kOrdBuckets - 1)),
 // and a counting sort over keys keeps the layout deterministic.
-constexpr int kOrdBlk = 1024;
+constexpr int kOrdBlk = 1024;      // atoms per order block
 constexpr int kOrdBuckets = 64;
+constexpr int kOrdMaxK = 8 * kOrdBuckets;   // keys of up to 8 species
 constexpr int kSegAlign = 32;  // species segments start on multiples of the atoms per block
 
 __device__ __forceinline__ int order_key(int t, int T, int nA) {
@@ -890,123 +891,190 @@ __device__ __forceinline__ int order_key(int t, int T, int nA) {
   return t * kOrdBuckets + (kOrdBuckets - 1 - min(max(nA, 0), kOrdBuckets - 1));
 }
 
-__global__ __launch_bounds__(kOrdBlk) void k_order_count(int N, int Npad, int T, const int* __restrict__ type,
-                                                         const int* __restrict__ cntA, int* __restrict__ blkcnt,
-                                                         int* __restrict__ order) {
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < Npad; q += gridDim.x * blockDim.x) order[q] = -1;
-  const int K = T * kOrdBuckets;
-  __shared__ int cnt[8 * kOrdBuckets];
-  for (int q = threadIdx.x; q < K; q += blockDim.x) cnt[q] = 0;
+struct OrderArgs {
+  int N, Npad, T, nblk;
+  const int* type;
+  const int* cntA;
+  int* blk;     // [nblk][K] key counts, then offsets
+  int* seg;     // [2T] species segment start and count
+  int* order;   // [Npad]
+};
+
+// LDS of the order bodies (ints)
+constexpr int kOrdCountLds = kOrdMaxK;
+constexpr int kOrdScanLds = 2 * kOrdMaxK + 16;
+constexpr int kOrdScatterLds = (kOrdBlk / kWave) * kOrdMaxK;
+
+// Key counts of order block ob (kOrdBlk atoms).
+template <int NT>
+__device__ __forceinline__ void order_count_body(const OrderArgs& a, int ob, int* cnt) {
+  const int K = a.T * kOrdBuckets;
+  for (int q = threadIdx.x; q < K; q += NT) cnt[q] = 0;
   __syncthreads();
-  const int i = blockIdx.x * kOrdBlk + threadIdx.x;
-  if (i < N) {
-    const int key = order_key(type[i], T, cntA[i]);
-    if (key >= 0) atomicAdd(&cnt[key], 1);
+  for (int u = 0; u < kOrdBlk; u += NT) {
+    const int i = ob * kOrdBlk + u + threadIdx.x;
+    if (i < a.N) {
+      const int key = order_key(a.type[i], a.T, a.cntA[i]);
+      if (key >= 0) atomicAdd(&cnt[key], 1);
+    }
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < K; q += blockDim.x) blkcnt[(size_t)blockIdx.x * K + q] = cnt[q];
+  for (int q = threadIdx.x; q < K; q += NT) a.blk[(size_t)ob * K + q] = cnt[q];
+  __syncthreads();
 }
 
-// One block, one thread per key: key totals, their exclusive scan in key
-// order with each species segment starting on a multiple of 8 atoms, then
-// the per-block offsets.  seg[2t], seg[2t+1] = start and count of species t.
-__global__ __launch_bounds__(8 * kOrdBuckets) void k_order_scan(int nblk, int T, int* __restrict__ blk,
-                                                               int* __restrict__ seg) {
-  constexpr int NT = 8 * kOrdBuckets;
-  const int K = T * kOrdBuckets;
-  // each bucket's rows are split into P parts, one thread per (bucket, part)
+// One block: key totals, their exclusive scan in key order with each species
+// segment starting on a multiple of kSegAlign atoms, then the per-block
+// offsets.  seg[2t], seg[2t+1] = start and count of species t.  Each key's
+// rows are split into P parts; a thread takes (key, part) slots.
+template <int NT>
+__device__ __forceinline__ void order_scan_body(const OrderArgs& a, int* sh) {
+  static_assert(2 * NT >= kOrdMaxK, "two keys per thread");
+  const int K = a.T * kOrdBuckets;
   const int P = max(1, NT / K);
-  const int k = threadIdx.x % K, p = threadIdx.x / K;
-  const bool act = threadIdx.x < K * P;
-  const int b0 = (int)((long long)nblk * p / P), b1 = (int)((long long)nblk * (p + 1) / P);
-  __shared__ int part[NT];
-  __shared__ int sc[NT];
-  __shared__ int sstart[9];
-  int mine = 0;
-  if (act)
+  int* part = sh;                 // [K * P] row sums of each slot
+  int* sc = sh + kOrdMaxK;        // [K] inclusive scan of the key totals
+  int* sstart = sc + kOrdMaxK;    // [8]
+  const int nslot = K * P;
+  // slot q = p K + k of this thread: q = threadIdx.x + r NT
+  for (int q = threadIdx.x; q < nslot; q += NT) {
+    const int k = q % K, p = q / K;
+    const int b0 = (int)((long long)a.nblk * p / P), b1 = (int)((long long)a.nblk * (p + 1) / P);
+    int mine = 0;
     for (int b = b0; b < b1; b += 8) {
       int v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = b + u < b1 ? blk[(size_t)(b + u) * K + k] : 0;
+      for (int u = 0; u < 8; ++u) v[u] = b + u < b1 ? a.blk[(size_t)(b + u) * K + k] : 0;
 #pragma unroll
       for (int u = 0; u < 8; ++u) mine += v[u];
     }
-  if (act) part[p * K + k] = mine;
+    part[q] = mine;
+  }
   __syncthreads();
-  int tot = 0, before = 0;   // bucket total, and the rows of earlier parts
-  if (act)
-    for (int q = 0; q < P; ++q) {
-      const int v = part[q * K + k];
-      tot += v;
-      before += q < p ? v : 0;
-    }
-  sc[threadIdx.x] = threadIdx.x < K ? tot : 0;
+  // key totals, two keys per thread (K <= 512), then an inclusive scan of the
+  // pair sums (Hillis-Steele over the 256 threads)
+  int tot2[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int k = 2 * threadIdx.x + h;
+    int t = 0;
+    if (k < K)
+      for (int p = 0; p < P; ++p) t += part[p * K + k];
+    tot2[h] = t;
+  }
+  sc[threadIdx.x] = tot2[0] + tot2[1];
   __syncthreads();
-  // inclusive scan over the buckets (Hillis-Steele)
   for (int d = 1; d < NT; d <<= 1) {
     const int v = (int)threadIdx.x >= d ? sc[threadIdx.x - d] : 0;
     __syncthreads();
     sc[threadIdx.x] += v;
     __syncthreads();
   }
+  const int incl_pair = sc[threadIdx.x];
+  __syncthreads();
+  // expand to per-key inclusive sums
+  {
+    const int k0 = 2 * threadIdx.x;
+    if (k0 < K) sc[k0] = incl_pair - tot2[1];
+    if (k0 + 1 < K) sc[k0 + 1] = incl_pair;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     int start = 0;
-    for (int t = 0; t < T; ++t) {
+    for (int t = 0; t < a.T; ++t) {
       const int lo = t == 0 ? 0 : sc[t * kOrdBuckets - 1];
       const int cnt = sc[(t + 1) * kOrdBuckets - 1] - lo;
       sstart[t] = start - lo;   // aligned start minus the unaligned prefix
-      seg[2 * t] = start;
-      seg[2 * t + 1] = cnt;
+      a.seg[2 * t] = start;
+      a.seg[2 * t + 1] = cnt;
       start += (cnt + kSegAlign - 1) / kSegAlign * kSegAlign;
     }
   }
   __syncthreads();
-  if (act) {
+  for (int q = threadIdx.x; q < nslot; q += NT) {
+    const int k = q % K, p = q / K;
+    const int b0 = (int)((long long)a.nblk * p / P), b1 = (int)((long long)a.nblk * (p + 1) / P);
+    int before = 0, tot = 0;   // rows of earlier parts, and the key's total
+    for (int pp = 0; pp < P; ++pp) {
+      const int v = part[pp * K + k];
+      tot += v;
+      before += pp < p ? v : 0;
+    }
     int off = sstart[k / kOrdBuckets] + sc[k] - tot + before;
     for (int b = b0; b < b1; b += 8) {
       int v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = b + u < b1 ? blk[(size_t)(b + u) * K + k] : 0;
+      for (int u = 0; u < 8; ++u) v[u] = b + u < b1 ? a.blk[(size_t)(b + u) * K + k] : 0;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        if (b + u < b1) blk[(size_t)(b + u) * K + k] = off;
+        if (b + u < b1) a.blk[(size_t)(b + u) * K + k] = off;
         off += v[u];
       }
     }
   }
+  __syncthreads();
 }
 
-// Rank of each atom among the atoms of its key: lanes before it in its
-// wavefront (one ballot per distinct key in the wavefront), then the
-// wavefronts before it in the block.
-__global__ __launch_bounds__(kOrdBlk) void k_order_scatter(int N, int T, const int* __restrict__ type,
-                                                           const int* __restrict__ cntA,
-                                                           const int* __restrict__ blkoff, int* __restrict__ order) {
-  constexpr int NW = kOrdBlk / kWave;
-  __shared__ int wcnt[NW][8 * kOrdBuckets];
-  const int K = T * kOrdBuckets;
-  const int i = blockIdx.x * kOrdBlk + threadIdx.x;
+// Rank of each atom of order block ob among the atoms of its key: lanes
+// before it in its wavefront (one ballot per distinct key in the wavefront),
+// then the wavefronts before it in the block.  The block's kOrdBlk atoms are
+// taken NT at a time; wcnt holds [kOrdBlk / 64][K] counts.
+template <int NT>
+__device__ __forceinline__ void order_scatter_body(const OrderArgs& a, int ob, int* wcnt) {
+  constexpr int NR = kOrdBlk / NT;   // rounds
+  constexpr int NWR = NT / kWave;    // wavefronts per round
+  const int K = a.T * kOrdBuckets;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  for (int q = threadIdx.x; q < NW * 8 * kOrdBuckets; q += blockDim.x) (&wcnt[0][0])[q] = 0;
+  for (int q = threadIdx.x; q < (kOrdBlk / kWave) * K; q += NT) wcnt[q] = 0;
   __syncthreads();
-  const int key = i < N ? order_key(type[i], T, cntA[i]) : -1;
+  int key[NR], rank[NR];
   const unsigned long long below = (1ull << lane) - 1ull;
-  int rank = 0;
-  unsigned long long rem = __ballot(key >= 0);
-  while (rem) {
-    const int leader = __ffsll(rem) - 1;
-    const int kk = __shfl(key, leader, kWave);
-    const unsigned long long m = __ballot(key == kk);
-    if (key == kk) rank = __popcll(m & below);
-    if (lane == leader) wcnt[wid][kk] = __popcll(m);
-    rem &= ~m;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int i = ob * kOrdBlk + r * NT + threadIdx.x;
+    key[r] = i < a.N ? order_key(a.type[i], a.T, a.cntA[i]) : -1;
+    rank[r] = 0;
+    const int vw = r * NWR + wid;
+    unsigned long long rem = __ballot(key[r] >= 0);
+    while (rem) {
+      const int leader = __ffsll(rem) - 1;
+      const int kk = __shfl(key[r], leader, kWave);
+      const unsigned long long m = __ballot(key[r] == kk);
+      if (key[r] == kk) rank[r] = __popcll(m & below);
+      if (lane == leader) wcnt[vw * K + kk] = __popcll(m);
+      rem &= ~m;
+    }
   }
   __syncthreads();
-  if (key >= 0) {
-    int before = 0;
-    for (int w = 0; w < wid; ++w) before += wcnt[w][key];
-    order[blkoff[(size_t)blockIdx.x * K + key] + before + rank] = i;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (key[r] >= 0) {
+      const int i = ob * kOrdBlk + r * NT + threadIdx.x;
+      const int vw = r * NWR + wid;
+      int before = 0;
+      for (int w = 0; w < vw; ++w) before += wcnt[w * K + key[r]];
+      a.order[a.blk[(size_t)ob * K + key[r]] + before + rank[r]] = i;
+    }
   }
+  __syncthreads();
+}
+
+// the separate kernels: a block of kOrdBlk threads per order block, 512
+// threads for the scan
+__global__ __launch_bounds__(kOrdBlk) void k_order_count(OrderArgs a) {
+  __shared__ int cnt[kOrdCountLds];
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < a.Npad; q += gridDim.x * blockDim.x) a.order[q] = -1;
+  order_count_body<kOrdBlk>(a, blockIdx.x, cnt);
+}
+
+__global__ __launch_bounds__(512) void k_order_scan(OrderArgs a) {
+  __shared__ int sh[kOrdScanLds];
+  order_scan_body<512>(a, sh);
+}
+
+__global__ __launch_bounds__(kOrdBlk) void k_order_scatter(OrderArgs a) {
+  __shared__ int wcnt[kOrdScatterLds];
+  order_scatter_body<kOrdBlk>(a, blockIdx.x, wcnt);
 }
 
 // ================================================================= helpers
@@ -1140,13 +1208,14 @@ struct GroupCtx {
 };
 
 // lane roles and the atom of this lane; every lane of the block stays alive
-__device__ __forceinline__ GroupCtx group_ctx(const int* __restrict__ order, const int* __restrict__ type, int Npad) {
+__device__ __forceinline__ GroupCtx group_ctx(const int* __restrict__ order, const int* __restrict__ type, int Npad,
+                                              int vb) {
   GroupCtx c;
   c.s = threadIdx.x & (kLPA - 1);
   c.g = c.s >> 2;
   c.p = c.s & 3;
   c.al = threadIdx.x / kLPA;
-  c.pa = blockIdx.x * kAPB + c.al;
+  c.pa = vb * kAPB + c.al;
   const int iraw = c.pa < Npad ? order[c.pa] : -1;
   c.valid = iraw >= 0;
   const unsigned long long vm = __ballot(c.valid);
@@ -1157,11 +1226,11 @@ __device__ __forceinline__ GroupCtx group_ctx(const int* __restrict__ order, con
   return c;
 }
 
-// Species of the block's atoms.  Segments start on block boundaries, so a
+// Species of block vb's atoms.  Segments start on block boundaries, so a
 // block holds one species, and its first position is an atom unless the
 // whole block is padding.
-__device__ __forceinline__ int block_species(const int* __restrict__ order, const int* __restrict__ type) {
-  const int ip = order[blockIdx.x * kAPB];
+__device__ __forceinline__ int block_species(const int* __restrict__ order, const int* __restrict__ type, int vb) {
+  const int ip = order[vb * kAPB];
   return ip >= 0 ? type[ip] : 0;
 }
 
@@ -1189,14 +1258,14 @@ __device__ __forceinline__ void stage_weights(float* wl, const float* __restrict
 // gives E_i and E' = dE_i/dG (D1.1-D1.5).  With forces on, every listed
 // pair's partial force f_ij = dE_i/dr_ij is stored (C3.6) with this atom's
 // share -sum_j f_ij (x) r_ij of the virial.
+// Block vb (32 atoms of the species order); lds: lds_forward bytes.
 template <class C, bool kTri>
-__global__ __launch_bounds__(256, 3) void k_forward(FwdArgs a) {
+__device__ __forceinline__ void forward_body(const FwdArgs& a, int vb, float* lds) {
   constexpr int T = C::T, NR = C::NR, NA = C::NA, KR = C::KR, KA = C::KA, Y = C::Y, D = C::D, LM = C::LMAX;
   constexpr int L3 = C::L3, L4 = C::L4, L5 = C::L5;
   using HS = HSplit<LM>;
   constexpr int YG = HS::YG;
   constexpr int DP = (D + 3) & ~3;
-  extern __shared__ __align__(16) float lds[];
   const int H = a.H;
   const int WS = H * DP + 2 * H;
   constexpr int RW = DP + NA * Y;         // LDS row per atom: G, S
@@ -1205,9 +1274,9 @@ __global__ __launch_bounds__(256, 3) void k_forward(FwdArgs a) {
   float* wl = lds + CT::size;            // [WS] of the block's species
   float* rows = wl + WS;                 // [kAPB][RW]
   stage_ctab<T, NA, KA>(ctab, a.cA);
-  if (a.do_mlp) stage_weights(wl, a.nn, a.nn_stride, block_species(a.order, a.type), H, D, DP);
+  if (a.do_mlp) stage_weights(wl, a.nn, a.nn_stride, block_species(a.order, a.type, vb), H, D, DP);
   __syncthreads();
-  const GroupCtx w = group_ctx(a.order, a.type, a.Npad);
+  const GroupCtx w = group_ctx(a.order, a.type, a.Npad, vb);
   const int N = a.N, i = w.i, I = w.I, pa = w.pa, s = w.s, g = w.g;
   float* row = rows + w.al * RW;
   float* rowS = row + DP;
@@ -1549,6 +1618,12 @@ __global__ __launch_bounds__(256, 3) void k_forward(FwdArgs a) {
   }
 }
 
+template <class C, bool kTri>
+__global__ __launch_bounds__(256, 3) void k_forward(FwdArgs a) {
+  extern __shared__ __align__(16) float lds[];
+  forward_body<C, kTri>(a, blockIdx.x, lds);
+}
+
 // F_i = sum_j f_ij - f_ji (Eq. 3), gathering f_ji through the reverse index;
 // 16 lanes per atom take list slots s, s + 16, ... (more loads in flight for
 // the dependent reverse reads) and are summed by DPP.
@@ -1574,11 +1649,12 @@ __device__ __forceinline__ void gather_list(int i, int s, const uint32_t* __rest
   }
 }
 
-__global__ __launch_bounds__(256) void k_force_gather(int N, PairLists nb, const float* __restrict__ fR,
-                                                      const float* __restrict__ fA, float* __restrict__ F,
-                                                      float* __restrict__ Fuser) {
+// logical block vb: atoms vb * 16 ..
+__device__ __forceinline__ void gather_body(int vb, int N, const PairLists& nb, const float* __restrict__ fR,
+                                            const float* __restrict__ fA, float* __restrict__ F,
+                                            float* __restrict__ Fuser) {
   const int s = threadIdx.x % kGatherLPA;
-  const int i = xcd_block() * (256 / kGatherLPA) + threadIdx.x / kGatherLPA;
+  const int i = vb * (256 / kGatherLPA) + threadIdx.x / kGatherLPA;
   float fx = 0.f, fy = 0.f, fz = 0.f;
   if (i < N) {
     gather_list(i, s, nb.idxR, nb.cntR, nb.revR, nb.capR, fR, fx, fy, fz);
@@ -1603,6 +1679,12 @@ __global__ __launch_bounds__(256) void k_force_gather(int N, PairLists nb, const
   }
 }
 
+__global__ __launch_bounds__(256) void k_force_gather(int N, PairLists nb, const float* __restrict__ fR,
+                                                      const float* __restrict__ fA, float* __restrict__ F,
+                                                      float* __restrict__ Fuser) {
+  gather_body(xcd_block(), N, nb, fR, fA, F, Fuser);
+}
+
 // ==================================================================== loss
 // One block per structure: E(n), W(n) and, with labels, the loss terms of
 // Eqs. 10-12 and the cotangents dL/dE(n), dL/dF_i, dL/dW(n).  Sums run in
@@ -1611,9 +1693,10 @@ constexpr int kRedBlk = 256;
 
 // Loss of Eqs. 9-12 from the per-structure partials, float64 in a fixed
 // order (one block).
+constexpr int kLossLds = 3 * kRedBlk * sizeof(double);
 __device__ void loss_final_block(int S, int N, float le, float lf, float lv, const double* lpart, float* loss,
-                                 int* flags) {
-  __shared__ double red[3][kRedBlk];
+                                 int* flags, void* lds) {
+  double (*red)[kRedBlk] = reinterpret_cast<double (*)[kRedBlk]>(lds);
   double acc[3] = {0, 0, 0};
   for (int s = threadIdx.x; s < S; s += kRedBlk)
     for (int q = 0; q < 3; ++q) acc[q] += lpart[3 * s + q];
@@ -1708,9 +1791,10 @@ __device__ __forceinline__ void struct_reduce(double (*red)[kRedBlk], const doub
 // Chunk partials of the large structures: a chunk of kStructChunk atoms
 // meets at most two structures of 2 kStructChunk atoms or more, those of its
 // first and last atoms (slots 0 and 1).
-__global__ __launch_bounds__(kRedBlk) void k_struct_part(StructArgs a) {
-  __shared__ double red[8][kRedBlk];
-  const int c0 = blockIdx.x * kStructChunk, c1 = min(c0 + kStructChunk, a.N);
+// chunk vb; lds: 8 kRedBlk doubles
+__device__ __forceinline__ void struct_part_body(const StructArgs& a, int vb, void* lds) {
+  double (*red)[kRedBlk] = reinterpret_cast<double (*)[kRedBlk]>(lds);
+  const int c0 = vb * kStructChunk, c1 = min(c0 + kStructChunk, a.N);
   const int sa = find_struct(a.aoff, a.S, c0), sb = find_struct(a.aoff, a.S, c1 - 1);
   for (int h = 0; h < 2; ++h) {
     const int st = h ? sb : sa;
@@ -1720,14 +1804,20 @@ __global__ __launch_bounds__(kRedBlk) void k_struct_part(StructArgs a) {
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     struct_accumulate(a, max(a0, c0), min(a1, c1), acc);
     struct_reduce(red, acc);
-    if (threadIdx.x < 8) a.spart[(2 * (size_t)blockIdx.x + h) * 8 + threadIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x < 8) a.spart[(2 * (size_t)vb + h) * 8 + threadIdx.x] = red[threadIdx.x][0];
     __syncthreads();
   }
 }
 
-__global__ __launch_bounds__(kRedBlk) void k_struct(StructArgs a) {
+__global__ __launch_bounds__(kRedBlk) void k_struct_part(StructArgs a) {
   __shared__ double red[8][kRedBlk];
-  const int s = blockIdx.x;
+  struct_part_body(a, blockIdx.x, red);
+}
+
+constexpr int kStructLds = 8 * kRedBlk * sizeof(double);
+// structure s; lds: kStructLds bytes
+__device__ __forceinline__ void struct_body(const StructArgs& a, int s, void* lds) {
+  double (*red)[kRedBlk] = reinterpret_cast<double (*)[kRedBlk]>(lds);
   const int a0 = a.aoff[s], a1 = a.aoff[s + 1];
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const bool lab = a.Et != nullptr;
@@ -1771,12 +1861,19 @@ __global__ __launch_bounds__(kRedBlk) void k_struct(StructArgs a) {
       a.lpart[3 * s + 2] = lv;
     }
   }
+  __syncthreads();   // red is read above before the next use of the LDS
+}
+
+__global__ __launch_bounds__(kRedBlk) void k_struct(StructArgs a) {
+  __shared__ double red[8][kRedBlk];
+  struct_body(a, blockIdx.x, red);
 }
 
 __global__ __launch_bounds__(kRedBlk) void k_loss_final(int S, int N, float le, float lf, float lv,
                                                         const double* __restrict__ lpart, float* __restrict__ loss,
                                                         int* __restrict__ flags) {
-  loss_final_block(S, N, le, lf, lv, lpart, loss, flags);
+  __shared__ double red[3][kRedBlk];
+  loss_final_block(S, N, le, lf, lv, lpart, loss, flags, red);
 }
 
 // ================================================================= adjoint
@@ -1799,8 +1896,9 @@ __global__ __launch_bounds__(kRedBlk) void k_loss_final(int S, int N, float le, 
 //            coupling that Algorithm 1 enumerates).
 // Outputs: per-atom vectors for the outer-product sums (W0, c^R) and, per
 // wavefront, the sums of the c^A, b0, w1, b1 partials over its 8 atoms.
+// Block vb (32 atoms of the species order); lds: lds_adjoint bytes.
 template <class C, bool kTri>
-__global__ __launch_bounds__(256, C::ADJ_WAVES) void k_adjoint(AdjArgs a) {
+__device__ __forceinline__ void adjoint_body(const AdjArgs& a, int vb, float* lds) {
   constexpr int T = C::T, NR = C::NR, NA = C::NA, KR = C::KR, KA = C::KA, Y = C::Y, D = C::D, LM = C::LMAX;
   constexpr int L3 = C::L3, L4 = C::L4, L5 = C::L5;
   using HS = HSplit<LM>;
@@ -1809,7 +1907,6 @@ __global__ __launch_bounds__(256, C::ADJ_WAVES) void k_adjoint(AdjArgs a) {
   constexpr int NAH = (NA + 1) / 2;          // channels per lane in the coefficient pass
   constexpr int RW = DP + 2 * NA * Y;        // LDS row per atom: Gdot, Sbar, A
   constexpr int PSA = T * NA * KA;
-  extern __shared__ __align__(16) float lds[];
   const int H = a.H;
   const int WS = H * DP + 2 * H;
   using CT = CTab<T, NA, KA>;
@@ -1817,12 +1914,12 @@ __global__ __launch_bounds__(256, C::ADJ_WAVES) void k_adjoint(AdjArgs a) {
   float* wl = lds + CT::size;            // [WS] of the block's species
   float* rows = wl + WS;                 // [kAPB][RW]
   stage_ctab<T, NA, KA>(ctab, a.cA);
-  stage_weights(wl, a.nn, a.nn_stride, block_species(a.order, a.type), H, D, DP);
+  stage_weights(wl, a.nn, a.nn_stride, block_species(a.order, a.type, vb), H, D, DP);
   __syncthreads();
-  const GroupCtx w = group_ctx(a.order, a.type, a.Npad);
+  const GroupCtx w = group_ctx(a.order, a.type, a.Npad, vb);
   const int N = a.N, i = w.i, I = w.I, pa = w.pa, s = w.s, g = w.g;
   const int lane = threadIdx.x & (kWave - 1);
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int wave = (vb * 256 + (int)threadIdx.x) / kWave;
   const bool first_atom = (lane >> 3) == 0;   // atom slot 0 of the wavefront writes the sums
   float* part = a.part + (size_t)wave * a.PW;
   float* row = rows + w.al * RW;
@@ -2200,6 +2297,12 @@ __global__ __launch_bounds__(256, C::ADJ_WAVES) void k_adjoint(AdjArgs a) {
   }
 }
 
+template <class C, bool kTri>
+__global__ __launch_bounds__(256, C::ADJ_WAVES) void k_adjoint(AdjArgs a) {
+  extern __shared__ __align__(16) float lds[];
+  adjoint_body<C, kTri>(a, blockIdx.x, lds);
+}
+
 // Sums over the atoms of each species of an outer product,
 //   out[I][b][m][v] = sum_p A1[m][p] B1[v][p] - A2[m][p] B2[v][p],
 // over block b's share of species I's atoms (species order).  Used for
@@ -2244,8 +2347,9 @@ __device__ __forceinline__ f32x4 ld_atoms4(const float* row, int p, int p1, bool
   return r;
 }
 
-__device__ __forceinline__ void outer_sum_block(const OuterArgs& o, int z, f32x4 (&red)[3][kOSTM * kOSTV][kWave]) {
-  const int I = blockIdx.y, b = blockIdx.x;
+constexpr int kOuterLds = 3 * kOSTM * kOSTV * kWave * sizeof(f32x4);
+__device__ __forceinline__ void outer_sum_block(const OuterArgs& o, int b, int I, int z,
+                                                f32x4 (&red)[3][kOSTM * kOSTV][kWave]) {
   if (b >= o.NB) return;
   const int nzv = (o.V + 16 * kOSTV - 1) / (16 * kOSTV);
   const int mz = z / nzv, vz = z % nzv;
@@ -2336,7 +2440,10 @@ __device__ __forceinline__ void outer_sum_block(const OuterArgs& o, int z, f32x4
       for (int y = 0; y < kOSTV; ++y) red[wv - 1][x * kOSTV + y][lane] = acc[x][y];
   }
   __syncthreads();
-  if (wv != 0) return;
+  if (wv != 0) {
+    __syncthreads();
+    return;
+  }
   float* out = o.out + ((size_t)I * o.NB + b) * o.M * o.V;
 #pragma unroll
   for (int x = 0; x < kOSTM; ++x)
@@ -2352,6 +2459,7 @@ __device__ __forceinline__ void outer_sum_block(const OuterArgs& o, int z, f32x4
         if (m < o.M && v < o.V) out[m * o.V + v] = s4[r];
       }
     }
+  __syncthreads();   // the other wavefronts wait here: red is read above
 }
 
 // dW0 and dc^R in one launch: grid z slices [0, nz0) take the first product,
@@ -2360,9 +2468,9 @@ __global__ __launch_bounds__(256) void k_outer_sum(OuterArgs o0, OuterArgs o1, i
   __shared__ f32x4 red[3][kOSTM * kOSTV][kWave];
   const int z = blockIdx.z;
   if (z < nz0)
-    outer_sum_block(o0, z, red);
+    outer_sum_block(o0, blockIdx.x, blockIdx.y, z, red);
   else
-    outer_sum_block(o1, z - nz0, red);
+    outer_sum_block(o1, blockIdx.x, blockIdx.y, z - nz0, red);
 }
 
 int outer_slices(int M, int V) {
@@ -2385,13 +2493,8 @@ struct LossArgs {
   int* flags;
 };
 
-__global__ __launch_bounds__(256) void k_part_reduce(int PW, const int* seg, const float* part, double* pp,
-                                                     LossArgs la) {
-  if ((int)blockIdx.y == (int)gridDim.y - 1 && la.on) {
-    if (blockIdx.x == 0) loss_final_block(la.S, la.N, la.le, la.lf, la.lv, la.lpart, la.loss, la.flags);
-    return;
-  }
-  const int I = blockIdx.y, b = blockIdx.x;
+// chunk b of species I's wavefront partials
+__device__ __forceinline__ void part_reduce_body(int PW, const int* seg, const float* part, double* pp, int b, int I) {
   const int start = seg[2 * I], count = seg[2 * I + 1];
   const int w0 = start / kAPW, w1 = count > 0 ? (start + count + kAPW - 1) / kAPW : w0;
   const int per = (w1 - w0 + kPRChunks - 1) / kPRChunks;
@@ -2409,6 +2512,16 @@ __global__ __launch_bounds__(256) void k_part_reduce(int PW, const int* seg, con
     for (; r < r1; ++r) sum += (double)part[(size_t)r * PW + slot];
     pp[((size_t)I * kPRChunks + b) * PW + slot] = sum;
   }
+}
+
+__global__ __launch_bounds__(256) void k_part_reduce(int PW, const int* seg, const float* part, double* pp,
+                                                     LossArgs la) {
+  __shared__ double red[3][kRedBlk];
+  if ((int)blockIdx.y == (int)gridDim.y - 1 && la.on) {
+    if (blockIdx.x == 0) loss_final_block(la.S, la.N, la.le, la.lf, la.lv, la.lpart, la.loss, la.flags, red);
+    return;
+  }
+  part_reduce_body(PW, seg, part, pp, blockIdx.x, blockIdx.y);
 }
 
 // Final gradient: 16 lanes per parameter; lane l sums rows l, l + 16, ... of
@@ -2477,8 +2590,9 @@ __device__ __forceinline__ bool adam_allowed(int* flags, int fl0, int st, float 
   return fl0 == 0 && st >= 1;
 }
 
-__global__ __launch_bounds__(256) void k_grad_final(GradArgs a) {
-  const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+// block vb: parameters 16 vb .. 16 vb + 15
+__device__ __forceinline__ void grad_final_body(const GradArgs& a, int vb) {
+  const int64_t q = ((int64_t)vb * 256 + threadIdx.x) >> 4;
   const int l = threadIdx.x & 15;
   const int P_R = a.T * a.T * a.NR * a.KR, P_A = a.T * a.T * a.NA * a.KA;
   const int blk = a.H * a.D + 2 * a.H + 1;
@@ -2535,6 +2649,8 @@ __global__ __launch_bounds__(256) void k_grad_final(GradArgs a) {
   }
 }
 
+__global__ __launch_bounds__(256) void k_grad_final(GradArgs a) { grad_final_body(a, blockIdx.x); }
+
 // Adam with the step counter read from device memory (graph replays).
 __global__ __launch_bounds__(256) void k_adam_dev(int64_t P, float* __restrict__ th, float* __restrict__ m,
                                                   float* __restrict__ v, const float* __restrict__ g,
@@ -2552,7 +2668,7 @@ __global__ __launch_bounds__(256) void k_adam_dev(int64_t P, float* __restrict__
 // replay uses (Adam reads the latched copy) and advance the caller's counter.
 // A step counter below 1 (Adam's bias correction needs step >= 1) raises
 // FL_STEP, which makes this replay skip its update.
-__global__ void k_graph_head(int* flags, int* step, int* cur) {
+__device__ __forceinline__ void graph_head(int* flags, int* step, int* cur) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     const int st = step[0];
     flags[0] = st < 1 ? FL_STEP : 0;
@@ -2560,6 +2676,8 @@ __global__ void k_graph_head(int* flags, int* step, int* cur) {
     step[0] = st + 1;
   }
 }
+__global__ void k_graph_head(int* flags, int* step, int* cur) { graph_head(flags, step, cur); }
+
 
 __global__ void k_fill_i32(int* p, int n, int v) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2569,6 +2687,202 @@ __global__ void k_fill_i32(int* p, int n, int v) {
 __global__ void k_fill_f32(float* p, int64_t n, float v) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q < n) p[q] = v;
+}
+
+// ============================================================ persistent step
+// The whole step after the neighbor build in one launch: the species order,
+// forward, force gather, per-structure sums and loss, adjoint, gradient
+// reductions and Adam, as phases of one persistent grid separated by a
+// software grid barrier.  The grid holds as many blocks as are resident at
+// once, each phase deals its work items (the blocks of the separate kernels)
+// to them, and every phase's intermediate stays in the same workspace arrays
+// as in the separate kernels.
+
+// Grid barrier, two levels.  The blocks of XCD x (blockIdx.x mod 8) count
+// their arrivals in a counter of their own (bar[kBarStride (x + 1)], one per
+// 64-byte line); the block that completes its XCD's count for barrier k adds
+// one to the device counter bar[0], and every block waits until that reaches
+// 8 k.  Same-address atomics from hundreds of blocks serialise at the memory
+// side, so one level costs tens of microseconds where two cost a few.  The
+// counters are zeroed by the step's head.  A wait longer than kBarrierTicks
+// of the 100 MHz constant clock, or a flag raised by a block that timed out,
+// makes the block leave with FL_BARRIER raised, so a grid whose blocks are
+// not all resident ends with an error, not a hang.
+// The wait polls with relaxed loads: an acquire load at device scope also
+// invalidates the L2 of the polling XCD, and dozens of waiting blocks would
+// keep invalidating the cache under the blocks still working.  A release
+// fence before the arrival and an acquire fence after the wait order the
+// phases' memory.
+constexpr uint64_t kBarrierTicks = 200000000ull;   // 2 s
+constexpr int kBarStride = 16;                     // words between counters
+constexpr int kBarWords = kBarStride * (kXCD + 1);
+__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned k, int* flags, int* abort_sh) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned per = gridDim.x / kXCD;   // blocks per XCD (gridDim.x is a multiple of 8)
+    const int x = blockIdx.x % kXCD;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned old = __hip_atomic_fetch_add(bar + kBarStride * (x + 1), 1u, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+    if (old == k * per - 1u) __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned target = k * (unsigned)kXCD;
+    const uint64_t t0 = wall_clock64();
+    int ok = 1;
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(2);
+      if ((__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FL_BARRIER) ||
+          wall_clock64() - t0 > kBarrierTicks) {
+        atomicOr(flags, FL_BARRIER);
+        ok = 0;
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *abort_sh = !ok;
+  }
+  __syncthreads();
+  return *abort_sh == 0;
+}
+
+// A phase's arguments, read again for each work item behind a compiler
+// barrier, into scalar registers.  Values derived from arguments that stay
+// the same across a phase's loop would otherwise be computed once before the
+// loop and kept live through the whole body (the per-atom bodies are sized
+// for the registers of one block's work); here nothing in the body is
+// invariant, so the loop body compiles as the separate kernel does.
+template <class T>
+__device__ __forceinline__ T item_args(const T& p) {
+  static_assert(sizeof(T) % 4 == 0, "read as words");
+  asm volatile("" ::: "memory");
+  T v;
+  const int* q = reinterpret_cast<const int*>(&p);
+  int* d = reinterpret_cast<int*>(&v);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) d[k] = __builtin_amdgcn_readfirstlane(q[k]);
+  return v;
+}
+
+// Work items [0, n) of a phase dealt to the persistent blocks: the blocks of
+// XCD x (blockIdx.x mod 8; gridDim.x is a multiple of 8) take the x-th
+// contiguous eighth, so items that share data share an L2.
+template <class F>
+__device__ __forceinline__ void for_items(int n, F&& f) {
+  const int per = gridDim.x / kXCD;
+  const int x = blockIdx.x % kXCD, r = blockIdx.x / kXCD;
+  const int q = n / kXCD, rem = n % kXCD;
+  const int lo = x * q + min(x, rem), cnt = q + (x < rem ? 1 : 0);
+  for (int j = r; j < cnt; j += per) f(lo + j);
+}
+
+struct StepArgs {
+  OrderArgs ord;
+  FwdArgs fwd;
+  PairLists nb;
+  float* F;
+  StructArgs st;
+  AdjArgs adj;
+  OuterArgs ow, oc;
+  int nzw, nzc, os_x;
+  int PW;
+  const int* seg;
+  double* pp;
+  LossArgs la;
+  GradArgs g;
+  int n_gf;        // blocks of the final gradient reduction
+  unsigned* bar;
+  int* flags;
+};
+
+// The arguments are read from device memory (written by k_step_head), not
+// from the kernel-argument segment: loads of kernel arguments are all issued
+// at entry and would stay live in registers through every phase.  Two
+// wavefronts per SIMD: at three (168 registers) the merged phases spill
+// several hundred bytes per lane, although each body alone fits.
+template <class C>
+__global__ __launch_bounds__(256, 2) void k_step(const StepArgs* pa) {
+  const StepArgs& a = *pa;
+  extern __shared__ __align__(16) float lds[];
+  __shared__ int abort_sh;
+  unsigned k = 0;
+#define NEP_BARRIER() \
+  if (!grid_barrier(a.bar, ++k, a.flags, &abort_sh)) return
+  // species order: key counts (and every slot cleared), offsets, ranks
+  for (int q = blockIdx.x * 256 + threadIdx.x; q < a.ord.Npad; q += (int)gridDim.x * 256) a.ord.order[q] = -1;
+  {
+    const int nblk = a.ord.nblk;
+    for_items(nblk, [&](int ob) { order_count_body<256>(item_args(a.ord), ob, reinterpret_cast<int*>(lds)); });
+  }
+  NEP_BARRIER();
+  if (blockIdx.x == 0) order_scan_body<256>(item_args(a.ord), reinterpret_cast<int*>(lds));
+  NEP_BARRIER();
+  {
+    const int nblk = a.ord.nblk;
+    for_items(nblk, [&](int ob) { order_scatter_body<256>(item_args(a.ord), ob, reinterpret_cast<int*>(lds)); });
+  }
+  NEP_BARRIER();
+  // forward: descriptors, network, partial forces
+  for_items(a.fwd.Npad / kAPB, [&](int vb) {
+    forward_body<C, false>(item_args(a.fwd), vb, lds);
+    __syncthreads();
+  });
+  NEP_BARRIER();
+  for_items((a.fwd.N + 256 / kGatherLPA - 1) / (256 / kGatherLPA), [&](int vb) {
+    const PairLists nb = item_args(a.nb);
+    const FwdArgs f = item_args(a.fwd);
+    gather_body(vb, f.N, nb, f.fR, f.fA, a.F, nullptr);
+  });
+  NEP_BARRIER();
+  // per-structure sums, loss partials and cotangents
+  if (a.st.split) {
+    for_items((a.st.N + kStructChunk - 1) / kStructChunk,
+              [&](int vb) { struct_part_body(item_args(a.st), vb, lds); });
+    NEP_BARRIER();
+  }
+  for_items(a.st.S, [&](int s) { struct_body(item_args(a.st), s, lds); });
+  NEP_BARRIER();
+  for_items(a.adj.Npad / kAPB, [&](int vb) {
+    adjoint_body<C, false>(item_args(a.adj), vb, lds);
+    __syncthreads();
+  });
+  NEP_BARRIER();
+  // outer-product sums, first stage of the partial sums, and the loss
+  {
+    const int T = a.ord.T;
+    const int os_x = a.os_x, nzw = a.nzw;
+    const int n_outer = os_x * T * (nzw + a.nzc), n_pr = kPRChunks * T;
+    auto& red = *reinterpret_cast<f32x4(*)[3][kOSTM * kOSTV][kWave]>(lds);
+    for_items(n_outer + n_pr + (a.la.on ? 1 : 0), [&](int v) {
+      if (v < n_outer) {
+        const int x = v % os_x, I = (v / os_x) % T, z = v / (os_x * T);
+        if (z < nzw)
+          outer_sum_block(item_args(a.ow), x, I, z, red);
+        else
+          outer_sum_block(item_args(a.oc), x, I, z - nzw, red);
+      } else if (v < n_outer + n_pr) {
+        const int u = v - n_outer;
+        part_reduce_body(a.PW, a.seg, a.adj.part, a.pp, u % kPRChunks, u / kPRChunks);
+      } else {
+        const LossArgs la = item_args(a.la);
+        loss_final_block(la.S, la.N, la.le, la.lf, la.lv, la.lpart, la.loss, la.flags, lds);
+        __syncthreads();
+      }
+    });
+  }
+  NEP_BARRIER();
+  // final gradient reduction with Adam
+  for_items(a.n_gf, [&](int vb) { grad_final_body(item_args(a.g), vb); });
+#undef NEP_BARRIER
+}
+
+// Head of the persistent step: the graph head, the step's arguments copied
+// to device memory, and the barrier's arrival counter cleared.
+__global__ void k_step_head(StepArgs a, StepArgs* dst, int* flags, int* step, int* cur) {
+  static_assert(sizeof(StepArgs) % 4 == 0, "copied as words");
+  const int* src = reinterpret_cast<const int*>(&a);
+  int* d = reinterpret_cast<int*>(dst);
+  for (int q = threadIdx.x; q < (int)(sizeof(StepArgs) / 4); q += blockDim.x) d[q] = src[q];
+  for (int q = threadIdx.x; q < kBarWords; q += blockDim.x) a.bar[q] = 0u;
+  graph_head(flags, step, cur);
 }
 
 // ================================================================ dispatch
@@ -2678,6 +2992,9 @@ struct Ops {
   size_t (*lds_fwd)(int);
   size_t (*lds_adj)(int);
   void (*high)(HighKernel, const HighArgs&, dim3, hipStream_t);   // null without degrees l > 4
+  // persistent step (null with degrees l > 4): launch, and resident blocks per CU
+  void (*step)(const StepArgs*, int, size_t, hipStream_t);
+  int (*step_occupancy)(size_t);
 };
 
 template <class C>
@@ -2725,11 +3042,30 @@ static void launch_high(HighKernel k, const HighArgs& a, dim3 grid, hipStream_t 
     launch_high_t<C, false>(k, a, grid, st);
 }
 template <class C>
+static void launch_step(const StepArgs* a, int grid, size_t lds, hipStream_t st) {
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_step<C>), dim3(grid), dim3(256), lds, st, a);
+}
+template <class C>
+static int step_occupancy(size_t lds) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_step<C>), 256, lds) !=
+      hipSuccess)
+    return 0;
+  return nb;
+}
+template <class C>
 static Ops make_ops() {
   void (*high)(HighKernel, const HighArgs&, dim3, hipStream_t) = nullptr;
-  if constexpr (C::YH > 0) high = &launch_high<C>;
+  void (*step)(const StepArgs*, int, size_t, hipStream_t) = nullptr;
+  int (*occ)(size_t) = nullptr;
+  if constexpr (C::YH > 0) {
+    high = &launch_high<C>;
+  } else {
+    step = &launch_step<C>;
+    occ = &step_occupancy<C>;
+  }
   return Ops{C::T, C::NR, C::NA, C::KR, C::KA, C::L3, C::L4, C::L5, C::D, C::Y, C::PS, C::YH,
-             &launch_forward<C>, &launch_adjoint<C>, &lds_forward<C>, &lds_adjoint<C>, high};
+             &launch_forward<C>, &launch_adjoint<C>, &lds_forward<C>, &lds_adjoint<C>, high, step, occ};
 }
 
 // Compiled-in model sizes (n_types, n_rad, n_ang, k_rad, k_ang, l3, l4, l5).
@@ -2781,7 +3117,7 @@ struct Layout {
   int N, S, T, D, Y, H, NR, TKR, Npad, nwaves, nblk, PW, NA, capR, capA;
   size_t order, seg, blk, astruct, revR, revA, G, Sst, Ep, X, eatom, fR, fA, wv, F, fbar, Es, Ws, eps, wbar, lpart,
       Gd, FRst, FPst, Gbr, beta, w1s, part, pp, w0part, crpart, Sh, Sdh, cgrid, cell, cpart, acell, aslot, cpos, spart,
-      cur_step, total;
+      cur_step, bar, sargs, total;
 };
 
 Layout make_layout(const nep_model* m, const Ops* o, int S, int N) {
@@ -2852,6 +3188,8 @@ Layout make_layout(const nep_model* m, const Ops* o, int S, int N) {
   L.cpos = take(16 * Nn);
   L.spart = take(8 * 16 * (Nn / kStructChunk + 1));
   L.cur_step = take(4);
+  L.bar = take(4 * kBarWords);
+  L.sargs = take(sizeof(StepArgs));
   L.total = off;
   return L;
 }
@@ -2944,7 +3282,12 @@ PairLists pair_lists(const Ctx& c, const nep_neighbors* nb) {
   return p;
 }
 
-void run_neighbors(const Ctx& c, nep_neighbors* nb, int32_t* flags, Prof* pr) {
+OrderArgs order_args(const Ctx& c, const nep_neighbors* nb) {
+  return OrderArgs{c.L.N, c.L.Npad, c.L.T, c.L.nblk, c.b->type, nb->cnt_ang, at<int>(c.ws, c.L.blk),
+                   at<int>(c.ws, c.L.seg), at<int>(c.ws, c.L.order)};
+}
+
+void run_neighbors(const Ctx& c, nep_neighbors* nb, int32_t* flags, Prof* pr, bool with_order = true) {
   const int N = c.L.N;
   if (N == 0) return;
   NbrArgs a;
@@ -3009,17 +3352,13 @@ void run_neighbors(const Ctx& c, nep_neighbors* nb, int32_t* flags, Prof* pr) {
     NEP_LAUNCH(pr, "reverse",
                hipLaunchKernelGGL(k_reverse, dim3(r.nbR + grid1(N, 256 / kRevLPAA)), dim3(256), 0, c.st, r));
   }
-  int* order = at<int>(c.ws, c.L.order);
-  int* blk = at<int>(c.ws, c.L.blk);
-  int* seg = at<int>(c.ws, c.L.seg);
+  if (!with_order) return;   // the persistent step computes the species order itself
+  const OrderArgs oa = order_args(c, nb);
   NEP_LAUNCH(pr, "order_count",
-             hipLaunchKernelGGL(k_order_count, dim3(c.L.nblk), dim3(kOrdBlk), 0, c.st, N, c.L.Npad, c.L.T, c.b->type,
-                                nb->cnt_ang, blk, order));
-  NEP_LAUNCH(pr, "order_scan",
-             hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(8 * kOrdBuckets), 0, c.st, c.L.nblk, c.L.T, blk, seg));
+             hipLaunchKernelGGL(k_order_count, dim3(c.L.nblk), dim3(kOrdBlk), 0, c.st, oa));
+  NEP_LAUNCH(pr, "order_scan", hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(512), 0, c.st, oa));
   NEP_LAUNCH(pr, "order_scatter",
-             hipLaunchKernelGGL(k_order_scatter, dim3(c.L.nblk), dim3(kOrdBlk), 0, c.st, N, c.L.T, c.b->type,
-                                nb->cnt_ang, blk, order));
+             hipLaunchKernelGGL(k_order_scatter, dim3(c.L.nblk), dim3(kOrdBlk), 0, c.st, oa));
 }
 
 FwdArgs fwd_args(const Ctx& c, const nep_neighbors* nb, const float* params) {
@@ -3102,6 +3441,35 @@ void launch_forward_pass(const Ctx& c, const nep_neighbors* nb, const float* par
   if (a.do_mlp && a.do_force) run_high(c, kHighForce, h, pr);
 }
 
+StructArgs struct_args(const Ctx& c, float* e_struct, float* virial, const nep_labels* lab, const float* lam) {
+  StructArgs s;
+  const int N = c.L.N;
+  s.S = c.b->n_struct;
+  s.N = N;
+  s.aoff = c.b->atom_offset;
+  s.eatom = at<float>(c.ws, c.L.eatom);
+  s.wv = at<float>(c.ws, c.L.wv);
+  s.F = at<float>(c.ws, c.L.F);
+  s.Et = lab ? lab->energy : nullptr;
+  s.Ft = lab ? lab->force : nullptr;
+  s.Wt = lab ? lab->virial : nullptr;
+  s.le = lam ? lam[0] : 0.f;
+  s.lf = lam ? lam[1] : 0.f;
+  s.lv = lam ? lam[2] : 0.f;
+  s.Es = at<float>(c.ws, c.L.Es);
+  s.Ws = at<float>(c.ws, c.L.Ws);
+  s.Es_user = e_struct;
+  s.Ws_user = virial;
+  s.eps = at<float>(c.ws, c.L.eps);
+  s.wbar = at<float>(c.ws, c.L.wbar);
+  s.fbar = at<float>(c.ws, c.L.fbar);
+  s.lpart = at<double>(c.ws, c.L.lpart);
+  // large structures take chunk partials first, unless the caller's bound rules them out
+  s.split = N >= 2 * kStructChunk && (c.b->max_atoms == 0 || c.b->max_atoms >= 2 * kStructChunk);
+  s.spart = at<double>(c.ws, c.L.spart);
+  return s;
+}
+
 void run_forward(const Ctx& c, const nep_neighbors* nb, const float* params, float* e_atom, float* e_struct,
                  float* force, float* virial, const nep_labels* lab, const float* lam, float* loss, int32_t* flags,
                  Prof* pr, bool defer_loss = false) {
@@ -3115,30 +3483,7 @@ void run_forward(const Ctx& c, const nep_neighbors* nb, const float* params, flo
                                   at<float>(c.ws, c.L.F), force));
   }
   if (S > 0) {
-    StructArgs s;
-    s.S = S;
-    s.N = N;
-    s.aoff = c.b->atom_offset;
-    s.eatom = at<float>(c.ws, c.L.eatom);
-    s.wv = at<float>(c.ws, c.L.wv);
-    s.F = at<float>(c.ws, c.L.F);
-    s.Et = lab ? lab->energy : nullptr;
-    s.Ft = lab ? lab->force : nullptr;
-    s.Wt = lab ? lab->virial : nullptr;
-    s.le = lam ? lam[0] : 0.f;
-    s.lf = lam ? lam[1] : 0.f;
-    s.lv = lam ? lam[2] : 0.f;
-    s.Es = at<float>(c.ws, c.L.Es);
-    s.Ws = at<float>(c.ws, c.L.Ws);
-    s.Es_user = e_struct;
-    s.Ws_user = virial;
-    s.eps = at<float>(c.ws, c.L.eps);
-    s.wbar = at<float>(c.ws, c.L.wbar);
-    s.fbar = at<float>(c.ws, c.L.fbar);
-    s.lpart = at<double>(c.ws, c.L.lpart);
-    // large structures take chunk partials first, unless the caller's bound rules them out
-    s.split = N >= 2 * kStructChunk && (c.b->max_atoms == 0 || c.b->max_atoms >= 2 * kStructChunk);
-    s.spart = at<double>(c.ws, c.L.spart);
+    const StructArgs s = struct_args(c, e_struct, virial, lab, lam);
     if (s.split)
       NEP_LAUNCH(pr, "struct_part",
                  hipLaunchKernelGGL(k_struct_part, dim3(grid1(N, kStructChunk)), dim3(kRedBlk), 0, c.st, s));
@@ -3151,55 +3496,103 @@ void run_forward(const Ctx& c, const nep_neighbors* nb, const float* params, flo
   }
 }
 
+AdjArgs adj_args(const Ctx& c, const nep_neighbors* nb, const float* params, const float* eps, const float* fbar,
+                 const float* wbar) {
+  const nep_model* m = c.m;
+  AdjArgs a;
+  a.N = c.L.N;
+  a.Npad = c.L.Npad;
+  a.H = m->hidden;
+  a.S = c.b->n_struct;
+  a.inv_rcR = 1.0f / m->rc_rad;
+  a.inv_rcA = 1.0f / m->rc_ang;
+  a.order = at<int>(c.ws, c.L.order);
+  a.astruct = at<int>(c.ws, c.L.astruct);
+  a.box = c.b->box;
+  a.tilt = c.b->tilt;
+  a.pos = c.b->pos;
+  a.type = c.b->type;
+  a.nb = pair_lists(c, nb);
+  const int T = m->n_types;
+  a.cR = params;
+  a.cA = params + (size_t)T * T * m->n_rad * m->k_rad;
+  a.nn = a.cA + (size_t)T * T * m->n_ang * m->k_ang;
+  a.nn_stride = m->hidden * c.o->D + 2 * m->hidden + 1;
+  a.Sst = at<float>(c.ws, c.L.Sst);
+  a.Ep = at<float>(c.ws, c.L.Ep);
+  a.X = at<float>(c.ws, c.L.X);
+  a.eps = eps;
+  a.fbar = fbar;
+  a.wbar = wbar;
+  a.Gd = at<float>(c.ws, c.L.Gd);
+  a.FRst = at<float>(c.ws, c.L.FRst);
+  a.FPst = at<float>(c.ws, c.L.FPst);
+  a.Gbr = at<float>(c.ws, c.L.Gbr);
+  a.beta = at<float>(c.ws, c.L.beta);
+  a.w1s = at<float>(c.ws, c.L.w1s);
+  a.part = at<float>(c.ws, c.L.part);
+  a.PW = c.L.PW;
+  return a;
+}
+
+// the two outer-product sums: dW0 (W) and dc^R (C)
+void outer_args(const Ctx& c, const AdjArgs& a, OuterArgs& ow, OuterArgs& oc) {
+  const nep_model* m = c.m;
+  const int* seg = at<int>(c.ws, c.L.seg);
+  ow = OuterArgs{c.L.Npad, m->hidden, c.o->D, kOSBlocksW, seg, a.beta, at<float>(c.ws, c.L.G), a.w1s, a.Gd,
+                 at<float>(c.ws, c.L.w0part)};
+  oc = OuterArgs{c.L.Npad, m->n_rad, c.L.TKR, kOSBlocksC, seg, a.Gbr, a.FRst, at<float>(c.ws, c.L.Ep), a.FPst,
+                 at<float>(c.ws, c.L.crpart)};
+}
+
+GradArgs grad_args(const Ctx& c, float* grad) {
+  const nep_model* m = c.m;
+  GradArgs g;
+  g.T = m->n_types;
+  g.NR = m->n_rad;
+  g.NA = m->n_ang;
+  g.KR = m->k_rad;
+  g.KA = m->k_ang;
+  g.H = m->hidden;
+  g.D = c.o->D;
+  g.PW = c.L.PW;
+  g.NBw = kOSBlocksW;
+  g.NBc = kOSBlocksC;
+  g.P = param_count(m);
+  g.pp = at<double>(c.ws, c.L.pp);
+  g.w0part = at<float>(c.ws, c.L.w0part);
+  g.crpart = at<float>(c.ws, c.L.crpart);
+  g.grad = grad;
+  g.adam = c.adam != nullptr;
+  if (c.adam) {
+    g.ad = c.adam->ad;
+    g.th = c.adam->th;
+    g.mm = c.adam->mm;
+    g.vv = c.adam->vv;
+    g.step = c.adam->step;
+    g.flags = c.adam->flags;
+  }
+  return g;
+}
+
+unsigned grad_final_blocks(const GradArgs& g) { return (unsigned)((g.P * 16 + 255) / 256); }
+
 // adjoint + gradient reductions; cotangents from eps/fbar/wbar pointers
 void run_adjoint(const Ctx& c, const nep_neighbors* nb, const float* params, const float* eps, const float* fbar,
                  const float* wbar, float* grad, Prof* pr, LossArgs la = LossArgs{}) {
   const nep_model* m = c.m;
   const int N = c.L.N;
   if (N > 0) {
-    AdjArgs a;
-    a.N = N;
-    a.Npad = c.L.Npad;
-    a.H = m->hidden;
-    a.S = c.b->n_struct;
-    a.inv_rcR = 1.0f / m->rc_rad;
-    a.inv_rcA = 1.0f / m->rc_ang;
-    a.order = at<int>(c.ws, c.L.order);
-    a.astruct = at<int>(c.ws, c.L.astruct);
-    a.box = c.b->box;
-    a.tilt = c.b->tilt;
-    a.pos = c.b->pos;
-    a.type = c.b->type;
-    a.nb = pair_lists(c, nb);
+    const AdjArgs a = adj_args(c, nb, params, eps, fbar, wbar);
     const int T = m->n_types;
-    a.cR = params;
-    a.cA = params + (size_t)T * T * m->n_rad * m->k_rad;
-    a.nn = a.cA + (size_t)T * T * m->n_ang * m->k_ang;
-    a.nn_stride = m->hidden * c.o->D + 2 * m->hidden + 1;
-    a.Sst = at<float>(c.ws, c.L.Sst);
-    a.Ep = at<float>(c.ws, c.L.Ep);
-    a.X = at<float>(c.ws, c.L.X);
-    a.eps = eps;
-    a.fbar = fbar;
-    a.wbar = wbar;
-    a.Gd = at<float>(c.ws, c.L.Gd);
-    a.FRst = at<float>(c.ws, c.L.FRst);
-    a.FPst = at<float>(c.ws, c.L.FPst);
-    a.Gbr = at<float>(c.ws, c.L.Gbr);
-    a.beta = at<float>(c.ws, c.L.beta);
-    a.w1s = at<float>(c.ws, c.L.w1s);
-    a.part = at<float>(c.ws, c.L.part);
-    a.PW = c.L.PW;
     const HighArgs h = high_args(c, nb, params, fbar, wbar);
     run_high(c, kHighTangent, h, pr);
     NEP_LAUNCH(pr, "adjoint", c.o->adjoint(a, dim3(c.L.Npad / kAPB), c.st));
     run_high(c, kHighCoef, h, pr);
     const int* seg = at<int>(c.ws, c.L.seg);
     {
-      const OuterArgs ow{c.L.Npad, m->hidden, c.o->D, kOSBlocksW, seg, a.beta, at<float>(c.ws, c.L.G), a.w1s,
-                         a.Gd, at<float>(c.ws, c.L.w0part)};
-      const OuterArgs oc{c.L.Npad, m->n_rad, c.L.TKR, kOSBlocksC, seg, a.Gbr, a.FRst, at<float>(c.ws, c.L.Ep),
-                         a.FPst, at<float>(c.ws, c.L.crpart)};
+      OuterArgs ow, oc;
+      outer_args(c, a, ow, oc);
       const int nzw = outer_slices(ow.M, ow.V), nzc = outer_slices(oc.M, oc.V);
       NEP_LAUNCH(pr, "outer_sums",
                  hipLaunchKernelGGL(k_outer_sum, dim3(std::max(kOSBlocksW, kOSBlocksC), T, nzw + nzc), dim3(256), 0,
@@ -3209,33 +3602,8 @@ void run_adjoint(const Ctx& c, const nep_neighbors* nb, const float* params, con
     NEP_LAUNCH(pr, "part_reduce",
                hipLaunchKernelGGL(k_part_reduce, dim3(kPRChunks, T + (la.on ? 1 : 0)), dim3(256), 0, c.st, c.L.PW,
                                   seg, a.part, pp, la));
-    GradArgs g;
-    g.T = T;
-    g.NR = m->n_rad;
-    g.NA = m->n_ang;
-    g.KR = m->k_rad;
-    g.KA = m->k_ang;
-    g.H = m->hidden;
-    g.D = c.o->D;
-    g.PW = c.L.PW;
-    g.NBw = kOSBlocksW;
-    g.NBc = kOSBlocksC;
-    g.P = param_count(m);
-    g.pp = pp;
-    g.w0part = at<float>(c.ws, c.L.w0part);
-    g.crpart = at<float>(c.ws, c.L.crpart);
-    g.grad = grad;
-    g.adam = c.adam != nullptr;
-    if (c.adam) {
-      g.ad = c.adam->ad;
-      g.th = c.adam->th;
-      g.mm = c.adam->mm;
-      g.vv = c.adam->vv;
-      g.step = c.adam->step;
-      g.flags = c.adam->flags;
-    }
-    const unsigned nblk_gf = (unsigned)((g.P * 16 + 255) / 256);
-    NEP_LAUNCH(pr, "grad_final", hipLaunchKernelGGL(k_grad_final, dim3(nblk_gf), dim3(256), 0, c.st, g));
+    const GradArgs g = grad_args(c, grad);
+    NEP_LAUNCH(pr, "grad_final", hipLaunchKernelGGL(k_grad_final, dim3(grad_final_blocks(g)), dim3(256), 0, c.st, g));
   } else {
     const int64_t P = param_count(m);
     hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, c.st, grad, P, 0.f);
@@ -3261,14 +3629,10 @@ int setup(Ctx& c, const nep_model* m, const nep_batch* b, void* ws, void* stream
   return NEP_OK;
 }
 
-int loss_grad_seq(Ctx& c, nep_neighbors* nb, const float* params, const nep_labels* labels, const float* lam,
-                  float* loss, float* grad, float* e_struct, float* force, float* virial, int32_t* flags, Prof* pr,
-                  bool with_neighbors) {
-  if (with_neighbors) run_neighbors(c, nb, flags, pr);
-  if (c.b->n_struct == 0) hipLaunchKernelGGL(k_fill_f32, dim3(1), dim3(64), 0, c.st, loss, (int64_t)4, 0.f);
-  // with atoms present the loss is summed by the adjoint's reduction launch
-  const int N = c.L.N, S = c.b->n_struct;
+// loss sum carried by the first reduction launch after the adjoint
+LossArgs loss_args(const Ctx& c, const nep_labels* labels, const float* lam, float* loss, int32_t* flags) {
   LossArgs la{};
+  const int N = c.L.N, S = c.b->n_struct;
   if (N > 0 && S > 0 && labels) {
     la.on = 1;
     la.S = S;
@@ -3280,10 +3644,71 @@ int loss_grad_seq(Ctx& c, nep_neighbors* nb, const float* params, const nep_labe
     la.loss = loss;
     la.flags = flags;
   }
+  return la;
+}
+
+int loss_grad_seq(Ctx& c, nep_neighbors* nb, const float* params, const nep_labels* labels, const float* lam,
+                  float* loss, float* grad, float* e_struct, float* force, float* virial, int32_t* flags, Prof* pr,
+                  bool with_neighbors) {
+  if (with_neighbors) run_neighbors(c, nb, flags, pr);
+  if (c.b->n_struct == 0) hipLaunchKernelGGL(k_fill_f32, dim3(1), dim3(64), 0, c.st, loss, (int64_t)4, 0.f);
+  // with atoms present the loss is summed by the adjoint's reduction launch
+  const LossArgs la = loss_args(c, labels, lam, loss, flags);
   run_forward(c, nb, params, nullptr, e_struct, force, virial, labels, lam, loss, flags, pr, la.on != 0);
   run_adjoint(c, nb, params, at<float>(c.ws, c.L.eps), at<float>(c.ws, c.L.fbar), at<float>(c.ws, c.L.wbar), grad,
               pr, la);
   return hip_ok();
+}
+
+// ---- persistent step: everything after the neighbor build in one launch
+size_t step_lds(const Ctx& c) {
+  size_t l = std::max(c.o->lds_fwd(c.m->hidden), c.o->lds_adj(c.m->hidden));
+  l = std::max(l, (size_t)kOrdScatterLds * sizeof(int));
+  l = std::max(l, (size_t)kOrdScanLds * sizeof(int));
+  l = std::max(l, (size_t)kStructLds);
+  l = std::max(l, (size_t)kOuterLds);
+  l = std::max(l, (size_t)kLossLds);
+  return l;
+}
+
+// Blocks of the persistent grid: as many as are resident at once, a multiple
+// of the XCD count; 0 when the kernel cannot run.
+int step_grid(const Ctx& c, size_t lds) {
+  if (!c.o->step) return 0;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  const int per = c.o->step_occupancy(lds);
+  return per * cus / kXCD * kXCD;
+}
+
+// The persistent step covers orthorhombic batches with atoms and structures,
+// for models without degrees l > 4.
+bool persistent_ok(const Ctx& c) { return c.o->step && !c.b->tilt && c.L.N > 0 && c.b->n_struct > 0; }
+
+StepArgs step_args(const Ctx& c, nep_neighbors* nb, const float* params, const nep_labels* labels,
+                   const float* lam, float* loss, float* grad, int32_t* flags) {
+  StepArgs a;
+  a.ord = order_args(c, nb);
+  a.fwd = fwd_args(c, nb, params);
+  a.nb = a.fwd.nb;
+  a.F = at<float>(c.ws, c.L.F);
+  a.st = struct_args(c, nullptr, nullptr, labels, lam);
+  a.adj = adj_args(c, nb, params, at<float>(c.ws, c.L.eps), at<float>(c.ws, c.L.fbar), at<float>(c.ws, c.L.wbar));
+  outer_args(c, a.adj, a.ow, a.oc);
+  a.nzw = outer_slices(a.ow.M, a.ow.V);
+  a.nzc = outer_slices(a.oc.M, a.oc.V);
+  a.os_x = std::max(kOSBlocksW, kOSBlocksC);
+  a.PW = c.L.PW;
+  a.seg = at<int>(c.ws, c.L.seg);
+  a.pp = at<double>(c.ws, c.L.pp);
+  a.la = loss_args(c, labels, lam, loss, flags);
+  a.g = grad_args(c, grad);
+  a.n_gf = (int)grad_final_blocks(a.g);
+  a.bar = at<unsigned>(c.ws, c.L.bar);
+  a.flags = flags;
+  return a;
 }
 
 struct GraphHandle {
@@ -3510,6 +3935,15 @@ int nep_train_step_graph_create(const nep_model* m, const nep_batch* b, nep_neig
   if (!labels || !lambda || !params || !mm || !vv || !grad || !loss || !d_step || !adam || !d_flags || !graph)
     return NEP_ERR_ARG;
   if ((rc = check_adam_config(adam))) return rc;
+  const bool persistent = (graph_flags & NEP_GRAPH_PERSISTENT) != 0;
+  size_t slds = 0;
+  int sgrid = 0;
+  if (persistent) {
+    if (!persistent_ok(c)) return NEP_ERR_ARG;
+    slds = step_lds(c);
+    sgrid = step_grid(c, slds);
+    if (sgrid < kXCD) return NEP_ERR_HIP;
+  }
   hipStream_t cap;
   if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return NEP_ERR_HIP;
   c.st = cap;
@@ -3519,15 +3953,23 @@ int nep_train_step_graph_create(const nep_model* m, const nep_batch* b, nep_neig
     return NEP_ERR_HIP;
   }
   int* cur = at<int>(c.ws, c.L.cur_step);
-  hipLaunchKernelGGL(k_graph_head, dim3(1), dim3(64), 0, cap, d_flags, d_step, cur);
   // Adam runs inside the gradient's final reduction
   const AdamFuse af{param_count(m), params, mm, vv, cur,
                     AdamDev{adam->lr_start, adam->lr_stop, adam->n_warmup, adam->n_total, adam->beta1, adam->beta2,
                             adam->eps},
                     d_flags};
   c.adam = &af;
-  loss_grad_seq(c, nb, params, labels, lambda, loss, grad, nullptr, nullptr, nullptr, d_flags, nullptr,
-                (graph_flags & NEP_GRAPH_CACHED_NEIGHBORS) == 0);
+  if (persistent) {
+    StepArgs* sa = at<StepArgs>(c.ws, c.L.sargs);
+    hipLaunchKernelGGL(k_step_head, dim3(1), dim3(64), 0, cap,
+                       step_args(c, nb, params, labels, lambda, loss, grad, d_flags), sa, d_flags, d_step, cur);
+    if ((graph_flags & NEP_GRAPH_CACHED_NEIGHBORS) == 0) run_neighbors(c, nb, d_flags, nullptr, false);
+    c.o->step(sa, sgrid, slds, cap);
+  } else {
+    hipLaunchKernelGGL(k_graph_head, dim3(1), dim3(64), 0, cap, d_flags, d_step, cur);
+    loss_grad_seq(c, nb, params, labels, lambda, loss, grad, nullptr, nullptr, nullptr, d_flags, nullptr,
+                  (graph_flags & NEP_GRAPH_CACHED_NEIGHBORS) == 0);
+  }
   const hipError_t e1 = hipStreamEndCapture(cap, &g);
   (void)hipStreamDestroy(cap);
   if (e1 != hipSuccess || !g) return NEP_ERR_HIP;
@@ -3587,6 +4029,7 @@ int nep_profile_loss_grad(const nep_model* m, const nep_batch* b, nep_neighbors*
 }
 
 int nep_flags_status(int32_t f) {
+  if (f & FL_BARRIER) return NEP_ERR_HIP;
   if (f & FL_BOX) return NEP_ERR_BOX;
   if (f & FL_TYPE) return NEP_ERR_TYPE;
   if (f & FL_POS) return NEP_ERR_POSITION;

@@ -270,17 +270,21 @@ def md_step(model, batch, nbrs, params, mass, vel, force, dt, n_steps, e_pot, ws
 
 
 GRAPH_CACHED_NEIGHBORS = 1
+GRAPH_PERSISTENT = 2
+NEP_FLAG_BARRIER = 64
 
 
 class TrainStepGraph:
     """One captured training step (neighbors, forward, loss, adjoint, Adam);
     replays advance the device step counter.  With cached_neighbors the graph
     skips the neighbor build and reuses the lists (and the reverse index and
-    species order in ws) from an earlier build_neighbors call."""
+    species order in ws) from an earlier build_neighbors call.  With
+    persistent everything after the neighbor build runs as one persistent
+    launch (NEP_GRAPH_PERSISTENT)."""
 
     def __init__(self, model, batch, nbrs, labels, lam, params, m, v, grad, loss, step, ws, flags,
                  lr_start=1e-3, lr_stop=1e-3, n_warmup=0, n_total=0, beta1=0.9, beta2=0.999, eps=1e-8,
-                 stream=None, cached_neighbors=False):
+                 stream=None, cached_neighbors=False, persistent=False):
         P = param_count(model)
         for t, name in ((params, "params"), (m, "m"), (v, "v"), (grad, "grad")):
             _want(t, torch.float32, P, name)
@@ -291,7 +295,8 @@ class TrainStepGraph:
         _check(_lib.load().nep_train_step_graph_create(
             C.byref(model.c()), C.byref(batch.c()), C.byref(nbrs.c()), C.byref(labels.c()), C.byref(_lam(lam)),
             _ptr(params), _ptr(m), _ptr(v), _ptr(grad), _ptr(loss), _ptr(step), C.byref(cfg), _ptr(ws),
-            _ptr(flags), GRAPH_CACHED_NEIGHBORS if cached_neighbors else 0, _stream(stream), C.byref(h)),
+            _ptr(flags), (GRAPH_CACHED_NEIGHBORS if cached_neighbors else 0) | (GRAPH_PERSISTENT if persistent else 0),
+            _stream(stream), C.byref(h)),
             "nep_train_step_graph_create")
         self.handle = h
 
