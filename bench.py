@@ -252,10 +252,11 @@ class Workload:
         log(f"workload {name}: {self.S} structures, {self.N} atoms, mean neighbors {self.cnt_r:.2f} / "
             f"{self.cnt_a:.2f}")
 
-    def batched(self, steps, warmup, lam, lr, stream, log, cached=False, persistent=False):
+    def batched(self, steps, warmup, lam, lr, stream, log, cached=False, persistent=False, tuning="cache"):
         """The captured train step replayed `steps` times after `warmup`
         replays; one event between consecutive replays.  persistent: the step
-        after the neighbor build as one persistent launch."""
+        after the neighbor build as one persistent launch; tuning: launch
+        choices (None: the library defaults, "cache": the autotuner's)."""
         import torch
         from paper_2507_00528_amd import nep
         nb, ws, fl = self.nbrs, self.ws, self.flags
@@ -270,7 +271,8 @@ class Workload:
         step = torch.ones(1, dtype=torch.int32, device="cuda")
         graph = nep.TrainStepGraph(self.model, self.dev, nb, self.labels, lam, params, m, v, grad, loss, step, ws,
                                    fl, lr_start=lr, lr_stop=lr, stream=stream, cached_neighbors=cached,
-                                   persistent=persistent)
+                                   persistent=persistent, tuning=tuning)
+        self.last_tuning = dict(graph.tuning)
         torch.cuda.synchronize()   # inputs were filled on the default stream
         with torch.cuda.stream(stream):
             for _ in range(warmup):
@@ -295,19 +297,28 @@ class Workload:
         graph.close()
         dist = {"median_ms": float(np.median(per)), "p10_ms": float(np.percentile(per, 10)),
                 "p90_ms": float(np.percentile(per, 90))}
-        log(f"{self.name} {'cached' if cached else 'batched'}{' persistent' if persistent else ''}: "
+        log(f"{self.name} {'cached' if cached else 'batched'}{' persistent' if persistent else ''} "
+            f"{graph.tuning or 'defaults'}: "
             f"{ms:.3f} ms/step (events), "
             f"{1e3 * wall / steps:.3f} ms/step (wall), median {dist['median_ms']:.3f}; "
             f"loss {loss_first[0]:.5g} -> {loss_last[0]:.5g}")
         return ms, dist, (loss_first, loss_last)
 
     def both_paths(self, steps, warmup, lam, lr, stream, log):
-        from paper_2507_00528_amd import nep
-        out = {"graph": self.batched(steps, warmup, lam, lr, stream, log)}
-        try:
-            out["persistent"] = self.batched(steps, warmup, lam, lr, stream, log, persistent=True)
-        except nep.NEPError as e:   # a batch or model the persistent step does not cover
-            log(f"{self.name}: no persistent step ({e})")
+        """The forms of the captured step: separate launches with the library's
+        hand-set launch choices, with the autotuner's cached choices (when it
+        has some for this size class), and the persistent form."""
+        from paper_2507_00528_amd import nep, tune
+        out = {"graph": self.batched(steps, warmup, lam, lr, stream, log, tuning=None)}
+        choices = tune.lookup(self.model, self.dev)
+        self.tuned_choices = choices
+        if choices:
+            out["graph_tuned"] = self.batched(steps, warmup, lam, lr, stream, log, tuning=choices)
+        if not (choices or {}).get("persistent"):
+            try:
+                out["persistent"] = self.batched(steps, warmup, lam, lr, stream, log, persistent=True, tuning=None)
+            except nep.NEPError as e:   # a batch or model the persistent step does not cover
+                log(f"{self.name}: no persistent step ({e})")
         return out
 
     def kernels(self, reps, lam, stream):
@@ -508,6 +519,7 @@ def main():
         kx = Wx.kernels(2, lam, stream)
         others[w] = {"workload": WORKLOAD_TEXT.get(w, w), "structures": Wx.S, "atoms": Wx.N,
                      "ms_per_step": msx, "value": Wx.N / (msx * 1e-3), "unit": "atoms/s", "path": bx,
+                     "tuned_choices": Wx.tuned_choices,
                      "step_paths_ms": {k: v[0] for k, v in px.items()},
                      "replay_distribution": distx,
                      "cached_neighbors": {"ms_per_step": msx_c, "value": Wx.N / (msx_c * 1e-3)},
@@ -547,6 +559,9 @@ def main():
                    "path": f"batched HIP-graph train step (neighbors+E/F/W+loss+grad+Adam), {best} form"},
         "step_paths": {k: {"ms_per_step": v[0], "value": N / (v[0] * 1e-3), "replay_distribution": v[1]}
                        for k, v in paths.items()},
+        "tuning": {"cached_choices": W.tuned_choices,
+                   "note": "graph: the library's hand-set launch choices; graph_tuned: the autotuner's cached "
+                           "choices for this size class (paper_2507_00528_amd/tune.py)"},
         "plain": plain_out,
         "roofline": roof,
         "replay_distribution": dist,

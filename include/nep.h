@@ -297,6 +297,31 @@ int nep_train_step_graph_create(const nep_model* model, const nep_batch* batch, 
                                 float* m, float* v, float* grad, float* loss, int32_t* d_step,
                                 const nep_adam_config* adam, void* ws, int32_t* d_flags,
                                 int32_t graph_flags, void* stream, void** graph);
+/* Launch choices of the captured step, picked per batch size class by the
+ * library's autotuner (paper_2507_00528_amd/tune.py) from timed replays; none
+ * changes a result beyond the order of floating-point sums.  0 in a field
+ * keeps the default (in brackets).
+ *   persistent      1: the persistent form of NEP_GRAPH_PERSISTENT [0]
+ *   outer_blocks_w  blocks per species of the W0 outer-product sum, 1..512 [192]
+ *   outer_blocks_c  blocks per species of the c_rad outer-product sum, 1..256 [64]
+ *   reduce_chunks   chunks per species of the first gradient-partial reduction, 1..512 [128]
+ *   cell_min_atoms  smallest structure searched through cell lists, >= 64 [1024]
+ *   gather_lanes    lanes per atom of the force gather, 8 or 16 [16]
+ *   forward_waves   wavefronts per SIMD the forward kernel is compiled for, 2 or 3 [3]
+ *   adjoint_waves   the same for the adjoint kernel [3; 2 with degrees l > 4]
+ * A value out of range is NEP_ERR_ARG. */
+typedef struct {
+  int32_t persistent, outer_blocks_w, outer_blocks_c, reduce_chunks, cell_min_atoms, gather_lanes,
+      forward_waves, adjoint_waves;
+} nep_tuning;
+
+/* nep_train_step_graph_create() with launch choices (tuning may be NULL). */
+int nep_train_step_graph_create_tuned(const nep_model* model, const nep_batch* batch, nep_neighbors* nbrs,
+                                      const nep_labels* labels, const float lambda[3], float* params,
+                                      float* m, float* v, float* grad, float* loss, int32_t* d_step,
+                                      const nep_adam_config* adam, void* ws, int32_t* d_flags,
+                                      int32_t graph_flags, const nep_tuning* tuning, void* stream,
+                                      void** graph);
 int nep_train_step_graph_launch(void* graph, void* stream);
 int nep_train_step_graph_destroy(void* graph);
 

@@ -37,6 +37,12 @@ class NepAdamConfig(C.Structure):
                 ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
 
 
+class NepTuning(C.Structure):
+    _fields_ = [("persistent", C.c_int32), ("outer_blocks_w", C.c_int32), ("outer_blocks_c", C.c_int32),
+                ("reduce_chunks", C.c_int32), ("cell_min_atoms", C.c_int32), ("gather_lanes", C.c_int32),
+                ("forward_waves", C.c_int32), ("adjoint_waves", C.c_int32)]
+
+
 P = C.POINTER
 VP = C.c_void_p
 I32 = C.c_int32
@@ -63,6 +69,9 @@ SIGNATURES = [
     ("nep_train_step_graph_create", C.c_int, [P(NepModel), P(NepBatch), P(NepNeighbors), P(NepLabels),
                                               P(F32 * 3), VP, VP, VP, VP, VP, VP, P(NepAdamConfig), VP, VP, I32,
                                               VP, P(VP)]),
+    ("nep_train_step_graph_create_tuned", C.c_int, [P(NepModel), P(NepBatch), P(NepNeighbors), P(NepLabels),
+                                                    P(F32 * 3), VP, VP, VP, VP, VP, VP, P(NepAdamConfig), VP, VP,
+                                                    I32, P(NepTuning), VP, P(VP)]),
     ("nep_train_step_graph_launch", C.c_int, [VP, VP]),
     ("nep_train_step_graph_destroy", C.c_int, [VP]),
     ("nep_profile_loss_grad", C.c_int, [P(NepModel), P(NepBatch), P(NepNeighbors), VP, P(NepLabels), P(F32 * 3),

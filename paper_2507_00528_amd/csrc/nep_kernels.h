@@ -31,8 +31,9 @@ struct NbrArgs {
   int* cntA;
   int* astruct;
   int* flags;
-  // cell-list search of large structures (cells = 0: all-pairs only)
-  int cells;
+  // cell-list search of structures of at least cell_min atoms (cells = 0:
+  // all-pairs only)
+  int cells, cell_min;
   int4* grid;    // [S] bins per axis (na, nb, nc, na nb nc), zero: all-pairs
   int* cell;     // [N+1] bin counts, then bin start offsets; [N] = binned atoms
   int* cpart;    // [N / kScanChunk + 1] per-chunk counts

@@ -517,7 +517,8 @@ __global__ __launch_bounds__(kNbrThreads) void k_neighbors(NbrArgs a) {
 // the bins are counted, scanned into start offsets, and the binned atoms
 // placed bin by bin as (x, y, z, j).  An atom whose lane buffer overflows is
 // left to the all-pairs kernel (acell[i] = -1), which runs afterwards.
-constexpr int kCellMinAtoms = 1024;
+constexpr int kCellMinAtoms = 1024;     // default smallest structure searched through cell lists
+constexpr int kCellMinAtomsLo = 64;     // smallest value a tuning may set
 constexpr double kCellPad = 0.05;
 constexpr int kScanChunk = 2048;   // bin ids per block of the offset scan
 
@@ -526,7 +527,7 @@ template <bool kTri>
 __device__ int4 cell_grid(const NbrArgs& a, int st) {
   const int4 none = make_int4(0, 0, 0, 0);
   const int n = a.aoff[st + 1] - a.aoff[st];
-  if (n < kCellMinAtoms) return none;
+  if (n < a.cell_min) return none;
   ScanCtx c;
   if (!init_ctx<kTri>(a, st, a.aoff[st], 0.f, 0.f, 0.f, c).fast_ok) return none;
   double ha, hb, hc;
@@ -1618,8 +1619,8 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int vb, float* ld
   }
 }
 
-template <class C, bool kTri>
-__global__ __launch_bounds__(256, 3) void k_forward(FwdArgs a) {
+template <class C, bool kTri, int W>
+__global__ __launch_bounds__(256, W) void k_forward(FwdArgs a) {
   extern __shared__ __align__(16) float lds[];
   forward_body<C, kTri>(a, blockIdx.x, lds);
 }
@@ -1627,12 +1628,13 @@ __global__ __launch_bounds__(256, 3) void k_forward(FwdArgs a) {
 // F_i = sum_j f_ij - f_ji (Eq. 3), gathering f_ji through the reverse index;
 // 16 lanes per atom take list slots s, s + 16, ... (more loads in flight for
 // the dependent reverse reads) and are summed by DPP.
-constexpr int kGatherLPA = 16;
+constexpr int kGatherLPA = 16;   // default lanes per atom (8 or 16)
+template <int LPA>
 __device__ __forceinline__ void gather_list(int i, int s, const uint32_t* __restrict__ idx, const int* __restrict__ cnt,
                                             const int* __restrict__ rev, int cap, const float* __restrict__ f,
                                             float& fx, float& fy, float& fz) {
   const int n = min(cnt[i], cap);
-  for (int k = s; k < n; k += kGatherLPA) {
+  for (int k = s; k < n; k += LPA) {
     const size_t o = (size_t)i * cap + k;
     const int j = (int)(idx[o] >> 5);
     const int rk = rev[o];
@@ -1649,24 +1651,28 @@ __device__ __forceinline__ void gather_list(int i, int s, const uint32_t* __rest
   }
 }
 
-// logical block vb: atoms vb * 16 ..
+// logical block vb: atoms vb * (256 / LPA) ..
+template <int LPA>
 __device__ __forceinline__ void gather_body(int vb, int N, const PairLists& nb, const float* __restrict__ fR,
                                             const float* __restrict__ fA, float* __restrict__ F,
                                             float* __restrict__ Fuser) {
-  const int s = threadIdx.x % kGatherLPA;
-  const int i = vb * (256 / kGatherLPA) + threadIdx.x / kGatherLPA;
+  static_assert(LPA == 8 || LPA == 16, "8 or 16 lanes per atom");
+  const int s = threadIdx.x % LPA;
+  const int i = vb * (256 / LPA) + threadIdx.x / LPA;
   float fx = 0.f, fy = 0.f, fz = 0.f;
   if (i < N) {
-    gather_list(i, s, nb.idxR, nb.cntR, nb.revR, nb.capR, fR, fx, fy, fz);
-    gather_list(i, s, nb.idxA, nb.cntA, nb.revA, nb.capA, fA, fx, fy, fz);
+    gather_list<LPA>(i, s, nb.idxR, nb.cntR, nb.revR, nb.capR, fR, fx, fy, fz);
+    gather_list<LPA>(i, s, nb.idxA, nb.cntA, nb.revA, nb.capA, fA, fx, fy, fz);
   }
-  // the 16 lanes of an atom: 8-lane groups, then the other half of the row
+  // the lanes of an atom: 8-lane groups, then (16 lanes) the other half of the row
   fx = grp8_sum(fx);
   fy = grp8_sum(fy);
   fz = grp8_sum(fz);
-  fx += dpp<kDppRowRor8>(fx);
-  fy += dpp<kDppRowRor8>(fy);
-  fz += dpp<kDppRowRor8>(fz);
+  if (LPA == 16) {
+    fx += dpp<kDppRowRor8>(fx);
+    fy += dpp<kDppRowRor8>(fy);
+    fz += dpp<kDppRowRor8>(fz);
+  }
   if (i < N && s == 0) {
     F[i] = fx;
     F[N + i] = fy;
@@ -1679,10 +1685,11 @@ __device__ __forceinline__ void gather_body(int vb, int N, const PairLists& nb, 
   }
 }
 
+template <int LPA>
 __global__ __launch_bounds__(256) void k_force_gather(int N, PairLists nb, const float* __restrict__ fR,
                                                       const float* __restrict__ fA, float* __restrict__ F,
                                                       float* __restrict__ Fuser) {
-  gather_body(xcd_block(), N, nb, fR, fA, F, Fuser);
+  gather_body<LPA>(xcd_block(), N, nb, fR, fA, F, Fuser);
 }
 
 // ==================================================================== loss
@@ -2297,8 +2304,8 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs& a, int vb, float* ld
   }
 }
 
-template <class C, bool kTri>
-__global__ __launch_bounds__(256, C::ADJ_WAVES) void k_adjoint(AdjArgs a) {
+template <class C, bool kTri, int W>
+__global__ __launch_bounds__(256, W) void k_adjoint(AdjArgs a) {
   extern __shared__ __align__(16) float lds[];
   adjoint_body<C, kTri>(a, blockIdx.x, lds);
 }
@@ -2319,7 +2326,8 @@ __global__ __launch_bounds__(256, C::ADJ_WAVES) void k_adjoint(AdjArgs a) {
 // consecutive 16-atom groups and are summed through LDS at the end.
 // blocks per species: the W0 sums stream about three times the data of the
 // c^R sums, so they get more blocks (all blocks are resident at once)
-constexpr int kOSBlocksW = 192, kOSBlocksC = 64;
+constexpr int kOSBlocksW = 192, kOSBlocksC = 64;            // defaults
+constexpr int kOSBlocksMaxW = 512, kOSBlocksMaxC = 256;
 constexpr int kOSTM = 4, kOSTV = 3;
 
 struct OuterArgs {
@@ -2481,7 +2489,8 @@ int outer_slices(int M, int V) {
 // First stage of the final reduction for the wavefront partials (c^A, b0,
 // w1, b1): block (b, I) sums, in float64 and in wave order, chunk b of the
 // wavefronts of species I; one thread per slot, so reads run along rows.
-constexpr int kPRChunks = 128;
+constexpr int kPRChunks = 128;   // default chunks per species
+constexpr int kPRChunksMax = 512;
 
 // Loss reduction carried by k_part_reduce (one extra row of blocks) so that a
 // loss-and-gradient pass spends no launch on it.
@@ -2494,10 +2503,11 @@ struct LossArgs {
 };
 
 // chunk b of species I's wavefront partials
-__device__ __forceinline__ void part_reduce_body(int PW, const int* seg, const float* part, double* pp, int b, int I) {
+__device__ __forceinline__ void part_reduce_body(int PW, const int* seg, const float* part, double* pp, int b, int I,
+                                                 int nch) {
   const int start = seg[2 * I], count = seg[2 * I + 1];
   const int w0 = start / kAPW, w1 = count > 0 ? (start + count + kAPW - 1) / kAPW : w0;
-  const int per = (w1 - w0 + kPRChunks - 1) / kPRChunks;
+  const int per = (w1 - w0 + nch - 1) / nch;
   const int r0 = w0 + b * per, r1 = min(w1, r0 + per);
   for (int slot = threadIdx.x; slot < PW; slot += blockDim.x) {
     double sum = 0.0;
@@ -2510,7 +2520,7 @@ __device__ __forceinline__ void part_reduce_body(int PW, const int* seg, const f
       for (int u = 0; u < 4; ++u) sum += (double)v[u];
     }
     for (; r < r1; ++r) sum += (double)part[(size_t)r * PW + slot];
-    pp[((size_t)I * kPRChunks + b) * PW + slot] = sum;
+    pp[((size_t)I * nch + b) * PW + slot] = sum;
   }
 }
 
@@ -2521,7 +2531,7 @@ __global__ __launch_bounds__(256) void k_part_reduce(int PW, const int* seg, con
     if (blockIdx.x == 0) loss_final_block(la.S, la.N, la.le, la.lf, la.lv, la.lpart, la.loss, la.flags, red);
     return;
   }
-  part_reduce_body(PW, seg, part, pp, blockIdx.x, blockIdx.y);
+  part_reduce_body(PW, seg, part, pp, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 // Final gradient: 16 lanes per parameter; lane l sums rows l, l + 16, ... of
@@ -2561,9 +2571,9 @@ __device__ float lr_at(const AdamDev& c, int64_t s) {
 }
 
 struct GradArgs {
-  int T, NR, NA, KR, KA, H, D, PW, NBw, NBc;
+  int T, NR, NA, KR, KA, H, D, PW, NBw, NBc, PRC;
   int64_t P;
-  const double* pp;      // [T][kPRChunks][PW]
+  const double* pp;      // [T][PRC][PW]
   const float* w0part;   // [T][NBw][H*D]
   const float* crpart;   // [T][NBc][NR*T*KR]
   float* grad;
@@ -2612,9 +2622,9 @@ __device__ __forceinline__ void grad_final_body(const GradArgs& a, int vb) {
       rows = a.NBc;
     } else if (qi < P_R + P_A) {
       const int I = (qi - P_R) / PSA, slot = (qi - P_R) % PSA;
-      dsrc = a.pp + (size_t)I * kPRChunks * a.PW + slot;
+      dsrc = a.pp + (size_t)I * a.PRC * a.PW + slot;
       stride = a.PW;
-      rows = kPRChunks;
+      rows = a.PRC;
     } else {
       const int I = (qi - P_R - P_A) / blk, o = (qi - P_R - P_A) % blk;
       if (o < HD) {
@@ -2622,9 +2632,9 @@ __device__ __forceinline__ void grad_final_body(const GradArgs& a, int vb) {
         stride = HD;
         rows = a.NBw;
       } else {
-        dsrc = a.pp + (size_t)I * kPRChunks * a.PW + PSA + (o - HD);
+        dsrc = a.pp + (size_t)I * a.PRC * a.PW + PSA + (o - HD);
         stride = a.PW;
-        rows = kPRChunks;
+        rows = a.PRC;
       }
     }
     if (fsrc) {
@@ -2829,7 +2839,7 @@ __global__ __launch_bounds__(256, 2) void k_step(const StepArgs* pa) {
   for_items((a.fwd.N + 256 / kGatherLPA - 1) / (256 / kGatherLPA), [&](int vb) {
     const PairLists nb = item_args(a.nb);
     const FwdArgs f = item_args(a.fwd);
-    gather_body(vb, f.N, nb, f.fR, f.fA, a.F, nullptr);
+    gather_body<kGatherLPA>(vb, f.N, nb, f.fR, f.fA, a.F, nullptr);
   });
   NEP_BARRIER();
   // per-structure sums, loss partials and cotangents
@@ -2849,7 +2859,8 @@ __global__ __launch_bounds__(256, 2) void k_step(const StepArgs* pa) {
   {
     const int T = a.ord.T;
     const int os_x = a.os_x, nzw = a.nzw;
-    const int n_outer = os_x * T * (nzw + a.nzc), n_pr = kPRChunks * T;
+    const int prc = a.g.PRC;
+    const int n_outer = os_x * T * (nzw + a.nzc), n_pr = prc * T;
     auto& red = *reinterpret_cast<f32x4(*)[3][kOSTM * kOSTV][kWave]>(lds);
     for_items(n_outer + n_pr + (a.la.on ? 1 : 0), [&](int v) {
       if (v < n_outer) {
@@ -2860,7 +2871,7 @@ __global__ __launch_bounds__(256, 2) void k_step(const StepArgs* pa) {
           outer_sum_block(item_args(a.oc), x, I, z - nzw, red);
       } else if (v < n_outer + n_pr) {
         const int u = v - n_outer;
-        part_reduce_body(a.PW, a.seg, a.adj.part, a.pp, u % kPRChunks, u / kPRChunks);
+        part_reduce_body(a.PW, a.seg, a.adj.part, a.pp, u % prc, u / prc, prc);
       } else {
         const LossArgs la = item_args(a.la);
         loss_final_block(la.S, la.N, la.le, la.lf, la.lv, la.lpart, la.loss, la.flags, lds);
@@ -2987,8 +2998,8 @@ enum HighKernel { kHighDesc, kHighForce, kHighTangent, kHighCoef };
 
 struct Ops {
   int T, NR, NA, KR, KA, L3, L4, L5, D, Y, PS, YH;
-  void (*forward)(const FwdArgs&, dim3, hipStream_t);
-  void (*adjoint)(const AdjArgs&, dim3, hipStream_t);
+  void (*forward)(const FwdArgs&, dim3, hipStream_t, int);
+  void (*adjoint)(const AdjArgs&, dim3, hipStream_t, int);
   size_t (*lds_fwd)(int);
   size_t (*lds_adj)(int);
   void (*high)(HighKernel, const HighArgs&, dim3, hipStream_t);   // null without degrees l > 4
@@ -3009,19 +3020,34 @@ static size_t lds_adjoint(int H) {
   return sizeof(float) * ((size_t)CTab<C::T, C::NA, C::KA>::size + (size_t)(H * DP + 2 * H) +
                           (size_t)kAPB * (DP + 2 * C::NA * C::Y));
 }
-template <class C>
-static void launch_forward(const FwdArgs& a, dim3 grid, hipStream_t st) {
+// the per-atom kernels are compiled for 2 and 3 wavefronts per SIMD
+template <class C, int W>
+static void launch_forward_w(const FwdArgs& a, dim3 grid, hipStream_t st) {
   if (a.tilt)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forward<C, true>), grid, dim3(256), lds_forward<C>(a.H), st, a);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forward<C, true, W>), grid, dim3(256), lds_forward<C>(a.H), st, a);
   else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forward<C, false>), grid, dim3(256), lds_forward<C>(a.H), st, a);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forward<C, false, W>), grid, dim3(256), lds_forward<C>(a.H), st, a);
 }
 template <class C>
-static void launch_adjoint(const AdjArgs& a, dim3 grid, hipStream_t st) {
-  if (a.tilt)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adjoint<C, true>), grid, dim3(256), lds_adjoint<C>(a.H), st, a);
+static void launch_forward(const FwdArgs& a, dim3 grid, hipStream_t st, int waves) {
+  if (waves == 2)
+    launch_forward_w<C, 2>(a, grid, st);
   else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adjoint<C, false>), grid, dim3(256), lds_adjoint<C>(a.H), st, a);
+    launch_forward_w<C, 3>(a, grid, st);
+}
+template <class C, int W>
+static void launch_adjoint_w(const AdjArgs& a, dim3 grid, hipStream_t st) {
+  if (a.tilt)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adjoint<C, true, W>), grid, dim3(256), lds_adjoint<C>(a.H), st, a);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adjoint<C, false, W>), grid, dim3(256), lds_adjoint<C>(a.H), st, a);
+}
+template <class C>
+static void launch_adjoint(const AdjArgs& a, dim3 grid, hipStream_t st, int waves) {
+  if (waves == 2)
+    launch_adjoint_w<C, 2>(a, grid, st);
+  else
+    launch_adjoint_w<C, 3>(a, grid, st);
 }
 template <class C, bool kTri>
 static void launch_high_t(HighKernel k, const HighArgs& a, dim3 grid, hipStream_t st) {
@@ -3175,9 +3201,9 @@ Layout make_layout(const nep_model* m, const Ops* o, int S, int N) {
   L.beta = take(4 * (size_t)L.H * Np);
   L.w1s = take(4 * (size_t)L.H * Np);
   L.part = take(4 * (size_t)L.nwaves * L.PW);
-  L.pp = take(8 * (size_t)L.T * kPRChunks * L.PW);
-  L.w0part = take(4 * (size_t)L.T * kOSBlocksW * L.H * L.D);
-  L.crpart = take(4 * (size_t)L.T * kOSBlocksC * L.NR * L.TKR);
+  L.pp = take(8 * (size_t)L.T * kPRChunksMax * L.PW);
+  L.w0part = take(4 * (size_t)L.T * kOSBlocksMaxW * L.H * L.D);
+  L.crpart = take(4 * (size_t)L.T * kOSBlocksMaxC * L.NR * L.TKR);
   L.Sh = take(4 * (size_t)Np * L.NA * o->YH);
   L.Sdh = take(4 * (size_t)Np * L.NA * o->YH);
   L.cgrid = take(16 * Ss);
@@ -3245,10 +3271,20 @@ struct Prof {
 
 int hip_ok() { return hipGetLastError() == hipSuccess ? NEP_OK : NEP_ERR_HIP; }
 
+// Launch choices of one evaluation (nep_tuning with the defaults filled in).
+struct Tune {
+  int persistent, outer_w, outer_c, reduce_chunks, cell_min, gather_lanes, forward_waves, adjoint_waves;
+};
+
+Tune default_tune(const Ops* o) {
+  return Tune{0, kOSBlocksW, kOSBlocksC, kPRChunks, kCellMinAtoms, kGatherLPA, 3, o->YH > 0 ? 2 : 3};
+}
+
 struct Ctx {
   const nep_model* m;
   const Ops* o;
   const nep_batch* b;
+  Tune tune;
   Layout L;
   void* ws;
   hipStream_t st;
@@ -3311,7 +3347,8 @@ void run_neighbors(const Ctx& c, nep_neighbors* nb, int32_t* flags, Prof* pr, bo
   a.flags = flags;
   // the cell-list kernels run unless the caller's bound rules out every structure
   const int S = c.b->n_struct;
-  a.cells = N >= kCellMinAtoms && (c.b->max_atoms == 0 || c.b->max_atoms >= kCellMinAtoms);
+  a.cell_min = c.tune.cell_min;
+  a.cells = N >= a.cell_min && (c.b->max_atoms == 0 || c.b->max_atoms >= a.cell_min);
   a.grid = at<int4>(c.ws, c.L.cgrid);
   a.cell = at<int>(c.ws, c.L.cell);
   a.cpart = at<int>(c.ws, c.L.cpart);
@@ -3437,7 +3474,7 @@ void run_high(const Ctx& c, HighKernel k, const HighArgs& h, Prof* pr) {
 void launch_forward_pass(const Ctx& c, const nep_neighbors* nb, const float* params, const FwdArgs& a, Prof* pr) {
   const HighArgs h = high_args(c, nb, params);
   run_high(c, kHighDesc, h, pr);
-  NEP_LAUNCH(pr, "forward", c.o->forward(a, dim3(c.L.Npad / kAPB), c.st));
+  NEP_LAUNCH(pr, "forward", c.o->forward(a, dim3(c.L.Npad / kAPB), c.st, c.tune.forward_waves));
   if (a.do_mlp && a.do_force) run_high(c, kHighForce, h, pr);
 }
 
@@ -3478,9 +3515,12 @@ void run_forward(const Ctx& c, const nep_neighbors* nb, const float* params, flo
     FwdArgs a = fwd_args(c, nb, params);
     a.eatom2 = e_atom;
     launch_forward_pass(c, nb, params, a, pr);
-    NEP_LAUNCH(pr, "force_gather",
-               hipLaunchKernelGGL(k_force_gather, dim3(grid1(N, 256 / kGatherLPA)), dim3(256), 0, c.st, N, a.nb, a.fR, a.fA,
-                                  at<float>(c.ws, c.L.F), force));
+    if (c.tune.gather_lanes == 8)
+      NEP_LAUNCH(pr, "force_gather", hipLaunchKernelGGL(k_force_gather<8>, dim3(grid1(N, 256 / 8)), dim3(256), 0, c.st,
+                                                        N, a.nb, a.fR, a.fA, at<float>(c.ws, c.L.F), force));
+    else
+      NEP_LAUNCH(pr, "force_gather", hipLaunchKernelGGL(k_force_gather<16>, dim3(grid1(N, 256 / 16)), dim3(256), 0,
+                                                        c.st, N, a.nb, a.fR, a.fA, at<float>(c.ws, c.L.F), force));
   }
   if (S > 0) {
     const StructArgs s = struct_args(c, e_struct, virial, lab, lam);
@@ -3539,9 +3579,9 @@ AdjArgs adj_args(const Ctx& c, const nep_neighbors* nb, const float* params, con
 void outer_args(const Ctx& c, const AdjArgs& a, OuterArgs& ow, OuterArgs& oc) {
   const nep_model* m = c.m;
   const int* seg = at<int>(c.ws, c.L.seg);
-  ow = OuterArgs{c.L.Npad, m->hidden, c.o->D, kOSBlocksW, seg, a.beta, at<float>(c.ws, c.L.G), a.w1s, a.Gd,
+  ow = OuterArgs{c.L.Npad, m->hidden, c.o->D, c.tune.outer_w, seg, a.beta, at<float>(c.ws, c.L.G), a.w1s, a.Gd,
                  at<float>(c.ws, c.L.w0part)};
-  oc = OuterArgs{c.L.Npad, m->n_rad, c.L.TKR, kOSBlocksC, seg, a.Gbr, a.FRst, at<float>(c.ws, c.L.Ep), a.FPst,
+  oc = OuterArgs{c.L.Npad, m->n_rad, c.L.TKR, c.tune.outer_c, seg, a.Gbr, a.FRst, at<float>(c.ws, c.L.Ep), a.FPst,
                  at<float>(c.ws, c.L.crpart)};
 }
 
@@ -3556,8 +3596,9 @@ GradArgs grad_args(const Ctx& c, float* grad) {
   g.H = m->hidden;
   g.D = c.o->D;
   g.PW = c.L.PW;
-  g.NBw = kOSBlocksW;
-  g.NBc = kOSBlocksC;
+  g.NBw = c.tune.outer_w;
+  g.NBc = c.tune.outer_c;
+  g.PRC = c.tune.reduce_chunks;
   g.P = param_count(m);
   g.pp = at<double>(c.ws, c.L.pp);
   g.w0part = at<float>(c.ws, c.L.w0part);
@@ -3587,7 +3628,7 @@ void run_adjoint(const Ctx& c, const nep_neighbors* nb, const float* params, con
     const int T = m->n_types;
     const HighArgs h = high_args(c, nb, params, fbar, wbar);
     run_high(c, kHighTangent, h, pr);
-    NEP_LAUNCH(pr, "adjoint", c.o->adjoint(a, dim3(c.L.Npad / kAPB), c.st));
+    NEP_LAUNCH(pr, "adjoint", c.o->adjoint(a, dim3(c.L.Npad / kAPB), c.st, c.tune.adjoint_waves));
     run_high(c, kHighCoef, h, pr);
     const int* seg = at<int>(c.ws, c.L.seg);
     {
@@ -3595,12 +3636,12 @@ void run_adjoint(const Ctx& c, const nep_neighbors* nb, const float* params, con
       outer_args(c, a, ow, oc);
       const int nzw = outer_slices(ow.M, ow.V), nzc = outer_slices(oc.M, oc.V);
       NEP_LAUNCH(pr, "outer_sums",
-                 hipLaunchKernelGGL(k_outer_sum, dim3(std::max(kOSBlocksW, kOSBlocksC), T, nzw + nzc), dim3(256), 0,
+                 hipLaunchKernelGGL(k_outer_sum, dim3(std::max(ow.NB, oc.NB), T, nzw + nzc), dim3(256), 0,
                                     c.st, ow, oc, nzw));
     }
     double* pp = at<double>(c.ws, c.L.pp);
     NEP_LAUNCH(pr, "part_reduce",
-               hipLaunchKernelGGL(k_part_reduce, dim3(kPRChunks, T + (la.on ? 1 : 0)), dim3(256), 0, c.st, c.L.PW,
+               hipLaunchKernelGGL(k_part_reduce, dim3(c.tune.reduce_chunks, T + (la.on ? 1 : 0)), dim3(256), 0, c.st, c.L.PW,
                                   seg, a.part, pp, la));
     const GradArgs g = grad_args(c, grad);
     NEP_LAUNCH(pr, "grad_final", hipLaunchKernelGGL(k_grad_final, dim3(grad_final_blocks(g)), dim3(256), 0, c.st, g));
@@ -3623,6 +3664,7 @@ int setup(Ctx& c, const nep_model* m, const nep_batch* b, void* ws, void* stream
   if ((rc = check_ws(ws))) return rc;
   c.m = m;
   c.b = b;
+  c.tune = default_tune(c.o);
   c.ws = ws;
   c.st = static_cast<hipStream_t>(stream);
   c.L = make_layout(m, c.o, b->n_struct, b->n_atom);
@@ -3699,7 +3741,7 @@ StepArgs step_args(const Ctx& c, nep_neighbors* nb, const float* params, const n
   outer_args(c, a.adj, a.ow, a.oc);
   a.nzw = outer_slices(a.ow.M, a.ow.V);
   a.nzc = outer_slices(a.oc.M, a.oc.V);
-  a.os_x = std::max(kOSBlocksW, kOSBlocksC);
+  a.os_x = std::max(a.ow.NB, a.oc.NB);
   a.PW = c.L.PW;
   a.seg = at<int>(c.ws, c.L.seg);
   a.pp = at<double>(c.ws, c.L.pp);
@@ -3720,6 +3762,28 @@ struct GraphHandle {
 // 1 - beta^step), eps >= 0 finite.
 bool adam_hparams_ok(float beta1, float beta2, float eps) {
   return beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f && std::isfinite(eps);
+}
+
+// Overrides of the launch choices; 0 keeps the default.  NEP_ERR_ARG out of range.
+int apply_tuning(Tune& t, const nep_tuning* u) {
+  if (!u) return NEP_OK;
+  auto set = [](int& dst, int v, int lo, int hi) {
+    if (v == 0) return true;
+    if (v < lo || v > hi) return false;
+    dst = v;
+    return true;
+  };
+  bool ok = u->persistent == 0 || u->persistent == 1;
+  t.persistent = u->persistent;
+  ok = ok && set(t.outer_w, u->outer_blocks_w, 1, kOSBlocksMaxW);
+  ok = ok && set(t.outer_c, u->outer_blocks_c, 1, kOSBlocksMaxC);
+  ok = ok && set(t.reduce_chunks, u->reduce_chunks, 1, kPRChunksMax);
+  ok = ok && set(t.cell_min, u->cell_min_atoms, kCellMinAtomsLo, 1 << 27);
+  ok = ok && (u->gather_lanes == 0 || u->gather_lanes == 8 || u->gather_lanes == 16);
+  if (u->gather_lanes) t.gather_lanes = u->gather_lanes;
+  ok = ok && set(t.forward_waves, u->forward_waves, 2, 3);
+  ok = ok && set(t.adjoint_waves, u->adjoint_waves, 2, 3);
+  return ok ? NEP_OK : NEP_ERR_ARG;
 }
 
 int check_adam_config(const nep_adam_config* a) {
@@ -3928,14 +3992,24 @@ int nep_train_step_graph_create(const nep_model* m, const nep_batch* b, nep_neig
                                 const float lambda[3], float* params, float* mm, float* vv, float* grad, float* loss,
                                 int32_t* d_step, const nep_adam_config* adam, void* ws, int32_t* d_flags,
                                 int32_t graph_flags, void* stream, void** graph) {
+  return nep_train_step_graph_create_tuned(m, b, nb, labels, lambda, params, mm, vv, grad, loss, d_step, adam, ws,
+                                           d_flags, graph_flags, nullptr, stream, graph);
+}
+
+int nep_train_step_graph_create_tuned(const nep_model* m, const nep_batch* b, nep_neighbors* nb,
+                                      const nep_labels* labels, const float lambda[3], float* params, float* mm,
+                                      float* vv, float* grad, float* loss, int32_t* d_step,
+                                      const nep_adam_config* adam, void* ws, int32_t* d_flags, int32_t graph_flags,
+                                      const nep_tuning* tuning, void* stream, void** graph) {
   Ctx c;
   int rc = setup(c, m, b, ws, stream);
   if (rc) return rc;
+  if ((rc = apply_tuning(c.tune, tuning))) return rc;
   if ((rc = check_nbrs(nb, b->n_atom))) return rc;
   if (!labels || !lambda || !params || !mm || !vv || !grad || !loss || !d_step || !adam || !d_flags || !graph)
     return NEP_ERR_ARG;
   if ((rc = check_adam_config(adam))) return rc;
-  const bool persistent = (graph_flags & NEP_GRAPH_PERSISTENT) != 0;
+  const bool persistent = (graph_flags & NEP_GRAPH_PERSISTENT) != 0 || c.tune.persistent;
   size_t slds = 0;
   int sgrid = 0;
   if (persistent) {

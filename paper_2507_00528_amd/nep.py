@@ -269,6 +269,19 @@ def md_step(model, batch, nbrs, params, mass, vel, force, dt, n_steps, e_pot, ws
                                    _ptr(e_pot), _ptr(e_kin), _ptr(ws), _ptr(flags), _stream(stream)), "nep_md_step")
 
 
+TUNING_FIELDS = ("persistent", "outer_blocks_w", "outer_blocks_c", "reduce_chunks", "cell_min_atoms",
+                 "gather_lanes", "forward_waves", "adjoint_waves")
+
+
+def tuning_struct(tuning):
+    """nep_tuning from a dict of launch choices (missing keys: defaults)."""
+    tuning = tuning or {}
+    unknown = set(tuning) - set(TUNING_FIELDS)
+    if unknown:
+        raise ValueError(f"unknown tuning keys {sorted(unknown)}")
+    return _lib.NepTuning(*[int(tuning.get(k, 0)) for k in TUNING_FIELDS])
+
+
 GRAPH_CACHED_NEIGHBORS = 1
 GRAPH_PERSISTENT = 2
 NEP_FLAG_BARRIER = 64
@@ -280,24 +293,34 @@ class TrainStepGraph:
     skips the neighbor build and reuses the lists (and the reverse index and
     species order in ws) from an earlier build_neighbors call.  With
     persistent everything after the neighbor build runs as one persistent
-    launch (NEP_GRAPH_PERSISTENT)."""
+    launch (NEP_GRAPH_PERSISTENT).  tuning: launch choices (nep_tuning) as a
+    dict, None for the defaults, or "cache" for the autotuner's choice for
+    this model and batch size class (defaults when it has none)."""
 
     def __init__(self, model, batch, nbrs, labels, lam, params, m, v, grad, loss, step, ws, flags,
                  lr_start=1e-3, lr_stop=1e-3, n_warmup=0, n_total=0, beta1=0.9, beta2=0.999, eps=1e-8,
-                 stream=None, cached_neighbors=False, persistent=False):
+                 stream=None, cached_neighbors=False, persistent=False, tuning="cache"):
         P = param_count(model)
         for t, name in ((params, "params"), (m, "m"), (v, "v"), (grad, "grad")):
             _want(t, torch.float32, P, name)
         _want(step, torch.int32, 1, "step")
         self._keep = (model, batch, nbrs, labels, params, m, v, grad, loss, step, ws, flags)
         cfg = _lib.NepAdamConfig(lr_start, lr_stop, n_warmup, n_total, beta1, beta2, eps)
+        if isinstance(tuning, str):
+            if tuning != "cache":
+                raise ValueError("tuning: a dict of launch choices, None (defaults) or 'cache'")
+            from . import tune
+            tuning = tune.lookup(model, batch)
+        self.tuning = dict(tuning or {})
+        if persistent:
+            self.tuning["persistent"] = 1
         h = C.c_void_p()
-        _check(_lib.load().nep_train_step_graph_create(
+        _check(_lib.load().nep_train_step_graph_create_tuned(
             C.byref(model.c()), C.byref(batch.c()), C.byref(nbrs.c()), C.byref(labels.c()), C.byref(_lam(lam)),
             _ptr(params), _ptr(m), _ptr(v), _ptr(grad), _ptr(loss), _ptr(step), C.byref(cfg), _ptr(ws),
-            _ptr(flags), (GRAPH_CACHED_NEIGHBORS if cached_neighbors else 0) | (GRAPH_PERSISTENT if persistent else 0),
+            _ptr(flags), GRAPH_CACHED_NEIGHBORS if cached_neighbors else 0, C.byref(tuning_struct(self.tuning)),
             _stream(stream), C.byref(h)),
-            "nep_train_step_graph_create")
+            "nep_train_step_graph_create_tuned")
         self.handle = h
 
     def launch(self, stream=None):

@@ -139,3 +139,22 @@ def test_noalloc_rejects_batches_beyond_its_static_scratch_on_the_host():
     rc = lib.nep_loss_grad_noalloc(C.byref(bad.c()), C.byref(b), C.byref(nb), fake, C.byref(lab), C.byref(lam),
                                    fake, fake, None, None, None, fake, None)
     assert rc == -1
+
+
+def test_tuned_graph_create_rejects_out_of_range_choices_before_launch():
+    lib = _lib.load()
+    m = nep.Model.of(synth.SIZES_SMALL).c()
+    b = _lib.NepBatch(0, 0, None, None, None, None)
+    nb = _lib.NepNeighbors(None, None, None, None)
+    lab = _lib.NepLabels(None, None, None)
+    lam = (C.c_float * 3)(1.0, 1.0, 0.1)
+    fake = C.c_void_p(0x100000)
+    cfg = _lib.NepAdamConfig(1e-3, 1e-3, 0, 0, 0.9, 0.999, 1e-8)
+    h = C.c_void_p()
+    for bad in ({"gather_lanes": 12}, {"forward_waves": 4}, {"outer_blocks_w": 513}, {"reduce_chunks": -1},
+                {"cell_min_atoms": 10}, {"persistent": 2}):
+        t = nep.tuning_struct(bad)
+        rc = lib.nep_train_step_graph_create_tuned(C.byref(m), C.byref(b), C.byref(nb), C.byref(lab), C.byref(lam),
+                                                   fake, fake, fake, fake, fake, fake, C.byref(cfg), fake, fake, 0,
+                                                   C.byref(t), None, C.byref(h))
+        assert rc == -1, bad
