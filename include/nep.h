@@ -71,8 +71,12 @@ enum {
  *   hidden: hidden neurons of the per-species tanh network (D1.1)
  *   rc_rad, rc_ang: cutoff radii (Eq. 2, A2.1), rc_ang <= rc_rad
  *   cap_rad, cap_ang: neighbor-list capacity per atom
- * Supported (n_types, n_rad, n_ang, k_rad, k_ang, l3, l4, l5) combinations are
- * compiled in; nep_model_supported() tells. */
+ * Supported: up to 4 species, n_rad <= 12, n_ang <= 8, k_rad and k_ang <= 12,
+ * l3 <= 8, l4 and l5 on or off (and the LDS of the chosen kernels within a
+ * gfx950 workgroup's 160 KiB, which bounds hidden).  A few shapes are
+ * compiled exactly; any other runs in the smallest compiled size class that
+ * holds it, with its parameters zero-padded on the device (exact: padded
+ * quantities contribute zeros).  nep_model_supported() tells. */
 typedef struct {
   int32_t n_types, n_rad, n_ang, k_rad, k_ang, l3, l4, l5, hidden;
   float rc_rad, rc_ang;
@@ -147,7 +151,8 @@ int64_t nep_param_count(const nep_model* model);
  * [4-body q_n][5-body q_n]. */
 int32_t nep_descriptor_count(const nep_model* model);
 
-/* NEP_OK if kernels for this model are compiled in, else NEP_ERR_ARG. */
+/* NEP_OK if the model runs (an exact compiled shape or a size class that
+ * holds it, see nep_model), else NEP_ERR_ARG. */
 int nep_model_supported(const nep_model* model);
 
 /* Bytes of workspace needed for a batch of n_struct structures, n_atom atoms. */

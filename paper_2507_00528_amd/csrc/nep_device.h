@@ -25,8 +25,11 @@ __device__ __forceinline__ cptr<T> as_const(const T* p) {
   return (cptr<T>)(p);
 }
 
-template <int T_, int NR_, int NA_, int KR_, int KA_, int L3_, int L4_, int L5_>
+// FW_ = 0: the per-atom kernels are compiled for 2 and 3 wavefronts per SIMD
+// (a launch choice); otherwise for FW_ only (the padded size classes).
+template <int T_, int NR_, int NA_, int KR_, int KA_, int L3_, int L4_, int L5_, int FW_ = 0>
 struct Cfg {
+  static constexpr int FIXED_WAVES = FW_;
   static constexpr int T = T_, NR = NR_, NA = NA_, KR = KR_, KA = KA_;
   static constexpr int L3 = L3_, L4 = L4_, L5 = L5_;
   // the per-atom kernels hold the harmonics of l <= 4 (and of the 4-/5-body

@@ -489,19 +489,23 @@ __global__ __launch_bounds__(256) void k_high_tangent(HighArgs a) {
 
 // The c^A gradient: for each pair, X_n = sum_lm (Sbar_nlm Y - A_nlm grad Y . w)
 // and Y_n = sum_lm A_nlm Y (sums over the lanes), then
-// dL/dc_nk^{IJ} += X_n f_k - Y_n (u.t) f'_k.  The 2 NA sums of a pair come
-// out of one scattered sum: lanes with (lane & 7) = n hold X_n, with
-// (lane & 7) = 4 + n hold Y_n; lane l then takes channel n = l & 3 and
-// coefficient slot (J, k) = (l >> 2) / KA, (l >> 2) % KA.
+// dL/dc_nk^{IJ} += X_n f_k - Y_n (u.t) f'_k.  Channels go in groups of four:
+// the 8 sums of a group (X of its channels, then Y) come out of one scattered
+// sum, lanes with (lane & 7) = e holding X of channel e and 4 + e holding Y.
+// Coefficient slots (channel, J, k) are dealt to the lanes: lane l takes
+// channel 4 cg + (l & 3) of group cg and slot (J, k) = 16 sg + (l >> 2) of
+// slot group sg, for every group pair (cg, sg).
 template <class C, bool kTri>
 __global__ __launch_bounds__(256) void k_high_coef(HighArgs a) {
   constexpr int T = C::T;
   NEP_HIGH_PROLOGUE(true, true)
-  static_assert(NA <= 4 && T * KA <= 16, "one coefficient slot per lane");
+  constexpr int NCG = (NA + 3) / 4, NSG = (T * KA + 15) / 16;
   const int ne = lane & 3, se = lane >> 2;
-  const int te = se / KA, ke = se % KA;
-  const bool slot = ne < NA && se < T * KA;
-  float cb = 0.f;
+  float cb[NCG][NSG];
+#pragma unroll
+  for (int cg = 0; cg < NCG; ++cg)
+#pragma unroll
+    for (int sg = 0; sg < NSG; ++sg) cb[cg][sg] = 0.f;
   float Sb[NA], Av[NA];
   auto start = [&](int u) {
     // Sbar = 2 (Gbar S~ - E' Sdot~), A = 2 E' S~ (signs as in the main adjoint)
@@ -519,24 +523,44 @@ __global__ __launch_bounds__(256) void k_high_coef(HighArgs a) {
     float v, gx, gy, gz;
     high_eval(h, rec[R::DZ * kWave + jj] * rec[R::IR * kWave + jj], pw + jj * kPwStride, v, gx, gy, gz);
     const float gwt = gx * rec[R::WX * kWave + jj] + gy * rec[R::WY * kWave + jj] + gz * rec[R::WZ * kWave + jj];
-    float xs[8];
-#pragma unroll
-    for (int n = 0; n < 4; ++n) {
-      xs[n] = n < NA ? fmaf(Sb[n < NA ? n : 0], v, -Av[n < NA ? n : 0] * gwt) : 0.f;
-      xs[4 + n] = n < NA ? Av[n < NA ? n : 0] * v : 0.f;
-    }
-    const float own = wave_scatter_sum<8>(xs);
-    const float other = xor4_val(own);
-    const bool lo = (lane & 4) == 0;
-    const float Xe = lo ? own : other, Ye = lo ? other : own;
     const int J = __float_as_int(rec[R::J * kWave + jj]);
     const float dt = rec[R::DT * kWave + jj];
-    const float fk = rec[(R::F + ke) * kWave + jj], fpk = rec[(R::FP + ke) * kWave + jj];
-    cb += (T == 1 || J == te) ? fmaf(Xe, fk, -Ye * dt * fpk) : 0.f;
+    const bool lo = (lane & 4) == 0;
+#pragma unroll
+    for (int cg = 0; cg < NCG; ++cg) {
+      float xs[8];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int n = 4 * cg + e;
+        const int nc = n < NA ? n : 0;
+        xs[e] = n < NA ? fmaf(Sb[nc], v, -Av[nc] * gwt) : 0.f;
+        xs[4 + e] = n < NA ? Av[nc] * v : 0.f;
+      }
+      const float own = wave_scatter_sum<8>(xs);
+      const float other = xor4_val(own);
+      const float Xe = lo ? own : other, Ye = lo ? other : own;
+#pragma unroll
+      for (int sg = 0; sg < NSG; ++sg) {
+        const int sl = 16 * sg + se;
+        const int te = sl / KA, ke = sl % KA;
+        const int kc = sl < T * KA ? ke : 0;
+        const float fk = rec[(R::F + kc) * kWave + jj], fpk = rec[(R::FP + kc) * kWave + jj];
+        cb[cg][sg] += (T == 1 || J == te) ? fmaf(Xe, fk, -Ye * dt * fpk) : 0.f;
+      }
+    }
   };
   auto finish = [&](int) {};
   high_walk<C, kTri, true, true>(a, gr, rec, pw, start, pair, finish);
-  if (slot) a.part[(size_t)wave * a.PW + (te * NA + ne) * KA + ke] += cb;
+#pragma unroll
+  for (int cg = 0; cg < NCG; ++cg)
+#pragma unroll
+    for (int sg = 0; sg < NSG; ++sg) {
+      const int n = 4 * cg + ne, sl = 16 * sg + se;
+      if (n < NA && sl < T * KA) {
+        const int te = sl / KA, ke = sl % KA;
+        a.part[(size_t)wave * a.PW + (te * NA + n) * KA + ke] += cb[cg][sg];
+      }
+    }
 }
 
 #undef NEP_HIGH_PROLOGUE

@@ -2896,6 +2896,74 @@ __global__ void k_step_head(StepArgs a, StepArgs* dst, int* flags, int* step, in
   graph_head(flags, step, cur);
 }
 
+// ============================================================ padded models
+// A model smaller than a compiled size class runs in that class with its
+// parameters zero-padded: radial and angular channels, Chebyshev terms and
+// species the model does not have get zero coefficients, and the network's
+// columns of descriptors it does not have (higher channels, degrees up to the
+// class's, the 4- and 5-body terms) get zero weights.  Every padded quantity
+// then adds an exact zero to the energies, forces and virials, and the
+// gradient entries of the model's own parameters are those of the class run.
+// PadDims maps a parameter of the model to its slot in the class layout.
+struct PadDims {
+  int T, NR, NA, KR, KA, D, H, l3, l4, l5;   // the model
+  int Tc, NRc, NAc, KRc, KAc, Dc, L3c;       // the class (4- and 5-body terms on)
+  int64_t P;                                 // parameters of the model
+};
+
+// class column of descriptor v of the model
+__device__ __forceinline__ int pad_col(const PadDims& d, int v) {
+  if (v < d.NR) return v;
+  v -= d.NR;
+  if (v < d.l3 * d.NA) return d.NRc + (v / d.NA) * d.NAc + v % d.NA;
+  v -= d.l3 * d.NA;
+  if (d.l4) {
+    if (v < d.NA) return d.NRc + d.L3c * d.NAc + v;
+    v -= d.NA;
+  }
+  return d.NRc + d.L3c * d.NAc + d.NAc + v;   // 5-body
+}
+
+__device__ __forceinline__ int64_t pad_index(const PadDims& d, int64_t q) {
+  const int64_t PR = (int64_t)d.T * d.T * d.NR * d.KR, PA = (int64_t)d.T * d.T * d.NA * d.KA;
+  const int64_t PRc = (int64_t)d.Tc * d.Tc * d.NRc * d.KRc, PAc = (int64_t)d.Tc * d.Tc * d.NAc * d.KAc;
+  if (q < PR) {
+    const int64_t k = q % d.KR, n = (q / d.KR) % d.NR, J = (q / ((int64_t)d.KR * d.NR)) % d.T;
+    const int64_t I = q / ((int64_t)d.KR * d.NR * d.T);
+    return ((I * d.Tc + J) * d.NRc + n) * d.KRc + k;
+  }
+  q -= PR;
+  if (q < PA) {
+    const int64_t k = q % d.KA, n = (q / d.KA) % d.NA, J = (q / ((int64_t)d.KA * d.NA)) % d.T;
+    const int64_t I = q / ((int64_t)d.KA * d.NA * d.T);
+    return PRc + ((I * d.Tc + J) * d.NAc + n) * d.KAc + k;
+  }
+  q -= PA;
+  const int64_t HD = (int64_t)d.H * d.D;
+  const int64_t blk = HD + 2 * d.H + 1, blkc = (int64_t)d.H * d.Dc + 2 * d.H + 1;
+  const int64_t I = q / blk, o = q % blk;
+  const int64_t base = PRc + PAc + I * blkc;
+  if (o < HD) return base + (o / d.D) * d.Dc + pad_col(d, (int)(o % d.D));
+  return base + (int64_t)d.H * d.Dc + (o - HD);   // b0, w1, b1
+}
+
+__global__ __launch_bounds__(256) void k_pad_params(PadDims d, const float* __restrict__ p, float* __restrict__ pc) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q < d.P) pc[pad_index(d, q)] = p[q];
+}
+
+__global__ __launch_bounds__(256) void k_unpad_grad(PadDims d, const float* __restrict__ gc, float* __restrict__ g) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q < d.P) g[q] = gc[pad_index(d, q)];
+}
+
+// descriptor rows [Dc][N] of the class to the model's [D][N]
+__global__ __launch_bounds__(256) void k_unpad_desc(PadDims d, int N, const float* __restrict__ Gc,
+                                                    float* __restrict__ G) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q < (int64_t)d.D * N) G[q] = Gc[(int64_t)pad_col(d, (int)(q / N)) * N + q % N];
+}
+
 // ================================================================ dispatch
 // ====================================================================== MD
 // Velocity Verlet for the inference path, in eV, A, fs and amu: the
@@ -3006,6 +3074,7 @@ struct Ops {
   // persistent step (null with degrees l > 4): launch, and resident blocks per CU
   void (*step)(const StepArgs*, int, size_t, hipStream_t);
   int (*step_occupancy)(size_t);
+  bool padded;   // a size class: models up to its sizes run zero-padded
 };
 
 template <class C>
@@ -3020,31 +3089,53 @@ static size_t lds_adjoint(int H) {
   return sizeof(float) * ((size_t)CTab<C::T, C::NA, C::KA>::size + (size_t)(H * DP + 2 * H) +
                           (size_t)kAPB * (DP + 2 * C::NA * C::Y));
 }
+// LDS of a workgroup on gfx950 (160 KiB per CU); dynamic LDS beyond 64 KiB is
+// requested from the runtime per kernel before its launch
+constexpr size_t kMaxLds = 160 * 1024;
+template <class K>
+static void allow_lds(K* k, size_t bytes) {
+  if (bytes > 64 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)bytes);
+}
+
 // the per-atom kernels are compiled for 2 and 3 wavefronts per SIMD
 template <class C, int W>
 static void launch_forward_w(const FwdArgs& a, dim3 grid, hipStream_t st) {
-  if (a.tilt)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forward<C, true, W>), grid, dim3(256), lds_forward<C>(a.H), st, a);
-  else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forward<C, false, W>), grid, dim3(256), lds_forward<C>(a.H), st, a);
+  const size_t lds = lds_forward<C>(a.H);
+  if (a.tilt) {
+    allow_lds(&k_forward<C, true, W>, lds);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forward<C, true, W>), grid, dim3(256), lds, st, a);
+  } else {
+    allow_lds(&k_forward<C, false, W>, lds);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_forward<C, false, W>), grid, dim3(256), lds, st, a);
+  }
 }
 template <class C>
 static void launch_forward(const FwdArgs& a, dim3 grid, hipStream_t st, int waves) {
-  if (waves == 2)
+  if constexpr (C::FIXED_WAVES != 0)
+    launch_forward_w<C, C::FIXED_WAVES>(a, grid, st);
+  else if (waves == 2)
     launch_forward_w<C, 2>(a, grid, st);
   else
     launch_forward_w<C, 3>(a, grid, st);
 }
 template <class C, int W>
 static void launch_adjoint_w(const AdjArgs& a, dim3 grid, hipStream_t st) {
-  if (a.tilt)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adjoint<C, true, W>), grid, dim3(256), lds_adjoint<C>(a.H), st, a);
-  else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adjoint<C, false, W>), grid, dim3(256), lds_adjoint<C>(a.H), st, a);
+  const size_t lds = lds_adjoint<C>(a.H);
+  if (a.tilt) {
+    allow_lds(&k_adjoint<C, true, W>, lds);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adjoint<C, true, W>), grid, dim3(256), lds, st, a);
+  } else {
+    allow_lds(&k_adjoint<C, false, W>, lds);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_adjoint<C, false, W>), grid, dim3(256), lds, st, a);
+  }
 }
 template <class C>
 static void launch_adjoint(const AdjArgs& a, dim3 grid, hipStream_t st, int waves) {
-  if (waves == 2)
+  if constexpr (C::FIXED_WAVES != 0)
+    launch_adjoint_w<C, C::FIXED_WAVES>(a, grid, st);
+  else if (waves == 2)
     launch_adjoint_w<C, 2>(a, grid, st);
   else
     launch_adjoint_w<C, 3>(a, grid, st);
@@ -3069,6 +3160,7 @@ static void launch_high(HighKernel k, const HighArgs& a, dim3 grid, hipStream_t 
 }
 template <class C>
 static void launch_step(const StepArgs* a, int grid, size_t lds, hipStream_t st) {
+  allow_lds(&k_step<C>, lds);
   hipLaunchKernelGGL(HIP_KERNEL_NAME(k_step<C>), dim3(grid), dim3(256), lds, st, a);
 }
 template <class C>
@@ -3084,23 +3176,33 @@ static Ops make_ops() {
   void (*high)(HighKernel, const HighArgs&, dim3, hipStream_t) = nullptr;
   void (*step)(const StepArgs*, int, size_t, hipStream_t) = nullptr;
   int (*occ)(size_t) = nullptr;
-  if constexpr (C::YH > 0) {
-    high = &launch_high<C>;
-  } else {
+  if constexpr (C::YH > 0) high = &launch_high<C>;
+  if constexpr (C::YH == 0 && C::FIXED_WAVES == 0) {
     step = &launch_step<C>;
     occ = &step_occupancy<C>;
   }
   return Ops{C::T, C::NR, C::NA, C::KR, C::KA, C::L3, C::L4, C::L5, C::D, C::Y, C::PS, C::YH,
-             &launch_forward<C>, &launch_adjoint<C>, &lds_forward<C>, &lds_adjoint<C>, high, step, occ};
+             &launch_forward<C>, &launch_adjoint<C>, &lds_forward<C>, &lds_adjoint<C>, high, step, occ,
+             C::FIXED_WAVES != 0};
 }
 
-// Compiled-in model sizes (n_types, n_rad, n_ang, k_rad, k_ang, l3, l4, l5).
+// Compiled-in model sizes (n_types, n_rad, n_ang, k_rad, k_ang, l3, l4, l5):
+// exact shapes, then size classes that run any model up to their sizes with
+// the parameters zero-padded (kPadClasses, smallest first).
 static const Ops kOps[] = {
     make_ops<Cfg<2, 5, 5, 9, 9, 4, 0, 0>>(),    // 3-body NEP, basis 8, n_max 4
     make_ops<Cfg<2, 7, 5, 11, 11, 4, 2, 1>>(),  // 3/4/5-body NEP, basis 10, n_max 6/4
     make_ops<Cfg<2, 3, 2, 4, 3, 4, 2, 1>>(),    // small two-species model
     make_ops<Cfg<1, 4, 3, 6, 5, 2, 2, 0>>(),    // small one-species model
     make_ops<Cfg<2, 5, 4, 8, 8, 8, 2, 1>>(),    // 3-body degrees up to l = 8, n_max 4/3
+};
+static const Ops kPadClasses[] = {
+    make_ops<Cfg<1, 12, 8, 12, 12, 4, 2, 1, 2>>(),
+    make_ops<Cfg<2, 12, 8, 12, 12, 4, 2, 1, 2>>(),
+    make_ops<Cfg<4, 12, 8, 12, 12, 4, 2, 1, 2>>(),
+    make_ops<Cfg<1, 12, 8, 12, 12, 8, 2, 1, 2>>(),
+    make_ops<Cfg<2, 12, 8, 12, 12, 8, 2, 1, 2>>(),
+    make_ops<Cfg<4, 12, 8, 12, 12, 8, 2, 1, 2>>(),
 };
 
 }  // namespace nep
@@ -3110,13 +3212,43 @@ using namespace nep;
 
 namespace {
 
-const Ops* find_ops(const nep_model* m) {
+// Kernels for a model: an exact compiled shape, else the smallest size class
+// that holds it (the model then runs zero-padded as the class model `cls`).
+struct Resolved {
+  const Ops* o = nullptr;
+  nep_model cls{};
+  bool pad = false;
+};
+
+Resolved resolve(const nep_model* m) {
+  Resolved r;
   for (const Ops& o : kOps)
     if (o.T == m->n_types && o.NR == m->n_rad && o.NA == m->n_ang && o.KR == m->k_rad && o.KA == m->k_ang &&
-        o.L3 == m->l3 && o.L4 == m->l4 && o.L5 == m->l5)
-      return &o;
-  return nullptr;
+        o.L3 == m->l3 && o.L4 == m->l4 && o.L5 == m->l5) {
+      r.o = &o;
+      r.cls = *m;
+      return r;
+    }
+  for (const Ops& o : kPadClasses)
+    if (o.T >= m->n_types && o.NR >= m->n_rad && o.NA >= m->n_ang && o.KR >= m->k_rad && o.KA >= m->k_ang &&
+        o.L3 >= m->l3 && o.L4 >= m->l4 && o.L5 >= m->l5) {
+      r.o = &o;
+      r.pad = true;
+      r.cls = *m;
+      r.cls.n_types = o.T;
+      r.cls.n_rad = o.NR;
+      r.cls.n_ang = o.NA;
+      r.cls.k_rad = o.KR;
+      r.cls.k_ang = o.KA;
+      r.cls.l3 = o.L3;
+      r.cls.l4 = o.L4;
+      r.cls.l5 = o.L5;
+      return r;
+    }
+  return r;
 }
+
+const Ops* find_ops(const nep_model* m) { return resolve(m).o; }
 
 int model_valid(const nep_model* m) {
   if (!m) return NEP_ERR_ARG;
@@ -3143,10 +3275,11 @@ struct Layout {
   int N, S, T, D, Y, H, NR, TKR, Npad, nwaves, nblk, PW, NA, capR, capA;
   size_t order, seg, blk, astruct, revR, revA, G, Sst, Ep, X, eatom, fR, fA, wv, F, fbar, Es, Ws, eps, wbar, lpart,
       Gd, FRst, FPst, Gbr, beta, w1s, part, pp, w0part, crpart, Sh, Sdh, cgrid, cell, cpart, acell, aslot, cpos, spart,
-      cur_step, bar, sargs, total;
+      cur_step, bar, sargs, prm, grd, Gtmp, total;
 };
 
-Layout make_layout(const nep_model* m, const Ops* o, int S, int N) {
+// m: the model the kernels run (the class model when padded)
+Layout make_layout(const nep_model* m, const Ops* o, int S, int N, bool pad = false) {
   Layout L{};
   L.N = N;
   L.S = S;
@@ -3216,6 +3349,12 @@ Layout make_layout(const nep_model* m, const Ops* o, int S, int N) {
   L.cur_step = take(4);
   L.bar = take(4 * kBarWords);
   L.sargs = take(sizeof(StepArgs));
+  // a padded model: the class-layout parameters and gradient, and the class
+  // descriptor rows of nep_descriptors
+  const size_t Pc = pad ? (size_t)param_count(m) : 0;
+  L.prm = take(4 * Pc);
+  L.grd = take(4 * Pc);
+  L.Gtmp = take(pad ? 4 * (size_t)L.D * Nn : 0);
   L.total = off;
   return L;
 }
@@ -3281,7 +3420,11 @@ Tune default_tune(const Ops* o) {
 }
 
 struct Ctx {
-  const nep_model* m;
+  const nep_model* m;    // the model the kernels run: the caller's, or its size class
+  const nep_model* mu;   // the caller's model
+  nep_model mcls;        // the size-class model of a padded run
+  bool pad = false;
+  PadDims pd{};
   const Ops* o;
   const nep_batch* b;
   Tune tune;
@@ -3329,7 +3472,7 @@ void run_neighbors(const Ctx& c, nep_neighbors* nb, int32_t* flags, Prof* pr, bo
   NbrArgs a;
   a.N = N;
   a.S = c.b->n_struct;
-  a.T = c.m->n_types;
+  a.T = c.mu->n_types;   // types are checked against the caller's model
   a.capR = c.m->cap_rad;
   a.capA = c.m->cap_ang;
   a.rcR = c.m->rc_rad;
@@ -3604,7 +3747,7 @@ GradArgs grad_args(const Ctx& c, float* grad) {
   g.w0part = at<float>(c.ws, c.L.w0part);
   g.crpart = at<float>(c.ws, c.L.crpart);
   g.grad = grad;
-  g.adam = c.adam != nullptr;
+  g.adam = c.adam != nullptr && !c.pad;   // a padded model's Adam runs on its own layout
   if (c.adam) {
     g.ad = c.adam->ad;
     g.th = c.adam->th;
@@ -3643,10 +3786,20 @@ void run_adjoint(const Ctx& c, const nep_neighbors* nb, const float* params, con
     NEP_LAUNCH(pr, "part_reduce",
                hipLaunchKernelGGL(k_part_reduce, dim3(c.tune.reduce_chunks, T + (la.on ? 1 : 0)), dim3(256), 0, c.st, c.L.PW,
                                   seg, a.part, pp, la));
-    const GradArgs g = grad_args(c, grad);
+    // a padded model: the class gradient in the workspace, then the model's
+    // entries, then Adam on the model's parameters
+    float* gk = c.pad ? at<float>(c.ws, c.L.grd) : grad;
+    const GradArgs g = grad_args(c, gk);
     NEP_LAUNCH(pr, "grad_final", hipLaunchKernelGGL(k_grad_final, dim3(grad_final_blocks(g)), dim3(256), 0, c.st, g));
+    if (c.pad) {
+      const unsigned nb = (unsigned)((c.pd.P + 255) / 256);
+      NEP_LAUNCH(pr, "unpad_grad", hipLaunchKernelGGL(k_unpad_grad, dim3(nb), dim3(256), 0, c.st, c.pd, gk, grad));
+      if (c.adam)
+        hipLaunchKernelGGL(k_adam_dev, dim3(nb), dim3(256), 0, c.st, c.pd.P, c.adam->th, c.adam->mm, c.adam->vv, grad,
+                           c.adam->step, c.adam->flags, c.adam->ad);
+    }
   } else {
-    const int64_t P = param_count(m);
+    const int64_t P = param_count(c.mu);
     hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, c.st, grad, P, 0.f);
     if (c.adam)
       hipLaunchKernelGGL(k_adam_dev, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, c.st, P, c.adam->th,
@@ -3654,21 +3807,74 @@ void run_adjoint(const Ctx& c, const nep_neighbors* nb, const float* params, con
   }
 }
 
-int setup(Ctx& c, const nep_model* m, const nep_batch* b, void* ws, void* stream) {
+PadDims pad_dims(const nep_model* m, const nep_model* cls) {
+  PadDims d;
+  d.T = m->n_types;
+  d.NR = m->n_rad;
+  d.NA = m->n_ang;
+  d.KR = m->k_rad;
+  d.KA = m->k_ang;
+  d.D = desc_count(m);
+  d.H = m->hidden;
+  d.l3 = m->l3;
+  d.l4 = m->l4;
+  d.l5 = m->l5;
+  d.Tc = cls->n_types;
+  d.NRc = cls->n_rad;
+  d.NAc = cls->n_ang;
+  d.KRc = cls->k_rad;
+  d.KAc = cls->k_ang;
+  d.Dc = desc_count(cls);
+  d.L3c = cls->l3;
+  d.P = param_count(m);
+  return d;
+}
+
+// kernels exist for the model and their LDS fits
+int model_supported(const nep_model* m, Resolved* out = nullptr) {
   int rc = model_valid(m);
   if (rc) return rc;
-  c.o = find_ops(m);
-  if (!c.o) return NEP_ERR_ARG;
-  if (c.o->lds_adj(m->hidden) > 64 * 1024 || c.o->lds_fwd(m->hidden) > 64 * 1024) return NEP_ERR_ARG;
+  const Resolved r = resolve(m);
+  if (!r.o) return NEP_ERR_ARG;
+  if (r.o->lds_adj(m->hidden) > kMaxLds || r.o->lds_fwd(m->hidden) > kMaxLds) return NEP_ERR_ARG;
+  if (out) *out = r;
+  return NEP_OK;
+}
+
+size_t workspace_size(const nep_model* m, int S, int N) {
+  const Resolved r = resolve(m);
+  return make_layout(&r.cls, r.o, S, N, r.pad).total;
+}
+
+int setup(Ctx& c, const nep_model* m, const nep_batch* b, void* ws, void* stream) {
+  Resolved r;
+  int rc = model_supported(m, &r);
+  if (rc) return rc;
   if ((rc = check_batch(b))) return rc;
   if ((rc = check_ws(ws))) return rc;
-  c.m = m;
+  c.o = r.o;
+  c.mu = m;
+  c.pad = r.pad;
+  c.mcls = r.cls;
+  c.m = r.pad ? &c.mcls : m;
+  if (r.pad) c.pd = pad_dims(m, &c.mcls);
   c.b = b;
   c.tune = default_tune(c.o);
   c.ws = ws;
   c.st = static_cast<hipStream_t>(stream);
-  c.L = make_layout(m, c.o, b->n_struct, b->n_atom);
+  c.L = make_layout(c.m, c.o, b->n_struct, b->n_atom, r.pad);
   return NEP_OK;
+}
+
+// The parameters the kernels read: the caller's, or for a padded model their
+// class-layout copy in the workspace (filled by launches on the call's stream).
+const float* kernel_params(const Ctx& c, const float* params) {
+  if (!c.pad) return params;
+  float* pc = at<float>(c.ws, c.L.prm);
+  const int64_t Pc = param_count(c.m);
+  hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((Pc + 255) / 256)), dim3(256), 0, c.st, pc, Pc, 0.f);
+  hipLaunchKernelGGL(k_pad_params, dim3((unsigned)((c.pd.P + 255) / 256)), dim3(256), 0, c.st, c.pd, params, pc);
+  return pc;
 }
 
 // loss sum carried by the first reduction launch after the adjoint
@@ -3830,17 +4036,13 @@ int32_t nep_descriptor_count(const nep_model* m) {
   return rc ? rc : desc_count(m);
 }
 
-int nep_model_supported(const nep_model* m) {
-  const int rc = model_valid(m);
-  if (rc) return rc;
-  return find_ops(m) ? NEP_OK : NEP_ERR_ARG;
-}
+int nep_model_supported(const nep_model* m) { return model_supported(m); }
 
 int nep_workspace_bytes(const nep_model* m, int32_t n_struct, int32_t n_atom, size_t* bytes) {
   int rc = nep_model_supported(m);
   if (rc) return rc;
   if (!bytes || n_struct < 0 || n_atom < 0 || n_atom >= (1 << 27)) return NEP_ERR_ARG;
-  *bytes = make_layout(m, find_ops(m), n_struct, n_atom).total;
+  *bytes = workspace_size(m, n_struct, n_atom);
   return NEP_OK;
 }
 
@@ -3863,11 +4065,15 @@ int nep_descriptors(const nep_model* m, const nep_batch* b, const nep_neighbors*
   if ((rc = check_nbrs(nb, b->n_atom))) return rc;
   if (b->n_atom > 0 && (!params || !G)) return NEP_ERR_ARG;
   if (b->n_atom == 0) return NEP_OK;
-  FwdArgs a = fwd_args(c, nb, params);
-  a.Guser = G;
+  const float* kp = kernel_params(c, params);
+  FwdArgs a = fwd_args(c, nb, kp);
+  a.Guser = c.pad ? at<float>(c.ws, c.L.Gtmp) : G;
   a.do_mlp = 0;
   a.do_force = 0;
-  launch_forward_pass(c, nb, params, a, nullptr);
+  launch_forward_pass(c, nb, kp, a, nullptr);
+  if (c.pad)
+    hipLaunchKernelGGL(k_unpad_desc, dim3((unsigned)(((int64_t)c.pd.D * b->n_atom + 255) / 256)), dim3(256), 0, c.st,
+                       c.pd, b->n_atom, a.Guser, G);
   return hip_ok();
 }
 
@@ -3878,7 +4084,8 @@ int nep_energy_force_virial(const nep_model* m, const nep_batch* b, const nep_ne
   if (rc) return rc;
   if ((rc = check_nbrs(nb, b->n_atom))) return rc;
   if (!params) return NEP_ERR_ARG;
-  run_forward(c, nb, params, e_atom, e_struct, force, virial, nullptr, nullptr, nullptr, nullptr, nullptr);
+  run_forward(c, nb, kernel_params(c, params), e_atom, e_struct, force, virial, nullptr, nullptr, nullptr, nullptr,
+              nullptr);
   return hip_ok();
 }
 
@@ -3907,6 +4114,7 @@ int nep_md_step(const nep_model* m, const nep_batch* b, float* pos, nep_neighbor
   a.ekin = at<float>(c.ws, c.L.eatom);   // reused after the last force evaluation
   a.hdt = 0.5f * dt;
   a.dt = dt;
+  params = kernel_params(c, params);
   for (int k = 0; k < n_steps; ++k) {
     hipLaunchKernelGGL(k_md_drift, dim3(grid1(N)), dim3(256), 0, c.st, a);
     run_neighbors(c, nb, d_flags, nullptr);
@@ -3926,6 +4134,7 @@ int nep_vjp(const nep_model* m, const nep_batch* b, const nep_neighbors* nb, con
   if ((rc = check_nbrs(nb, b->n_atom))) return rc;
   if (!params || !grad) return NEP_ERR_ARG;
   if (b->n_atom > 0 && (!e_bar || !f_bar || !v_bar)) return NEP_ERR_ARG;
+  params = kernel_params(c, params);
   if (b->n_atom > 0) {
     FwdArgs a = fwd_args(c, nb, params);
     a.do_force = 0;
@@ -3945,8 +4154,8 @@ int nep_loss_grad(const nep_model* m, const nep_batch* b, const nep_neighbors* n
   if (!params || !labels || !lambda || !loss || !grad) return NEP_ERR_ARG;
   if (b->n_struct > 0 && (!labels->energy || !labels->virial)) return NEP_ERR_ARG;
   if (b->n_atom > 0 && !labels->force) return NEP_ERR_ARG;
-  return loss_grad_seq(c, const_cast<nep_neighbors*>(nb), params, labels, lambda, loss, grad, e_struct, force, virial,
-                       d_flags, nullptr, false);
+  return loss_grad_seq(c, const_cast<nep_neighbors*>(nb), kernel_params(c, params), labels, lambda, loss, grad,
+                       e_struct, force, virial, d_flags, nullptr, false);
 }
 
 int nep_loss_grad_noalloc(const nep_model* m, const nep_batch* b, nep_neighbors* nb, const float* params,
@@ -3955,7 +4164,7 @@ int nep_loss_grad_noalloc(const nep_model* m, const nep_batch* b, nep_neighbors*
   int rc = nep_model_supported(m);
   if (rc) return rc;
   if ((rc = check_batch(b))) return rc;
-  if (make_layout(m, find_ops(m), b->n_struct, b->n_atom).total > (size_t)NEP_STATIC_SCRATCH_BYTES)
+  if (workspace_size(m, b->n_struct, b->n_atom) > (size_t)NEP_STATIC_SCRATCH_BYTES)
     return NEP_ERR_SCRATCH;
   void* ws = nullptr;
   if ((rc = static_scratch(&ws))) return rc;
@@ -3965,7 +4174,8 @@ int nep_loss_grad_noalloc(const nep_model* m, const nep_batch* b, nep_neighbors*
   if (!params || !labels || !lambda || !loss || !grad || !d_flags) return NEP_ERR_ARG;
   if (b->n_struct > 0 && (!labels->energy || !labels->virial)) return NEP_ERR_ARG;
   if (b->n_atom > 0 && !labels->force) return NEP_ERR_ARG;
-  return loss_grad_seq(c, nb, params, labels, lambda, loss, grad, e_struct, force, virial, d_flags, nullptr, true);
+  return loss_grad_seq(c, nb, kernel_params(c, params), labels, lambda, loss, grad, e_struct, force, virial, d_flags,
+                       nullptr, true);
 }
 
 int nep_adam_step(int64_t P, float* params, float* mm, float* vv, const float* grad, float lr, float beta1,
@@ -4041,8 +4251,9 @@ int nep_train_step_graph_create_tuned(const nep_model* m, const nep_batch* b, ne
     c.o->step(sa, sgrid, slds, cap);
   } else {
     hipLaunchKernelGGL(k_graph_head, dim3(1), dim3(64), 0, cap, d_flags, d_step, cur);
-    loss_grad_seq(c, nb, params, labels, lambda, loss, grad, nullptr, nullptr, nullptr, d_flags, nullptr,
-                  (graph_flags & NEP_GRAPH_CACHED_NEIGHBORS) == 0);
+    // a padded model's class-layout parameters are refreshed by every replay
+    loss_grad_seq(c, nb, kernel_params(c, params), labels, lambda, loss, grad, nullptr, nullptr, nullptr, d_flags,
+                  nullptr, (graph_flags & NEP_GRAPH_CACHED_NEIGHBORS) == 0);
   }
   const hipError_t e1 = hipStreamEndCapture(cap, &g);
   (void)hipStreamDestroy(cap);
@@ -4088,7 +4299,8 @@ int nep_profile_loss_grad(const nep_model* m, const nep_batch* b, nep_neighbors*
   if (!labels || !lambda || !params || !loss || !grad || !d_flags || !n_kernels) return NEP_ERR_ARG;
   Prof pr;
   pr.st = c.st;
-  rc = loss_grad_seq(c, nb, params, labels, lambda, loss, grad, nullptr, nullptr, nullptr, d_flags, &pr, true);
+  rc = loss_grad_seq(c, nb, kernel_params(c, params), labels, lambda, loss, grad, nullptr, nullptr, nullptr, d_flags,
+                     &pr, true);
   if (hipStreamSynchronize(c.st) != hipSuccess) rc = NEP_ERR_HIP;
   const int n = (int)pr.names.size();
   *n_kernels = n;

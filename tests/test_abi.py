@@ -41,10 +41,13 @@ def test_counts_match_the_oracle_layout():
 
 def test_unsupported_and_invalid_models():
     m = nep.Model.of(synth.SIZES_SMALL)
-    m.k_rad = 7
+    m.n_rad = 13          # beyond the largest size class (12 radial channels)
     assert not nep.model_supported(m)
     with pytest.raises(nep.NEPError):
         nep.workspace_bytes(m, 1, 10)
+    m = nep.Model.of(synth.SIZES_SMALL)
+    m.n_types = 5         # beyond four species
+    assert not nep.model_supported(m)
     bad = nep.Model.of(synth.SIZES_SMALL)
     bad.rc_ang = 7.0   # rc_ang > rc_rad
     assert _lib.load().nep_param_count(C.byref(bad.c())) == -1
@@ -135,7 +138,7 @@ def test_noalloc_rejects_batches_beyond_its_static_scratch_on_the_host():
     assert lib.nep_status_string(-9).decode() != "unknown status"
     # an unsupported model is rejected first
     bad = nep.Model.of(synth.SIZES_SMALL)
-    bad.k_rad = 7
+    bad.n_rad = 13
     rc = lib.nep_loss_grad_noalloc(C.byref(bad.c()), C.byref(b), C.byref(nb), fake, C.byref(lab), C.byref(lam),
                                    fake, fake, None, None, None, fake, None)
     assert rc == -1
@@ -158,3 +161,23 @@ def test_tuned_graph_create_rejects_out_of_range_choices_before_launch():
                                                    fake, fake, fake, fake, fake, fake, C.byref(cfg), fake, fake, 0,
                                                    C.byref(t), None, C.byref(h))
         assert rc == -1, bad
+
+
+def test_size_classes_accept_the_grid_of_model_sizes():
+    """Any model with up to 4 species, 12 radial and 8 angular channels, 12
+    Chebyshev terms, 3-body degrees up to 8 and the 4-/5-body terms on or off
+    runs (zero-padded into a size class); the caller's parameter count is
+    unchanged and the workspace covers the class."""
+    import itertools
+    base = nep.Model.of(synth.SIZES_SMALL)
+    for T, nr, na, kr, ka, l3, l4, l5 in itertools.product((1, 2, 3, 4), (1, 9, 12), (0, 5, 8), (1, 7, 12),
+                                                           (3, 12), (0, 2, 4, 6, 8), (0, 2), (0, 1)):
+        m = nep.Model(T, nr, na, kr, ka, l3, l4, l5, 24, 6.0, 4.0)
+        assert nep.model_supported(m), (T, nr, na, kr, ka, l3, l4, l5)
+        sz = synth.NEPSizes(T, nr, na, kr, ka, l3, l4, l5, 24)
+        assert nep.param_count(m) == sz.n_params
+        assert nep.descriptor_count(m) == sz.n_desc
+    m = nep.Model(3, 4, 3, 6, 5, 4, 2, 1, 12, 6.0, 4.0)
+    assert nep.workspace_bytes(m, 4, 300) > nep.workspace_bytes(nep.Model(2, 3, 2, 4, 3, 4, 2, 1, 12, 6.0, 4.0),
+                                                                  4, 300)
+    assert base.n_rad == 5

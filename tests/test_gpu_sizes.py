@@ -1,0 +1,130 @@
+"""Models of sizes no kernel is compiled for exactly, run through the size
+classes (zero-padded parameters), against the FP64 oracle through the C ABI:
+three species, the 3/4/5-body model with 3-body degrees up to 8, and nine
+radial channels.  Bars as in the other parity tests (energy per atom 1e-5;
+descriptors, forces, virials and every gradient block 1e-4 norm-wise)."""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from paper_2507_00528_amd import synth
+
+from gpu_util import TOL_E, TOL_F, Case, GPURun, param_blocks, rel
+
+pytestmark = pytest.mark.gpu
+
+# (n_types, n_rad, n_ang, k_rad, k_ang, l3, l4, l5, hidden)
+SIZES = {
+    "three_species": synth.NEPSizes(n_types=3, n_rad=4, n_ang=3, k_rad=6, k_ang=5, l3=4, l4=2, l5=1, hidden=12),
+    "c2_l8": replace(synth.SIZES_LARGE, l3=8),
+    "n_rad9": replace(synth.SIZES_SMALL, n_rad=9),
+    "four_species_l6": synth.NEPSizes(n_types=4, n_rad=6, n_ang=8, k_rad=12, k_ang=7, l3=6, l4=0, l5=1, hidden=10),
+}
+
+
+def _structures(name):
+    if name == "c2_l8":
+        return synth.config_structures("c2", n_struct=8)
+    rng = np.random.default_rng(23)
+    T = SIZES[name].n_types
+    sts = [synth.random_structure(rng, n, 0.031, 2.5, kind) for n, kind in
+           ((20, "liquid"), (47, "amorphous"), (96, "liquid"), (150, "amorphous"))]
+    return [synth.Structure(s.pos, s.box, rng.integers(0, T, s.n).astype(np.int32)) for s in sts]
+
+
+_CACHE = {}
+
+
+def case(name):
+    if name not in _CACHE:
+        c = Case(SIZES[name], _structures(name))
+        r = GPURun(c)
+        print(f"[size {name}] S={c.batch.n_struct} N={c.batch.n_atom} P={c.sizes.n_params}", flush=True)
+        assert r.nep.model_supported(r.model)
+        r.neighbors()
+        _CACHE[name] = (c, r)
+    return _CACHE[name]
+
+
+NAMES = list(SIZES)
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_padded_descriptors_and_energy_force_virial(name):
+    import torch
+    c, r = case(name)
+    assert int(r.flags.item()) == 0
+    D = c.sizes.n_desc
+    G = torch.zeros(D * c.batch.n_atom, device="cuda")
+    r.nep.descriptors(r.model, r.batch, r.nbrs, r.params, G, r.ws)
+    torch.cuda.synchronize()
+    got = G.cpu().numpy().reshape(D, -1).T
+    ref = np.concatenate(c.pred["G"], 0)
+    for v in range(D):
+        assert rel(got[:, v], ref[:, v]) < TOL_F, f"descriptor {v}"
+    e_atom, e_s, F, W = r.efw()
+    sizes = np.diff(c.batch.atom_offset)
+    assert rel(e_s / sizes, c.pred["E"] / sizes) < TOL_E
+    assert rel(e_atom, np.concatenate(c.pred["Ei"])) < TOL_E
+    assert rel(F, np.concatenate(c.pred["F"], 0)) < TOL_F
+    assert rel(W, c.pred["W"]) < TOL_F
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_padded_loss_and_gradient(name):
+    c, r = case(name)
+    loss, grad, e_s, F, W = r.loss_grad()
+    assert int(r.flags.item()) == 0
+    np.testing.assert_allclose(loss, c.loss, rtol=1e-4)
+    for blk, sl in param_blocks(c.sizes).items():
+        assert rel(grad[sl], c.grad[sl]) < TOL_F, blk
+
+
+@pytest.mark.parametrize("name", ["three_species", "c2_l8"])
+def test_padded_vjp_random_cotangents(name):
+    import torch
+    c, r = case(name)
+    rng = np.random.default_rng(8)
+    eb = rng.normal(size=c.batch.n_struct)
+    fb = rng.normal(size=(c.batch.n_atom, 3))
+    vb = rng.normal(size=(c.batch.n_struct, 6))
+    ref = c.oracle.cotangent_grad(c.theta, c.structures, eb, fb, vb, nbr_cache=c.nbrs)
+    grad = torch.zeros(c.sizes.n_params, device="cuda")
+    r.nep.vjp(r.model, r.batch, r.nbrs, r.params, torch.tensor(eb, dtype=torch.float32, device="cuda"),
+              torch.tensor(np.ascontiguousarray(fb.T).reshape(-1), dtype=torch.float32, device="cuda"),
+              torch.tensor(vb.reshape(-1), dtype=torch.float32, device="cuda"), grad, r.ws)
+    g = grad.cpu().numpy()
+    for blk, sl in param_blocks(c.sizes).items():
+        assert rel(g[sl], ref[sl]) < TOL_F, blk
+
+
+def test_padded_train_step_graph_matches_eager_steps():
+    """Three replays of the captured step (parameters refreshed into the class
+    layout each replay, Adam on the model's own layout) against eager
+    loss-and-gradient calls plus Adam steps."""
+    import torch
+    c, r = case("three_species")
+    nep = r.nep
+    P = c.sizes.n_params
+    pg = r.params.clone()
+    m, v, grad, loss = (torch.zeros(n, device="cuda") for n in (P, P, P, 4))
+    step = torch.ones(1, dtype=torch.int32, device="cuda")
+    nb = nep.Neighbors(r.model, r.N)
+    ws = nep.workspace(r.model, r.S, r.N)
+    flags = torch.zeros(1, dtype=torch.int32, device="cuda")
+    g = nep.TrainStepGraph(r.model, r.batch, nb, r.labels, c.lam, pg, m, v, grad, loss, step, ws, flags,
+                           lr_start=1e-2, lr_stop=1e-2)
+    pe = r.params.clone()
+    me, ve = torch.zeros(P, device="cuda"), torch.zeros(P, device="cuda")
+    ge, le = torch.zeros(P, device="cuda"), torch.zeros(4, device="cuda")
+    for k in range(1, 4):
+        g.launch()
+        nep.loss_grad(r.model, r.batch, r.nbrs, pe, r.labels, c.lam, le, ge, r.ws, r.flags)
+        nep.adam_step(pe, me, ve, ge, 1e-2, k)
+        torch.cuda.synchronize()
+        assert int(flags.item()) == 0 and int(r.flags.item()) == 0
+        np.testing.assert_allclose(loss.cpu().numpy(), le.cpu().numpy(), rtol=1e-5)
+        assert rel(grad.cpu().numpy(), ge.cpu().numpy()) < 1e-5
+        np.testing.assert_allclose(pg.cpu().numpy(), pe.cpu().numpy(), rtol=0, atol=1e-6)
+    g.close()
