@@ -1191,6 +1191,18 @@ __device__ __forceinline__ float csel(int g, int i) {
   return g ? (q1 >= 0 ? clm(q1) : 0.f) : (q0 >= 0 ? clm(q0) : 0.f);
 }
 
+// The per-atom rows of the angular sums (S, Sdot, Sbar, A), in LDS and in
+// HBM, are kept in harmonic-group order: entry e of group g of channel n at
+// n YR + g YG + e, YR = 2 YG.  A lane of group g then reaches its entries as
+// its base plus constant offsets, with no per-entry address selects (which
+// the adjoint otherwise kept live, and spilled, across its network phase).
+template <int LM>
+struct HRow {
+  static constexpr int YG = HSplit<LM>::YG, YR = 2 * YG;
+  // whether entry e of group g is a harmonic (not padding)
+  static constexpr bool real(int g, int e) { return HSplit<LM>::q(g, e) >= 0; }
+};
+
 // E' of q_nl for the two l blocks of harmonic group g (l = 1, 4 or l = 2, 3)
 template <int NR, int NA, int L3, int D>
 __device__ __forceinline__ void ep_blocks(const float (&Ep)[D], int n, int g, float& eA, float& eB) {
@@ -1269,7 +1281,8 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int vb, float* ld
   constexpr int DP = (D + 3) & ~3;
   const int H = a.H;
   const int WS = H * DP + 2 * H;
-  constexpr int RW = DP + NA * Y;         // LDS row per atom: G, S
+  constexpr int YR = HRow<LM>::YR;
+  constexpr int RW = DP + NA * YR;        // LDS row per atom: G, S (group order)
   using CT = CTab<T, NA, KA>;
   float* ctab = lds;                     // [T][T][NA][KAP]
   float* wl = lds + CT::size;            // [WS] of the block's species
@@ -1399,11 +1412,8 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int vb, float* ld
     for (int n = 0; n < NA; ++n)
 #pragma unroll
       for (int e = 0; e < YG; ++e) {
-        const int q = g ? HS::q(1, e) : HS::q(0, e);
-        if (q >= 0) {
-          rowS[n * Y + q] = Sg[n][e];
-          if (w.valid && a.Sst) a.Sst[(size_t)(n * Y + q) * a.Npad + pa] = Sg[n][e];
-        }
+        rowS[n * YR + g * YG + e] = Sg[n][e];   // zero at padding entries
+        if (w.valid && a.Sst) a.Sst[(size_t)(n * YR + g * YG + e) * a.Npad + pa] = Sg[n][e];
       }
   }
   if constexpr (C::YH > 0) {
@@ -1515,10 +1525,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int vb, float* ld
     for (int n = 0; n < NA; ++n) {
       float Sn[YG];
 #pragma unroll
-      for (int e = 0; e < YG; ++e) {
-        const int q = g ? HS::q(1, e) : HS::q(0, e);
-        Sn[e] = q >= 0 ? rowS[n * Y + q] : 0.f;
-      }
+      for (int e = 0; e < YG; ++e) Sn[e] = rowS[n * YR + g * YG + e];
       float eA, eBv;
       ep_blocks<NR, NA, L3, D>(Ep, n, g, eA, eBv);
       float a4[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, a5[3] = {0.f, 0.f, 0.f};
@@ -1912,7 +1919,8 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs& a, int vb, float* ld
   constexpr int YG = HS::YG;
   constexpr int DP = (D + 3) & ~3;
   constexpr int NAH = (NA + 1) / 2;          // channels per lane in the coefficient pass
-  constexpr int RW = DP + 2 * NA * Y;        // LDS row per atom: Gdot, Sbar, A
+  constexpr int YR = HRow<LM>::YR;
+  constexpr int RW = DP + 2 * NA * YR;       // LDS row per atom: Gdot, Sbar, A (group order)
   constexpr int PSA = T * NA * KA;
   const int H = a.H;
   const int WS = H * DP + 2 * H;
@@ -1931,7 +1939,7 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs& a, int vb, float* ld
   float* part = a.part + (size_t)wave * a.PW;
   float* row = rows + w.al * RW;
   float* rowSb = row + DP;
-  float* rowA = rowSb + NA * Y;
+  float* rowA = rowSb + NA * YR;
   const int st = a.astruct[i];
   const Cell cell = load_cell<kTri>(a.box, a.tilt, st);
   const float xi = a.pos[i], yi = a.pos[N + i], zi = a.pos[2 * N + i];
@@ -2051,24 +2059,18 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs& a, int vb, float* ld
     for (int n = 0; n < NA; ++n)
       if (w.p == (n & 3)) {
 #pragma unroll
-        for (int e = 0; e < YG; ++e) {
-          const int q = g ? HS::q(1, e) : HS::q(0, e);
-          if (q >= 0) rowSb[n * Y + q] = Sd[n][e];
-        }
+        for (int e = 0; e < YG; ++e) rowSb[n * YR + g * YG + e] = Sd[n][e];   // zero at padding entries
       }
     lds_lane_exchange();
     for (int n = w.p; n < NA; n += 4) {
       float Sn[YG], Sdn[YG];
 #pragma unroll
       for (int e = 0; e < YG; ++e) {
-        const int q = g ? HS::q(1, e) : HS::q(0, e);
-        const int qc = q >= 0 ? q : 0;
-        // unconditional loads from valid addresses, then the mask: a guarded
-        // load would become a branch that waits for each value in turn
-        const float v = a.Sst[(size_t)(n * Y + qc) * a.Npad + pa];
-        const float d = rowSb[n * Y + qc];
-        Sn[e] = (w.valid && q >= 0) ? v : 0.f;
-        Sdn[e] = q >= 0 ? d : 0.f;
+        // unconditional loads, then the mask: a guarded load would become a
+        // branch that waits for each value in turn
+        const float v = a.Sst[(size_t)(n * YR + g * YG + e) * a.Npad + pa];
+        Sn[e] = w.valid ? v : 0.f;
+        Sdn[e] = rowSb[n * YR + g * YG + e];
       }
       float qa = 0.f, qb = 0.f;
 #pragma unroll
@@ -2090,10 +2092,7 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs& a, int vb, float* ld
         if (g == 0) row[NR + L3 * NA + (L4 ? NA : 0) + n] = 4.0f * P * SS;
       }
 #pragma unroll
-      for (int e = 0; e < YG; ++e) {
-        const int q = g ? HS::q(1, e) : HS::q(0, e);
-        if (q >= 0) rowA[n * Y + q] = Sn[e];
-      }
+      for (int e = 0; e < YG; ++e) rowA[n * YR + g * YG + e] = Sn[e];
     }
   }
   if constexpr (C::YH > 0) {
@@ -2176,10 +2175,8 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs& a, int vb, float* ld
       float Sn[YG], Sdn[YG];
 #pragma unroll
       for (int e = 0; e < YG; ++e) {
-        const int q = g ? HS::q(1, e) : HS::q(0, e);
-        const float va = rowA[n * Y + (q >= 0 ? q : 0)], vb = rowSb[n * Y + (q >= 0 ? q : 0)];
-        Sn[e] = q >= 0 ? va : 0.f;
-        Sdn[e] = q >= 0 ? vb : 0.f;
+        Sn[e] = rowA[n * YR + g * YG + e];
+        Sdn[e] = rowSb[n * YR + g * YG + e];
       }
       // E' and Gbar of the descriptors built from these sums
       const float vA = a.Ep[(size_t)(NR + (lAc - 1) * NA + n) * Np + pa];
@@ -2210,7 +2207,7 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs& a, int vb, float* ld
       }
 #pragma unroll
       for (int e = 0; e < YG; ++e) {
-        const int q = g ? HS::q(1, e) : HS::q(0, e);
+        const bool real = g ? HRow<LM>::real(1, e) : HRow<LM>::real(0, e);
         const float c2 = 2.0f * csel<HS>(g, e);
         const float eL = e < nAg ? eA : eB, gL = e < nAg ? gA : gB;
         float Av = c2 * eL * Sn[e];
@@ -2223,10 +2220,8 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs& a, int vb, float* ld
           Av += 4.0f * e5 * P * Sn[e];
           Sb += 4.0f * g5 * P * Sn[e] - e5 * (8.0f * SS * Sn[e] + 4.0f * P * Sdn[e]);
         }
-        if (q >= 0) {
-          rowA[n * Y + q] = Av;
-          rowSb[n * Y + q] = Sb;
-        }
+        rowA[n * YR + g * YG + e] = real ? Av : 0.f;
+        rowSb[n * YR + g * YG + e] = real ? Sb : 0.f;
       }
     }
   }
@@ -2261,14 +2256,19 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs& a, int vb, float* ld
     for (int j = 0; j < NAH; ++j) {
       const int n = g * NAH + j;
       const bool on = n < NA;
-      const float* sb = rowSb + (on ? n : 0) * Y;
-      const float* av = rowA + (on ? n : 0) * Y;
+      const float* sb = rowSb + (on ? n : 0) * YR;
+      const float* av = rowA + (on ? n : 0) * YR;
       float X = 0.f, Yv = 0.f;
 #pragma unroll
-      for (int qq = 0; qq < Y; ++qq) {
-        X = fmaf(sb[qq], B[qq], fmaf(-av[qq], gbt[qq], X));
-        Yv = fmaf(av[qq], B[qq], Yv);
-      }
+      for (int gg = 0; gg < 2; ++gg)
+#pragma unroll
+        for (int e = 0; e < YG; ++e) {
+          const int qq = HS::q(gg, e);
+          if (qq >= 0) {
+            X = fmaf(sb[gg * YG + e], B[qq], fmaf(-av[gg * YG + e], gbt[qq], X));
+            Yv = fmaf(av[gg * YG + e], B[qq], Yv);
+          }
+        }
       X = on ? X : 0.f;
       const float Yd = on ? Yv * dt : 0.f;
 #pragma unroll
@@ -3065,7 +3065,7 @@ __global__ __launch_bounds__(256) void k_struct_sum(const int* __restrict__ aoff
 enum HighKernel { kHighDesc, kHighForce, kHighTangent, kHighCoef };
 
 struct Ops {
-  int T, NR, NA, KR, KA, L3, L4, L5, D, Y, PS, YH;
+  int T, NR, NA, KR, KA, L3, L4, L5, D, Y, PS, YH, YR;
   void (*forward)(const FwdArgs&, dim3, hipStream_t, int);
   void (*adjoint)(const AdjArgs&, dim3, hipStream_t, int);
   size_t (*lds_fwd)(int);
@@ -3081,13 +3081,13 @@ template <class C>
 static size_t lds_forward(int H) {
   const int DP = (C::D + 3) & ~3;
   return sizeof(float) * ((size_t)CTab<C::T, C::NA, C::KA>::size + (size_t)(H * DP + 2 * H) +
-                          (size_t)kAPB * (DP + C::NA * C::Y));
+                          (size_t)kAPB * (DP + C::NA * HRow<C::LMAX>::YR));
 }
 template <class C>
 static size_t lds_adjoint(int H) {
   const int DP = (C::D + 3) & ~3;
   return sizeof(float) * ((size_t)CTab<C::T, C::NA, C::KA>::size + (size_t)(H * DP + 2 * H) +
-                          (size_t)kAPB * (DP + 2 * C::NA * C::Y));
+                          (size_t)kAPB * (DP + 2 * C::NA * HRow<C::LMAX>::YR));
 }
 // LDS of a workgroup on gfx950 (160 KiB per CU); dynamic LDS beyond 64 KiB is
 // requested from the runtime per kernel before its launch
@@ -3182,7 +3182,7 @@ static Ops make_ops() {
     occ = &step_occupancy<C>;
   }
   return Ops{C::T, C::NR, C::NA, C::KR, C::KA, C::L3, C::L4, C::L5, C::D, C::Y, C::PS, C::YH,
-             &launch_forward<C>, &launch_adjoint<C>, &lds_forward<C>, &lds_adjoint<C>, high, step, occ,
+             HRow<C::LMAX>::YR, &launch_forward<C>, &launch_adjoint<C>, &lds_forward<C>, &lds_adjoint<C>, high, step, occ,
              C::FIXED_WAVES != 0};
 }
 
@@ -3313,7 +3313,7 @@ Layout make_layout(const nep_model* m, const Ops* o, int S, int N, bool pad = fa
   L.revR = take(4 * (size_t)L.capR * Nn);
   L.revA = take(4 * (size_t)L.capA * Nn);
   L.G = take(4 * (size_t)L.D * Np);
-  L.Sst = take(4 * (size_t)L.NA * L.Y * Np);
+  L.Sst = take(4 * (size_t)L.NA * o->YR * Np);
   L.Ep = take(4 * (size_t)L.D * Np);
   L.X = take(4 * (size_t)L.H * Np);
   L.eatom = take(4 * Nn);
