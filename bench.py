@@ -77,7 +77,7 @@ def flop_model(sz, mR: float, mA: float) -> dict:
            + NA * (8 * Y + 4 * q4 + 2 * q5)                              # Sbar, A
            + mA * (6 * NA * Y + 4 * NA * KA))                            # X_n, Y_n, angular coefficient gradient
     outer = 4 * H * D + 4 * NR * T * KR   # dW0 and dc^R, contracted over atoms (one launch)
-    out = {"forward": fwd, "adjoint": adj, "outer_sums": outer}
+    out = {"forward": fwd, "adjoint": adj, "outer_sums_reduce": outer}
     if YH:
         hv, hg = 2 * YH, 3 * YH    # harmonic values and gradients of l = 5..l3
         out["high_desc"] = mA * (geo + basis(KA) + 2 * NA * KA + hv + 2 * NA * YH) + 2 * NA * YH

@@ -1061,13 +1061,7 @@ __device__ __forceinline__ void order_scatter_body(const OrderArgs& a, int ob, i
 }
 
 // the separate kernels: a block of kOrdBlk threads per order block, 512
-// threads for the scan
-__global__ __launch_bounds__(kOrdBlk) void k_order_count(OrderArgs a) {
-  __shared__ int cnt[kOrdCountLds];
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < a.Npad; q += gridDim.x * blockDim.x) a.order[q] = -1;
-  order_count_body<kOrdBlk>(a, blockIdx.x, cnt);
-}
-
+// threads for the scan (the counts run in k_reverse_count)
 __global__ __launch_bounds__(512) void k_order_scan(OrderArgs a) {
   __shared__ int sh[kOrdScanLds];
   order_scan_body<512>(a, sh);
@@ -1076,6 +1070,25 @@ __global__ __launch_bounds__(512) void k_order_scan(OrderArgs a) {
 __global__ __launch_bounds__(kOrdBlk) void k_order_scatter(OrderArgs a) {
   __shared__ int wcnt[kOrdScatterLds];
   order_scatter_body<kOrdBlk>(a, blockIdx.x, wcnt);
+}
+
+// The reverse index and the species-order counts in one launch (both read
+// only the neighbor lists): the first nrev blocks, numbered XCD-aware among
+// themselves, take the reverse index; the rest count one order block each
+// and clear the order slots.
+__global__ __launch_bounds__(256) void k_reverse_count(RevArgs r, OrderArgs o, int nrev) {
+  __shared__ int cnt[kOrdCountLds];
+  if ((int)blockIdx.x < nrev) {
+    const int b = xcd_block_of(blockIdx.x, nrev);
+    if (b < r.nbR)
+      reverse_block<kRevLPAR>(b, r.N, r.idxR, r.cntR, r.capR, r.revR);
+    else
+      reverse_block<kRevLPAA>(b - r.nbR, r.N, r.idxA, r.cntA, r.capA, r.revA);
+    return;
+  }
+  const int ob = blockIdx.x - nrev;
+  for (int q = ob * 256 + threadIdx.x; q < o.Npad; q += o.nblk * 256) o.order[q] = -1;
+  order_count_body<256>(o, ob, cnt);
 }
 
 // ================================================================= helpers
@@ -2470,17 +2483,6 @@ __device__ __forceinline__ void outer_sum_block(const OuterArgs& o, int b, int I
   __syncthreads();   // the other wavefronts wait here: red is read above
 }
 
-// dW0 and dc^R in one launch: grid z slices [0, nz0) take the first product,
-// the rest the second (each alone leaves most of the GPU idle)
-__global__ __launch_bounds__(256) void k_outer_sum(OuterArgs o0, OuterArgs o1, int nz0) {
-  __shared__ f32x4 red[3][kOSTM * kOSTV][kWave];
-  const int z = blockIdx.z;
-  if (z < nz0)
-    outer_sum_block(o0, blockIdx.x, blockIdx.y, z, red);
-  else
-    outer_sum_block(o1, blockIdx.x, blockIdx.y, z - nz0, red);
-}
-
 int outer_slices(int M, int V) {
   const int nzm = (M + 16 * kOSTM - 1) / (16 * kOSTM), nzv = (V + 16 * kOSTV - 1) / (16 * kOSTV);
   return nzm * nzv;
@@ -2492,7 +2494,7 @@ int outer_slices(int M, int V) {
 constexpr int kPRChunks = 128;   // default chunks per species
 constexpr int kPRChunksMax = 512;
 
-// Loss reduction carried by k_part_reduce (one extra row of blocks) so that a
+// Loss reduction carried by k_outer_reduce (one extra block) so that a
 // loss-and-gradient pass spends no launch on it.
 struct LossArgs {
   int on, S, N;
@@ -2524,15 +2526,38 @@ __device__ __forceinline__ void part_reduce_body(int PW, const int* seg, const f
   }
 }
 
-__global__ __launch_bounds__(256) void k_part_reduce(int PW, const int* seg, const float* part, double* pp,
-                                                     LossArgs la) {
-  __shared__ double red[3][kRedBlk];
-  if ((int)blockIdx.y == (int)gridDim.y - 1 && la.on) {
-    if (blockIdx.x == 0) loss_final_block(la.S, la.N, la.le, la.lf, la.lv, la.lpart, la.loss, la.flags, red);
-    return;
+// The outer-product sums, the first stage of the wavefront partial sums and
+// the loss sum in one launch (all three read only the adjoint's outputs):
+// blocks [0, n_outer) take the outer products (block x of species I, output
+// slice z; slices [0, nzw) of dW0, the rest of dc^R), the next prc T blocks
+// the partial sums, the last one the loss.
+struct OuterReduceArgs {
+  OuterArgs ow, oc;
+  int nzw, nzc, os_x, T, PW, prc;
+  const int* seg;
+  const float* part;
+  double* pp;
+  LossArgs la;
+};
+
+__global__ __launch_bounds__(256) void k_outer_reduce(OuterReduceArgs a) {
+  __shared__ f32x4 red[3][kOSTM * kOSTV][kWave];
+  const int T = a.T, n_outer = a.os_x * T * (a.nzw + a.nzc), n_pr = a.prc * T;
+  const int v = blockIdx.x;
+  if (v < n_outer) {
+    const int x = v % a.os_x, I = (v / a.os_x) % T, z = v / (a.os_x * T);
+    if (z < a.nzw)
+      outer_sum_block(a.ow, x, I, z, red);
+    else
+      outer_sum_block(a.oc, x, I, z - a.nzw, red);
+  } else if (v < n_outer + n_pr) {
+    const int u = v - n_outer;
+    part_reduce_body(a.PW, a.seg, a.part, a.pp, u % a.prc, u / a.prc, a.prc);
+  } else if (a.la.on) {
+    loss_final_block(a.la.S, a.la.N, a.la.le, a.la.lf, a.la.lv, a.la.lpart, a.la.loss, a.la.flags, red);
   }
-  part_reduce_body(PW, seg, part, pp, blockIdx.x, blockIdx.y, gridDim.x);
 }
+
 
 // Final gradient: 16 lanes per parameter; lane l sums rows l, l + 16, ... of
 // that parameter's partials in float64, then a fixed xor tree adds the 16
@@ -3526,16 +3551,16 @@ void run_neighbors(const Ctx& c, nep_neighbors* nb, int32_t* flags, Prof* pr, bo
                      : (a.cells ? k_neighbors<false, true> : k_neighbors<false, false>);
     NEP_LAUNCH(pr, "neighbors", hipLaunchKernelGGL(k, dim3(grid1(N, kNbrAPB)), dim3(kNbrThreads), 0, c.st, a));
   }
-  {
-    RevArgs r{N, grid1(N, 256 / kRevLPAR), nb->idx_rad, nb->cnt_rad, c.m->cap_rad, at<int>(c.ws, c.L.revR),
-              nb->idx_ang, nb->cnt_ang, c.m->cap_ang, at<int>(c.ws, c.L.revA)};
-    NEP_LAUNCH(pr, "reverse",
-               hipLaunchKernelGGL(k_reverse, dim3(r.nbR + grid1(N, 256 / kRevLPAA)), dim3(256), 0, c.st, r));
+  const RevArgs r{N, grid1(N, 256 / kRevLPAR), nb->idx_rad, nb->cnt_rad, c.m->cap_rad, at<int>(c.ws, c.L.revR),
+                  nb->idx_ang, nb->cnt_ang, c.m->cap_ang, at<int>(c.ws, c.L.revA)};
+  const int nrev = r.nbR + grid1(N, 256 / kRevLPAA);
+  if (!with_order) {   // the persistent step computes the species order itself
+    NEP_LAUNCH(pr, "reverse", hipLaunchKernelGGL(k_reverse, dim3(nrev), dim3(256), 0, c.st, r));
+    return;
   }
-  if (!with_order) return;   // the persistent step computes the species order itself
   const OrderArgs oa = order_args(c, nb);
-  NEP_LAUNCH(pr, "order_count",
-             hipLaunchKernelGGL(k_order_count, dim3(c.L.nblk), dim3(kOrdBlk), 0, c.st, oa));
+  NEP_LAUNCH(pr, "reverse_order_count",
+             hipLaunchKernelGGL(k_reverse_count, dim3(nrev + c.L.nblk), dim3(256), 0, c.st, r, oa, nrev));
   NEP_LAUNCH(pr, "order_scan", hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(512), 0, c.st, oa));
   NEP_LAUNCH(pr, "order_scatter",
              hipLaunchKernelGGL(k_order_scatter, dim3(c.L.nblk), dim3(kOrdBlk), 0, c.st, oa));
@@ -3773,19 +3798,23 @@ void run_adjoint(const Ctx& c, const nep_neighbors* nb, const float* params, con
     run_high(c, kHighTangent, h, pr);
     NEP_LAUNCH(pr, "adjoint", c.o->adjoint(a, dim3(c.L.Npad / kAPB), c.st, c.tune.adjoint_waves));
     run_high(c, kHighCoef, h, pr);
-    const int* seg = at<int>(c.ws, c.L.seg);
     {
-      OuterArgs ow, oc;
-      outer_args(c, a, ow, oc);
-      const int nzw = outer_slices(ow.M, ow.V), nzc = outer_slices(oc.M, oc.V);
-      NEP_LAUNCH(pr, "outer_sums",
-                 hipLaunchKernelGGL(k_outer_sum, dim3(std::max(ow.NB, oc.NB), T, nzw + nzc), dim3(256), 0,
-                                    c.st, ow, oc, nzw));
+      OuterReduceArgs ra;
+      outer_args(c, a, ra.ow, ra.oc);
+      ra.nzw = outer_slices(ra.ow.M, ra.ow.V);
+      ra.nzc = outer_slices(ra.oc.M, ra.oc.V);
+      ra.os_x = std::max(ra.ow.NB, ra.oc.NB);
+      ra.T = T;
+      ra.PW = c.L.PW;
+      ra.prc = c.tune.reduce_chunks;
+      ra.seg = at<int>(c.ws, c.L.seg);
+      ra.part = a.part;
+      ra.pp = at<double>(c.ws, c.L.pp);
+      ra.la = la;
+      const int nblk = ra.os_x * T * (ra.nzw + ra.nzc) + ra.prc * T + (la.on ? 1 : 0);
+      NEP_LAUNCH(pr, "outer_sums_reduce",
+                 hipLaunchKernelGGL(k_outer_reduce, dim3(nblk), dim3(256), 0, c.st, ra));
     }
-    double* pp = at<double>(c.ws, c.L.pp);
-    NEP_LAUNCH(pr, "part_reduce",
-               hipLaunchKernelGGL(k_part_reduce, dim3(c.tune.reduce_chunks, T + (la.on ? 1 : 0)), dim3(256), 0, c.st, c.L.PW,
-                                  seg, a.part, pp, la));
     // a padded model: the class gradient in the workspace, then the model's
     // entries, then Adam on the model's parameters
     float* gk = c.pad ? at<float>(c.ws, c.L.grd) : grad;
