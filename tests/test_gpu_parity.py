@@ -196,3 +196,48 @@ def test_graph_with_cached_neighbors_matches_eager():
         np.testing.assert_allclose(params_g.cpu().numpy(), params_e.cpu().numpy(), rtol=0, atol=1e-7)
     assert int(flags2.item()) == 0
     g.close()
+
+
+def sub_blocks(sz):
+    """name -> indices of each species-pair block of c_rad and c_ang, each
+    species' W0, b0 and w1, and each b1 on its own."""
+    T, H, D = sz.n_types, sz.hidden, sz.n_desc
+    out = {}
+    o = 0
+    for name, n, k in (("c_rad", sz.n_rad, sz.k_rad), ("c_ang", sz.n_ang, sz.k_ang)):
+        for I in range(T):
+            for J in range(T):
+                out[f"{name}[{I},{J}]"] = np.arange(o, o + n * k)
+                o += n * k
+    blk = H * D + 2 * H + 1
+    for I in range(T):
+        b = o + I * blk
+        out[f"W0[{I}]"] = np.arange(b, b + H * D)
+        out[f"b0[{I}]"] = np.arange(b + H * D, b + H * D + H)
+        out[f"w1[{I}]"] = np.arange(b + H * D + H, b + H * D + 2 * H)
+        out[f"b1[{I}]"] = np.array([b + blk - 1])
+    return out
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_gradient_sub_blocks_against_their_own_size(name):
+    """Every species-pair block of the coefficients, every species' network
+    block and each b1 alone, measured against its own magnitude (the block
+    tolerance of the other tests is relative to the largest entry of a whole
+    block)."""
+    c, r = case(name)
+    loss, grad, e_s, F, W = r.loss_grad()
+    for blk, idx in sub_blocks(c.sizes).items():
+        assert rel(grad[idx], c.grad[idx]) < TOL_F, blk
+
+
+@pytest.mark.parametrize("name", ["c0", "c2_head"])
+def test_per_structure_energies_and_virials_one_by_one(name):
+    """Each structure's energy per atom and virial against the oracle on its
+    own (not only norm-wise over the batch)."""
+    c, r = case(name)
+    e_atom, e_s, F, W = r.efw()
+    sizes = np.diff(c.batch.atom_offset)
+    for s in range(c.batch.n_struct):
+        assert abs(e_s[s] - c.pred["E"][s]) / sizes[s] < TOL_E * max(np.abs(c.pred["E"] / sizes).max(), 1e-3), s
+        assert rel(W[s], c.pred["W"][s]) < 10 * TOL_F, s
