@@ -121,8 +121,8 @@ struct HighArgs {
   const int* type;
   PairLists nb;
   const float* cA;
-  float* Sh;          // [Npad][NA][YH] sums S~ of the orthonormal harmonics
-  float* Sdh;         // [Npad][NA][YH] their tangents
+  float* Sh;          // [Npad][YH][NA] sums S~ of the orthonormal harmonics
+  float* Sdh;         // [Npad][YH][NA] their tangents
   float* G;           // [D][Npad] descriptor rows (q_nl of l > 4 written here)
   const float* Ep;    // [D][Npad] dE/dG
   float* Gd;          // [D][Npad] descriptor tangents

@@ -3173,7 +3173,9 @@ static void launch_high_t(HighKernel k, const HighArgs& a, dim3 grid, hipStream_
     case kHighTangent:
       hipLaunchKernelGGL(HIP_KERNEL_NAME(k_high_tangent<C, kTri>), grid, dim3(256), 0, st, a);
       break;
-    case kHighCoef: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_high_coef<C, kTri>), grid, dim3(256), 0, st, a); break;
+    case kHighCoef:   // one wavefront per block
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_high_coef<C, kTri>), dim3(grid.x * 4), dim3(kWave), 0, st, a);
+      break;
   }
 }
 template <class C>
