@@ -31,6 +31,19 @@ namespace nep {
 
 constexpr int kPwStride = 19;   // words per pair in the power table (odd: no bank conflicts)
 
+constexpr double high_cx_sqrt(double x) {
+  double r = x > 1.0 ? x : 1.0;   // Newton from above
+  for (int it = 0; it < 100; ++it) r = 0.5 * (r + x / r);
+  return r;
+}
+
+// N_lM^2 = (2l + 1) / (4 pi) (l - M)! / (l + M)!, times 2 for M > 0
+constexpr double high_norm2(int l, int M) {
+  double v = (2.0 * l + 1.0) / (4.0 * 3.141592653589793);
+  for (int k = l - M + 1; k <= l + M; ++k) v /= (double)k;
+  return M > 0 ? 2.0 * v : v;
+}
+
 struct HighLane {
   int l;
   bool on;
@@ -40,63 +53,68 @@ struct HighLane {
   float sD1, sD2;            // dP/dx = sD1 pw[iD1], dP/dy = sD2 pw[iD2]
 };
 
-__device__ __forceinline__ HighLane high_lane(int c, int L3) {
-  HighLane h;
-  h.l = 5;
-  h.on = false;
-  int M = 0, off = 0;
-  bool sine = false;
-  for (int l = 5; l <= L3; ++l) {
-    const int w = 2 * l + 1;
-    if (c >= off && c < off + w) {
-      const int mi = c - off;
+// The 56 harmonics of l = 5..8 in lane order (harmonic c = l^2 - 25 + m,
+// M = (m + 1) / 2, sine for even m > 0), built at compile time: N Q_l^M as
+// z^par H(z^2) with the coefficients of Q_l^M from the recurrence
+//   Q_M^M = (2M-1)!!,  (l-M) Q_l = (2l-1) z Q_{l-1} - (l+M-1) Q_{l-2}.
+struct HighLanes {
+  HighLane h[56];
+};
+
+constexpr HighLanes make_high_lanes() {
+  HighLanes t{};
+  int c = 0;
+  for (int l = 5; l <= 8; ++l)
+    for (int mi = 0; mi <= 2 * l; ++mi, ++c) {
+      HighLane& h = t.h[c];
+      const int M = (mi + 1) >> 1;
+      const bool sine = mi > 0 && (mi & 1) == 0;
+      double q0[9] = {}, q1[9] = {};
+      double df = 1.0;
+      for (int k = 1; k <= M; ++k) df *= 2.0 * k - 1.0;
+      q1[0] = df;
+      for (int lp = M + 1; lp <= l; ++lp) {
+        double qn[9] = {};
+        for (int p = 0; p < 9; ++p)
+          qn[p] = ((2.0 * lp - 1.0) * (p > 0 ? q1[p - 1] : 0.0) - (lp + M - 1.0) * q0[p]) / (double)(lp - M);
+        for (int p = 0; p < 9; ++p) {
+          q0[p] = q1[p];
+          q1[p] = qn[p];
+        }
+      }
+      const double nrm = high_cx_sqrt(high_norm2(l, M));
       h.l = l;
-      M = (mi + 1) >> 1;
-      sine = mi > 0 && (mi & 1) == 0;
       h.on = true;
+      h.par = ((l - M) & 1) != 0;
+      for (int k = 0; k < 5; ++k) {
+        const int p = 2 * k + (h.par ? 1 : 0);   // Q has degree l <= 8
+        h.a[k] = p < 9 ? (float)(nrm * q1[p]) : 0.f;
+      }
+      for (int k = 0; k < 4; ++k) h.b[k] = (float)(k + 1) * h.a[k + 1];
+      // d/dx (x+iy)^M = M (x+iy)^(M-1), d/dy (x+iy)^M = i M (x+iy)^(M-1)
+      const int m1 = M > 0 ? M - 1 : 0;
+      h.iP = (sine ? 9 : 0) + M;
+      h.iD1 = (sine ? 9 : 0) + m1;
+      h.iD2 = (sine ? 0 : 9) + m1;
+      h.sD1 = (float)M;
+      h.sD2 = sine ? (float)M : -(float)M;
     }
-    off += w;
+  return t;
+}
+__constant__ const HighLanes kHighLanes = make_high_lanes();
+
+// Harmonic c of l = 5..L3 for lane c; lanes past the last harmonic are off
+// (zero polynomial).
+__device__ __forceinline__ HighLane high_lane(int c, int L3) {
+  const bool on = c < (L3 + 1) * (L3 + 1) - 25;
+  HighLane h = kHighLanes.h[on ? c : 0];
+  h.on = on;
+  if (!on) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) h.a[k] = 0.f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) h.b[k] = 0.f;
   }
-  // coefficients of Q_l^M in powers of z, by the recurrence
-  //   Q_M^M = (2M-1)!!,  (l-M) Q_l = (2l-1) z Q_{l-1} - (l+M-1) Q_{l-2}
-  double q0[9], q1[9];
-#pragma unroll
-  for (int p = 0; p < 9; ++p) q0[p] = q1[p] = 0.0;
-  double df = 1.0;
-  for (int k = 1; k <= M; ++k) df *= (double)(2 * k - 1);
-  q1[0] = df;
-  for (int lp = M + 1; lp <= h.l; ++lp) {
-    double qn[9];
-#pragma unroll
-    for (int p = 0; p < 9; ++p)
-      qn[p] = ((2.0 * lp - 1.0) * (p > 0 ? q1[p - 1] : 0.0) - (lp + M - 1.0) * q0[p]) / (double)(lp - M);
-#pragma unroll
-    for (int p = 0; p < 9; ++p) {
-      q0[p] = q1[p];
-      q1[p] = qn[p];
-    }
-  }
-  double nrm = (2.0 * h.l + 1.0) / (4.0 * 3.141592653589793);
-  for (int k = h.l - M + 1; k <= h.l + M; ++k) nrm /= (double)k;
-  if (M > 0) nrm *= 2.0;
-  nrm = h.on ? sqrt(nrm) : 0.0;
-  h.par = ((h.l - M) & 1) != 0;
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    double v = 0.0;
-#pragma unroll
-    for (int p = 0; p < 9; ++p) v = (p == 2 * k + (h.par ? 1 : 0)) ? q1[p] : v;
-    h.a[k] = (float)(nrm * v);
-  }
-#pragma unroll
-  for (int k = 0; k < 4; ++k) h.b[k] = (float)(k + 1) * h.a[k + 1];
-  // d/dx (x+iy)^M = M (x+iy)^(M-1), d/dy (x+iy)^M = i M (x+iy)^(M-1)
-  const int m1 = M > 0 ? M - 1 : 0;
-  h.iP = (sine ? 9 : 0) + M;
-  h.iD1 = (sine ? 9 : 0) + m1;
-  h.iD2 = (sine ? 0 : 9) + m1;
-  h.sD1 = (float)M;
-  h.sD2 = sine ? (float)M : -(float)M;
   return h;
 }
 
@@ -159,7 +177,7 @@ __device__ __forceinline__ float wave_scatter_sum(const float (&x)[V]) {
 // kTan: tangent fields.
 template <int NA, bool kTan>
 struct HighRec {
-  static constexpr int DX = 0, DY = 1, DZ = 2, IR = 3, U = 4, G = 5, GP = G + NA;
+  static constexpr int DX = 0, DY = 1, DZ = 2, IR = 3, G = 4, GP = G + NA;
   static constexpr int DT = GP + NA, WX = DT + 1, WY = DT + 2, WZ = DT + 3;
   static constexpr int W = kTan ? WZ + 1 : DT;
 };
@@ -229,7 +247,6 @@ __device__ __forceinline__ void high_stage(const HighArgs& a, const HighGroup& g
     rec[R::DY * kWave + lane] = q.dy;
     rec[R::DZ * kWave + lane] = q.dz;
     rec[R::IR * kWave + lane] = q.inv_r;
-    rec[R::U * kWave + lane] = __int_as_float(u);
     float c = 1.f, s = 0.f;
     float* p = pw + lane * kPwStride;
 #pragma unroll
@@ -258,31 +275,32 @@ __device__ __forceinline__ void high_stage(const HighArgs& a, const HighGroup& g
 
 // Walks the group's pair stream: start(u) before the first pair of slot u,
 // pair(u, jj) for each staged pair jj of slot u, finish(u) after its last pair
-// (also for slots without pairs).
+// (also for slots without pairs).  Each slot's pairs in a chunk are a range
+// known from the pair counts, so no per-pair test decides where a slot ends,
+// and the loop over a range is unrolled to keep several pairs' LDS reads in
+// flight.  A slot belongs to the chunk holding its first pair (start) and
+// the one holding its last (finish); an empty slot to the chunk holding its
+// position in the stream, or the last chunk.
 template <class C, bool kTri, bool kTan, class Start, class Pair, class Finish>
 __device__ __forceinline__ void high_walk(const HighArgs& a, const HighGroup& gr, float* rec, float* pw,
                                           Start&& start, Pair&& pair, Finish&& finish) {
-  using R = HighRec<C::NA, kTan>;
-  int cur = 0;
-  start(0);
-  for (int c0 = 0; c0 < gr.total; c0 += kWave) {
+  const int total = gr.total;
+  for (int c0 = 0; c0 < (total > 0 ? total : 1); c0 += kWave) {
     high_stage<C, kTri, kTan>(a, gr, c0, rec, pw);
-    const int np = min(kWave, gr.total - c0);
-    for (int jj = 0; jj < np; ++jj) {
-      const int u = __float_as_int(rec[R::U * kWave + jj]);
-      while (cur < u) {
-        finish(cur);
-        ++cur;
-        start(cur);
-      }
-      pair(cur, jj);
+    const int c1 = min(c0 + kWave, total);
+    const bool last = c1 == total;
+#pragma unroll
+    for (int u = 0; u < kAPW; ++u) {
+      const int b = gr.cum[u], e = gr.cum[u + 1];
+      const bool starts = b >= c0 && (b < c1 || (b == e && last));
+      const bool ends = b == e ? starts : e > c0 && e <= c1;
+      if (starts) start(u);
+      const int j1 = min(e, c1) - c0;
+#pragma unroll 4
+      for (int jj = max(b, c0) - c0; jj < j1; ++jj) pair(u, jj);
+      if (ends) finish(u);
     }
     lds_lane_exchange();
-  }
-  for (;;) {
-    finish(cur);
-    if (++cur == kAPW) break;
-    start(cur);
   }
 }
 
@@ -355,7 +373,7 @@ __global__ __launch_bounds__(256) void k_high_desc(HighArgs a) {
   };
   auto finish = [&](int u) {
     const int pa = gr.pa0 + u;
-    if (a.order[pa] < 0) return;
+    if (!((gr.occ >> u) & 1u)) return;
     if (lane < YH)
 #pragma unroll
       for (int n = 0; n < NA; ++n) a.Sh[high_slot<C>(pa, n, lane)] = S[n];
@@ -389,7 +407,7 @@ __global__ __launch_bounds__(256) void k_high_tangent(HighArgs a) {
   };
   auto finish = [&](int u) {
     const int pa = gr.pa0 + u;
-    if (a.order[pa] < 0) return;
+    if (!((gr.occ >> u) & 1u)) return;
     if (lane < YH)
 #pragma unroll
       for (int n = 0; n < NA; ++n) a.Sdh[high_slot<C>(pa, n, lane)] = Sd[n];
@@ -417,19 +435,6 @@ __global__ __launch_bounds__(256) void k_high_tangent(HighArgs a) {
 // and dQhat_l^M / dz from the derivative of the same recurrence.  Harmonic
 // (l, M) is then Y = Qhat Re (x + iy)^M (m = 2M - 1, or m = 0) and
 // Y = Qhat Im (x + iy)^M (m = 2M), number l^2 - 25 + m as in high_lane.
-
-constexpr double high_cx_sqrt(double x) {
-  double r = x > 1.0 ? x : 1.0;   // Newton from above
-  for (int it = 0; it < 100; ++it) r = 0.5 * (r + x / r);
-  return r;
-}
-
-// N_lM^2 = (2l + 1) / (4 pi) (l - M)! / (l + M)!, times 2 for M > 0
-constexpr double high_norm2(int l, int M) {
-  double v = (2.0 * l + 1.0) / (4.0 * 3.141592653589793);
-  for (int k = l - M + 1; k <= l + M; ++k) v /= (double)k;
-  return M > 0 ? 2.0 * v : v;
-}
 
 struct HighTab {
   float q0[9];     // Qhat_M^M
