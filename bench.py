@@ -105,7 +105,7 @@ def step_flops_formula(sz, mR: float, mA: float) -> float:
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in ("paper_2507_00528_amd/csrc/nep_lib.hip", "paper_2507_00528_amd/csrc/nep_device.h",
-              "paper_2507_00528_amd/csrc/nep_kernels.h"):
+              "paper_2507_00528_amd/csrc/nep_kernels.h", "paper_2507_00528_amd/csrc/nep_highl.h"):
         h.update(open(os.path.join(ROOT, f), "rb").read())
     return h.hexdigest()[:16]
 
