@@ -1,12 +1,14 @@
 """Expected values for the full-size GPU parity tests, written by the FP64
 oracle only.
 
-    python tests/golden/make_golden.py c2 c3
+    python tests/golden/make_golden.py c2 c3 c4
 
 For each workload: seeded structures (synth.config_structures), student
 parameters, seeded random labels (synth.random_labels), and from the oracle:
 the loss and its gradient, per-structure energies and virials, energies and
-forces of 256 sampled atoms, per-atom neighbor counts and a SHA-256 digest of
+forces of 256 sampled atoms, energies and forces of every atom of sampled
+whole structures (the largest structure and up to 31 (c2) or 63 (c4) more;
+the single c3 cell whole), per-atom neighbor counts and a SHA-256 digest of
 the canonical neighbor lists (i, j, code as int64, global atom indices).
 """
 import hashlib
@@ -64,9 +66,19 @@ def make(name):
     F = np.concatenate(pred["F"], 0)
     Ei = np.concatenate(pred["Ei"], 0)
     sample = np.sort(np.random.default_rng(99).choice(N, min(256, N), replace=False))
+    # whole structures: the largest, then a seeded draw of the rest
+    nst = {"c2": 32, "c4": 64}.get(name, S)
+    sizes = np.diff(offs)
+    big = int(np.argmax(sizes))
+    rest = np.setdiff1d(np.arange(S), [big])
+    pick = np.random.default_rng(98).choice(rest, min(nst, S) - 1, replace=False) if S > 1 else rest
+    struct_sample = np.sort(np.concatenate([[big], pick]).astype(np.int64))
+    atoms = np.concatenate([np.arange(offs[k], offs[k + 1]) for k in struct_sample])
     out = os.path.join(HERE, f"full_{name}.npz")
     np.savez_compressed(out, loss=loss, grad=grad, e_struct=pred["E"], virial=pred["W"], sample=sample,
-                        force_sample=F[sample], eatom_sample=Ei[sample], cnt_rad=cnt_r, cnt_ang=cnt_a)
+                        force_sample=F[sample], eatom_sample=Ei[sample], cnt_rad=cnt_r, cnt_ang=cnt_a,
+                        struct_sample=struct_sample, struct_natoms=sizes[struct_sample].astype(np.int64),
+                        force_struct=F[atoms].astype(np.float32), eatom_struct=Ei[atoms])
     meta = {"workload": name, "n_struct": S, "n_atom": N, "lambda": LAM, "seeds": synth.SEEDS,
             "sha256_rad": canonical_digest(glob_r), "sha256_ang": canonical_digest(glob_a),
             "oracle_seconds": round(time.time() - t0, 1)}
@@ -75,5 +87,5 @@ def make(name):
 
 
 if __name__ == "__main__":
-    for name in sys.argv[1:] or ["c2", "c3"]:
+    for name in sys.argv[1:] or ["c2", "c3", "c4"]:
         make(name)

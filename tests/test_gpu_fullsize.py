@@ -5,8 +5,11 @@ values that tests/golden/make_golden.py wrote with the FP64 oracle.
 
 Neighbor lists are compared bit-exactly through per-atom counts and a SHA-256
 digest of the canonical (i, j, code) lists; loss, every gradient block,
-per-structure energies and virials, and forces/energies of 256 sampled atoms
-within the norm-wise tolerances."""
+per-structure energies and virials, forces/energies of 256 sampled atoms and
+of every atom of sampled whole structures (the largest among them; all of the
+27,000-atom cell) within the norm-wise tolerances, each sampled structure's
+forces also on their own.  Every structure's forces sum to zero (Newton's
+third law, which holds at any size) to 1e-5 of the sum of their norms."""
 import hashlib
 import json
 import os
@@ -82,9 +85,22 @@ def test_full_size_against_golden(name):
     sizes = np.diff(batch.atom_offset)
     assert rel(e_s.cpu().numpy() / sizes, gd["e_struct"] / sizes) < TOL_E
     assert rel(W.cpu().numpy().reshape(-1, 6), gd["virial"]) < TOL_F
-    Fs = F.cpu().numpy().reshape(3, N).T[gd["sample"]]
-    assert rel(Fs, gd["force_sample"]) < TOL_F
-    assert rel(e_atom.cpu().numpy()[gd["sample"]], gd["eatom_sample"]) < TOL_E
+    Fa = F.cpu().numpy().reshape(3, N).T
+    ea = e_atom.cpu().numpy()
+    assert rel(Fa[gd["sample"]], gd["force_sample"]) < TOL_F
+    assert rel(ea[gd["sample"]], gd["eatom_sample"]) < TOL_E
+    offs = batch.atom_offset
+    atoms = np.concatenate([np.arange(offs[k], offs[k + 1]) for k in gd["struct_sample"]])
+    assert rel(Fa[atoms], gd["force_struct"]) < TOL_F
+    assert rel(ea[atoms], gd["eatom_struct"]) < TOL_E
+    o = 0
+    for k in gd["struct_sample"]:
+        n = int(offs[k + 1] - offs[k])
+        assert rel(Fa[offs[k]:offs[k + 1]], gd["force_struct"][o:o + n]) < TOL_F, f"structure {k}"
+        o += n
+    for k in range(S):
+        Fk = Fa[offs[k]:offs[k + 1]].astype(np.float64)
+        assert np.linalg.norm(Fk.sum(0)) <= 1e-5 * np.linalg.norm(Fk, axis=1).sum(), f"force sum, structure {k}"
 
     if name == "c2":
         # the captured train step the benchmark replays computes the same gradient

@@ -267,3 +267,21 @@ def test_oracle_gradient_matches_stored_differences_on_the_64_structure_batch():
     trunc = np.abs(fd - fd2) / 3
     assert int(d["n_struct"]) == 64 and len(fd) == 50
     assert np.all(np.abs(fd - g) <= 1e-6 * np.abs(g) + 3 * trunc + 1e-11 * np.abs(g).max())
+
+
+@pytest.mark.parametrize("name", ["c2", "c3", "c4"])
+def test_stored_full_size_forces_sum_to_zero_per_structure(name):
+    """The oracle's forces stored for whole structures of the full-size
+    workloads (tests/golden/make_golden.py) obey Newton's third law: each
+    structure's forces sum to zero, here to 1e-6 of the sum of their norms
+    (FP64 sums, stored as float32: the bound covers float32 rounding)."""
+    import os
+    here = os.path.dirname(os.path.abspath(__file__))
+    gd = np.load(os.path.join(here, "golden", f"full_{name}.npz"))
+    o = 0
+    for k, n in zip(gd["struct_sample"], gd["struct_natoms"]):
+        n = int(n)
+        F = gd["force_struct"][o:o + n].astype(np.float64)
+        o += n
+        assert np.linalg.norm(F.sum(0)) <= 1e-6 * np.linalg.norm(F, axis=1).sum(), k
+    assert o == len(gd["force_struct"])
