@@ -173,14 +173,17 @@ __device__ __forceinline__ float wave_scatter_sum(const float (&x)[V]) {
   return atoms8_sum(r);
 }
 
-// Per-wave LDS record of up to 64 pairs, field-major: rec[f * 64 + slot].
-// kTan: tangent fields.
+// Per-wave LDS record of up to 64 pairs, pair-major: pair jj's W words at
+// rec[jj W], read by every lane at once (one address, so 16-byte reads serve
+// four fields each).  kTan: w_x, w_y, w_z, u.t first, then g_n and g'_n;
+// otherwise g_n only.  The pair's direction cosine z sits in word kPwZ of its
+// power-table row.
 template <int NA, bool kTan>
 struct HighRec {
-  static constexpr int DX = 0, DY = 1, DZ = 2, IR = 3, G = 4, GP = G + NA;
-  static constexpr int DT = GP + NA, WX = DT + 1, WY = DT + 2, WZ = DT + 3;
-  static constexpr int W = kTan ? WZ + 1 : DT;
+  static constexpr int WX = 0, WY = 1, WZ = 2, DT = 3, G = kTan ? 4 : 0, GP = G + NA;
+  static constexpr int W = kTan ? GP + NA : G + NA;
 };
+constexpr int kPwZ = 18;
 
 // The 8 atom slots of a wavefront and their pair counts.
 struct HighGroup {
@@ -239,16 +242,13 @@ __device__ __forceinline__ void high_stage(const HighArgs& a, const HighGroup& g
         s0 = fmaf(cJ[n * KA + kk], f[kk], s0);
         s1 = fmaf(cJ[n * KA + kk], fp[kk], s1);
       }
-      rec[(R::G + n) * kWave + lane] = s0;
-      rec[(R::GP + n) * kWave + lane] = s1;
+      rec[lane * R::W + R::G + n] = s0;
+      if constexpr (kTan) rec[lane * R::W + R::GP + n] = s1;
     }
     const float ux = q.dx * q.inv_r, uy = q.dy * q.inv_r, uz = q.dz * q.inv_r;
-    rec[R::DX * kWave + lane] = q.dx;
-    rec[R::DY * kWave + lane] = q.dy;
-    rec[R::DZ * kWave + lane] = q.dz;
-    rec[R::IR * kWave + lane] = q.inv_r;
     float c = 1.f, s = 0.f;
     float* p = pw + lane * kPwStride;
+    p[kPwZ] = uz;
 #pragma unroll
     for (int m = 0; m < 9; ++m) {
       p[m] = c;
@@ -264,10 +264,10 @@ __device__ __forceinline__ void high_stage(const HighArgs& a, const HighGroup& g
       const float ty = (a.fbar[a.N + q.j] - a.fbar[a.N + i]) + wb[1] * q.dy + wb[4] * q.dz;
       const float tz = (a.fbar[2 * a.N + q.j] - a.fbar[2 * a.N + i]) + wb[2] * q.dz + wb[5] * q.dx;
       const float dt = ux * tx + uy * ty + uz * tz;
-      rec[R::DT * kWave + lane] = dt;
-      rec[R::WX * kWave + lane] = (tx - dt * ux) * q.inv_r;
-      rec[R::WY * kWave + lane] = (ty - dt * uy) * q.inv_r;
-      rec[R::WZ * kWave + lane] = (tz - dt * uz) * q.inv_r;
+      rec[lane * R::W + R::DT] = dt;
+      rec[lane * R::W + R::WX] = (tx - dt * ux) * q.inv_r;
+      rec[lane * R::W + R::WY] = (ty - dt * uy) * q.inv_r;
+      rec[lane * R::W + R::WZ] = (tz - dt * uz) * q.inv_r;
     }
   }
   lds_lane_exchange();
@@ -347,7 +347,7 @@ __device__ __forceinline__ size_t high_slot(int pa, int n, int lane) {
 #define NEP_HIGH_PROLOGUE(TAN)                                           \
   constexpr int NA = C::NA, L3 = C::L3, YH = C::YH;                      \
   using R = HighRec<NA, TAN>;                                            \
-  __shared__ float recs[4][R::W * kWave];                                \
+  __shared__ __align__(16) float recs[4][R::W * kWave];                  \
   __shared__ float pws[4][kWave * kPwStride];                            \
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;  \
   const int wave = blockIdx.x * 4 + wv;                                  \
@@ -367,9 +367,11 @@ __global__ __launch_bounds__(256) void k_high_desc(HighArgs a) {
   };
   auto pair = [&](int, int jj) {
     float v, gx, gy, gz;
-    high_eval(h, rec[R::DZ * kWave + jj] * rec[R::IR * kWave + jj], pw + jj * kPwStride, v, gx, gy, gz);
+    const float* pj = pw + jj * kPwStride;
+    const float* rj = rec + jj * R::W;
+    high_eval(h, pj[kPwZ], pj, v, gx, gy, gz);
 #pragma unroll
-    for (int n = 0; n < NA; ++n) S[n] = fmaf(rec[(R::G + n) * kWave + jj], v, S[n]);
+    for (int n = 0; n < NA; ++n) S[n] = fmaf(rj[R::G + n], v, S[n]);
   };
   auto finish = [&](int u) {
     const int pa = gr.pa0 + u;
@@ -397,13 +399,15 @@ __global__ __launch_bounds__(256) void k_high_tangent(HighArgs a) {
   };
   auto pair = [&](int, int jj) {
     float v, gx, gy, gz;
-    high_eval(h, rec[R::DZ * kWave + jj] * rec[R::IR * kWave + jj], pw + jj * kPwStride, v, gx, gy, gz);
+    const float* pj = pw + jj * kPwStride;
+    const float* rj = rec + jj * R::W;
+    high_eval(h, pj[kPwZ], pj, v, gx, gy, gz);
     // Sdot = sum_j g'_n (u.t) Y + g_n grad p . (t - (u.t) u) / r
-    const float gwt = gx * rec[R::WX * kWave + jj] + gy * rec[R::WY * kWave + jj] + gz * rec[R::WZ * kWave + jj];
-    const float vdt = v * rec[R::DT * kWave + jj];
+    const float gwt = gx * rj[R::WX] + gy * rj[R::WY] + gz * rj[R::WZ];
+    const float vdt = v * rj[R::DT];
 #pragma unroll
     for (int n = 0; n < NA; ++n)
-      Sd[n] = fmaf(rec[(R::GP + n) * kWave + jj], vdt, fmaf(rec[(R::G + n) * kWave + jj], gwt, Sd[n]));
+      Sd[n] = fmaf(rj[R::GP + n], vdt, fmaf(rj[R::G + n], gwt, Sd[n]));
   };
   auto finish = [&](int u) {
     const int pa = gr.pa0 + u;
