@@ -141,36 +141,27 @@ __device__ __forceinline__ void high_eval(const HighLane& h, float z, const floa
   gz = dQ * P;
 }
 
-// Sums of V = 4 or 8 values over the 64 lanes, scattered: on return the lanes
-// with (lane & (V - 1)) == v hold the total of value v.  A butterfly over
-// lane bits 0, 1 (and 2) halves the values a lane carries at each step, so the
-// V sums take V - 1 lane exchanges before the sum over the 8 groups instead
-// of 3 V.
-template <int V>
-__device__ __forceinline__ float wave_scatter_sum(const float (&x)[V]) {
-  static_assert(V == 4 || V == 8, "4 or 8 values");
+// Sums of 8 values over the 64 lanes, scattered: on return the lanes with
+// (lane & 7) == v hold the total of value v.  A butterfly over lane bits 0,
+// 1 and 2 halves the values a lane carries at each step, so the 8 sums take
+// 7 lane exchanges before the sum over the 8 groups instead of 24.
+__device__ __forceinline__ float wave_scatter_sum8(const float (&x)[8]) {
   const int lane = threadIdx.x & (kWave - 1);
   const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
-  float y[V / 2];
+  float y[4];
 #pragma unroll
-  for (int w = 0; w < V / 2; ++w) {   // y[w]: value 2w + b0
+  for (int w = 0; w < 4; ++w) {   // y[w]: value 2w + b0
     const float send = b0 ? x[2 * w] : x[2 * w + 1];
     y[w] = (b0 ? x[2 * w + 1] : x[2 * w]) + dpp<kDppXor1>(send);
   }
-  float z[V / 4];
+  float z[2];
 #pragma unroll
-  for (int u = 0; u < V / 4; ++u) {   // z[u]: value 4u + 2 b1 + b0
+  for (int u = 0; u < 2; ++u) {   // z[u]: value 4u + 2 b1 + b0
     const float send = b1 ? y[2 * u] : y[2 * u + 1];
     z[u] = (b1 ? y[2 * u + 1] : y[2 * u]) + dpp<kDppXor2>(send);
   }
-  float r;
-  if constexpr (V == 8) {             // value lane & 7 over the 8-lane group
-    const float send = b2 ? z[0] : z[1];
-    r = (b2 ? z[1] : z[0]) + xor4_val(send);
-  } else {                            // value lane & 3 over the quad, then the group
-    r = z[0] + xor4_val(z[0]);
-  }
-  return atoms8_sum(r);
+  const float send = b2 ? z[0] : z[1];   // value lane & 7 over the 8-lane group
+  return atoms8_sum((b2 ? z[1] : z[0]) + xor4_val(send));
 }
 
 // Per-wave LDS record of up to 64 pairs, pair-major: pair jj's W words at
@@ -331,7 +322,7 @@ __device__ __forceinline__ void high_rows_store(const float (&vals)[(C::L3 - 4) 
     float xs[8];
 #pragma unroll
     for (int v = 0; v < 8; ++v) xs[v] = g0 + v < NV ? vals[g0 + v < NV ? g0 + v : 0] : 0.f;
-    const float t = wave_scatter_sum<8>(xs);
+    const float t = wave_scatter_sum8(xs);
     if (lane < 8 && g0 + lane < NV) rows[(size_t)(C::NR + 4 * C::NA + g0 + lane) * Npad + pa] = t;
   }
 }

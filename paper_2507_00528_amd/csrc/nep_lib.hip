@@ -86,11 +86,24 @@ struct PosTile {
   int base;
 };
 
+// A value the compiler cannot see through.  The float64 paths below run for
+// few candidates of the single-image scan; taking their inputs through this
+// keeps their conversions inside the branch instead of being computed ahead
+// of the test for every candidate.
+__device__ __forceinline__ int opaque_int(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+__device__ __forceinline__ float opaque_float(float v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 // float64 predicate of Eq. 2 for the pair (i, j) over the candidate shifts;
 // calls emit(j, code, is_angular) in ascending code order
 template <class Emit>
 __device__ __forceinline__ void exact_pair(const ScanCtx& c, const PosTile& t, int j, Emit& emit) {
-  const int q = j - t.base;
+  const int q = opaque_int(j - t.base);
   const double x0 = __dadd_rn((double)t.x[q], -c.xi);
   const unsigned mx = axis_candidates(x0, c.Lx, c.rcR);
   if (!mx) return;
@@ -126,7 +139,7 @@ __device__ __forceinline__ void exact_pair(const ScanCtx& c, const PosTile& t, i
 // prunes sc, dy prunes (sb, sc), then dx is formed per surviving shift.
 template <class Emit>
 __device__ __forceinline__ void exact_pair_tri(const ScanCtx& c, const PosTile& t, int j, Emit& emit) {
-  const int q = j - t.base;
+  const int q = opaque_int(j - t.base);
   const double z0 = __dadd_rn((double)t.z[q], -c.zi);
   const unsigned mz = axis_candidates(z0, c.Lz, c.rcR);
   if (!mz) return;
@@ -255,10 +268,11 @@ __device__ __forceinline__ void keep_one(const ScanCtx& c, const PosTile& t, int
   // condition), so the shift s = -k always has a code
   const int code = 13 - (int)fmaf(9.f, kx, fmaf(3.f, ky, kz));
   const bool decided = r2 < c.inR2;
-  const bool in = decided && !(j == c.i && code == 13);
+  const bool in = decided & ((j != c.i) | (code != 13));   // bitwise: no branch per candidate
   bool ang = r2 < c.inA2;
   buf[kNbrThreads * min(nR, kNbrBuf)] = ((uint32_t)j << 5) | (uint32_t)(code & 31);
-  if (in && !ang && r2 < c.outA2) ang = image_d2<kTri>(c, px, py, pz, kx, ky, kz) < c.rcA2;
+  if (in && !ang && r2 < c.outA2)
+    ang = image_d2<kTri>(c, opaque_float(px), opaque_float(py), opaque_float(pz), kx, ky, kz) < c.rcA2;
   angmask |= (in && ang && nR < kNbrBuf) ? (1u << nR) : 0u;
   nR += in ? 1 : 0;
   nA += (in && ang) ? 1 : 0;
@@ -270,11 +284,13 @@ __device__ __forceinline__ void keep_one(const ScanCtx& c, const PosTile& t, int
 template <bool kTri, class Keep>
 __device__ __forceinline__ void scan_keep(const ScanCtx& c, const PosTile& t, int jb, int je, uint32_t* buf,
                                           int& nR, int& nA, uint32_t& angmask, Keep& keep) {
+  // one loop per case: a shared loop let the float64 coordinate differences
+  // of the exact path be computed ahead of the test for every candidate
+  if (!c.fast) {
+    for (int j = jb; j < je; ++j) exact_any<kTri>(c, t, j, keep);
+    return;
+  }
   for (int j = jb; j < je; ++j) {
-    if (!c.fast) {
-      exact_any<kTri>(c, t, j, keep);
-      continue;
-    }
     const int q = j - t.base;
     keep_one<kTri>(c, t, j, t.x[q], t.y[q], t.z[q], buf, nR, nA, angmask, keep);
   }
