@@ -730,9 +730,16 @@ __global__ __launch_bounds__(kNbrThreads) void k_cell_neighbors(NbrArgs a) {
           const int lo = h ? r1lo : r0lo, hi = h ? r1hi : r0hi;
           if (lo > hi) continue;
           const int cb = a.cell[row + lo], ce = a.cell[row + hi + 1];
-          for (int q = cb + ((s - run) & 7); q < ce; q += 8) {
-            const float4 p = a.cpos[q];
-            keep_one<kTri>(c, t, __float_as_int(p.w), p.x, p.y, p.z, mybuf, nR, nA, angmask, keep);
+          // four of this lane's candidates per step, their loads issued
+          // together (a run of three bins is about three candidates per lane)
+          for (int q0 = cb + ((s - run) & 7); q0 < ce; q0 += 32) {
+            float4 p[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) p[u] = a.cpos[min(q0 + 8 * u, ce - 1)];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              if (q0 + 8 * u < ce)
+                keep_one<kTri>(c, t, __float_as_int(p[u].w), p[u].x, p[u].y, p[u].z, mybuf, nR, nA, angmask, keep);
           }
           run += ce - cb;
         }
