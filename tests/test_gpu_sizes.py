@@ -128,3 +128,35 @@ def test_padded_train_step_graph_matches_eager_steps():
         assert rel(grad.cpu().numpy(), ge.cpu().numpy()) < 1e-5
         np.testing.assert_allclose(pg.cpu().numpy(), pe.cpu().numpy(), rtol=0, atol=1e-6)
     g.close()
+
+
+def test_padded_high_degree_dense_cell():
+    """A class with eight angular channels (three species, n_ang 6, degrees
+    up to 8, run in the four-species class) on a dense cell of about 90
+    angular neighbors per atom: the c^A gradient's second phase then takes
+    two coefficient slots per lane and four neighbor-species registers, over
+    about a dozen 64-pair chunks per atom group, each staging the table again."""
+    import torch
+    sizes = synth.NEPSizes(n_types=3, n_rad=5, n_ang=6, k_rad=7, k_ang=9, l3=8, l4=2, l5=1, hidden=10)
+    rng = np.random.default_rng(31)
+    L = 7.0
+    box = np.full(3, L)
+    pos = synth.wrap32(rng.uniform(0, L, (110, 3)), box)
+    st = synth.Structure(pos, box.astype(np.float32), (np.arange(110) % 3).astype(np.int32), "dense")
+    c = Case(sizes, [st])
+    r = GPURun(c, cap_rad=512, cap_ang=256)
+    print(f"[size dense l8] N={c.batch.n_atom} P={sizes.n_params}", flush=True)
+    assert r.nep.model_supported(r.model)
+    r.neighbors()
+    torch.cuda.synchronize()
+    assert int(r.flags.item()) == 0
+    _, cnt = r.lists("ang")
+    assert cnt.max() > 64
+    e_atom, e_s, F, W = r.efw()
+    assert rel(e_atom, np.concatenate(c.pred["Ei"])) < TOL_E
+    assert rel(F, np.concatenate(c.pred["F"], 0)) < TOL_F
+    assert rel(W, c.pred["W"]) < TOL_F
+    loss, grad, *_ = r.loss_grad()
+    np.testing.assert_allclose(loss, c.loss, rtol=1e-4)
+    for blk, sl in param_blocks(c.sizes).items():
+        assert rel(grad[sl], c.grad[sl]) < TOL_F, blk
