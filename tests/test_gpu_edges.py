@@ -153,11 +153,14 @@ def test_isolated_atom_and_vacuum_cluster():
         assert rel(grad[sl], c.grad[sl]) < TOL_F, blk
 
 
-def test_empty_batch():
+@pytest.mark.parametrize("sizes", ["small", "l8"])
+def test_empty_batch(sizes):
+    """No atoms: every entry point returns without a launch of zero blocks
+    (with degrees l > 4 too), the loss and gradient are zero."""
     import torch
     from paper_2507_00528_amd import nep
     b = synth.Batch([])
-    sz = synth.SIZES_SMALL
+    sz = synth.SIZES_SMALL if sizes == "small" else synth.SIZES_L8
     model = nep.Model.of(sz)
     db = nep.DeviceBatch(b)
     nb = nep.Neighbors(model, 0)
@@ -173,6 +176,11 @@ def test_empty_batch():
     assert int(fl.item()) == 0
     assert (grad.cpu().numpy() == 0).all()
     assert (loss.cpu().numpy() == 0).all()
+    e = torch.zeros(0, device="cuda")
+    grad.fill_(7.0)
+    nep.vjp(model, db, nb, params, e, e, e, grad, ws)
+    torch.cuda.synchronize()
+    assert (grad.cpu().numpy() == 0).all()
 
 
 def test_predicate_rounding_order():
