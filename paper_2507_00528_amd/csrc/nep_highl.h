@@ -818,8 +818,11 @@ struct HighCoefShape {
 // forms X_n, Y_n of pair p.  Phase two: lane (n, k) adds up the chunk's
 // pairs for its coefficient slots, one register per neighbor species J.
 // One wavefront per block: the LDS per wavefront is the occupancy limit.
+// With n_ang <= 4 the table leaves room for about 10 wavefronts per CU, and
+// the register budget is set to match (3 per SIMD); the wider classes' table
+// allows fewer, and they keep the default budget.
 template <class C, bool kTri>
-__global__ __launch_bounds__(kWave, 3) void k_high_coef(HighArgs a) {
+__global__ __launch_bounds__(kWave, C::NA <= 4 ? 3 : 1) void k_high_coef(HighArgs a) {
   using S = HighCoefShape<C>;
   constexpr int T = C::T, NA = C::NA, KA = C::KA, L3 = C::L3, YH = C::YH, AS = S::AS, RS = S::RS;
   __shared__ __align__(16) float lds[S::WORDS];
