@@ -1126,10 +1126,21 @@ struct CTab {
 
 template <int T, int NA, int KA>
 __device__ __forceinline__ void stage_ctab(float* ct, const float* __restrict__ cA) {
-  constexpr int KAP = CTab<T, NA, KA>::KAP;
-  for (int q = threadIdx.x; q < CTab<T, NA, KA>::size; q += blockDim.x) {
-    const int k = q % KAP, r = q / KAP;
-    ct[q] = k < KA ? cA[r * KA + k] : 0.f;
+  constexpr int KAP = CTab<T, NA, KA>::KAP, SZ = CTab<T, NA, KA>::size, U = 8;
+  // U words per thread per round, the loads issued before the stores
+  for (int base = 0; base < SZ; base += U * (int)blockDim.x) {
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = base + u * (int)blockDim.x + (int)threadIdx.x;
+      const int k = q % KAP, r = q / KAP;
+      v[u] = (q < SZ && k < KA) ? cA[r * KA + k] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = base + u * (int)blockDim.x + (int)threadIdx.x;
+      if (q < SZ) ct[q] = v[u];
+    }
   }
 }
 
@@ -1283,22 +1294,29 @@ __device__ __forceinline__ int block_species(const int* __restrict__ order, cons
   return ip >= 0 ? type[ip] : 0;
 }
 
-// stage species I's W0 (rows padded to DP floats), b0 and w1 into LDS
-__device__ __forceinline__ void stage_weights(float* wl, const float* __restrict__ nn, int nn_stride, int I, int H,
-                                              int D, int DP) {
-  const int WS = H * DP + 2 * H;
+// LDS words of the staged weights: whole 64-word rows, so that the direct
+// loads below never write past them
+__host__ __device__ constexpr int weights_words(int H, int DP) { return (H * DP + 2 * H + 63) / 64 * 64; }
+
+// Species I's W0 (rows padded to DP words), b0 and w1 into LDS with direct
+// global-to-LDS loads (gfx950 global_load_lds_dword: each wavefront writes
+// 64 consecutive words and holds no registers for them), issued at the
+// block's start and waited for by wait_weights() before the network, so
+// their latency overlaps the pair passes instead of preceding them.  W0's
+// padding words (d >= D, never read) receive W0[0][0].
+__device__ __forceinline__ void stage_weights_async(float* wl, const float* __restrict__ nn, int nn_stride, int I,
+                                                    int H, int D, int DP) {
+  const int WS = H * DP + 2 * H, WSP = weights_words(H, DP);
   const float* w = nn + (size_t)I * nn_stride;
-  for (int q = threadIdx.x; q < WS; q += blockDim.x) {
-    float v = 0.f;
-    if (q < H * DP) {
-      const int mu = q / DP, d = q % DP;
-      if (d < D) v = w[mu * D + d];
-    } else {
-      v = w[H * D + (q - H * DP)];
-    }
-    wl[q] = v;
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  for (int c0 = wv * kWave; c0 < WSP; c0 += nw * kWave) {
+    const int q = c0 + lane;
+    const int mu = q / DP, d = q % DP;
+    const int src = q < H * DP ? (d < D ? mu * D + d : 0) : (q < WS ? H * D + (q - H * DP) : 0);
+    __builtin_amdgcn_global_load_lds(w + src, (__attribute__((address_space(3))) void*)(wl + c0), 4, 0, 0);
   }
 }
+__device__ __forceinline__ void wait_weights() { __builtin_amdgcn_s_waitcnt(0); }
 
 // ================================================================= forward
 // Per atom: radial sums F[J][k] = sum_{j of type J} f_k(r_ij) give
@@ -1316,16 +1334,17 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int vb, float* ld
   constexpr int YG = HS::YG;
   constexpr int DP = (D + 3) & ~3;
   const int H = a.H;
-  const int WS = H * DP + 2 * H;
   constexpr int YR = HRow<LM>::YR;
   constexpr int RW = DP + NA * YR;        // LDS row per atom: G, S (group order)
   using CT = CTab<T, NA, KA>;
   float* ctab = lds;                     // [T][T][NA][KAP]
-  float* wl = lds + CT::size;            // [WS] of the block's species
-  float* rows = wl + WS;                 // [kAPB][RW]
+  float* wl = lds + CT::size;            // weights of the block's species
+  float* rows = wl + weights_words(H, DP);   // [kAPB][RW]
   stage_ctab<T, NA, KA>(ctab, a.cA);
-  if (a.do_mlp) stage_weights(wl, a.nn, a.nn_stride, block_species(a.order, a.type, vb), H, D, DP);
   __syncthreads();
+  // issued after the barrier (a barrier waits for every outstanding load) and
+  // waited for before the next one, ahead of the network
+  if (a.do_mlp) stage_weights_async(wl, a.nn, a.nn_stride, block_species(a.order, a.type, vb), H, D, DP);
   const GroupCtx w = group_ctx(a.order, a.type, a.Npad, vb);
   const int N = a.N, i = w.i, I = w.I, pa = w.pa, s = w.s, g = w.g;
   float* row = rows + w.al * RW;
@@ -1459,6 +1478,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int vb, float* ld
       row[v] = w.valid ? x : 0.f;
     }
   }
+  wait_weights();   // this wavefront's weight loads have landed; the barrier covers the others'
   __syncthreads();
   float G[D];
 #pragma unroll
@@ -1959,14 +1979,14 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs& a, int vb, float* ld
   constexpr int RW = DP + 2 * NA * YR;       // LDS row per atom: Gdot, Sbar, A (group order)
   constexpr int PSA = T * NA * KA;
   const int H = a.H;
-  const int WS = H * DP + 2 * H;
   using CT = CTab<T, NA, KA>;
   float* ctab = lds;                     // [T][T][NA][KAP]
-  float* wl = lds + CT::size;            // [WS] of the block's species
-  float* rows = wl + WS;                 // [kAPB][RW]
+  float* wl = lds + CT::size;            // weights of the block's species
+  float* rows = wl + weights_words(H, DP);   // [kAPB][RW]
   stage_ctab<T, NA, KA>(ctab, a.cA);
-  stage_weights(wl, a.nn, a.nn_stride, block_species(a.order, a.type, vb), H, D, DP);
   __syncthreads();
+  // as in the forward: issued after the barrier, waited for before the next
+  stage_weights_async(wl, a.nn, a.nn_stride, block_species(a.order, a.type, vb), H, D, DP);
   const GroupCtx w = group_ctx(a.order, a.type, a.Npad, vb);
   const int N = a.N, i = w.i, I = w.I, pa = w.pa, s = w.s, g = w.g;
   const int lane = threadIdx.x & (kWave - 1);
@@ -2138,6 +2158,7 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs& a, int vb, float* ld
       row[v] = w.valid ? x : 0.f;
     }
   }
+  wait_weights();   // this wavefront's weight loads have landed; the barrier covers the others'
   __syncthreads();
   float Gd[D];
 #pragma unroll
@@ -3128,13 +3149,13 @@ struct Ops {
 template <class C>
 static size_t lds_forward(int H) {
   const int DP = (C::D + 3) & ~3;
-  return sizeof(float) * ((size_t)CTab<C::T, C::NA, C::KA>::size + (size_t)(H * DP + 2 * H) +
+  return sizeof(float) * ((size_t)CTab<C::T, C::NA, C::KA>::size + (size_t)weights_words(H, DP) +
                           (size_t)kAPB * (DP + C::NA * HRow<C::LMAX>::YR));
 }
 template <class C>
 static size_t lds_adjoint(int H) {
   const int DP = (C::D + 3) & ~3;
-  return sizeof(float) * ((size_t)CTab<C::T, C::NA, C::KA>::size + (size_t)(H * DP + 2 * H) +
+  return sizeof(float) * ((size_t)CTab<C::T, C::NA, C::KA>::size + (size_t)weights_words(H, DP) +
                           (size_t)kAPB * (DP + 2 * C::NA * HRow<C::LMAX>::YR));
 }
 // LDS of a workgroup on gfx950 (160 KiB per CU); dynamic LDS beyond 64 KiB is
