@@ -94,7 +94,7 @@ def oracle_lists(case, which):
     return out
 
 
-class GPURun:
+class DeviceRun:
     """Device-side state for one case."""
 
     def __init__(self, case, cap_rad=64, cap_ang=32):

@@ -12,7 +12,7 @@ import pytest
 
 from paper_2507_00528_amd import synth
 
-from gpu_util import TOL_E, TOL_F, Case, GPURun, oracle_lists, param_blocks, rel
+from gpu_util import TOL_E, TOL_F, Case, DeviceRun, oracle_lists, param_blocks, rel
 from _helpers import cluster
 
 pytestmark = pytest.mark.gpu
@@ -29,7 +29,7 @@ def test_overflow_keeps_the_canonical_prefix():
     import torch
     from paper_2507_00528_amd import nep
     c = Case(synth.SIZES_SMALL, synth.config_structures("c0")[:3], with_oracle=False)
-    r = GPURun(c, cap_rad=8, cap_ang=4)
+    r = DeviceRun(c, cap_rad=8, cap_ang=4)
     print(f"[overflow] N={c.batch.n_atom}", flush=True)
     r.neighbors()
     torch.cuda.synchronize()
@@ -56,13 +56,13 @@ def test_reverse_index_complete_under_overflow():
     a = Case(synth.SIZES_SMALL, c0[:3], with_oracle=False)
     b = Case(synth.SIZES_SMALL, c0[3:6], with_oracle=False)
     assert a.batch.n_atom == b.batch.n_atom and a.batch.n_struct == b.batch.n_struct
-    r = GPURun(a, cap_rad=8, cap_ang=4)
+    r = DeviceRun(a, cap_rad=8, cap_ang=4)
     r.ws.zero_()
     print(f"[reverse overflow] N={a.batch.n_atom}", flush=True)
     r.neighbors()
     assert int(r.flags.item()) & nep.NEP_FLAG_NBR_OVERFLOW
     _, _, F_fresh, _ = r.efw()
-    other = GPURun(b, cap_rad=8, cap_ang=4)
+    other = DeviceRun(b, cap_rad=8, cap_ang=4)
     other.ws = r.ws
     other.neighbors()
     other.efw()
@@ -76,7 +76,7 @@ def test_dense_cell_spills_lane_buffers_and_stays_exact():
     import torch
     sts = [dense_cell(1, 80, 6.5), dense_cell(2, 56, 6.2)]
     c = Case(synth.SIZES_TINY, sts)
-    r = GPURun(c, cap_rad=512, cap_ang=256)
+    r = DeviceRun(c, cap_rad=512, cap_ang=256)
     print(f"[dense] N={c.batch.n_atom}", flush=True)
     r.neighbors()
     torch.cuda.synchronize()
@@ -137,7 +137,7 @@ def test_isolated_atom_and_vacuum_cluster():
                           np.array([1], np.int32), "isolated")
     sts = [iso, cluster(), synth.config_structures("c0")[0]]
     c = Case(synth.SIZES_LARGE, sts)
-    r = GPURun(c)
+    r = DeviceRun(c)
     print(f"[vacuum] N={c.batch.n_atom}", flush=True)
     r.neighbors()
     torch.cuda.synchronize()
@@ -212,7 +212,7 @@ def test_predicate_rounding_order():
         sts.append(synth.Structure(pos, np.full(3, 20.0, np.float32), np.array([0, 1], np.int32), "edge"))
     sz = dataclasses.replace(synth.SIZES_SMALL, rc_ang=3.0)
     c = Case(sz, sts, with_oracle=False)
-    r = GPURun(c)
+    r = DeviceRun(c)
     print(f"[rounding order] N={c.batch.n_atom}", flush=True)
     r.neighbors()
     torch.cuda.synchronize()

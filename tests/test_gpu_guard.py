@@ -7,7 +7,7 @@ import pytest
 
 from paper_2507_00528_amd import synth
 
-from gpu_util import Case, GPURun
+from gpu_util import Case, DeviceRun
 
 pytestmark = pytest.mark.gpu
 
@@ -16,7 +16,7 @@ def _graph_run(cap_rad, cap_ang, step0):
     import torch
     from paper_2507_00528_amd import nep
     c = Case(synth.SIZES_SMALL, synth.config_structures("c0")[:3], with_oracle=False)
-    r = GPURun(c, cap_rad=cap_rad, cap_ang=cap_ang)
+    r = DeviceRun(c, cap_rad=cap_rad, cap_ang=cap_ang)
     P = r.params.numel()
     g = torch.Generator(device="cpu").manual_seed(5)
     m = (0.01 * torch.randn(P, generator=g)).cuda()

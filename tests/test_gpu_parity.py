@@ -6,7 +6,7 @@ import pytest
 
 from paper_2507_00528_amd import synth
 
-from gpu_util import TOL_E, TOL_F, Case, GPURun, oracle_lists, param_blocks, rel
+from gpu_util import TOL_E, TOL_F, Case, DeviceRun, oracle_lists, param_blocks, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -33,7 +33,7 @@ _CACHE = {}
 def case(name):
     if name not in _CACHE:
         c = _cases()[name]()
-        r = GPURun(c)
+        r = DeviceRun(c)
         print(f"[case {name}] S={c.batch.n_struct} N={c.batch.n_atom}", flush=True)
         r.neighbors()
         _CACHE[name] = (c, r)

@@ -14,7 +14,7 @@ import pytest
 
 from paper_2507_00528_amd import synth
 
-from gpu_util import TOL_F, Case, GPURun, param_blocks, rel, structures
+from gpu_util import TOL_F, Case, DeviceRun, param_blocks, rel, structures
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -52,7 +52,7 @@ def test_persistent_step_matches_oracle_and_separate_launches(name):
     else:
         small = [synth.random_structure(rng, n, 0.031, 2.4, "liquid") for n in (10, 13, 40)]
         case = Case(synth.SIZES_MONO, [synth.Structure(s.pos, s.box, np.zeros(s.n, np.int32)) for s in small])
-    r = GPURun(case)
+    r = DeviceRun(case)
     print(f"[persistent {name}] S={r.S} N={r.N}", flush=True)
     pers = _graph(r.nep, r.model, r.batch, r.labels, case.lam, r.params, r.N, r.S, True)
     sep = _graph(r.nep, r.model, r.batch, r.labels, case.lam, r.params, r.N, r.S, False)
@@ -107,7 +107,7 @@ def test_persistent_step_rejects_what_it_does_not_cover():
     tri = [synth.triclinic_structure(rng, 40, 0.031, 2.5)]
     for sizes, sts in ((synth.SIZES_LARGE, tri), (synth.SIZES_L8, synth.config_structures("c0"))):
         case = Case(sizes, sts, with_oracle=False)
-        r = GPURun(case)
+        r = DeviceRun(case)
         with pytest.raises(nep.NEPError) as e:
             _graph(nep, r.model, r.batch, r.labels, case.lam, r.params, r.N, r.S, True)
         assert e.value.code == -1

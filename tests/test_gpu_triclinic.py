@@ -14,7 +14,7 @@ import pytest
 from paper_2507_00528_amd import md, synth
 
 from _helpers import grid_structure, hmat, sheared, widths
-from gpu_util import TOL_E, TOL_F, Case, GPURun, oracle_lists, param_blocks, rel
+from gpu_util import TOL_E, TOL_F, Case, DeviceRun, oracle_lists, param_blocks, rel
 
 pytestmark = pytest.mark.gpu
 RC = synth.SIZES_LARGE.rc_rad
@@ -35,7 +35,7 @@ def test_triclinic_batch_against_oracle():
     w = [widths(hmat(st.box, st.tilt if st.tilt is not None else np.zeros(3))).min() for st in sts]
     assert min(w[:3]) >= WIDE and RC <= w[3] < WIDE     # both decision paths are taken
     c = Case(synth.SIZES_LARGE, sts)
-    r = GPURun(c)
+    r = DeviceRun(c)
     print(f"[triclinic] N={c.batch.n_atom} widths={np.round(w, 2).tolist()}", flush=True)
     r.neighbors()
     torch.cuda.synchronize()
@@ -63,7 +63,7 @@ def test_sheared_cell_matches_the_orthorhombic_crystal(L, tilt):
     st = grid_structure(4, 48, L)
     tri = sheared(st, tilt)
     c = Case(synth.SIZES_LARGE, [st])
-    r = GPURun(GPUCase(c, [tri]))
+    r = DeviceRun(GPUCase(c, [tri]))
     print(f"[sheared] L={L} tilt={tilt}", flush=True)
     r.neighbors()
     torch.cuda.synchronize()

@@ -10,7 +10,7 @@ import pytest
 
 from paper_2507_00528_amd import synth, tune
 
-from gpu_util import TOL_F, Case, GPURun, param_blocks, rel, structures
+from gpu_util import TOL_F, Case, DeviceRun, param_blocks, rel, structures
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -51,7 +51,7 @@ def test_tuned_choices_match_oracle(k):
     rng = np.random.default_rng(17)
     sts = synth.config_structures("c2", n_struct=6) + [synth.random_structure(rng, 600, 0.031, 2.7, "amorphous")]
     case = _case_cache(sts)
-    r = GPURun(case)
+    r = DeviceRun(case)
     print(f"[tuning {CHOICES[k]}] S={r.S} N={r.N}", flush=True)
     loss, grad = _step(r, CHOICES[k])
     np.testing.assert_allclose(loss, case.loss, rtol=1e-4)

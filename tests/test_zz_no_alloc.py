@@ -9,7 +9,7 @@ import pytest
 
 from paper_2507_00528_amd import synth
 
-from gpu_util import TOL_E, TOL_F, Case, GPURun, param_blocks, rel
+from gpu_util import TOL_E, TOL_F, Case, DeviceRun, param_blocks, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -58,7 +58,7 @@ def test_noalloc_matches_workspace_path_twice_second_smaller():
     second = [synth.random_structure(rng, n, 0.031, 2.5, "amorphous") for n in (17, 40, 96)]
     for k, sts in enumerate((first, second)):
         case = Case(synth.SIZES_LARGE, sts, with_oracle=(k == 0))
-        r = GPURun(case)
+        r = DeviceRun(case)
         print(f"[noalloc call {k + 1}] S={r.S} N={r.N}", flush=True)
         got = _run_noalloc(r)
         r.neighbors()
