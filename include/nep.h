@@ -314,10 +314,14 @@ int nep_train_step_graph_create(const nep_model* model, const nep_batch* batch, 
  *   gather_lanes    lanes per atom of the force gather, 8 or 16 [16]
  *   forward_waves   wavefronts per SIMD the forward kernel is compiled for, 2 or 3 [3]
  *   adjoint_waves   the same for the adjoint kernel [3; 2 with degrees l > 4]
+ *   reverse_branch  where the reverse index of the lists runs: 1 in the launch
+ *                   that also counts the species order, 2 on a branch of its
+ *                   own that overlaps the species order and the forward pass
+ *                   and joins before the force gather [1]
  * A value out of range is NEP_ERR_ARG. */
 typedef struct {
   int32_t persistent, outer_blocks_w, outer_blocks_c, reduce_chunks, cell_min_atoms, gather_lanes,
-      forward_waves, adjoint_waves;
+      forward_waves, adjoint_waves, reverse_branch;
 } nep_tuning;
 
 /* nep_train_step_graph_create() with launch choices (tuning may be NULL). */

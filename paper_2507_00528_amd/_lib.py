@@ -40,7 +40,8 @@ class NepAdamConfig(C.Structure):
 class NepTuning(C.Structure):
     _fields_ = [("persistent", C.c_int32), ("outer_blocks_w", C.c_int32), ("outer_blocks_c", C.c_int32),
                 ("reduce_chunks", C.c_int32), ("cell_min_atoms", C.c_int32), ("gather_lanes", C.c_int32),
-                ("forward_waves", C.c_int32), ("adjoint_waves", C.c_int32)]
+                ("forward_waves", C.c_int32), ("adjoint_waves", C.c_int32),
+                ("reverse_branch", C.c_int32)]
 
 
 P = C.POINTER

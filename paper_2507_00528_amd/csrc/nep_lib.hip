@@ -3483,11 +3483,12 @@ int hip_ok() { return hipGetLastError() == hipSuccess ? NEP_OK : NEP_ERR_HIP; }
 
 // Launch choices of one evaluation (nep_tuning with the defaults filled in).
 struct Tune {
-  int persistent, outer_w, outer_c, reduce_chunks, cell_min, gather_lanes, forward_waves, adjoint_waves;
+  int persistent, outer_w, outer_c, reduce_chunks, cell_min, gather_lanes, forward_waves, adjoint_waves,
+      reverse_branch;
 };
 
 Tune default_tune(const Ops* o) {
-  return Tune{0, kOSBlocksW, kOSBlocksC, kPRChunks, kCellMinAtoms, kGatherLPA, 3, o->YH > 0 ? 2 : 3};
+  return Tune{0, kOSBlocksW, kOSBlocksC, kPRChunks, kCellMinAtoms, kGatherLPA, 3, o->YH > 0 ? 2 : 3, 1};
 }
 
 struct Ctx {
@@ -3505,6 +3506,11 @@ struct Ctx {
   // the captured training step: Adam after the gradient, fused into its
   // final reduction
   const struct AdamFuse* adam = nullptr;
+  // the captured step's side branch: the reverse index runs there, beside the
+  // species order and the forward pass, and rejoins before the force gather
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  mutable bool rev_pending = false;
 };
 
 struct AdamFuse {
@@ -3605,8 +3611,18 @@ void run_neighbors(const Ctx& c, nep_neighbors* nb, int32_t* flags, Prof* pr, bo
     return;
   }
   const OrderArgs oa = order_args(c, nb);
-  NEP_LAUNCH(pr, "reverse_order_count",
-             hipLaunchKernelGGL(k_reverse_count, dim3(nrev + c.L.nblk), dim3(256), 0, c.st, r, oa, nrev));
+  if (c.side) {
+    (void)hipEventRecord(c.fork, c.st);
+    (void)hipStreamWaitEvent(c.side, c.fork, 0);
+    NEP_LAUNCH(pr, "reverse", hipLaunchKernelGGL(k_reverse, dim3(nrev), dim3(256), 0, c.side, r));
+    (void)hipEventRecord(c.join, c.side);
+    c.rev_pending = true;
+    NEP_LAUNCH(pr, "order_count",
+               hipLaunchKernelGGL(k_reverse_count, dim3(c.L.nblk), dim3(256), 0, c.st, r, oa, 0));
+  } else {
+    NEP_LAUNCH(pr, "reverse_order_count",
+               hipLaunchKernelGGL(k_reverse_count, dim3(nrev + c.L.nblk), dim3(256), 0, c.st, r, oa, nrev));
+  }
   NEP_LAUNCH(pr, "order_scan", hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(512), 0, c.st, oa));
   NEP_LAUNCH(pr, "order_scatter",
              hipLaunchKernelGGL(k_order_scatter, dim3(c.L.nblk), dim3(kOrdBlk), 0, c.st, oa));
@@ -3729,6 +3745,10 @@ void run_forward(const Ctx& c, const nep_neighbors* nb, const float* params, flo
     FwdArgs a = fwd_args(c, nb, params);
     a.eatom2 = e_atom;
     launch_forward_pass(c, nb, params, a, pr);
+    if (c.rev_pending) {
+      (void)hipStreamWaitEvent(c.st, c.join, 0);
+      c.rev_pending = false;
+    }
     if (c.tune.gather_lanes == 8)
       NEP_LAUNCH(pr, "force_gather", hipLaunchKernelGGL(k_force_gather<8>, dim3(grid1(N, 256 / 8)), dim3(256), 0, c.st,
                                                         N, a.nb, a.fR, a.fA, at<float>(c.ws, c.L.F), force));
@@ -4064,6 +4084,7 @@ int apply_tuning(Tune& t, const nep_tuning* u) {
   if (u->gather_lanes) t.gather_lanes = u->gather_lanes;
   ok = ok && set(t.forward_waves, u->forward_waves, 2, 3);
   ok = ok && set(t.adjoint_waves, u->adjoint_waves, 2, 3);
+  ok = ok && set(t.reverse_branch, u->reverse_branch, 1, 2);
   return ok ? NEP_OK : NEP_ERR_ARG;
 }
 
@@ -4306,8 +4327,23 @@ int nep_train_step_graph_create_tuned(const nep_model* m, const nep_batch* b, ne
   hipStream_t cap;
   if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return NEP_ERR_HIP;
   c.st = cap;
+  // the reverse index's own branch (a stream of default priority, as every stream here)
+  auto drop_side = [&c]() {
+    if (c.side) (void)hipStreamDestroy(c.side);
+    if (c.fork) (void)hipEventDestroy(c.fork);
+    if (c.join) (void)hipEventDestroy(c.join);
+    c.side = nullptr;
+  };
+  if (!persistent && c.tune.reverse_branch == 2 && (hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking) != hipSuccess ||
+                      hipEventCreateWithFlags(&c.fork, hipEventDisableTiming) != hipSuccess ||
+                      hipEventCreateWithFlags(&c.join, hipEventDisableTiming) != hipSuccess)) {
+    drop_side();
+    (void)hipStreamDestroy(cap);
+    return NEP_ERR_HIP;
+  }
   hipGraph_t g = nullptr;
   if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    drop_side();
     (void)hipStreamDestroy(cap);
     return NEP_ERR_HIP;
   }
@@ -4332,6 +4368,7 @@ int nep_train_step_graph_create_tuned(const nep_model* m, const nep_batch* b, ne
   }
   const hipError_t e1 = hipStreamEndCapture(cap, &g);
   (void)hipStreamDestroy(cap);
+  drop_side();
   if (e1 != hipSuccess || !g) return NEP_ERR_HIP;
   hipGraphExec_t ex;
   if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {

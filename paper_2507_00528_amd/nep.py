@@ -270,7 +270,7 @@ def md_step(model, batch, nbrs, params, mass, vel, force, dt, n_steps, e_pot, ws
 
 
 TUNING_FIELDS = ("persistent", "outer_blocks_w", "outer_blocks_c", "reduce_chunks", "cell_min_atoms",
-                 "gather_lanes", "forward_waves", "adjoint_waves")
+                 "gather_lanes", "forward_waves", "adjoint_waves", "reverse_branch")
 
 
 def tuning_struct(tuning):

@@ -37,6 +37,7 @@ SPACE = {
     "reduce_chunks": [128, 64, 256],
     "gather_lanes": [16, 8],
     "cell_min_atoms": [1024, 512, 2048],
+    "reverse_branch": [1, 2],
 }
 DEFAULTS = {k: v[0] for k, v in SPACE.items()}
 

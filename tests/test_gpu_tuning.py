@@ -17,8 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 CHOICES = [
     {"outer_blocks_w": 96, "outer_blocks_c": 32, "reduce_chunks": 64, "gather_lanes": 8, "forward_waves": 2,
-     "adjoint_waves": 2},
-    {"outer_blocks_w": 384, "outer_blocks_c": 128, "reduce_chunks": 256, "cell_min_atoms": 512},
+     "adjoint_waves": 2, "reverse_branch": 2},
+    {"outer_blocks_w": 384, "outer_blocks_c": 128, "reduce_chunks": 256, "cell_min_atoms": 512, "reverse_branch": 2},
     {"persistent": 1, "outer_blocks_w": 128, "reduce_chunks": 64},
 ]
 
