@@ -1375,24 +1375,25 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, int vb, float* ld
       for (int kk = 0; kk < KR; ++kk) FR[t][kk] = fmaf(m, f[kk], FR[t][kk]);
     }
   }
-  // q_n from this lane's partial sums, then summed over the 8 lanes
-  // (scattered: q_n in lane n & 7)
+  // the basis sums over the 8 lanes, then q_n = sum c^R F by lane n & 7
   {
-    float qn[NR];
 #pragma unroll
-    for (int n = 0; n < NR; ++n) {
-      float acc = 0.f;
+    for (int t = 0; t < T; ++t)
 #pragma unroll
-      for (int t = 0; t < T; ++t)
+      for (int k = 0; k < KR; ++k) FR[t][k] = grp8_sum(FR[t][k]);
 #pragma unroll
-        for (int k = 0; k < KR; ++k) acc = fmaf(cRI[(t * NR + n) * KR + k], FR[t][k], acc);
-      qn[n] = acc;
+    for (int n0 = 0; n0 < NR; n0 += kLPA) {
+      const int n = n0 + s;
+      if (n < NR) {
+        const cptr<float> cn = cRI + n * KR;
+        float acc = 0.f;
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+          for (int k = 0; k < KR; ++k) acc = fmaf(cn[t * NR * KR + k], FR[t][k], acc);
+        row[n] = acc;
+      }
     }
-    float qo[(NR + 7) / 8];
-    rs_group8(qn, qo);
-#pragma unroll
-    for (int r = 0; r < (NR + 7) / 8; ++r)
-      if (8 * r + s < NR) row[8 * r + s] = qo[r];
   }
 
   // ---- angular sums S_nlm: harmonic group g, pairs p, p+4, ...
@@ -2047,16 +2048,20 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs& a, int vb, float* ld
         a.FPst[(size_t)e * a.Npad + pa] = FP[t][k];
       }
     }
+  // every lane holds the sums: lane s takes channels n = s, s + 8, ... at once
 #pragma unroll
-  for (int n = 0; n < NR; ++n)
-    if (s == (n & 7)) {
+  for (int n0 = 0; n0 < NR; n0 += kLPA) {
+    const int n = n0 + s;
+    if (n < NR) {
+      const cptr<float> cn = cRI + n * KR;
       float acc = 0.f;
 #pragma unroll
       for (int t = 0; t < T; ++t)
 #pragma unroll
-        for (int k = 0; k < KR; ++k) acc = fmaf(cRI[(t * NR + n) * KR + k], FP[t][k], acc);
+        for (int k = 0; k < KR; ++k) acc = fmaf(cn[t * NR * KR + k], FP[t][k], acc);
       row[n] = acc;
     }
+  }
 
   // ---- angular tangent pass: Sdot_nlm = sum_j g'_n (r_hat.t) B_lm + g_n grad B_lm . t
   float Sd[NA][YG];
