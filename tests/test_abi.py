@@ -155,7 +155,7 @@ def test_tuned_graph_create_rejects_out_of_range_choices_before_launch():
     cfg = _lib.NepAdamConfig(1e-3, 1e-3, 0, 0, 0.9, 0.999, 1e-8)
     h = C.c_void_p()
     for bad in ({"gather_lanes": 12}, {"forward_waves": 4}, {"outer_blocks_w": 513}, {"reduce_chunks": -1},
-                {"cell_min_atoms": 10}, {"persistent": 2}):
+                {"cell_min_atoms": 10}, {"persistent": 2}, {"reverse_branch": 3}, {"reverse_branch": -1}):
         t = nep.tuning_struct(bad)
         rc = lib.nep_train_step_graph_create_tuned(C.byref(m), C.byref(b), C.byref(nb), C.byref(lab), C.byref(lam),
                                                    fake, fake, fake, fake, fake, fake, C.byref(cfg), fake, fake, 0,
