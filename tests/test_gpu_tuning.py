@@ -103,3 +103,44 @@ def test_cached_choices_full_size_against_golden(name):
     for blk, sl in param_blocks(sz).items():
         assert rel(gg[sl], gd["grad"][sl]) < TOL_F, blk
     g.close()
+
+
+def test_reverse_branch_replays_equal_single_stream():
+    """The captured step with the reverse index on its own branch (a second
+    stream joined before the force gather) gives, replay after replay with
+    eager work in between, bit for bit the loss, gradient and Adam update of
+    the single-stream step: the branch only moves the launch."""
+    import torch
+    from paper_2507_00528_amd import nep
+    rng = np.random.default_rng(17)
+    sts = synth.config_structures("c2", n_struct=6) + [synth.random_structure(rng, 600, 0.031, 2.7, "amorphous")]
+    case = _case_cache(sts)
+    r = DeviceRun(case)
+    P = r.params.numel()
+    print(f"[reverse branch] S={r.S} N={r.N}", flush=True)
+
+    def make(choice):
+        st = dict(params=r.params.clone(), m=torch.zeros(P, device="cuda"), v=torch.zeros(P, device="cuda"),
+                  grad=torch.zeros(P, device="cuda"), loss=torch.zeros(4, device="cuda"),
+                  step=torch.ones(1, dtype=torch.int32, device="cuda"),
+                  flags=torch.zeros(1, dtype=torch.int32, device="cuda"))
+        st["g"] = nep.TrainStepGraph(r.model, r.batch, nep.Neighbors(r.model, r.N), r.labels, case.lam,
+                                     st["params"], st["m"], st["v"], st["grad"], st["loss"], st["step"],
+                                     nep.workspace(r.model, r.S, r.N), st["flags"], lr_start=1e-3, lr_stop=1e-3,
+                                     tuning={"reverse_branch": choice})
+        return st
+
+    one, two = make(1), make(2)
+    for _ in range(3):
+        one["g"].launch()
+        two["g"].launch()
+        torch.cuda.synchronize()
+        # eager work between replays
+        nep.build_neighbors(r.model, r.batch, r.nbrs, r.ws, r.flags)
+        torch.cuda.synchronize()
+        for k in ("loss", "grad", "params", "m", "v"):
+            assert torch.equal(one[k], two[k]), k
+        assert int(one["flags"].item()) == 0 and int(two["flags"].item()) == 0
+    assert int(two["step"].item()) == 4
+    one["g"].close()
+    two["g"].close()
